@@ -1,0 +1,155 @@
+"""Model topologies as plain node lists (no arithmetic).
+
+A model is a dict ``{"name", "nodes", "in_channels", "out_channels"}``.  Nodes
+are evaluated in list order; node 0 is the input.  Node kinds:
+
+* ``{"op": "input", "channels": C}``
+* ``{"op": "conv", "src": i, "cin", "cout", "k", "dilation", "stride",
+  "pad_l", "pad_r", "pre_act", "post_act"}`` -- a 1-D convolution in the
+  correlation form of the paper's Eq. 1, with dilation, stride and the
+  zero padding the layer was *trained* with (left ``pad_l``, right ``pad_r``).
+* ``{"op": "convt", "src": i, "cin", "cout", "k", "stride", "pad",
+  "pre_act"}`` -- a transposed convolution (paper Sec. 2.1) that upsamples
+  time by ``stride`` and crops ``pad`` frames on each side.
+* ``{"op": "add", "src": i, "src2": j}`` -- two parallel branches summed
+  (paper Sec. 3.2).
+
+``pre_act`` = 1 applies LeakyReLU(slope 0.2) to the node's input before the
+convolution; ``post_act`` = 2 applies tanh to the conv output.
+
+Weights are one flat float32 array, consumed in node order: for ``conv``
+``W[cout][cin][k]`` then ``b[cout]``; for ``convt`` ``W[cin][cout][k]`` (the
+PyTorch ConvTranspose1d layout) then ``b[cout]``.
+"""
+
+LRELU_SLOPE = 0.2
+
+ACT_NONE = 0
+ACT_LRELU = 1
+ACT_TANH = 2
+
+
+def _input(c):
+    return {"op": "input", "channels": int(c)}
+
+
+def _conv(src, cin, cout, k, dilation=1, stride=1, pad_l=None, pad_r=None,
+          pre_act=ACT_NONE, post_act=ACT_NONE):
+    if pad_l is None:
+        # symmetric "same" padding of a stride-1 conv: d(k-1)/2 each side
+        tot = dilation * (k - 1)
+        pad_l = tot // 2
+        pad_r = tot - pad_l
+    return {"op": "conv", "src": int(src), "cin": int(cin), "cout": int(cout),
+            "k": int(k), "dilation": int(dilation), "stride": int(stride),
+            "pad_l": int(pad_l), "pad_r": int(pad_r),
+            "pre_act": int(pre_act), "post_act": int(post_act)}
+
+
+def _convt(src, cin, cout, ratio, pre_act=ACT_LRELU):
+    # kernel 2r, symmetric crop r/2: T frames in -> T*r frames out
+    assert ratio % 2 == 0, "ratio must be even for a symmetric crop"
+    return {"op": "convt", "src": int(src), "cin": int(cin), "cout": int(cout),
+            "k": 2 * int(ratio), "stride": int(ratio), "pad": int(ratio) // 2,
+            "pre_act": int(pre_act)}
+
+
+def _add(a, b):
+    return {"op": "add", "src": int(a), "src2": int(b)}
+
+
+def stack3():
+    """Plain 3-layer cached conv stack: 1->16 (k3,d1), 16->16 (k3,d2),
+    16->16 (k3,d4), symmetric padding, LeakyReLU 0.2 between layers."""
+    nodes = [_input(1),
+             _conv(0, 1, 16, 3, 1),
+             _conv(1, 16, 16, 3, 2, pre_act=ACT_LRELU),
+             _conv(2, 16, 16, 3, 4, pre_act=ACT_LRELU)]
+    return {"name": "stack3", "nodes": nodes, "in_channels": 1, "out_channels": 16}
+
+
+def decoder(name, latent, widths, ratios, dilations, out_k=7):
+    """RAVE-style decoder: input conv k3 latent->widths[0]; per stage
+    LeakyReLU -> ConvTranspose1d(stride r, k=2r) widths[s]->widths[s+1], then
+    one residual block per dilation d: x + Conv_k3,d(LeakyReLU(x)); finally
+    tanh(Conv_k7(LeakyReLU(x))) to one channel."""
+    assert len(widths) == len(ratios) + 1
+    nodes = [_input(latent), _conv(0, latent, widths[0], 3, 1)]
+    for s, r in enumerate(ratios):
+        cin, cout = widths[s], widths[s + 1]
+        nodes.append(_convt(len(nodes) - 1, cin, cout, r))
+        for d in dilations:
+            x = len(nodes) - 1
+            nodes.append(_conv(x, cout, cout, 3, d, pre_act=ACT_LRELU))
+            nodes.append(_add(x, len(nodes) - 1))
+    nodes.append(_conv(len(nodes) - 1, widths[-1], 1, out_k, 1,
+                       pre_act=ACT_LRELU, post_act=ACT_TANH))
+    return {"name": name, "nodes": nodes, "in_channels": latent, "out_channels": 1}
+
+
+def rave_decoder_b():
+    """Decoder with 16 latent channels, widths 512->256->128->64->32,
+    ratios [4,4,4,2] (128 samples per latent frame), dilations 1, 3, 9."""
+    return decoder("rave_b", 16, [512, 256, 128, 64, 32], [4, 4, 4, 2], [1, 3, 9])
+
+
+def wide_decoder():
+    """Wide decoder: 128 latent channels, widths 768->384->192->96->48,
+    ratios [8,8,4,2] (512 samples per latent frame), dilations 1, 3, 9, 27."""
+    return decoder("wide", 128, [768, 384, 192, 96, 48], [8, 8, 4, 2], [1, 3, 9, 27])
+
+
+def strided_unit(aligned=False):
+    """Cached conv then a strided conv (paper Sec. 3.1).
+
+    ``aligned=False``: Conv k5 (right pad 2) -> Conv K=4, S=2, pads 1/1, so
+    R + D_c = 3 is odd and the strided layer needs one extra delay frame.
+    ``aligned=True``: Conv k3 (right pad 1) -> same strided conv, R + D_c = 2,
+    no extra delay needed."""
+    k0 = 3 if aligned else 5
+    nodes = [_input(2),
+             _conv(0, 2, 8, k0, 1),
+             _conv(1, 8, 8, 4, 1, stride=2, pad_l=1, pad_r=1, pre_act=ACT_LRELU)]
+    return {"name": "strided_aligned" if aligned else "strided",
+            "nodes": nodes, "in_channels": 2, "out_channels": 8}
+
+
+def branch_unit():
+    """Two parallel convs of the same input, (k3, d1) and (k5, d2), summed
+    (paper Sec. 3.2): their post-reconfiguration delays are 1 and 4 frames."""
+    nodes = [_input(4),
+             _conv(0, 4, 8, 3, 1),
+             _conv(0, 4, 8, 5, 2),
+             _add(1, 2)]
+    return {"name": "branch", "nodes": nodes, "in_channels": 4, "out_channels": 8}
+
+
+def encoder(name="encoder", ratios=(4, 4, 4, 2), widths=(16, 32, 64, 128, 256), latent=16):
+    """RAVE-style strided-conv encoder: Conv k7 1->widths[0], then per ratio
+    r: LeakyReLU -> Conv(k=2r+1, stride r, pads r/r), then LeakyReLU -> Conv k3
+    to the latent size.  Input buffers must be multiples of prod(ratios)."""
+    nodes = [_input(1), _conv(0, 1, widths[0], 7, 1)]
+    for s, r in enumerate(ratios):
+        nodes.append(_conv(len(nodes) - 1, widths[s], widths[s + 1], 2 * r + 1, 1,
+                           stride=r, pad_l=r, pad_r=r, pre_act=ACT_LRELU))
+    nodes.append(_conv(len(nodes) - 1, widths[len(ratios)], latent, 3, 1, pre_act=ACT_LRELU))
+    return {"name": name, "nodes": nodes, "in_channels": 1, "out_channels": latent}
+
+
+def model_by_name(name):
+    table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder,
+             "strided": lambda: strided_unit(False),
+             "strided_aligned": lambda: strided_unit(True),
+             "branch": branch_unit, "encoder": encoder}
+    return table[name]()
+
+
+def n_weights(model):
+    """Number of float32 values in the flat weight array of ``model``."""
+    n = 0
+    for nd in model["nodes"]:
+        if nd["op"] == "conv":
+            n += nd["cout"] * nd["cin"] * nd["k"] + nd["cout"]
+        elif nd["op"] == "convt":
+            n += nd["cin"] * nd["cout"] * nd["k"] + nd["cout"]
+    return n
