@@ -1,0 +1,242 @@
+#!/usr/bin/env python
+"""Throughput of streamed decoding on one MI355X.
+
+Workload (the serving configuration): the RAVE-style decoder (16 latent
+channels, widths 512->256->128->64->32, ratios [4,4,4,2], dilations 1/3/9,
+128 output samples per latent frame) with 256 concurrent streams; every step
+each stream processes its next buffer, whose length is drawn uniformly from
+{1, 2, 4, 8, 16, 32} latent frames.  One step = one batched pass of the whole
+streaming path over all 256 buffers (closed loop: every stream always has its
+next buffer ready).  Inputs are seeded N(0,1) latents already resident in HBM.
+
+Prints one JSON line: output samples/s, the roofline fraction of the
+dominant kernel (per-launch HIP events on the processing stream), the
+per-step latency percentiles, the same workload at the other precisions, and
+the FP64 CPU oracle timed on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import scgen  # noqa: E402
+
+BUF_CHOICES = (1, 2, 4, 8, 16, 32)
+N_STREAMS = 256
+LATENT = 16
+SPF = 128          # output samples per latent frame
+HBM_PEAK = 8.0e12  # B/s
+PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
+PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
+DTYPE = {0: "fp32", 1: "bf16", 2: "fp8e4m3"}
+
+
+def op_accounting(p):
+    """Algorithmic FLOPs and HBM bytes of one op summed over its timed
+    launches: inputs read once, outputs written once, state (caches, carries,
+    delay lines) read and written once per stream, weights read once per
+    launch."""
+    fin, fout, ent, L = p["frames_in"], p["frames_out"], p["entries"], p["launches"]
+    wb = {0: 4, 1: 2, 2: 1}[p["precision"]]
+    if p["kind"] == 1:
+        flops = 2.0 * fout * p["cout"] * p["cin"] * p["k"]
+        byts = 4.0 * (fin * p["cin"] + fout * p["cout"] + ent * 2 * p["cache_len"] * p["cin"])
+        byts += L * (wb * p["cout"] * p["cin"] * p["k"] + 4 * p["cout"])
+    elif p["kind"] == 2:
+        flops = 2.0 * fout * p["cout"] * 2 * p["cin"]
+        byts = 4.0 * (fin * p["cin"] + fout * p["cout"] + ent * 2 * p["cache_len"] * p["cout"])
+        byts += L * (wb * p["cout"] * p["cin"] * p["k"] + 4 * p["cout"])
+    else:
+        flops = 1.0 * fout * p["cout"]
+        byts = 4.0 * (3 * fout * p["cout"] + ent * 2 * (p["a0"] + p["a1"]) * p["cout"])
+    return flops, byts
+
+
+def roofline(prof):
+    best = max(prof, key=lambda p: p["ms"])
+    flops, byts = op_accounting(best)
+    sec = best["ms"] * 1e-3
+    peak_f = PEAK[best["precision"]] if best["impl"] == 1 else PEAK[0]
+    ridge = peak_f / HBM_PEAK
+    if flops / max(byts, 1.0) >= ridge:
+        bound = "mfma" if best["impl"] == 1 else "alu"
+        ach, peak, unit = flops / sec / 1e12, peak_f / 1e12, "TFLOP/s"
+    else:
+        bound, ach, peak, unit = "hbm", byts / sec / 1e9, HBM_PEAK / 1e9, "GB/s"
+    kname = {1: "conv", 2: "convt", 3: "delay_add"}[best["kind"]]
+    impl = "mfma" if best["impl"] == 1 else "valu"
+    return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": None,
+            "kernel": "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
+                kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"]),
+            "avg_launch_us": round(best["ms"] * 1e3 / max(best["launches"], 1), 2),
+            "share_of_step": round(best["ms"] / sum(p["ms"] for p in prof), 3)}
+
+
+class Workload:
+    """256 streams, pre-drawn buffer lengths and device-resident inputs."""
+
+    def __init__(self, sc, torch, model, steps, seed=7):
+        self.sc, self.torch = sc, torch
+        self.model = model
+        self.streams = [sc.Stream(model, max(BUF_CHOICES)) for _ in range(N_STREAMS)]
+        self.lens = np.array([scgen.buffer_lengths(steps, BUF_CHOICES, seed * 100003 + i)
+                              for i in range(N_STREAMS)], dtype=np.int64)   # [stream][step]
+        self.inputs = []
+        for i in range(N_STREAMS):
+            tot = int(self.lens[i].sum())
+            x = torch.from_numpy(scgen.stream_latents(LATENT, tot, i)).cuda()
+            cuts = np.concatenate([[0], np.cumsum(self.lens[i])])
+            self.inputs.append([x[:, cuts[j]:cuts[j + 1]].contiguous() for j in range(steps)])
+        self.outs = [torch.empty((1, max(BUF_CHOICES) * SPF), device="cuda") for _ in range(N_STREAMS)]
+        self.step_i = 0
+        torch.cuda.synchronize()
+
+    def samples(self, j):
+        return int(self.lens[:, j].sum()) * SPF
+
+    def step(self):
+        j = self.step_i
+        xs = [self.inputs[i][j] for i in range(N_STREAMS)]
+        outs = [self.outs[i][:, :int(self.lens[i, j]) * SPF] for i in range(N_STREAMS)]
+        self.sc.process_batch(self.model, self.streams, xs, outs)
+        self.step_i += 1
+
+
+def timed_run(sc, torch, model, warmup, steps, profile=False):
+    wl = Workload(sc, torch, model, warmup + steps)
+    for _ in range(warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    if profile:
+        model.profile(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record()
+    samples = 0
+    for k in range(steps):
+        samples += wl.samples(warmup + k)
+        wl.step()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    gpu_s = evs[0].elapsed_time(evs[-1]) * 1e-3
+    prof = model.profile_read() if profile else None
+    if profile:
+        model.profile(False)
+    return {"samples": samples, "gpu_s": gpu_s, "wall_s": wall, "step_ms": step_ms, "prof": prof}
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle (offline decoder) on whole 64-frame streams of the same
+    latents, one after another, until the time budget is spent."""
+    from oracle import offline
+    import threadpoolctl
+    m = scgen.rave_decoder_b()
+    w = scgen.init_weights(m)
+    offline.forward(m, w, scgen.stream_latents(LATENT, 4, 0))     # warm BLAS
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info] or [1])
+    t0 = time.perf_counter()
+    samples = 0
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        y = offline.forward(m, w, scgen.stream_latents(LATENT, 64, n))
+        samples += y.shape[1]
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(samples / dt, 1), "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d streams x 64 latent frames (%d output samples) of the same decoder, "
+                      "offline FP64 numpy, %.1f s" % (n, samples, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--precision", default="bf16", choices=list(PREC_NAME))
+    ap.add_argument("--compare", default="fp32,fp8", help="other precisions timed on the same workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: streams are independent and the path has no cross-GPU "
+              "step; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2204_07064_amd as sc
+
+    m = scgen.rave_decoder_b()
+    w = scgen.init_weights(m)
+
+    def make(prec):
+        scales = None
+        if prec == "fp8":
+            scales = calibrate(sc, torch, m, w)
+        return sc.Model(m, w, prec, act_scales=scales)
+
+    model = make(args.precision)
+    run = timed_run(sc, torch, model, args.warmup, args.steps)
+    prof_run = timed_run(sc, torch, model, args.warmup, args.steps, profile=True)
+    prof = prof_run["prof"]
+    used = sorted({p["precision"] for p in prof if p["impl"] == 1})
+    value = run["samples"] / run["gpu_s"]
+    out = {
+        "metric": "output audio samples/sec at 256 streams (BF16/FP8 vs FP32); p99 buffer latency",
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(run["gpu_s"] * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[max(used)] if used else "fp32",
+        "data": "synthetic",
+        "config": {"workload": "rave_b decoder serving mix: 256 streams, buffers uniform over "
+                               "{1,2,4,8,16,32} latent frames, closed loop",
+                   "streams": N_STREAMS, "precision": args.precision,
+                   "mean_buffer_frames": float(np.mean(BUF_CHOICES))},
+        "latency_ms": {"p50": round(float(np.percentile(run["step_ms"], 50)), 4),
+                       "p99": round(float(np.percentile(run["step_ms"], 99)), 4),
+                       "note": "closed loop: every buffer of a step completes with the step"},
+        "rtf": round(1.0 / (value / N_STREAMS / 44100.0), 6),
+        "roofline": roofline(prof),
+        "per_kernel": [{"node": p["node"], "kind": p["kind"], "impl": p["impl"], "prec": p["precision"],
+                        "cin": p["cin"], "cout": p["cout"], "d": p["dilation"],
+                        "avg_us": round(p["ms"] * 1e3 / max(p["launches"], 1), 2)} for p in prof],
+    }
+    comp = {}
+    for prec in [c for c in args.compare.split(",") if c and c != args.precision]:
+        try:
+            mod2 = make(prec)
+            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4))
+            comp[prec] = round(r2["samples"] / r2["gpu_s"], 1)
+            mod2.close()
+        except Exception as e:  # report, do not hide
+            comp[prec] = "failed: %s" % e
+    out["compare_samples_per_s"] = comp
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def calibrate(sc, torch, m, w, frames=64, n_streams=4):
+    """Static FP8 activation scales: the FP32 path's max |activated input| of
+    every layer over a few seeded calibration streams, times 1.25."""
+    cal = sc.Model(m, w, "fp32", options=2)
+    cal.enable_amax(True)
+    for i in range(n_streams):
+        st = sc.Stream(cal, frames)
+        st.process(torch.from_numpy(scgen.latents(LATENT, frames, 1 + i)).cuda())
+    amax = cal.read_amax()
+    cal.close()
+    return np.maximum(amax * 1.25, 1e-6)
+
+
+if __name__ == "__main__":
+    main()

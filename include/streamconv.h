@@ -1,0 +1,203 @@
+/*
+ * streamconv.h -- C ABI of the MI355X (gfx950) streaming convolution library.
+ *
+ * The library streams a non-causal 1-D convolutional network buffer by
+ * buffer ("Streamable neural audio synthesis with non-causal convolutions",
+ * Caillon & Esling, 2022):
+ *   - cached padding (Sec. 2.2, Fig. 1): each convolution keeps the last
+ *     frames of its input on the device and prepends them to the next buffer;
+ *   - post-training causal reconfiguration (Sec. 3): right padding becomes
+ *     extra left padding, so every layer lags by its right padding;
+ *   - stride alignment (Sec. 3.1, Eq. 2) and parallel-branch alignment
+ *     (Sec. 3.2, Eq. 3) with extra delays;
+ *   - transposed convolutions streamed with an FP32 overlap carry.
+ * The concatenated output of any split of an input into buffers equals the
+ * offline (zero-padded) model's output delayed by a fixed latency D
+ * (Sec. 4.2), apart from a warm-up transient of the zero-initialised caches
+ * (removable with SC_FLAG_WARMUP_MASK).
+ *
+ * Conventions for every function:
+ *   - Device pointers are HIP device memory on the model's device; host
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes and keeps device buffers alive until the HIP stream has passed
+ *     the call.  The library owns every object it returns and all device
+ *     memory it allocates (weights, per-stream state, workspaces).
+ *   - `hip_stream` is a hipStream_t (NULL = the null stream).  Processing
+ *     calls are asynchronous on it and return after enqueueing.
+ *   - Every function returning sc_status validates its arguments first; on
+ *     any error it changes no state and sc_last_error() returns a message
+ *     (thread-local, valid until the next failing call on that thread).
+ *   - Calls on one sc_stream must be serialized by the caller; different
+ *     streams of one model may be driven from different threads (the model
+ *     serializes their device work internally).
+ */
+#ifndef STREAMCONV_H
+#define STREAMCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sc_model sc_model;    /* immutable after create: plan + device weights */
+typedef struct sc_stream sc_stream;  /* one live stream: caches, carries, delay lines */
+
+typedef enum {
+  SC_OK = 0,
+  SC_EINVAL = -1,       /* bad argument, malformed model */
+  SC_ENOMEM = -2,       /* device or host allocation failed */
+  SC_EBUDGET = -3,      /* memory budget exhausted */
+  SC_ELENGTH = -4,      /* buffer length 0, above the stream's maximum, or not a
+                           multiple of the model's total stride */
+  SC_EDEVICE = -5,      /* a HIP call or kernel launch failed */
+  SC_ESTATE = -6,       /* the stream saw a device error; call stream_reset */
+  SC_EUNSUPPORTED = -7  /* valid model that this build cannot stream */
+} sc_status;
+
+typedef enum {
+  SC_FP32 = 0,          /* FP32 weights and activations */
+  SC_BF16 = 1,          /* BF16 (RNE) conv operands on the wide layers, FP32 accumulate */
+  SC_FP8E4M3 = 2        /* OCP FP8 e4m3 conv operands on the wide layers, per-output-
+                           channel weight scales, static per-layer activation scales */
+} sc_precision;
+
+enum {
+  SC_OP_INPUT = 0,
+  SC_OP_CONV = 1,       /* Eq. 1 correlation with dilation, stride, zero padding */
+  SC_OP_CONVT = 2,      /* transposed conv, kernel 2*stride, crop pad_l == pad_r */
+  SC_OP_ADD = 3         /* sum of two parallel branches (Sec. 3.2) */
+};
+
+enum { SC_ACT_NONE = 0, SC_ACT_LRELU = 1, SC_ACT_TANH = 2 };  /* LeakyReLU slope 0.2 */
+
+enum {
+  SC_FLAG_WARMUP_MASK = 1u  /* every layer writes exact zeros at stream positions
+                               before its own latency: the output is then the
+                               offline output delayed by D from the first sample,
+                               with zeros before D */
+};
+
+/* One node of the model graph.  Nodes are listed in evaluation order and
+ * node 0 is the input.  Offline semantics (what the stream reproduces):
+ *  CONV : y[co][j] = b[co] + sum_ci sum_k W[co][ci][k] * xp[ci][j*stride + dilation*k]
+ *         with xp = pre_act(x) zero-padded by pad_l / pad_r (paper Eq. 1 plus
+ *         dilation, stride, padding, Sec. 2.1); post_act applied after.
+ *         Weights W[cout][cin][k] then b[cout].
+ *  CONVT: y = crop_pad(f) + b, f[co][i*stride + k] += W[ci][co][k] * pre_act(x)[ci][i];
+ *         k must equal 2*stride and pad_l == pad_r (the crop).  Weights
+ *         W[cin][cout][k] (PyTorch layout) then b[cout].
+ *  ADD  : y = x[src] + x[src2] (same channels, same frame rate).
+ *  INPUT: cout = channels. */
+typedef struct {
+  int32_t op;
+  int32_t src, src2;
+  int32_t cin, cout, k, dilation, stride, pad_l, pad_r;
+  int32_t pre_act, post_act;
+} sc_node;
+
+typedef struct {
+  int32_t in_channels, out_channels;
+  int32_t out_num, out_den;        /* output frames per input frame (num/den) */
+  int32_t input_multiple;          /* input buffer lengths must be multiples of this */
+  int32_t n_launch;                /* kernels launched per processing step */
+  int64_t latency;                 /* D: output frame n = offline output frame n - D */
+  int64_t warmup;                  /* c_L: first offline index guaranteed exact without
+                                      SC_FLAG_WARMUP_MASK (0 with it) */
+  int64_t state_bytes_per_stream;  /* caches + carries + delay lines, one copy, FP32 */
+  int64_t state_alloc_per_stream;  /* bytes actually allocated per stream (double-buffered) */
+  int64_t weight_bytes;            /* device bytes of packed weights */
+} sc_model_info;
+
+/* Plan a model on the host only (no device work): the post-training
+ * reconfiguration of Sec. 3 -- per-node delays, Eq. 2 stride delays, Eq. 3
+ * branch delays, cache lengths, latency D and warm-up window.  Fills `out`.
+ * Errors: SC_EINVAL (malformed graph), SC_EUNSUPPORTED. */
+sc_status sc_plan(const sc_node* nodes, int32_t n_nodes, sc_model_info* out);
+
+/* Build a model on `device`.  `weights` is a host array of n_weights FP32
+ * values laid out as described for sc_node.  `act_scales` (host, may be
+ * NULL) gives, for SC_FP8E4M3, one static activation scale per CONV/CONVT
+ * node in node order (amax of that layer's activated input; NULL = the
+ * scales set by sc_model_set_act_scales later, required before processing).
+ * Copies everything it needs; the caller may free its arrays on return. */
+enum {
+  SC_MODEL_NO_FUSION = 1u,  /* run residual sums as explicit delay-line + add kernels
+                               instead of the fused centre-tap skip */
+  SC_MODEL_NO_MFMA = 2u     /* run every layer on the FP32 wavefront-FMA kernels
+                               (precision must be SC_FP32) */
+};
+sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
+                          size_t n_weights, sc_precision precision, const float* act_scales,
+                          uint32_t options, int32_t device, sc_model** out);
+sc_status sc_model_info_get(const sc_model* model, sc_model_info* out);
+/* Number of CONV/CONVT nodes (the length of an act_scales array). */
+int32_t sc_model_n_layers(const sc_model* model);
+/* Replace the static FP8 activation scales (host array, sc_model_n_layers
+ * values).  Only between processing calls. */
+sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);
+/* Record, for every CONV/CONVT node, max |pre_act(input)| over all frames
+ * processed by `model` (an SC_FP32 model) since the last call with reset=1,
+ * into the host array `amax_out` (sc_model_n_layers values).  Synchronizes
+ * the model's device work. */
+sc_status sc_model_read_amax(sc_model* model, float* amax_out, int32_t reset);
+sc_status sc_model_enable_amax(sc_model* model, int32_t enable);
+/* The caller guarantees every stream of the model was destroyed first. */
+void sc_model_destroy(sc_model* model);
+
+/* Open a stream: allocates and zeroes (on `hip_stream`) its state.  Buffers
+ * passed to it may hold 1..max_buffer_frames input frames. */
+sc_status stream_create(sc_model* model, int32_t max_buffer_frames, uint32_t flags,
+                        void* hip_stream, sc_stream** out);
+/* Process one buffer.  d_in: device [in_channels][n_frames] FP32 (channel-
+ * major, like a PyTorch NCL tensor without the batch dim).  d_out: device
+ * [out_channels][n_frames * out_num / out_den] FP32, fully written.
+ * Errors: SC_ELENGTH (no state change), SC_EINVAL, SC_ESTATE, SC_EDEVICE. */
+sc_status stream_process(sc_stream* stream, const float* d_in, int32_t n_frames, float* d_out,
+                         void* hip_stream);
+/* Zero all caches, carries and delay lines and the position counter. */
+sc_status stream_reset(sc_stream* stream, void* hip_stream);
+/* Input frames processed since creation / the last reset. */
+int64_t stream_position(const sc_stream* stream);
+void stream_destroy(sc_stream* stream);
+
+/* Process one buffer for each of n streams of the same model in one batched
+ * pass (one launch per layer for all streams; uneven lengths allowed).  The
+ * arrays are host arrays of n entries; each stream may appear at most once.
+ * Each stream's result is bitwise identical to processing it alone. */
+sc_status sc_process_batch(sc_model* model, int32_t n, sc_stream* const* streams,
+                           const float* const* d_in, const int32_t* n_frames,
+                           float* const* d_out, void* hip_stream);
+
+/* ---- tracing: per-launch timing with HIP events on the processing stream ---- */
+typedef struct {
+  int32_t kind;        /* 1 conv (with fused skip if residual), 2 transposed conv, 3 delay-line sum */
+  int32_t impl;        /* 0 FP32 wavefront FMA, 1 MFMA implicit GEMM */
+  int32_t precision;   /* sc_precision of this launch's operands */
+  int32_t node;        /* node whose output the launch writes */
+  int32_t cin, cout, k, dilation, stride, cache_len, residual;
+  int32_t a0, a1;      /* delay-line lengths of a delay-line sum */
+  int32_t rate_in_num, rate_in_den, rate_out_num, rate_out_den;  /* frames per input frame */
+  double ms;           /* summed event-measured duration since profiling was enabled */
+  int64_t launches;    /* launches timed */
+  int64_t frames_in;   /* summed input frames (at the launch's input rate) */
+  int64_t frames_out;  /* summed output frames (at its output rate) */
+  int64_t entries;     /* summed streams over the timed launches */
+} sc_op_profile;
+
+/* Enable (1) or disable (0) per-launch timing; enabling clears the sums.
+ * While enabled every launch is bracketed by two hipEventRecord calls on the
+ * processing stream. */
+sc_status sc_model_profile(sc_model* model, int32_t enable);
+/* Synchronizes, then fills up to `max_ops` records (one per launch of a
+ * step, in launch order) and sets *n_ops to the number of launches per step. */
+sc_status sc_model_profile_read(sc_model* model, sc_op_profile* out, int32_t max_ops, int32_t* n_ops);
+
+const char* sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STREAMCONV_H */

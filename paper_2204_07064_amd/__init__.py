@@ -1,0 +1,162 @@
+"""Streaming non-causal convolutions on MI355X (gfx950).
+
+Python binding of the HIP library ``libstreamconv.so`` (C ABI in
+``include/streamconv.h``).  The binding only marshals arguments: PyTorch
+supplies device memory and HIP streams, every step of the computation runs in
+the library's kernels.
+
+    model = Model(node_list_model, weights_f32, precision="bf16")
+    s = Stream(model, max_buffer_frames=32)
+    y = s.process(x)          # x: cuda float32 [in_channels][T]
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import ScError, check, lib, nodes_array  # noqa: F401
+
+__all__ = ["Model", "Stream", "process_batch", "plan", "ScError", "lib"]
+
+
+def _stream_handle(hip_stream):
+    if hip_stream is not None:
+        return ctypes.c_void_p(int(hip_stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def plan(model):
+    """Host-only planning (no GPU): latency, warm-up window, state bytes..."""
+    arr = nodes_array(model)
+    info = _native.ScModelInfo()
+    check(lib().sc_plan(arr, len(arr), ctypes.byref(info)))
+    return _native.info_dict(info)
+
+
+class Model:
+    def __init__(self, model, weights, precision="fp32", act_scales=None, options=0, device=0):
+        L = lib()
+        self.spec = model
+        arr = nodes_array(model)
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+        self._w = w
+        sc = None
+        if act_scales is not None:
+            sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
+        h = ctypes.c_void_p()
+        check(L.sc_model_create(arr, len(arr), w.ctypes.data_as(_native.c_fp), w.size,
+                                _native.PRECISION[precision],
+                                sc.ctypes.data_as(_native.c_fp) if sc is not None else None,
+                                int(options), int(device), ctypes.byref(h)))
+        self.handle = h
+        self.precision = precision
+        self.device = device
+        info = _native.ScModelInfo()
+        check(L.sc_model_info_get(h, ctypes.byref(info)))
+        self.info = _native.info_dict(info)
+        self.n_layers = L.sc_model_n_layers(h)
+
+    @property
+    def latency(self):
+        return self.info["latency"]
+
+    @property
+    def warmup(self):
+        return self.info["warmup"]
+
+    def out_frames(self, n_frames):
+        return n_frames * self.info["out_num"] // self.info["out_den"]
+
+    def set_act_scales(self, scales):
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float32))
+        assert sc.size == self.n_layers
+        check(lib().sc_model_set_act_scales(self.handle, sc.ctypes.data_as(_native.c_fp)))
+
+    def enable_amax(self, on=True):
+        check(lib().sc_model_enable_amax(self.handle, int(bool(on))))
+
+    def read_amax(self, reset=False):
+        out = np.zeros(max(self.n_layers, 1), np.float32)
+        check(lib().sc_model_read_amax(self.handle, out.ctypes.data_as(_native.c_fp), int(bool(reset))))
+        return out[:self.n_layers]
+
+    def profile(self, enable=True):
+        check(lib().sc_model_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        n = ctypes.c_int32()
+        check(lib().sc_model_profile_read(self.handle, None, 0, ctypes.byref(n)))
+        arr = (_native.ScOpProfile * max(n.value, 1))()
+        check(lib().sc_model_profile_read(self.handle, arr, n.value, ctypes.byref(n)))
+        return [{f: getattr(arr[i], f) for f, _ in _native.ScOpProfile._fields_} for i in range(n.value)]
+
+    def close(self):
+        if self.handle:
+            lib().sc_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    def __init__(self, model, max_buffer_frames, warmup_mask=False, hip_stream=None):
+        self.model = model
+        self.max_buffer_frames = int(max_buffer_frames)
+        h = ctypes.c_void_p()
+        flags = _native.SC_FLAG_WARMUP_MASK if warmup_mask else 0
+        check(lib().stream_create(model.handle, self.max_buffer_frames, flags,
+                                  _stream_handle(hip_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def process_into(self, x, out, n_frames=None, hip_stream=None):
+        """x: cuda float32 [C_in][T]; out: cuda float32 [C_out][T_out]."""
+        T = int(x.shape[-1]) if n_frames is None else int(n_frames)
+        check(lib().stream_process(self.handle, ctypes.c_void_p(x.data_ptr()), T,
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream)))
+        return out
+
+    def process(self, x, hip_stream=None):
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        T = int(x.shape[-1])
+        out = torch.empty((self.model.info["out_channels"], self.model.out_frames(T)),
+                          dtype=torch.float32, device=x.device)
+        return self.process_into(x, out, T, hip_stream)
+
+    def reset(self, hip_stream=None):
+        check(lib().stream_reset(self.handle, _stream_handle(hip_stream)))
+
+    @property
+    def position(self):
+        return lib().stream_position(self.handle)
+
+    def close(self):
+        if self.handle:
+            lib().stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def process_batch(model, streams, xs, outs=None, hip_stream=None):
+    """One batched step: buffer xs[i] (cuda [C_in][T_i]) for streams[i]."""
+    import torch
+    n = len(streams)
+    if outs is None:
+        outs = [torch.empty((model.info["out_channels"], model.out_frames(int(x.shape[-1]))),
+                            dtype=torch.float32, device=x.device) for x in xs]
+    sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+    ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    ous = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    tf = (ctypes.c_int32 * n)(*[int(x.shape[-1]) for x in xs])
+    check(lib().sc_process_batch(model.handle, n, sh, ins, tf, ous, _stream_handle(hip_stream)))
+    return outs

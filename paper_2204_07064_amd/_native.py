@@ -1,0 +1,135 @@
+"""ctypes binding of ``libstreamconv.so`` (argument marshalling only).
+
+Every function of ``include/streamconv.h`` is exposed under the same name on
+the object returned by :func:`lib`.  Loading fails loudly when the library
+has not been built: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libstreamconv.so")
+
+c_i32 = ctypes.c_int32
+c_u32 = ctypes.c_uint32
+c_i64 = ctypes.c_int64
+c_size = ctypes.c_size_t
+c_vp = ctypes.c_void_p
+c_fp = ctypes.POINTER(ctypes.c_float)
+
+SC_OK = 0
+STATUS = {0: "SC_OK", -1: "SC_EINVAL", -2: "SC_ENOMEM", -3: "SC_EBUDGET", -4: "SC_ELENGTH",
+          -5: "SC_EDEVICE", -6: "SC_ESTATE", -7: "SC_EUNSUPPORTED"}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
+SC_FLAG_WARMUP_MASK = 1
+SC_MODEL_NO_FUSION = 1
+SC_MODEL_NO_MFMA = 2
+OPS = {"input": 0, "conv": 1, "convt": 2, "add": 3}
+
+# every symbol the header declares (checked by the CPU test suite)
+EXPORTS = [
+    "sc_plan", "sc_model_create", "sc_model_info_get", "sc_model_n_layers",
+    "sc_model_set_act_scales", "sc_model_read_amax", "sc_model_enable_amax", "sc_model_destroy",
+    "stream_create", "stream_process", "stream_reset", "stream_position", "stream_destroy",
+    "sc_process_batch", "sc_last_error", "sc_model_profile", "sc_model_profile_read",
+]
+
+
+class ScNode(ctypes.Structure):
+    _fields_ = [("op", c_i32), ("src", c_i32), ("src2", c_i32), ("cin", c_i32), ("cout", c_i32),
+                ("k", c_i32), ("dilation", c_i32), ("stride", c_i32), ("pad_l", c_i32),
+                ("pad_r", c_i32), ("pre_act", c_i32), ("post_act", c_i32)]
+
+
+class ScModelInfo(ctypes.Structure):
+    _fields_ = [("in_channels", c_i32), ("out_channels", c_i32), ("out_num", c_i32),
+                ("out_den", c_i32), ("input_multiple", c_i32), ("n_launch", c_i32),
+                ("latency", c_i64), ("warmup", c_i64), ("state_bytes_per_stream", c_i64),
+                ("state_alloc_per_stream", c_i64), ("weight_bytes", c_i64)]
+
+
+class ScOpProfile(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("impl", c_i32), ("precision", c_i32), ("node", c_i32),
+                ("cin", c_i32), ("cout", c_i32), ("k", c_i32), ("dilation", c_i32), ("stride", c_i32),
+                ("cache_len", c_i32), ("residual", c_i32), ("a0", c_i32), ("a1", c_i32),
+                ("rate_in_num", c_i32), ("rate_in_den", c_i32), ("rate_out_num", c_i32),
+                ("rate_out_den", c_i32), ("ms", ctypes.c_double), ("launches", c_i64),
+                ("frames_in", c_i64), ("frames_out", c_i64), ("entries", c_i64)]
+
+
+class ScError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_LIB = None
+
+
+def _sig(lib, name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+
+
+def lib():
+    """Load the built library (raises if it is missing)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libstreamconv.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    _sig(L, "sc_plan", c_i32, [P(ScNode), c_i32, P(ScModelInfo)])
+    _sig(L, "sc_model_create", c_i32, [P(ScNode), c_i32, c_fp, c_size, c_i32, c_fp, c_u32, c_i32, P(c_vp)])
+    _sig(L, "sc_model_info_get", c_i32, [c_vp, P(ScModelInfo)])
+    _sig(L, "sc_model_n_layers", c_i32, [c_vp])
+    _sig(L, "sc_model_set_act_scales", c_i32, [c_vp, c_fp])
+    _sig(L, "sc_model_read_amax", c_i32, [c_vp, c_fp, c_i32])
+    _sig(L, "sc_model_enable_amax", c_i32, [c_vp, c_i32])
+    _sig(L, "sc_model_destroy", None, [c_vp])
+    _sig(L, "stream_create", c_i32, [c_vp, c_i32, c_u32, c_vp, P(c_vp)])
+    _sig(L, "stream_process", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
+    _sig(L, "stream_reset", c_i32, [c_vp, c_vp])
+    _sig(L, "stream_position", c_i64, [c_vp])
+    _sig(L, "stream_destroy", None, [c_vp])
+    _sig(L, "sc_process_batch", c_i32, [c_vp, c_i32, P(c_vp), P(c_vp), P(c_i32), P(c_vp), c_vp])
+    _sig(L, "sc_last_error", ctypes.c_char_p, [])
+    _sig(L, "sc_model_profile", c_i32, [c_vp, c_i32])
+    _sig(L, "sc_model_profile_read", c_i32, [c_vp, P(ScOpProfile), c_i32, P(c_i32)])
+    _LIB = L
+    return L
+
+
+def check(status):
+    if status != SC_OK:
+        msg = lib().sc_last_error()
+        raise ScError(status, msg.decode() if msg else "")
+    return status
+
+
+def nodes_array(model):
+    """Marshal a node-list model (dicts) into a ScNode array."""
+    arr = (ScNode * len(model["nodes"]))()
+    for i, nd in enumerate(model["nodes"]):
+        a = arr[i]
+        a.op = OPS[nd["op"]]
+        a.src = nd.get("src", -1)
+        a.src2 = nd.get("src2", -1)
+        if nd["op"] == "input":
+            a.cout = nd["channels"]
+            continue
+        if nd["op"] == "add":
+            continue
+        a.cin, a.cout, a.k, a.stride = nd["cin"], nd["cout"], nd["k"], nd["stride"]
+        a.pre_act = nd.get("pre_act", 0)
+        a.post_act = nd.get("post_act", 0)
+        if nd["op"] == "conv":
+            a.dilation, a.pad_l, a.pad_r = nd["dilation"], nd["pad_l"], nd["pad_r"]
+        else:
+            a.dilation, a.pad_l, a.pad_r = 1, nd["pad"], nd["pad"]
+    return arr
+
+
+def info_dict(info):
+    return {f: getattr(info, f) for f, _ in ScModelInfo._fields_}

@@ -1,0 +1,54 @@
+// Kernel launch interfaces (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+#include "sc_device.h"
+
+namespace sc {
+
+// Arguments common to the conv-like kernels of one op in one step.
+struct LayerArgs {
+  const Entry* ents;
+  int32_t n_ent;
+  const float* in_buf;     // packed [frames][cin] at the input rate, or null: user input
+  const float* in_buf2;    // delay-add second branch
+  float* out_buf;          // packed [frames][cout] at the output rate, or null: user output
+  const void* W;           // packed weights (layout per kernel)
+  const float* B;          // bias [cout]
+  const float* wscale;     // FP8: per-output-row weight scale (dequantization)
+  float act_scale;         // FP8: static activation scale (amax / 448)
+  int32_t cin, cout, k, dil, stride, L, pre_act, post_act, residual, skip_off;
+  int32_t A0, A1;
+  int64_t in_num, in_den, out_num, out_den;
+  int64_t delay;           // output lag (frames at the output rate) for the warm-up mask
+  int64_t state_off, state_len, state_off2, state_len2;
+  int64_t n_in;            // total input frames of the step at the input rate
+  int64_t n_out;           // total output frames of the step at the output rate
+};
+
+hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
+hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);
+hipError_t launch_delay_add(const LayerArgs& a, hipStream_t s);
+// max |pre_act(x)| over the step's new input frames of a layer -> atomic max into *amax
+hipError_t launch_amax(const LayerArgs& a, float* amax, hipStream_t s);
+
+// MFMA implicit-GEMM kernels for wide layers; prec: 0 FP32, 1 BF16, 2 FP8 e4m3.
+hipError_t launch_conv_mfma(const LayerArgs& a, int prec, hipStream_t s);
+hipError_t launch_convt_mfma(const LayerArgs& a, int prec, hipStream_t s);
+bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec);
+bool convt_mfma_supported(int cin, int cout, int r, int prec);
+// Host packing of weights into the MFMA kernels' tile order (and, for FP8,
+// per-output-row scales).  conv: W[cout][cin][k]; convt: W[cin][cout][2r].
+void pack_conv_mfma(const float* w, int cout, int cin, int k, int prec, std::vector<uint8_t>& out,
+                    std::vector<float>& wscale);
+void pack_convt_mfma(const float* w, int cin, int cout, int r, int prec, std::vector<uint8_t>& out,
+                     std::vector<float>& wscale);
+
+// Zero n floats (a kernel rather than a memset so that it is safe to capture
+// into a HIP graph).
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+
+}  // namespace sc

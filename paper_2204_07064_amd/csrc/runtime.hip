@@ -1,0 +1,620 @@
+// Runtime and C ABI: models (plan + device weights), streams (device state),
+// batched processing steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "kernels.h"
+#include "sc_internal.h"
+
+namespace sc {
+
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error_cstr() { return g_err.c_str(); }
+
+}  // namespace sc
+
+using namespace sc;
+
+namespace {
+
+constexpr int kRing = 16;
+
+sc_status fail(sc_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+sc_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return SC_EDEVICE;
+}
+
+// Device copies of one op's weights.
+struct OpDev {
+  void* W = nullptr;        // packed weights (fp32 / bf16 / fp8 by impl)
+  float* B = nullptr;       // bias
+  float* wscale = nullptr;  // fp8 per-row scales
+  int prec = 0;             // precision of this op's kernel
+};
+
+// A slot of the descriptor ring: pinned host staging + device copy + event.
+struct DescSlot {
+  Entry* host = nullptr;
+  Entry* dev = nullptr;
+  int cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+}  // namespace
+
+struct sc_model {
+  int device = 0;
+  sc_precision prec = SC_FP32;
+  uint32_t options = 0;
+  Plan plan;
+  std::vector<OpDev> opdev;
+  std::vector<float> act_scales;   // per layer (FP8)
+  bool have_scales = false;
+  int64_t weight_bytes = 0;
+  // workspace
+  std::vector<float*> ws;
+  int64_t ws_cap = 0;              // input frames
+  // descriptors
+  DescSlot ring[kRing];
+  int ring_next = 0;
+  // cross-stream ordering of steps
+  hipEvent_t last_done = nullptr;
+  bool has_last = false;
+  // calibration
+  float* d_amax = nullptr;
+  bool amax_on = false;
+  // tracing
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_events;        // pool, used in pairs
+  size_t prof_used = 0;                       // events recorded since the last fold
+  std::vector<int32_t> prof_op;               // op index of each recorded pair
+  std::vector<int64_t> prof_in, prof_out, prof_ent;  // per recorded pair
+  std::vector<sc_op_profile> prof;            // per op sums
+  std::mutex mu;
+};
+
+struct sc_stream {
+  sc_model* m = nullptr;
+  float* d_state = nullptr;
+  int32_t max_frames = 0;
+  uint32_t flags = 0;
+  int64_t pos = 0;
+  int parity = 0;
+  bool bad = false;
+};
+
+namespace {
+
+// Packs a conv's W[co][ci][k] into [k][ci][co] (FP32 wavefront kernels).
+std::vector<float> pack_conv_valu(const float* w, int cout, int cin, int k) {
+  std::vector<float> p((size_t)cout * cin * k);
+  for (int co = 0; co < cout; ++co)
+    for (int ci = 0; ci < cin; ++ci)
+      for (int kk = 0; kk < k; ++kk) p[((size_t)kk * cin + ci) * cout + co] = w[((size_t)co * cin + ci) * k + kk];
+  return p;
+}
+
+// Packs a transposed conv's W[ci][co][2r] into [h][phi][ci][co] with
+// h = 0 -> tap phi + r (previous frame), h = 1 -> tap phi (current frame).
+std::vector<float> pack_convt_valu(const float* w, int cin, int cout, int r) {
+  std::vector<float> p((size_t)2 * r * cin * cout);
+  for (int h = 0; h < 2; ++h)
+    for (int phi = 0; phi < r; ++phi)
+      for (int ci = 0; ci < cin; ++ci)
+        for (int co = 0; co < cout; ++co) {
+          const int tap = h == 0 ? phi + r : phi;
+          p[(((size_t)h * r + phi) * cin + ci) * cout + co] = w[((size_t)ci * cout + co) * (2 * r) + tap];
+        }
+  return p;
+}
+
+template <class T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_model(sc_model* m) {
+  if (!m) return;
+  hipSetDevice(m->device);
+  hipDeviceSynchronize();
+  for (auto& o : m->opdev) {
+    hipFree(o.W);
+    hipFree(o.B);
+    hipFree(o.wscale);
+  }
+  for (float* p : m->ws) hipFree(p);
+  for (hipEvent_t ev : m->prof_events) hipEventDestroy(ev);
+  for (auto& s : m->ring) {
+    if (s.host) hipHostFree(s.host);
+    if (s.dev) hipFree(s.dev);
+    if (s.done) hipEventDestroy(s.done);
+  }
+  if (m->last_done) hipEventDestroy(m->last_done);
+  hipFree(m->d_amax);
+  delete m;
+}
+
+LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, int n_ent, int64_t total_T) {
+  LayerArgs a{};
+  a.ents = dents;
+  a.n_ent = n_ent;
+  a.in_buf = op.in_buf >= 0 ? m->ws[op.in_buf] : nullptr;
+  a.in_buf2 = op.in_buf2 >= 0 ? m->ws[op.in_buf2] : nullptr;
+  a.out_buf = op.out_buf >= 0 ? m->ws[op.out_buf] : nullptr;
+  const size_t oi = &op - &m->plan.ops[0];
+  a.W = m->opdev[oi].W;
+  a.B = m->opdev[oi].B;
+  a.wscale = m->opdev[oi].wscale;
+  a.act_scale = (op.layer >= 0 && m->have_scales) ? m->act_scales[op.layer] / 448.0f : 1.0f;
+  a.cin = op.cin; a.cout = op.cout; a.k = op.k; a.dil = op.dil; a.stride = op.stride;
+  a.L = op.cache_len; a.pre_act = op.pre_act; a.post_act = op.post_act;
+  a.residual = op.residual; a.skip_off = op.skip_off;
+  a.A0 = op.A0; a.A1 = op.A1;
+  a.in_num = op.in_rate.num; a.in_den = op.in_rate.den;
+  a.out_num = op.out_rate.num; a.out_den = op.out_rate.den;
+  a.delay = op.out_delay;
+  a.state_off = op.state_off; a.state_len = op.state_len;
+  a.state_off2 = op.state_off2; a.state_len2 = op.state_len2;
+  a.n_in = op.in_rate.of(total_T);
+  a.n_out = op.out_rate.of(total_T);
+  return a;
+}
+
+sc_status ensure_workspace(sc_model* m, int64_t frames) {
+  if (frames <= m->ws_cap) return SC_OK;
+  int64_t cap = std::max<int64_t>(frames, 2 * m->ws_cap);
+  const int64_t mult = m->plan.input_multiple;
+  cap = (cap + mult - 1) / mult * mult;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  for (float*& p : m->ws) { hipFree(p); p = nullptr; }
+  m->ws.assign(m->plan.buf_floats.size(), nullptr);
+  for (size_t b = 0; b < m->plan.buf_floats.size(); ++b) {
+    const int64_t n = m->plan.buf_floats[b].of(cap) + 1;
+    e = hipMalloc(reinterpret_cast<void**>(&m->ws[b]), (size_t)n * sizeof(float));
+    if (e != hipSuccess) {
+      m->ws_cap = 0;
+      return fail(SC_ENOMEM, "workspace allocation failed");
+    }
+  }
+  m->ws_cap = cap;
+  return SC_OK;
+}
+
+// Records the start event of a timed launch and hands out its end event.
+hipError_t prof_begin(sc_model* m, int oi, const LayerArgs& a, hipStream_t hs, hipEvent_t* ev_end) {
+  while (m->prof_events.size() < m->prof_used + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    m->prof_events.push_back(ev);
+  }
+  hipEvent_t b = m->prof_events[m->prof_used];
+  *ev_end = m->prof_events[m->prof_used + 1];
+  m->prof_used += 2;
+  m->prof_op.push_back(oi);
+  m->prof_in.push_back(a.n_in);
+  m->prof_out.push_back(a.n_out);
+  m->prof_ent.push_back(a.n_ent);
+  return hipEventRecord(b, hs);
+}
+
+// Waits for the recorded events and adds their durations to the per-op sums.
+hipError_t prof_fold(sc_model* m) {
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < m->prof_op.size(); ++i) {
+    e = hipEventSynchronize(m->prof_events[2 * i + 1]);
+    if (e != hipSuccess) break;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, m->prof_events[2 * i], m->prof_events[2 * i + 1]);
+    if (e != hipSuccess) break;
+    sc_op_profile& p = m->prof[m->prof_op[i]];
+    p.ms += ms;
+    p.launches += 1;
+    p.frames_in += m->prof_in[i];
+    p.frames_out += m->prof_out[i];
+    p.entries += m->prof_ent[i];
+  }
+  m->prof_used = 0;
+  m->prof_op.clear();
+  m->prof_in.clear();
+  m->prof_out.clear();
+  m->prof_ent.clear();
+  return e;
+}
+
+sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                   const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
+  // ---- validation (no state change on failure) ----
+  if (n <= 0 || !streams || !d_in || !n_frames || !d_out) return fail(SC_EINVAL, "null argument or n <= 0");
+  if (m->prec == SC_FP8E4M3 && !m->have_scales) return fail(SC_EINVAL, "FP8 model has no activation scales");
+  int64_t total = 0;
+  std::unordered_set<const sc_stream*> seen;
+  for (int i = 0; i < n; ++i) {
+    const sc_stream* s = streams[i];
+    if (!s || s->m != m) return fail(SC_EINVAL, "stream is null or belongs to another model");
+    if (!seen.insert(s).second) return fail(SC_EINVAL, "a stream appears twice in one batch");
+    if (s->bad) return fail(SC_ESTATE, "stream saw a device error; call stream_reset");
+    const int32_t T = n_frames[i];
+    if (T < 1 || T > s->max_frames || T % m->plan.input_multiple != 0)
+      return fail(SC_ELENGTH, "buffer length must be in [1, max_buffer_frames] and a multiple of the total stride");
+    if (!d_in[i] || !d_out[i]) return fail(SC_EINVAL, "null device buffer");
+    total += T;
+  }
+  if (total > INT32_MAX / 2) return fail(SC_ELENGTH, "batch too large");
+  hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  sc_status st = ensure_workspace(m, total);
+  if (st != SC_OK) return st;
+
+  // ---- descriptors ----
+  DescSlot& slot = m->ring[m->ring_next];
+  m->ring_next = (m->ring_next + 1) % kRing;
+  if (slot.pending) {
+    e = hipEventSynchronize(slot.done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    slot.pending = false;
+  }
+  if (slot.cap < n) {
+    if (slot.host) hipHostFree(slot.host);
+    if (slot.dev) hipFree(slot.dev);
+    slot.host = nullptr;
+    slot.dev = nullptr;
+    const int cap = std::max(n, 64);
+    if (hipHostMalloc(reinterpret_cast<void**>(&slot.host), cap * sizeof(Entry), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&slot.dev), cap * sizeof(Entry)) != hipSuccess) {
+      slot.cap = 0;
+      return fail(SC_ENOMEM, "descriptor allocation failed");
+    }
+    slot.cap = cap;
+  }
+  if (!slot.done) {
+    e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  }
+  int32_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    Entry& en = slot.host[i];
+    en.in = d_in[i];
+    en.out = d_out[i];
+    en.state = streams[i]->d_state;
+    en.T = n_frames[i];
+    en.off = off;
+    en.parity = streams[i]->parity;
+    en.flags = (int32_t)streams[i]->flags;
+    en.pos = streams[i]->pos;
+    off += n_frames[i];
+  }
+  if (m->has_last) {
+    e = hipStreamWaitEvent(hs, m->last_done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  e = hipMemcpyAsync(slot.dev, slot.host, n * sizeof(Entry), hipMemcpyHostToDevice, hs);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+
+  // ---- launches ----
+  for (const Op& op : m->plan.ops) {
+    const LayerArgs a = layer_args(m, op, slot.dev, n, total);
+    if (m->amax_on && op.layer >= 0) {
+      e = launch_amax(a, m->d_amax + op.layer, hs);
+      if (e != hipSuccess) break;
+    }
+    const size_t oi = &op - &m->plan.ops[0];
+    const int prec = m->opdev[oi].prec;
+    hipEvent_t ev_end = nullptr;
+    if (m->prof_on) {
+      e = prof_begin(m, (int)oi, a, hs, &ev_end);
+      if (e != hipSuccess) break;
+    }
+    if (op.kind == K_CONV) {
+      e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
+    } else if (op.kind == K_CONVT) {
+      e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, hs) : launch_convt_valu(a, hs);
+    } else {
+      e = launch_delay_add(a, hs);
+    }
+    if (e != hipSuccess) break;
+    if (ev_end) {
+      e = hipEventRecord(ev_end, hs);
+      if (e != hipSuccess) break;
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
+  if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
+  if (e != hipSuccess) {
+    for (int i = 0; i < n; ++i) streams[i]->bad = true;
+    return hip_fail(e, "kernel launch");
+  }
+  slot.pending = true;
+  m->has_last = true;
+  for (int i = 0; i < n; ++i) {
+    streams[i]->pos += n_frames[i];
+    streams[i]->parity ^= 1;
+  }
+  return SC_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+void fill_info(const Plan& p, sc_model_info* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->in_channels = p.in_channels;
+  out->out_channels = p.out_channels;
+  out->out_num = (int32_t)p.out_rate.num;
+  out->out_den = (int32_t)p.out_rate.den;
+  out->input_multiple = p.input_multiple;
+  out->n_launch = (int32_t)p.ops.size();
+  out->latency = p.latency;
+  out->warmup = p.warmup;
+  out->state_bytes_per_stream = p.state_floats * (int64_t)sizeof(float);
+  out->state_alloc_per_stream = 2 * p.state_floats * (int64_t)sizeof(float);
+}
+
+sc_status zero_state(sc_stream* s, hipStream_t hs) {
+  sc_model* m = s->m;
+  hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (m->has_last) {
+    e = hipStreamWaitEvent(hs, m->last_done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  e = launch_fill_zero(s->d_state, std::max<int64_t>(2 * m->plan.state_floats, 1), hs);
+  if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
+  if (e != hipSuccess) return hip_fail(e, "state reset");
+  m->has_last = true;
+  s->pos = 0;
+  s->parity = 0;
+  s->bad = false;
+  return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sc_last_error(void) { return last_error_cstr(); }
+
+sc_status sc_plan(const sc_node* nodes, int32_t n_nodes, sc_model_info* out) {
+  if (!out) return fail(SC_EINVAL, "null output");
+  Plan p;
+  std::string err;
+  sc_status st = build_plan(nodes, n_nodes, 0, p, err);
+  if (st != SC_OK) return fail(st, err);
+  fill_info(p, out);
+  return SC_OK;
+}
+
+sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights, size_t n_weights,
+                          sc_precision precision, const float* act_scales, uint32_t options, int32_t device,
+                          sc_model** out) {
+  if (!out) return fail(SC_EINVAL, "null output");
+  *out = nullptr;
+  if (precision != SC_FP32 && precision != SC_BF16 && precision != SC_FP8E4M3)
+    return fail(SC_EINVAL, "unknown precision");
+  if ((options & SC_MODEL_NO_MFMA) && precision != SC_FP32)
+    return fail(SC_EINVAL, "SC_MODEL_NO_MFMA needs SC_FP32");
+  sc_model* m = new (std::nothrow) sc_model();
+  if (!m) return fail(SC_ENOMEM, "host allocation failed");
+  std::string err;
+  sc_status st = build_plan(nodes, n_nodes, options, m->plan, err);
+  if (st != SC_OK) { delete m; return fail(st, err); }
+  if (!weights || (int64_t)n_weights != m->plan.n_weights) {
+    delete m;
+    return fail(SC_EINVAL, "weights missing or of the wrong length (expected " +
+                               std::to_string(m->plan.n_weights) + ")");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    delete m;
+    return fail(SC_EDEVICE, "no such HIP device");
+  }
+  m->device = device;
+  m->prec = precision;
+  m->options = options;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->last_done, hipEventDisableTiming);
+  if (e != hipSuccess) { delete m; return hip_fail(e, "device setup"); }
+  const int n_layers = (int)m->plan.layer_node.size();
+  if (act_scales) {
+    m->act_scales.assign(act_scales, act_scales + n_layers);
+    m->have_scales = true;
+  } else {
+    m->act_scales.assign(n_layers, 1.0f);
+  }
+  const int prec_id = precision == SC_FP32 ? 0 : (precision == SC_BF16 ? 1 : 2);
+  m->opdev.resize(m->plan.ops.size());
+  for (size_t i = 0; i < m->plan.ops.size(); ++i) {
+    Op& op = m->plan.ops[i];
+    OpDev& od = m->opdev[i];
+    if (op.kind == K_DELAY_ADD) continue;
+    const float* w = weights + op.w_off;
+    const float* b = weights + op.b_off;
+    bool mfma = false;
+    if (!(options & SC_MODEL_NO_MFMA) && op.in_buf >= 0 && op.out_buf >= 0) {
+      if (op.kind == K_CONV) mfma = conv_mfma_supported(op.cin, op.cout, op.k, op.stride, prec_id);
+      else mfma = convt_mfma_supported(op.cin, op.cout, op.stride, prec_id);
+    }
+    op.impl = mfma ? IMPL_MFMA : IMPL_VALU;
+    od.prec = mfma ? prec_id : 0;
+    if (mfma) {
+      std::vector<uint8_t> packed;
+      std::vector<float> wscale;
+      if (op.kind == K_CONV) pack_conv_mfma(w, op.cout, op.cin, op.k, prec_id, packed, wscale);
+      else pack_convt_mfma(w, op.cin, op.cout, op.stride, prec_id, packed, wscale);
+      e = upload(reinterpret_cast<uint8_t**>(&od.W), packed.data(), packed.size());
+      if (e == hipSuccess && !wscale.empty()) e = upload(&od.wscale, wscale.data(), wscale.size());
+      m->weight_bytes += (int64_t)packed.size() + (int64_t)wscale.size() * 4;
+    } else {
+      std::vector<float> packed = op.kind == K_CONV ? pack_conv_valu(w, op.cout, op.cin, op.k)
+                                                    : pack_convt_valu(w, op.cin, op.cout, op.stride);
+      e = upload(reinterpret_cast<float**>(&od.W), packed.data(), packed.size());
+      m->weight_bytes += (int64_t)packed.size() * 4;
+    }
+    if (e == hipSuccess) e = upload(&od.B, b, (size_t)op.cout);
+    m->weight_bytes += (int64_t)op.cout * 4;
+    if (e != hipSuccess) { free_model(m); return hip_fail(e, "weight upload"); }
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
+  if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }
+  *out = m;
+  return SC_OK;
+}
+
+sc_status sc_model_info_get(const sc_model* m, sc_model_info* out) {
+  if (!m || !out) return fail(SC_EINVAL, "null argument");
+  fill_info(m->plan, out);
+  out->weight_bytes = m->weight_bytes;
+  int n_mfma = 0;
+  (void)n_mfma;
+  return SC_OK;
+}
+
+int32_t sc_model_n_layers(const sc_model* m) { return m ? (int32_t)m->plan.layer_node.size() : -1; }
+
+sc_status sc_model_set_act_scales(sc_model* m, const float* s) {
+  if (!m || !s) return fail(SC_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(m->mu);
+  const int n = (int)m->plan.layer_node.size();
+  for (int i = 0; i < n; ++i)
+    if (!(s[i] > 0.f) || !std::isfinite(s[i])) return fail(SC_EINVAL, "activation scales must be positive and finite");
+  m->act_scales.assign(s, s + n);
+  m->have_scales = true;
+  return SC_OK;
+}
+
+sc_status sc_model_enable_amax(sc_model* m, int32_t enable) {
+  if (!m) return fail(SC_EINVAL, "null model");
+  std::lock_guard<std::mutex> g(m->mu);
+  m->amax_on = enable != 0;
+  return SC_OK;
+}
+
+sc_status sc_model_read_amax(sc_model* m, float* out, int32_t reset) {
+  if (!m || !out) return fail(SC_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(m->mu);
+  const int n = (int)m->plan.layer_node.size();
+  hipError_t e = hipSetDevice(m->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess && n > 0) e = hipMemcpy(out, m->d_amax, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset && n > 0) e = hipMemset(m->d_amax, 0, n * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "amax readback");
+  return SC_OK;
+}
+
+void sc_model_destroy(sc_model* m) { free_model(m); }
+
+sc_status sc_model_profile(sc_model* m, int32_t enable) {
+  if (!m) return fail(SC_EINVAL, "null model");
+  std::lock_guard<std::mutex> g(m->mu);
+  hipSetDevice(m->device);
+  hipError_t e = prof_fold(m);
+  if (e != hipSuccess) return hip_fail(e, "profile fold");
+  m->prof_on = enable != 0;
+  if (m->prof_on) {
+    m->prof.assign(m->plan.ops.size(), sc_op_profile{});
+    for (size_t i = 0; i < m->plan.ops.size(); ++i) {
+      const Op& op = m->plan.ops[i];
+      sc_op_profile& p = m->prof[i];
+      p.kind = op.kind;
+      p.impl = op.impl;
+      p.precision = m->opdev[i].prec;
+      p.node = op.node;
+      p.cin = op.cin; p.cout = op.cout; p.k = op.k; p.dilation = op.dil; p.stride = op.stride;
+      p.cache_len = op.cache_len; p.residual = op.residual; p.a0 = op.A0; p.a1 = op.A1;
+      p.rate_in_num = (int32_t)op.in_rate.num; p.rate_in_den = (int32_t)op.in_rate.den;
+      p.rate_out_num = (int32_t)op.out_rate.num; p.rate_out_den = (int32_t)op.out_rate.den;
+    }
+  }
+  return SC_OK;
+}
+
+sc_status sc_model_profile_read(sc_model* m, sc_op_profile* out, int32_t max_ops, int32_t* n_ops) {
+  if (!m || !n_ops) return fail(SC_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(m->mu);
+  hipSetDevice(m->device);
+  hipError_t e = prof_fold(m);
+  if (e != hipSuccess) return hip_fail(e, "profile fold");
+  *n_ops = (int32_t)m->plan.ops.size();
+  for (int i = 0; out && i < max_ops && i < (int)m->prof.size(); ++i) out[i] = m->prof[i];
+  return SC_OK;
+}
+
+sc_status stream_create(sc_model* m, int32_t max_frames, uint32_t flags, void* hip_stream, sc_stream** out) {
+  if (!m || !out) return fail(SC_EINVAL, "null argument");
+  *out = nullptr;
+  if (max_frames < 1 || max_frames % m->plan.input_multiple != 0)
+    return fail(SC_ELENGTH, "max_buffer_frames must be >= 1 and a multiple of the total stride");
+  if (flags & ~(uint32_t)SC_FLAG_WARMUP_MASK) return fail(SC_EINVAL, "unknown flags");
+  std::lock_guard<std::mutex> g(m->mu);
+  hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  sc_stream* s = new (std::nothrow) sc_stream();
+  if (!s) return fail(SC_ENOMEM, "host allocation failed");
+  s->m = m;
+  s->max_frames = max_frames;
+  s->flags = flags;
+  const size_t bytes = (size_t)std::max<int64_t>(2 * m->plan.state_floats, 1) * sizeof(float);
+  e = hipMalloc(reinterpret_cast<void**>(&s->d_state), bytes);
+  if (e != hipSuccess) { delete s; return fail(SC_ENOMEM, "state allocation failed"); }
+  sc_status st = zero_state(s, static_cast<hipStream_t>(hip_stream));
+  if (st != SC_OK) { hipFree(s->d_state); delete s; return st; }
+  *out = s;
+  return SC_OK;
+}
+
+sc_status stream_process(sc_stream* s, const float* d_in, int32_t n_frames, float* d_out, void* hip_stream) {
+  if (!s) return fail(SC_EINVAL, "null stream");
+  std::lock_guard<std::mutex> g(s->m->mu);
+  return run_step(s->m, 1, &s, &d_in, &n_frames, &d_out, static_cast<hipStream_t>(hip_stream));
+}
+
+sc_status sc_process_batch(sc_model* m, int32_t n, sc_stream* const* streams, const float* const* d_in,
+                           const int32_t* n_frames, float* const* d_out, void* hip_stream) {
+  if (!m) return fail(SC_EINVAL, "null model");
+  std::lock_guard<std::mutex> g(m->mu);
+  return run_step(m, n, streams, d_in, n_frames, d_out, static_cast<hipStream_t>(hip_stream));
+}
+
+sc_status stream_reset(sc_stream* s, void* hip_stream) {
+  if (!s) return fail(SC_EINVAL, "null stream");
+  std::lock_guard<std::mutex> g(s->m->mu);
+  return zero_state(s, static_cast<hipStream_t>(hip_stream));
+}
+
+int64_t stream_position(const sc_stream* s) { return s ? s->pos : -1; }
+
+void stream_destroy(sc_stream* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->m->mu);
+    hipSetDevice(s->m->device);
+    if (s->m->has_last) hipEventSynchronize(s->m->last_done);
+    hipFree(s->d_state);
+  }
+  delete s;
+}
+
+}  // extern "C"

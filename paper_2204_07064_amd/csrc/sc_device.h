@@ -1,0 +1,41 @@
+// Device-side descriptors shared by the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "streamconv.h"
+
+namespace sc {
+
+// One stream's part of a processing step.  The runtime writes one Entry per
+// stream into device memory before the step's launches.
+struct Entry {
+  const float* in;   // user input, channel-major [in_channels][T]
+  float* out;        // user output, channel-major [out_channels][T * out_rate]
+  float* state;      // the stream's state block (FP32, double-buffered regions)
+  int32_t T;         // input frames in this buffer
+  int32_t off;       // sum of T over the previous entries of the step
+  int32_t parity;    // state copy holding the current caches (the other is written)
+  int32_t flags;     // SC_FLAG_* of the stream
+  int64_t pos;       // input frames processed before this buffer
+};
+
+// Frames of `rate` (num/den per input frame) for t input frames.
+__device__ __host__ inline int64_t at_rate(int64_t t, int64_t num, int64_t den) { return t * num / den; }
+
+// Largest entry e with start(e) <= x, start(e) = off_e * num / den + e * extra.
+__device__ inline int find_entry(const Entry* ents, int n, int64_t x, int64_t num, int64_t den,
+                                 int64_t extra) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t st = at_rate(ents[mid].off, num, den) + (int64_t)mid * extra;
+    if (st <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline float lrelu(float v) { return v >= 0.f ? v : 0.2f * v; }
+
+}  // namespace sc

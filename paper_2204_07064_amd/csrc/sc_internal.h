@@ -1,0 +1,78 @@
+// Internal types shared by the planner, the runtime and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "streamconv.h"
+
+namespace sc {
+
+// A non-negative rational number of frames per model-input frame.
+struct Frac {
+  int64_t num = 1, den = 1;
+  static int64_t gcd(int64_t a, int64_t b) {
+    while (b) { int64_t t = a % b; a = b; b = t; }
+    return a < 0 ? -a : a;
+  }
+  Frac() = default;
+  Frac(int64_t n, int64_t d) : num(n), den(d) { int64_t g = gcd(n, d); if (g) { num /= g; den /= g; } }
+  Frac mul(int64_t k) const { return Frac(num * k, den); }
+  Frac div(int64_t k) const { return Frac(num, den * k); }
+  bool operator==(const Frac& o) const { return num == o.num && den == o.den; }
+  // frames of this rate for `t` input frames (t must make it integral)
+  int64_t of(int64_t t) const { return t * num / den; }
+};
+
+enum OpKind : int32_t { K_CONV = 1, K_CONVT = 2, K_DELAY_ADD = 3 };
+
+// Which kernel family runs an op.
+enum Impl : int32_t { IMPL_VALU = 0, IMPL_MFMA = 1 };
+
+// One launch of a processing step (a conv with optional fused residual, a
+// transposed conv, or a delay-line sum).
+struct Op {
+  int32_t kind = 0;
+  int32_t impl = IMPL_VALU;
+  int32_t node = -1;          // node whose output this op writes
+  int32_t conv_node = -1;     // node that owns the weights (conv / convt)
+  int32_t src = -1, src2 = -1;
+  int32_t cin = 0, cout = 0, k = 0, dil = 1, stride = 1, pad_l = 0, pad_r = 0;
+  int32_t pre_act = 0, post_act = 0;
+  int32_t residual = 0;       // fused skip: out += raw window row (t + skip_off)
+  int32_t skip_off = 0;
+  int32_t cache_len = 0;      // conv: cached input frames L; convt: carry frames
+  int32_t extra_delay = 0;    // Eq. 2 D_a of a strided conv
+  int32_t A0 = 0, A1 = 0;     // delay-line lengths of a delay-add (Eq. 3)
+  Frac in_rate, out_rate;
+  int64_t out_delay = 0;      // lag of the output stream, in its own frames
+  int64_t state_off = 0, state_len = 0;     // floats; copies at off and off + len
+  int64_t state_off2 = 0, state_len2 = 0;   // second delay line of a delay-add
+  int32_t in_buf = -1, in_buf2 = -1, out_buf = -1;  // -1: user input / user output
+  int32_t layer = -1;         // index among conv/convt nodes
+  int64_t w_off = 0, b_off = 0;             // offsets into the FP32 weight array
+};
+
+struct Plan {
+  std::vector<sc_node> nodes;
+  std::vector<Op> ops;
+  std::vector<int64_t> delay, warm;
+  std::vector<Frac> rate;
+  std::vector<int32_t> layer_node;   // conv/convt node of each layer
+  std::vector<Frac> buf_floats;      // floats per input frame of each workspace buffer
+  int32_t in_channels = 0, out_channels = 0;
+  int32_t input_multiple = 1;
+  Frac out_rate;
+  int64_t latency = 0, warmup = 0;
+  int64_t state_floats = 0;          // one copy of all state
+  int64_t n_weights = 0;
+};
+
+// Builds the streaming plan (post-training reconfiguration) of a node list.
+sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& plan,
+                     std::string& err);
+
+void set_error(const std::string& msg);
+
+}  // namespace sc

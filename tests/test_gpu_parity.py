@@ -1,0 +1,146 @@
+"""GPU parity of the streaming library against the FP64 oracle (FP32 path),
+and the method's invariants on the device: the streamed output equals the
+offline output delayed by the latency (paper Sec. 4.2), bitwise independent of
+the buffer split, of batching with other streams, and of reset."""
+import numpy as np
+import pytest
+
+import scgen
+from oracle import metrics
+from gpu_helpers import log, oracle_compare, run_stream, weights_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def _sc():
+    import paper_2204_07064_amd as sc
+    return sc
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("name,frames,buf,options", [
+    ("stack3", 16384, 512, 0),          # 3-layer stack, 32 buffers of 512
+    ("rave_b", 256, 16, 0),             # decoder, 16 buffers of 16 latent frames
+    ("rave_b", 40, 1, 0),               # 1-frame buffers, below the receptive field
+    ("rave_b", 96, 16, 2),              # every layer on the FP32 wavefront kernels
+    ("rave_b", 64, 9, 1),               # residual sums as explicit delay lines
+    ("strided", 256, 8, 0),             # Eq. 2 alignment delay D_a = 1
+    ("strided_aligned", 256, 6, 0),
+    ("branch", 300, 7, 0),              # Eq. 3 branch delays (3, 0)
+    ("encoder", 128 * 40, 128 * 3, 0),  # strided encoder, buffers multiple of 128
+])
+def test_fp32_parity(name, frames, buf, options):
+    sc = _sc()
+    log("parity %s frames=%d buf=%d options=%d" % (name, frames, buf, options))
+    m, w = weights_for(name)
+    x = scgen.stream_latents(m["in_channels"], frames, 0)
+    mod = sc.Model(m, w, "fp32", options=options)
+    splits = scgen.split_lengths(frames, buf)
+    s = run_stream(mod, x, splits)
+    err, snr, _ = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
+    log("  max-abs %.3e snr %.1f dB" % (err, snr))
+    assert err <= FP32_TOL
+
+
+def test_split_invariance_bitwise():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    x = scgen.stream_latents(16, 64, 3)
+    mod = sc.Model(m, w, "fp32")
+    ref = run_stream(mod, x, [64])
+    for seed in range(3):
+        s = run_stream(mod, x, scgen.random_split(64, seed, 12))
+        assert np.array_equal(s, ref)
+
+
+def test_fusion_is_bitwise_equal_to_delay_lines():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    x = scgen.stream_latents(16, 48, 4)
+    a = run_stream(sc.Model(m, w, "fp32"), x, [5, 11, 32])
+    b = run_stream(sc.Model(m, w, "fp32", options=1), x, [5, 11, 32])
+    assert np.array_equal(a, b)
+
+
+def test_warmup_mask():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    x = scgen.stream_latents(16, 48, 5)
+    mod = sc.Model(m, w, "fp32")
+    s = run_stream(mod, x, [7, 9, 32], warmup_mask=True)
+    D = mod.latency
+    assert np.all(s[:, :D] == 0.0)
+    err, _, _ = oracle_compare(m, w, x, s, D, 0)
+    assert err <= FP32_TOL
+
+
+def test_reset_equals_fresh():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "fp32")
+    x = scgen.stream_latents(16, 32, 6)
+    st = sc.Stream(mod, 32)
+    run_stream(mod, scgen.stream_latents(16, 13, 7), [13], stream=st)
+    st.reset()
+    assert st.position == 0
+    a = run_stream(mod, x, [10, 22], stream=st)
+    b = run_stream(mod, x, [10, 22])
+    assert np.array_equal(a, b)
+
+
+def test_batch_equals_alone_bitwise():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "fp32")
+    lens = [1, 4, 16, 2, 32, 8, 3]
+    xs = [scgen.stream_latents(16, 3 * n, 20 + i) for i, n in enumerate(lens)]
+    alone = [run_stream(mod, x, [n, n, n]) for x, n in zip(xs, lens)]
+    streams = [sc.Stream(mod, 32) for _ in lens]
+    outs = [[] for _ in lens]
+    for step in range(3):
+        xd = [torch.from_numpy(x[:, step * n:(step + 1) * n].copy()).cuda() for x, n in zip(xs, lens)]
+        ys = sc.process_batch(mod, streams, xd)
+        for i, y in enumerate(ys):
+            outs[i].append(y)
+    torch.cuda.synchronize()
+    for i in range(len(lens)):
+        got = torch.cat(outs[i], dim=1).cpu().double().numpy()
+        assert np.array_equal(got, alone[i]), i
+
+
+def test_bad_length_changes_nothing():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "fp32")
+    st = sc.Stream(mod, 16)
+    x = scgen.stream_latents(16, 32, 8)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty((1, 128 * 17), device="cuda")
+    with pytest.raises(sc.ScError) as ei:
+        st.process_into(xd[:, :17].contiguous(), out)       # above max_buffer_frames
+    assert ei.value.status == -4
+    with pytest.raises(sc.ScError):
+        st.process_into(xd[:, :1].contiguous(), out, n_frames=0)
+    assert st.position == 0
+    a = run_stream(mod, x, [16, 16], stream=st)
+    b = run_stream(mod, x, [16, 16])
+    assert np.array_equal(a, b)
+
+
+def test_encoder_rejects_misaligned_buffer():
+    sc = _sc()
+    m, w = weights_for("encoder")
+    mod = sc.Model(m, w, "fp32")
+    st = sc.Stream(mod, 256)
+    x = torch.zeros((1, 100), device="cuda")
+    with pytest.raises(sc.ScError) as ei:
+        st.process(x)
+    assert ei.value.status == -4
