@@ -143,7 +143,8 @@ sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);
  * the model's device work. */
 sc_status sc_model_read_amax(sc_model* model, float* amax_out, int32_t reset);
 sc_status sc_model_enable_amax(sc_model* model, int32_t enable);
-/* The caller guarantees every stream of the model was destroyed first. */
+/* Releases the caller's reference.  The model's memory is freed once its
+ * last stream has been destroyed as well. */
 void sc_model_destroy(sc_model* model);
 
 /* Open a stream: allocates and zeroes (on `hip_stream`) its state.  Buffers

@@ -9,6 +9,7 @@ the library's kernels.
     s = Stream(model, max_buffer_frames=32)
     y = s.process(x)          # x: cuda float32 [in_channels][T]
 """
+import atexit
 import ctypes
 
 import numpy as np
@@ -17,6 +18,16 @@ from . import _native
 from ._native import ScError, check, lib, nodes_array  # noqa: F401
 
 __all__ = ["Model", "Stream", "process_batch", "plan", "ScError", "lib"]
+
+
+_EXITING = [False]
+
+
+@atexit.register
+def _at_exit():
+    # objects still alive at interpreter exit are left to the process teardown:
+    # the HIP runtime may already be gone when their finalizers would run
+    _EXITING[0] = True
 
 
 def _stream_handle(hip_stream):
@@ -92,9 +103,9 @@ class Model:
         return [{f: getattr(arr[i], f) for f, _ in _native.ScOpProfile._fields_} for i in range(n.value)]
 
     def close(self):
-        if self.handle:
+        if self.handle and not _EXITING[0]:
             lib().sc_model_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -136,9 +147,9 @@ class Stream:
         return lib().stream_position(self.handle)
 
     def close(self):
-        if self.handle:
+        if self.handle and not _EXITING[0]:
             lib().stream_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

@@ -1,15 +1,541 @@
-// MFMA implicit-GEMM kernels for the wide layers (placeholder: not yet enabled).
+// MFMA implicit-GEMM kernels for the wide layers (gfx950).
+//
+// A cached stride-1 conv is the GEMM  Out[n][m] = sum_kk A[m][kk] * B[kk][n]
+// with m the output channel, n a frame of the step's packed frame space
+// (frames of all streams back to back, so one tile may span several
+// streams), and kk = tap * cin + ci.  Column n of B is gathered from the
+// window [cache | new frames] of n's stream: row t + dilation * tap, with
+// LeakyReLU and the operand rounding applied on the way into LDS.
+//
+// A transposed conv with kernel 2r is, per input frame q, the GEMM row block
+// m = phi * cout + co over kk = h * cin + ci, where h = 0 reads frame q - 1
+// (taps phi + r) and h = 1 reads frame q (taps phi).  Each stream gets one
+// extra column q = T that only holds the h = 0 half: it is written as the
+// FP32 overlap carry, and column q = 0 of the next buffer starts its
+// accumulator from that carry.  Both halves are padded to whole K chunks, so
+// every output frame runs the same chain of MFMAs whatever the buffer split.
+//
+// Precision: FP32 (v_mfma_f32_16x16x4_f32), BF16 RNE (v_mfma_f32_16x16x32_bf16)
+// or OCP FP8 e4m3 (v_mfma_scale_f32_16x16x128_f8f6f4, unit block scales) with a
+// per-row weight scale and a static activation scale applied in the FP32
+// epilogue.  Accumulation, bias, skip, carry and caches are FP32.
+//
+// Tiling: 256 threads = 4 waves; workgroup tile MT x NT (MT * NT = 4096),
+// each wave a 32 x 32 tile = 2 x 2 MFMA 16x16 blocks.  Each K chunk is 128
+// bytes of every A row and B column (32 FP32, 64 BF16 or 128 FP8 values); lane
+// group g = lane / 16 owns bytes [32g, 32g + 32) of a row, the same slice for A
+// and B, so the reduction is over the same K elements for both operands.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
 
 #include "kernels.h"
 
 namespace sc {
 
-bool conv_mfma_supported(int, int, int, int, int) { return false; }
-bool convt_mfma_supported(int, int, int, int) { return false; }
-void pack_conv_mfma(const float*, int, int, int, int, std::vector<uint8_t>&, std::vector<float>&) {}
-void pack_convt_mfma(const float*, int, int, int, int, std::vector<uint8_t>&, std::vector<float>&) {}
-hipError_t launch_conv_mfma(const LayerArgs&, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_convt_mfma(const LayerArgs&, int, hipStream_t) { return hipErrorNotSupported; }
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunkBytes = 128;
+constexpr int kRowStride = 144;   // padded LDS row (bytes)
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct Prec;
+template <> struct Prec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; };
+template <> struct Prec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; };
+template <> struct Prec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; };
+
+// ---- operand conversion ------------------------------------------------------
+__device__ inline uint32_t pack_bf16(float lo, float hi) {
+  bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return u;
+}
+
+__device__ inline float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
+
+__device__ inline uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  int v = 0;
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(a), sat448(b), v, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), v, true);
+  return (uint32_t)v;
+}
+
+// Converts 8 floats to the operand type and stores them at `dst` (LDS).
+template <int PREC>
+__device__ inline void store8(unsigned char* dst, const float* v) {
+  if constexpr (PREC == 0) {
+    f4* d = reinterpret_cast<f4*>(dst);
+    d[0] = f4{v[0], v[1], v[2], v[3]};
+    d[1] = f4{v[4], v[5], v[6], v[7]};
+  } else if constexpr (PREC == 1) {
+    uint4 u;
+    u.x = pack_bf16(v[0], v[1]);
+    u.y = pack_bf16(v[2], v[3]);
+    u.z = pack_bf16(v[4], v[5]);
+    u.w = pack_bf16(v[6], v[7]);
+    *reinterpret_cast<uint4*>(dst) = u;
+  } else {
+    uint2 u;
+    u.x = pack_fp8x4(v[0], v[1], v[2], v[3]);
+    u.y = pack_fp8x4(v[4], v[5], v[6], v[7]);
+    *reinterpret_cast<uint2*>(dst) = u;
+  }
+}
+
+// 32-byte fragment of one lane (its slice of a 128-byte chunk row).
+struct Frag {
+  uint4 lo, hi;
+};
+
+template <int PREC>
+__device__ inline f4 mfma_chunk(const Frag& a, const Frag& b, f4 acc) {
+  if constexpr (PREC == 0) {
+    float av[8], bv[8];
+    __builtin_memcpy(av, &a, 32);
+    __builtin_memcpy(bv, &b, 32);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+  } else if constexpr (PREC == 1) {
+    bf16x8 a0, a1, b0, b1;
+    __builtin_memcpy(&a0, &a.lo, 16);
+    __builtin_memcpy(&a1, &a.hi, 16);
+    __builtin_memcpy(&b0, &b.lo, 16);
+    __builtin_memcpy(&b1, &b.hi, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
+  } else {
+    i8v av, bv;
+    __builtin_memcpy(&av, &a, 32);
+    __builtin_memcpy(&bv, &b, 32);
+    // formats 0/0 = FP8 e4m3 for both operands; E8M0 block scales 127 = 1.0
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+  }
+  return acc;
+}
+
+// Per-column context of the column a thread gathers.
+struct Col {
+  bool valid;
+  int ei;
+  int64_t t;         // conv: local output frame; convt: q
+  int64_t in_start;  // first packed input frame of the stream
+  int64_t Tin;       // input frames of the stream (input rate)
+  const float* cache;  // conv: current cache copy (raw FP32 [L][cin])
+};
+
+template <bool CONVT>
+__device__ inline Col column(const LayerArgs& a, int64_t n, int64_t n_cols) {
+  Col c{};
+  c.valid = n < n_cols;
+  if (!c.valid) return c;
+  if (CONVT) {
+    c.ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 1);
+  } else {
+    c.ei = find_entry(a.ents, a.n_ent, n, a.out_num, a.out_den, 0);
+  }
+  const Entry& e = a.ents[c.ei];
+  c.in_start = at_rate(e.off, a.in_num, a.in_den);
+  c.Tin = at_rate(e.T, a.in_num, a.in_den);
+  if (CONVT) {
+    c.t = n - c.in_start - c.ei;
+  } else {
+    c.t = n - at_rate(e.off, a.out_num, a.out_den);
+    c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+  }
+  return c;
+}
+
+// Loads 8 consecutive input channels (kk .. kk + 7 of the K dimension) of a
+// column, raw FP32; zeros for padding or absent frames.
+template <bool CONVT>
+__device__ inline void gather8(const LayerArgs& a, const Col& c, int kk, int Kreal, int half_pad, float* v) {
+  const float* src = nullptr;
+  if (c.valid) {
+    if (CONVT) {
+      // K layout: [h = 0: half_pad][h = 1: half_pad], real channels first in each half
+      const int h = kk >= half_pad;
+      const int ci = kk - h * half_pad;
+      const int64_t row = c.t - 1 + h;
+      if (ci < a.cin && row >= 0 && row < c.Tin) src = a.in_buf + (c.in_start + row) * a.cin + ci;
+    } else if (kk < Kreal) {
+      const int tap = kk / a.cin;
+      const int ci = kk - tap * a.cin;
+      const int64_t row = c.t + (int64_t)a.dil * tap;
+      if (row < a.L) src = c.cache + row * a.cin + ci;
+      else src = a.in_buf + (c.in_start + row - a.L) * a.cin + ci;
+    }
+  }
+  if (src) {
+    const f4 x0 = *reinterpret_cast<const f4*>(src);
+    const f4 x1 = *reinterpret_cast<const f4*>(src + 4);
+    v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+    v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0.f;
+  }
+}
+
+template <int PREC, int MT, int NT, bool CONVT>
+__global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_cols, int n_mt, int n_nt,
+                                                        int Kpad, int Kreal, int half_pad, int Mreal,
+                                                        int extra_blocks) {
+  constexpr int KC = Prec<PREC>::kKc;
+  constexpr int ES = Prec<PREC>::kEsize;
+  constexpr int TPC = kThreads / NT;          // threads per B column
+  constexpr int SE = KC / TPC;                // elements each thread gathers per chunk
+  constexpr int WM = MT / 32;                 // waves along M
+  static_assert(WM * (NT / 32) == 4, "4 waves of 32x32");
+  static_assert(SE % 8 == 0, "gather groups of 8");
+
+  __shared__ __attribute__((aligned(16))) unsigned char lds_a[2][MT * kRowStride];
+  __shared__ __attribute__((aligned(16))) unsigned char lds_b[2][NT * kRowStride];
+
+  const int tid = threadIdx.x;
+  const int64_t n_tiles = (int64_t)n_mt * n_nt;
+  // ---- conv cache update blocks (after the GEMM tiles) ----
+  if (!CONVT && (int64_t)blockIdx.x >= n_tiles) {
+    const int64_t per_ent = (int64_t)a.L * a.cin;
+    const int64_t total = (int64_t)a.n_ent * per_ent;
+    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kThreads + tid; j < total;
+         j += (int64_t)extra_blocks * kThreads) {
+      const int ei = (int)(j / per_ent);
+      const int64_t rem = j % per_ent;
+      const int64_t i = rem / a.cin;
+      const int ci = (int)(rem % a.cin);
+      const Entry& e = a.ents[ei];
+      const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
+      const int64_t row = Tin + i;
+      float v;
+      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + row * a.cin + ci];
+      else v = a.in_buf[(at_rate(e.off, a.in_num, a.in_den) + row - a.L) * a.cin + ci];
+      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = v;
+    }
+    return;
+  }
+  const int mt = (int)(blockIdx.x % n_mt);
+  const int64_t nt = blockIdx.x / n_mt;
+  const int m0 = mt * MT;
+  const int64_t n0 = nt * NT;
+
+  // the column this thread gathers
+  const int my_col = tid % NT;
+  const int my_seg = tid / NT;
+  const Col gc = column<CONVT>(a, n0 + my_col, n_cols);
+
+  const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
+  const int row_bytes = Kpad * ES;
+  const int n_chunks = Kpad / KC;
+  const bool pre = a.pre_act != 0;
+  const float qs = (PREC == 2) ? 1.0f / a.act_scale : 1.0f;
+
+  // A chunk: MT rows x 128 bytes = MT * 8 pieces of 16 B
+  constexpr int A_PIECES = MT * 8 / kThreads;
+  uint4 areg[A_PIECES];
+  float breg[SE];
+
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int p = 0; p < A_PIECES; ++p) {
+      const int piece = tid + p * kThreads;
+      const int r = piece >> 3, seg = piece & 7;
+      areg[p] = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r) * row_bytes + c * kChunkBytes + seg * 16);
+    }
+#pragma unroll
+    for (int g = 0; g < SE / 8; ++g) {
+      const int kk = c * KC + my_seg * SE + g * 8;
+      gather8<CONVT>(a, gc, kk, Kreal, half_pad, breg + g * 8);
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < A_PIECES; ++p) {
+      const int piece = tid + p * kThreads;
+      const int r = piece >> 3, seg = piece & 7;
+      *reinterpret_cast<uint4*>(&lds_a[buf][r * kRowStride + seg * 16]) = areg[p];
+    }
+#pragma unroll
+    for (int g = 0; g < SE / 8; ++g) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        float x = breg[g * 8 + i];
+        if (pre) x = lrelu(x);
+        v[i] = x * qs;
+      }
+      store8<PREC>(&lds_b[buf][my_col * kRowStride + (my_seg * SE + g * 8) * ES], v);
+    }
+  };
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  // accumulators; a transposed conv's column q = 0 starts from the carry
+  f4 acc[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    f4 init = {0.f, 0.f, 0.f, 0.f};
+    if (CONVT) {
+      const int64_t n = n0 + wn * 32 + j * 16 + lr;
+      if (n < n_cols) {
+        const int ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 1);
+        const Entry& e = a.ents[ei];
+        const int64_t q = n - at_rate(e.off, a.in_num, a.in_den) - ei;
+        if (q == 0) {
+          // the lane's 4 rows of each 16-row block: m = m0 + wm*32 + i*16 + lg*4 + {0..3}
+          const float* carry = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int m = m0 + wm * 32 + i * 16 + lg * 4;
+            f4 cv = {0.f, 0.f, 0.f, 0.f};
+            if (m < Mreal) cv = *reinterpret_cast<const f4*>(carry + m);
+            acc[i][j] = cv;
+          }
+          continue;
+        }
+      }
+    }
+    acc[0][j] = init;
+    acc[1][j] = init;
+  }
+
+  load_chunk(0);
+  for (int c = 0; c < n_chunks; ++c) {
+    const int buf = c & 1;
+    store_chunk(buf);
+    __syncthreads();
+    if (c + 1 < n_chunks) load_chunk(c + 1);
+    Frag fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const unsigned char* p = &lds_a[buf][(wm * 32 + i * 16 + lr) * kRowStride + lg * 32];
+      fa[i].lo = *reinterpret_cast<const uint4*>(p);
+      fa[i].hi = *reinterpret_cast<const uint4*>(p + 16);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const unsigned char* p = &lds_b[buf][(wn * 32 + j * 16 + lr) * kRowStride + lg * 32];
+      fb[j].lo = *reinterpret_cast<const uint4*>(p);
+      fb[j].hi = *reinterpret_cast<const uint4*>(p + 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_chunk<PREC>(fa[i], fb[j], acc[i][j]);
+  }
+
+  // ---- epilogue: lane holds rows m..m+3 of column n for each (i, j) ----
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t n = n0 + wn * 32 + j * 16 + lr;
+    if (n >= n_cols) continue;
+    const Col c = column<CONVT>(a, n, n_cols);
+    const Entry& e = a.ents[c.ei];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = m0 + wm * 32 + i * 16 + lg * 4;
+      if (m >= Mreal) continue;
+      f4 v = acc[i][j];
+      if (PREC == 2) {
+        const f4 ws = *reinterpret_cast<const f4*>(a.wscale + m);
+        v = v * (ws * a.act_scale);
+      }
+      if (CONVT) {
+        const int co = m % a.cout;
+        const int phi = m / a.cout;
+        if (c.t >= c.Tin) {
+          // carry column: FP32 partial sums of the next buffer's first frame
+          float* carry_out = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
+          *reinterpret_cast<f4*>(carry_out + m) = acc[i][j];
+          continue;
+        }
+        const f4 b = *reinterpret_cast<const f4*>(a.B + co);
+        v = v + b;
+        const int64_t t = c.t * a.stride + phi;
+        if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay)
+          v = f4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f4*>(a.out_buf + (c.in_start * a.stride + c.t * a.stride) * a.cout + m) = v;
+      } else {
+        const f4 b = *reinterpret_cast<const f4*>(a.B + m);
+        v = v + b;
+        if (a.residual) {
+          const int64_t row = c.t + a.skip_off;
+          const float* sp = row < a.L ? c.cache + row * a.cin
+                                      : a.in_buf + (c.in_start + row - a.L) * a.cin;
+          v = v + *reinterpret_cast<const f4*>(sp + m);
+        }
+        if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + c.t < a.delay)
+          v = f4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f4*>(a.out_buf + n * a.cout + m) = v;
+      }
+    }
+  }
+}
+
+// ---- host side -------------------------------------------------------------------
+int esize(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
+int kchunk(int prec) { return prec == 0 ? 32 : (prec == 1 ? 64 : 128); }
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP FP8 E4M3FN, round to nearest even, saturating to +-448 (finite input).
+uint8_t fp8_e4m3_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint8_t sign = (u >> 31) ? 0x80 : 0;
+  float a = std::fabs(f);
+  if (!(a > 0.f)) return sign;
+  if (a >= 448.f) return sign | 0x7E;
+  int e;
+  std::frexp(a, &e);              // a = m * 2^e, m in [0.5, 1)
+  int exp = e - 1;                // a = 1.f * 2^exp
+  if (exp < -6) exp = -6;         // subnormal range shares the minimum exponent
+  const float q = std::ldexp(a, 3 - exp);   // value in units of the ulp (2^(exp-3))
+  float r = std::nearbyint(q);             // ties to even under the default rounding mode
+  int mant = (int)r;
+  if (mant >= 16) { exp += 1; mant >>= 1; }  // carried into the next binade
+  if (exp > 8 || (exp == 8 && mant > 14)) return sign | 0x7E;
+  if (mant < 8) return sign | (uint8_t)mant;                      // subnormal (exp == -6)
+  return sign | (uint8_t)(((exp + 7) << 3) | (mant - 8));
+}
+
+// Packs rows of FP32 values (row m of length Kreal values, mapped into a padded
+// row by `kpos`) into the operand type; FP8 gets a per-row scale.
+template <class RowFn, class PosFn>
+void pack_rows(int M, int Mpad, int Kpad, int prec, RowFn value, PosFn kpos, int Kreal, std::vector<uint8_t>& out,
+               std::vector<float>& wscale) {
+  const int es = esize(prec);
+  out.assign((size_t)Mpad * Kpad * es, 0);
+  if (prec == 2) wscale.assign((size_t)Mpad, 1.0f);
+  for (int m = 0; m < M; ++m) {
+    float s = 1.0f;
+    if (prec == 2) {
+      float amax = 0.f;
+      for (int k = 0; k < Kreal; ++k) amax = std::max(amax, std::fabs(value(m, k)));
+      s = amax > 0.f ? amax / 448.f : 1.0f;
+      wscale[m] = s;
+    }
+    for (int k = 0; k < Kreal; ++k) {
+      const float w = value(m, k);
+      uint8_t* dst = &out[((size_t)m * Kpad + kpos(k)) * es];
+      if (prec == 0) {
+        std::memcpy(dst, &w, 4);
+      } else if (prec == 1) {
+        const uint16_t h = bf16_rne(w);
+        std::memcpy(dst, &h, 2);
+      } else {
+        *dst = fp8_e4m3_rne(w / s);
+      }
+    }
+  }
+}
+
+// Tile shape per GEMM M (output rows).
+void tile_for(int M, int& MT, int& NT) {
+  if (M <= 32) { MT = 32; NT = 128; }
+  else if (M <= 64) { MT = 64; NT = 64; }
+  else { MT = 64; NT = 64; }
+}
+
+template <int PREC, int MT, int NT, bool CONVT>
+hipError_t launch_t(const LayerArgs& a, int64_t n_cols, int Kpad, int Kreal, int half_pad, int M,
+                    hipStream_t s) {
+  const int n_mt = (M + MT - 1) / MT;
+  const int64_t n_nt = (n_cols + NT - 1) / NT;
+  int extra = 0;
+  if (!CONVT) {
+    const int64_t items = (int64_t)a.n_ent * a.L * a.cin;
+    extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
+  }
+  const int64_t grid = (int64_t)n_mt * n_nt + extra;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT>), dim3((unsigned)grid), dim3(kThreads), 0, s, a, n_cols,
+                     n_mt, (int)n_nt, Kpad, Kreal, half_pad, M, extra);
+  return hipGetLastError();
+}
+
+template <bool CONVT>
+hipError_t dispatch(const LayerArgs& a, int prec, int64_t n_cols, int Kpad, int Kreal, int half_pad, int M,
+                    hipStream_t s) {
+  int MT, NT;
+  tile_for(M, MT, NT);
+#define SC_CASE(P, A, B)                                                                       \
+  if (prec == P && MT == A && NT == B) return launch_t<P, A, B, CONVT>(a, n_cols, Kpad, Kreal, half_pad, M, s);
+  SC_CASE(0, 32, 128) SC_CASE(0, 64, 64)
+  SC_CASE(1, 32, 128) SC_CASE(1, 64, 64)
+  SC_CASE(2, 32, 128) SC_CASE(2, 64, 64)
+#undef SC_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec) {
+  (void)k;
+  return stride == 1 && cin % 8 == 0 && cout % 16 == 0 && cin >= 32 && cout >= 32 && prec >= 0 && prec <= 2;
+}
+
+bool convt_mfma_supported(int cin, int cout, int r, int prec) {
+  return cin % 8 == 0 && cout % 4 == 0 && cin >= 32 && r * cout >= 32 && (r * cout) % 16 == 0 && prec >= 0 &&
+         prec <= 2;
+}
+
+void pack_conv_mfma(const float* w, int cout, int cin, int k, int prec, std::vector<uint8_t>& out,
+                    std::vector<float>& wscale) {
+  int MT, NT;
+  tile_for(cout, MT, NT);
+  const int Kreal = k * cin;
+  const int Kpad = round_up(Kreal, kchunk(prec));
+  const int Mpad = round_up(cout, MT);
+  // row m, column kk = tap * cin + ci  <-  W[m][ci][tap]
+  pack_rows(cout, Mpad, Kpad, prec,
+            [&](int m, int kk) { const int tap = kk / cin, ci = kk % cin; return w[((size_t)m * cin + ci) * k + tap]; },
+            [](int kk) { return kk; }, Kreal, out, wscale);
+}
+
+void pack_convt_mfma(const float* w, int cin, int cout, int r, int prec, std::vector<uint8_t>& out,
+                     std::vector<float>& wscale) {
+  const int M = r * cout;
+  int MT, NT;
+  tile_for(M, MT, NT);
+  const int half = round_up(cin, kchunk(prec));
+  const int Kpad = 2 * half;
+  const int Mpad = round_up(M, MT);
+  // row m = phi * cout + co; column kk = h * cin + ci: h = 0 -> tap phi + r, h = 1 -> tap phi
+  pack_rows(M, Mpad, Kpad, prec,
+            [&](int m, int kk) {
+              const int phi = m / cout, co = m % cout;
+              const int h = kk / cin, ci = kk % cin;
+              const int tap = h == 0 ? phi + r : phi;
+              return w[((size_t)ci * cout + co) * (2 * r) + tap];
+            },
+            [&](int kk) { return (kk / cin) * half + kk % cin; }, 2 * cin, out, wscale);
+}
+
+hipError_t launch_conv_mfma(const LayerArgs& a, int prec, hipStream_t s) {
+  const int Kreal = a.k * a.cin;
+  const int Kpad = round_up(Kreal, kchunk(prec));
+  return dispatch<false>(a, prec, a.n_out, Kpad, Kreal, 0, a.cout, s);
+}
+
+hipError_t launch_convt_mfma(const LayerArgs& a, int prec, hipStream_t s) {
+  const int half = round_up(a.cin, kchunk(prec));
+  return dispatch<true>(a, prec, a.n_in + a.n_ent, 2 * half, 2 * a.cin, half, a.stride * a.cout, s);
+}
 
 }  // namespace sc

@@ -80,6 +80,8 @@ struct sc_model {
   // calibration
   float* d_amax = nullptr;
   bool amax_on = false;
+  // lifetime: the model itself plus one reference per live stream
+  int refs = 1;
   // tracing
   bool prof_on = false;
   std::vector<hipEvent_t> prof_events;        // pool, used in pairs
@@ -524,7 +526,21 @@ sc_status sc_model_read_amax(sc_model* m, float* out, int32_t reset) {
   return SC_OK;
 }
 
-void sc_model_destroy(sc_model* m) { free_model(m); }
+namespace {
+// Drops one reference; frees the model when none is left.
+void model_unref(sc_model* m) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    last = --m->refs == 0;
+  }
+  if (last) free_model(m);
+}
+}  // namespace
+
+void sc_model_destroy(sc_model* m) {
+  if (m) model_unref(m);
+}
 
 sc_status sc_model_profile(sc_model* m, int32_t enable) {
   if (!m) return fail(SC_EINVAL, "null model");
@@ -581,6 +597,7 @@ sc_status stream_create(sc_model* m, int32_t max_frames, uint32_t flags, void* h
   if (e != hipSuccess) { delete s; return fail(SC_ENOMEM, "state allocation failed"); }
   sc_status st = zero_state(s, static_cast<hipStream_t>(hip_stream));
   if (st != SC_OK) { hipFree(s->d_state); delete s; return st; }
+  m->refs++;
   *out = s;
   return SC_OK;
 }
@@ -608,13 +625,15 @@ int64_t stream_position(const sc_stream* s) { return s ? s->pos : -1; }
 
 void stream_destroy(sc_stream* s) {
   if (!s) return;
+  sc_model* m = s->m;
   {
-    std::lock_guard<std::mutex> g(s->m->mu);
-    hipSetDevice(s->m->device);
-    if (s->m->has_last) hipEventSynchronize(s->m->last_done);
+    std::lock_guard<std::mutex> g(m->mu);
+    hipSetDevice(m->device);
+    if (m->has_last) hipEventSynchronize(m->last_done);
     hipFree(s->d_state);
   }
   delete s;
+  model_unref(m);
 }
 
 }  // extern "C"
