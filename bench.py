@@ -226,16 +226,9 @@ def main():
 
 
 def calibrate(sc, torch, m, w, frames=64, n_streams=4):
-    """Static FP8 activation scales: the FP32 path's max |activated input| of
-    every layer over a few seeded calibration streams, times 1.25."""
-    cal = sc.Model(m, w, "fp32", options=2)
-    cal.enable_amax(True)
-    for i in range(n_streams):
-        st = sc.Stream(cal, frames)
-        st.process(torch.from_numpy(scgen.latents(LATENT, frames, 1 + i)).cuda())
-    amax = cal.read_amax()
-    cal.close()
-    return np.maximum(amax * 1.25, 1e-6)
+    """Static FP8 activation scales from four seeded calibration streams."""
+    from paper_2204_07064_amd import calibrate as cal
+    return cal.act_scales(sc, m, w, [scgen.latents(LATENT, frames, 1 + i) for i in range(n_streams)])
 
 
 if __name__ == "__main__":

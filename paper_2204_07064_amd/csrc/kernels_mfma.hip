@@ -238,15 +238,16 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
 
   // A chunk: MT rows x 128 bytes = MT * 8 pieces of 16 B
   constexpr int A_PIECES = MT * 8 / kThreads;
-  uint4 areg[A_PIECES];
+  static_assert(A_PIECES == 1 || A_PIECES == 2, "MT of 32 or 64");
+  uint4 areg0, areg1;   // this thread's 16-byte pieces of the A chunk (registers)
   float breg[SE];
 
-  auto load_chunk = [&](int c) {
-#pragma unroll
-    for (int p = 0; p < A_PIECES; ++p) {
-      const int piece = tid + p * kThreads;
-      const int r = piece >> 3, seg = piece & 7;
-      areg[p] = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r) * row_bytes + c * kChunkBytes + seg * 16);
+  auto load_chunk = [&](int c) __attribute__((always_inline)) {
+    {
+      const int r = tid >> 3, seg = tid & 7;
+      areg0 = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r) * row_bytes + c * kChunkBytes + seg * 16);
+      if constexpr (A_PIECES == 2)
+        areg1 = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r + 32) * row_bytes + c * kChunkBytes + seg * 16);
     }
 #pragma unroll
     for (int g = 0; g < SE / 8; ++g) {
@@ -254,12 +255,11 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
       gather8<CONVT>(a, gc, kk, Kreal, half_pad, breg + g * 8);
     }
   };
-  auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < A_PIECES; ++p) {
-      const int piece = tid + p * kThreads;
-      const int r = piece >> 3, seg = piece & 7;
-      *reinterpret_cast<uint4*>(&lds_a[buf][r * kRowStride + seg * 16]) = areg[p];
+  auto store_chunk = [&](int buf) __attribute__((always_inline)) {
+    {
+      const int r = tid >> 3, seg = tid & 7;
+      *reinterpret_cast<uint4*>(&lds_a[buf][r * kRowStride + seg * 16]) = areg0;
+      if constexpr (A_PIECES == 2) *reinterpret_cast<uint4*>(&lds_a[buf][(r + 32) * kRowStride + seg * 16]) = areg1;
     }
 #pragma unroll
     for (int g = 0; g < SE / 8; ++g) {
@@ -283,29 +283,24 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   f4 acc[2][2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    f4 init = {0.f, 0.f, 0.f, 0.f};
+    const float* carry = nullptr;
     if (CONVT) {
       const int64_t n = n0 + wn * 32 + j * 16 + lr;
       if (n < n_cols) {
         const int ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 1);
         const Entry& e = a.ents[ei];
-        const int64_t q = n - at_rate(e.off, a.in_num, a.in_den) - ei;
-        if (q == 0) {
-          // the lane's 4 rows of each 16-row block: m = m0 + wm*32 + i*16 + lg*4 + {0..3}
-          const float* carry = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int m = m0 + wm * 32 + i * 16 + lg * 4;
-            f4 cv = {0.f, 0.f, 0.f, 0.f};
-            if (m < Mreal) cv = *reinterpret_cast<const f4*>(carry + m);
-            acc[i][j] = cv;
-          }
-          continue;
-        }
+        if (n - at_rate(e.off, a.in_num, a.in_den) - ei == 0)
+          carry = e.state + a.state_off + (int64_t)e.parity * a.state_len;
       }
     }
-    acc[0][j] = init;
-    acc[1][j] = init;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      // the lane's rows of this 16-row block: m .. m + 3
+      const int m = m0 + wm * 32 + i * 16 + lg * 4;
+      f4 cv = {0.f, 0.f, 0.f, 0.f};
+      if (carry && m < Mreal) cv = *reinterpret_cast<const f4*>(carry + m);
+      acc[i][j] = cv;
+    }
   }
 
   load_chunk(0);

@@ -209,15 +209,18 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
   }
 
   // ---- state layout (double-buffered copies) ----------------------------------
+  // every region starts on a 16-float (64-byte) boundary for vector access
+  auto align16 = [](int64_t x) { return (x + 15) / 16 * 16; };
   int64_t soff = 0, one = 0;
   for (auto& op : plan.ops) {
     op.state_off = soff;
-    soff += 2 * op.state_len;
+    soff = align16(soff + 2 * op.state_len);
     op.state_off2 = soff;
-    soff += 2 * op.state_len2;
+    soff = align16(soff + 2 * op.state_len2);
     one += op.state_len + op.state_len2;
   }
   plan.state_floats = one;
+  plan.state_alloc_floats = soff;
 
   // ---- workspace buffers with reuse after the last reader ---------------------
   std::vector<int32_t> last_use(n, -1);

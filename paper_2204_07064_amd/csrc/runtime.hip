@@ -371,7 +371,7 @@ void fill_info(const Plan& p, sc_model_info* out) {
   out->latency = p.latency;
   out->warmup = p.warmup;
   out->state_bytes_per_stream = p.state_floats * (int64_t)sizeof(float);
-  out->state_alloc_per_stream = 2 * p.state_floats * (int64_t)sizeof(float);
+  out->state_alloc_per_stream = std::max<int64_t>(p.state_alloc_floats, 1) * (int64_t)sizeof(float);
 }
 
 sc_status zero_state(sc_stream* s, hipStream_t hs) {
@@ -382,7 +382,7 @@ sc_status zero_state(sc_stream* s, hipStream_t hs) {
     e = hipStreamWaitEvent(hs, m->last_done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  e = launch_fill_zero(s->d_state, std::max<int64_t>(2 * m->plan.state_floats, 1), hs);
+  e = launch_fill_zero(s->d_state, std::max<int64_t>(m->plan.state_alloc_floats, 1), hs);
   if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
   if (e != hipSuccess) return hip_fail(e, "state reset");
   m->has_last = true;
@@ -592,7 +592,7 @@ sc_status stream_create(sc_model* m, int32_t max_frames, uint32_t flags, void* h
   s->m = m;
   s->max_frames = max_frames;
   s->flags = flags;
-  const size_t bytes = (size_t)std::max<int64_t>(2 * m->plan.state_floats, 1) * sizeof(float);
+  const size_t bytes = (size_t)std::max<int64_t>(m->plan.state_alloc_floats, 1) * sizeof(float);
   e = hipMalloc(reinterpret_cast<void**>(&s->d_state), bytes);
   if (e != hipSuccess) { delete s; return fail(SC_ENOMEM, "state allocation failed"); }
   sc_status st = zero_state(s, static_cast<hipStream_t>(hip_stream));

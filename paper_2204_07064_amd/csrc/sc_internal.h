@@ -66,6 +66,7 @@ struct Plan {
   Frac out_rate;
   int64_t latency = 0, warmup = 0;
   int64_t state_floats = 0;          // one copy of all state
+  int64_t state_alloc_floats = 0;    // both copies, with alignment padding
   int64_t n_weights = 0;
 };
 
