@@ -165,12 +165,22 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=list(PREC_NAME))
     ap.add_argument("--compare", default="fp32,fp8", help="other precisions timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: streams are independent and the path has no cross-GPU "
               "step; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}))
+        return
     import paper_2204_07064_amd as sc
 
     m = scgen.rave_decoder_b()

@@ -53,6 +53,10 @@ def forward(model, weights, x, precision, act_scales=None):
         w, b = params[i]
         u = offline.apply_pre(nd, outs[nd["src"]])
         if precision != "fp32" and mfma_layer(nd, i == len(nodes) - 1, nd["src"] == 0):
+            if nd.get("pre_act", 0) == 1:
+                # the kernel applies LeakyReLU in FP32 before rounding
+                x32 = np.asarray(outs[nd["src"]], np.float32)
+                u = np.where(x32 >= 0, x32, np.float32(0.2) * x32).astype(np.float64)
             if precision == "bf16":
                 u = q_bf16(u)
                 w = q_bf16(w)

@@ -47,6 +47,11 @@ def test_mfma_fp32_matches_wavefront_fp32():
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_single_stream_precision(prec):
+    """Whole decoder, one stream, 16 buffers of 16 frames, against the oracle.
+    (Network-level comparison with the rounding emulation is loose by nature:
+    the FP32 accumulation already changes a few rounding decisions, and those
+    cascade through the 16 rounded layers -- the per-layer test below is the
+    tight one.)"""
     sc = _sc()
     m, w = weights_for("rave_b")
     scales = _fp8_scales(sc, m, w, 16) if prec == "fp8" else None
@@ -56,13 +61,76 @@ def test_single_stream_precision(prec):
     err, snr, y = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
     ye = emulate.forward(m, w, x, prec, scales)
     sw, ew = metrics.aligned(s, ye, mod.latency, mod.warmup)
-    snr_emul = metrics.snr_db(sw, ew)
-    log("%s: vs oracle max-abs %.3e SNR %.2f dB; vs rounding emulation SNR %.1f dB" % (prec, err, snr, snr_emul))
-    assert snr_emul >= 60.0          # the kernel rounds what it is meant to round
+    log("%s: vs oracle max-abs %.3e SNR %.2f dB; vs rounding emulation SNR %.1f dB"
+        % (prec, err, snr, metrics.snr_db(sw, ew)))
     if prec == "bf16":
         assert snr >= BF16_SNR
     else:
         assert snr >= 15.0           # see test_fp8_snr_target for the 30 dB target
+
+
+def _one_layer_model(kind, c_in, c_out, dil=3, ratio=4):
+    """identity k1 conv (FP32 wavefront, exact copy) -> layer under test (MFMA)
+    -> identity k1 conv to the output (exact copy)."""
+    nodes = [{"op": "input", "channels": c_in},
+             {"op": "conv", "src": 0, "cin": c_in, "cout": c_in, "k": 1, "dilation": 1, "stride": 1,
+              "pad_l": 0, "pad_r": 0, "pre_act": 0, "post_act": 0}]
+    if kind == "residual":
+        nodes.append({"op": "conv", "src": 1, "cin": c_in, "cout": c_in, "k": 3, "dilation": dil, "stride": 1,
+                      "pad_l": dil, "pad_r": dil, "pre_act": 1, "post_act": 0})
+        nodes.append({"op": "add", "src": 1, "src2": 2})
+        c_last = c_in
+    elif kind == "conv":
+        nodes.append({"op": "conv", "src": 1, "cin": c_in, "cout": c_out, "k": 3, "dilation": dil, "stride": 1,
+                      "pad_l": dil, "pad_r": dil, "pre_act": 1, "post_act": 0})
+        c_last = c_out
+    else:
+        nodes.append({"op": "convt", "src": 1, "cin": c_in, "cout": c_out, "k": 2 * ratio, "stride": ratio,
+                      "pad": ratio // 2, "pre_act": 1})
+        c_last = c_out
+    nodes.append({"op": "conv", "src": len(nodes) - 1, "cin": c_last, "cout": c_last, "k": 1, "dilation": 1,
+                  "stride": 1, "pad_l": 0, "pad_r": 0, "pre_act": 0, "post_act": 0})
+    m = {"name": "one_" + kind, "nodes": nodes, "in_channels": c_in, "out_channels": c_last}
+    rng = np.random.default_rng(11)
+    parts = []
+    for nd in nodes:
+        if nd["op"] not in ("conv", "convt"):
+            continue
+        if nd["k"] == 1:
+            parts += [np.eye(nd["cout"], dtype=np.float32).reshape(-1), np.zeros(nd["cout"], np.float32)]
+        else:
+            shape = (nd["cout"], nd["cin"], nd["k"]) if nd["op"] == "conv" else (nd["cin"], nd["cout"], nd["k"])
+            parts += [(rng.uniform(-1, 1, size=shape) / np.sqrt(nd["cin"] * 2)).astype(np.float32).ravel(),
+                      rng.uniform(-0.1, 0.1, size=nd["cout"]).astype(np.float32)]
+    return m, np.concatenate(parts)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("kind,c_in,c_out", [("residual", 64, 64), ("conv", 96, 128), ("convt", 128, 32),
+                                             ("convt", 64, 48)])
+def test_mfma_layer_rounding(prec, kind, c_in, c_out):
+    """One MFMA layer, streamed in uneven buffers (cache / carry paths) with
+    the warm-up mask: equals the offline layer evaluated in FP64 on the same
+    rounded operands up to FP32 accumulation (relative 1e-5)."""
+    sc = _sc()
+    m, w = _one_layer_model(kind, c_in, c_out)
+    layer_scales = np.full(3, 3.0, np.float32)
+    mod = sc.Model(m, w, prec, act_scales=layer_scales if prec == "fp8" else None)
+    frames = 200
+    x = scgen.stream_latents(c_in, frames, 9)
+    s = run_stream(mod, x, [1, 7, 32, 3, 64, 5, 88], warmup_mask=True)
+    ye = emulate.forward(m, w, x, prec, layer_scales)
+    D = mod.latency
+    err = np.max(np.abs(s[:, D:] - ye[:, :ye.shape[1] - D]))
+    ref = np.max(np.abs(ye))
+    log("%s %s %d->%d: max-abs vs rounding emulation %.3e (|y|max %.2f)" % (prec, kind, c_in, c_out, err, ref))
+    assert np.all(s[:, :D] == 0)
+    # FP32 / BF16 MFMA: FP32 accumulation, 1e-5.  The FP8 f8f6f4 MFMA was
+    # measured at up to 2.5e-5 relative on identical operands (its internal
+    # accumulation is coarser than FP32); one mis-rounded FP8 operand would
+    # cost ~1e-3, so 1e-4 still pins the rounding.
+    tol = 1e-4 if prec == "fp8" else 1e-5
+    assert err <= tol * ref
 
 
 @pytest.mark.xfail(reason="plain e4m3 (3 mantissa bits, ~29 dB per rounded layer) on all 16 wide "
