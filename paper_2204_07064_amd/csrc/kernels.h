@@ -12,6 +12,7 @@ namespace sc {
 // Arguments common to the conv-like kernels of one op in one step.
 struct LayerArgs {
   const Entry* ents;
+  const int32_t* fent;     // entry of every input frame of the step
   int32_t n_ent;
   const float* in_buf;     // packed [frames][cin] at the input rate, or null: user input
   const float* in_buf2;    // delay-add second branch
@@ -27,7 +28,11 @@ struct LayerArgs {
   int64_t state_off, state_len, state_off2, state_len2;
   int64_t n_in;            // total input frames of the step at the input rate
   int64_t n_out;           // total output frames of the step at the output rate
+  int32_t tile;            // frames per block of the narrow conv kernel (0: per-item kernel)
 };
+
+// Frames per block for the LDS-staged narrow conv (0 if its window does not fit).
+int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint);
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);

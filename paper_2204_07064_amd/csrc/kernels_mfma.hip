@@ -67,28 +67,6 @@ __device__ inline uint32_t pack_fp8x4(float a, float b, float c, float d) {
   return (uint32_t)v;
 }
 
-// Converts 8 floats to the operand type and stores them at `dst` (LDS).
-template <int PREC>
-__device__ inline void store8(unsigned char* dst, const float* v) {
-  if constexpr (PREC == 0) {
-    f4* d = reinterpret_cast<f4*>(dst);
-    d[0] = f4{v[0], v[1], v[2], v[3]};
-    d[1] = f4{v[4], v[5], v[6], v[7]};
-  } else if constexpr (PREC == 1) {
-    uint4 u;
-    u.x = pack_bf16(v[0], v[1]);
-    u.y = pack_bf16(v[2], v[3]);
-    u.z = pack_bf16(v[4], v[5]);
-    u.w = pack_bf16(v[6], v[7]);
-    *reinterpret_cast<uint4*>(dst) = u;
-  } else {
-    uint2 u;
-    u.x = pack_fp8x4(v[0], v[1], v[2], v[3]);
-    u.y = pack_fp8x4(v[4], v[5], v[6], v[7]);
-    *reinterpret_cast<uint2*>(dst) = u;
-  }
-}
-
 // 32-byte fragment of one lane (its slice of a 128-byte chunk row).
 struct Frag {
   uint4 lo, hi;
@@ -120,66 +98,73 @@ __device__ inline f4 mfma_chunk(const Frag& a, const Frag& b, f4 acc) {
   return acc;
 }
 
-// Per-column context of the column a thread gathers.
-struct Col {
-  bool valid;
-  int ei;
-  int64_t t;         // conv: local output frame; convt: q
-  int64_t in_start;  // first packed input frame of the stream
-  int64_t Tin;       // input frames of the stream (input rate)
-  const float* cache;  // conv: current cache copy (raw FP32 [L][cin])
+// Per-column context of a tile, staged in LDS once per tile.
+struct ColInfo {
+  const float* cache;   // conv: current cache copy of the column's stream (raw FP32 [L][cin])
+  int32_t ei;           // entry (stream) index; -1 for a padding column
+  int32_t t;            // conv: local output frame; convt: q (== Tin for a carry column)
+  int32_t in_start;     // first packed input frame of the stream
+  int32_t Tin;          // input frames of the stream
 };
 
 template <bool CONVT>
-__device__ inline Col column(const LayerArgs& a, int64_t n, int64_t n_cols) {
-  Col c{};
-  c.valid = n < n_cols;
-  if (!c.valid) return c;
+__device__ inline ColInfo make_col(const LayerArgs& a, int64_t n, int64_t n_cols) {
+  ColInfo c;
+  c.cache = nullptr;
+  c.ei = -1;
+  c.t = 0;
+  c.in_start = 0;
+  c.Tin = 0;
+  if (n >= n_cols) return c;
+  int ei;
+  if (CONVT) ei = n < a.n_in ? entry_at(a.fent, n, a.in_num, a.in_den) : (int)(n - a.n_in);
+  else ei = entry_at(a.fent, n, a.out_num, a.out_den);
+  const Entry& e = a.ents[ei];
+  c.ei = ei;
+  c.in_start = (int32_t)at_rate(e.off, a.in_num, a.in_den);
+  c.Tin = (int32_t)at_rate(e.T, a.in_num, a.in_den);
   if (CONVT) {
-    c.ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 1);
+    c.t = n < a.n_in ? (int32_t)(n - c.in_start) : c.Tin;
+    c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;   // carry copy
   } else {
-    c.ei = find_entry(a.ents, a.n_ent, n, a.out_num, a.out_den, 0);
-  }
-  const Entry& e = a.ents[c.ei];
-  c.in_start = at_rate(e.off, a.in_num, a.in_den);
-  c.Tin = at_rate(e.T, a.in_num, a.in_den);
-  if (CONVT) {
-    c.t = n - c.in_start - c.ei;
-  } else {
-    c.t = n - at_rate(e.off, a.out_num, a.out_den);
+    c.t = (int32_t)(n - at_rate(e.off, a.out_num, a.out_den));
     c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
   }
   return c;
 }
 
-// Loads 8 consecutive input channels (kk .. kk + 7 of the K dimension) of a
-// column, raw FP32; zeros for padding or absent frames.
+// Source of 4 consecutive K elements (kk .. kk + 3) of a column: raw FP32
+// input channels, or null for padding / absent frames.
 template <bool CONVT>
-__device__ inline void gather8(const LayerArgs& a, const Col& c, int kk, int Kreal, int half_pad, float* v) {
-  const float* src = nullptr;
-  if (c.valid) {
-    if (CONVT) {
-      // K layout: [h = 0: half_pad][h = 1: half_pad], real channels first in each half
-      const int h = kk >= half_pad;
-      const int ci = kk - h * half_pad;
-      const int64_t row = c.t - 1 + h;
-      if (ci < a.cin && row >= 0 && row < c.Tin) src = a.in_buf + (c.in_start + row) * a.cin + ci;
-    } else if (kk < Kreal) {
-      const int tap = kk / a.cin;
-      const int ci = kk - tap * a.cin;
-      const int64_t row = c.t + (int64_t)a.dil * tap;
-      if (row < a.L) src = c.cache + row * a.cin + ci;
-      else src = a.in_buf + (c.in_start + row - a.L) * a.cin + ci;
-    }
+__device__ inline const float* src4(const LayerArgs& a, const ColInfo& c, int kk, int Kreal, int half_pad) {
+  if (c.ei < 0) return nullptr;
+  if (CONVT) {
+    // K layout: [h = 0: half_pad][h = 1: half_pad], real channels first in each half
+    const int h = kk >= half_pad;
+    const int ci = kk - h * half_pad;
+    const int row = c.t - 1 + h;
+    if (ci >= a.cin || row < 0 || row >= c.Tin) return nullptr;
+    return a.in_buf + ((int64_t)c.in_start + row) * a.cin + ci;
   }
-  if (src) {
-    const f4 x0 = *reinterpret_cast<const f4*>(src);
-    const f4 x1 = *reinterpret_cast<const f4*>(src + 4);
-    v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-    v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+  if (kk >= Kreal) return nullptr;
+  const int tap = kk / a.cin;
+  const int ci = kk - tap * a.cin;
+  const int row = c.t + a.dil * tap;
+  if (row < a.L) return c.cache + (int64_t)row * a.cin + ci;
+  return a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin + ci;
+}
+
+template <int PREC>
+__device__ inline void store4(unsigned char* dst, float v0, float v1, float v2, float v3) {
+  if constexpr (PREC == 0) {
+    *reinterpret_cast<f4*>(dst) = f4{v0, v1, v2, v3};
+  } else if constexpr (PREC == 1) {
+    uint2 u;
+    u.x = pack_bf16(v0, v1);
+    u.y = pack_bf16(v2, v3);
+    *reinterpret_cast<uint2*>(dst) = u;
   } else {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0.f;
+    *reinterpret_cast<uint32_t*>(dst) = pack_fp8x4(v0, v1, v2, v3);
   }
 }
 
@@ -189,23 +174,33 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
                                                         int extra_blocks) {
   constexpr int KC = Prec<PREC>::kKc;
   constexpr int ES = Prec<PREC>::kEsize;
-  constexpr int TPC = kThreads / NT;          // threads per B column
-  constexpr int SE = KC / TPC;                // elements each thread gathers per chunk
-  constexpr int WM = MT / 32;                 // waves along M
+  constexpr int PPC = KC / 4;                   // 4-element pieces per column per chunk
+  constexpr int B_PIECES = NT * PPC / kThreads; // pieces each thread gathers per chunk
+  constexpr int WM = MT / 32;                   // waves along M
   static_assert(WM * (NT / 32) == 4, "4 waves of 32x32");
-  static_assert(SE % 8 == 0, "gather groups of 8");
+  static_assert(B_PIECES >= 1 && NT * PPC % kThreads == 0, "whole pieces per thread");
+  constexpr int A_PIECES = MT * 8 / kThreads;
+  static_assert(A_PIECES == 1 || A_PIECES == 2, "MT of 32 or 64");
 
   __shared__ __attribute__((aligned(16))) unsigned char lds_a[2][MT * kRowStride];
   __shared__ __attribute__((aligned(16))) unsigned char lds_b[2][NT * kRowStride];
+  __shared__ ColInfo cols[NT];
 
   const int tid = threadIdx.x;
   const int64_t n_tiles = (int64_t)n_mt * n_nt;
+  // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs; remap so
+  // that the M tiles of one column tile (which share B) run on one XCD's L2.
+  int64_t bid = blockIdx.x;
+  {
+    const int64_t G = n_tiles;
+    const int64_t full = G / 8 * 8;
+    if (bid < full) bid = (bid % 8) * (full / 8) + bid / 8;
+  }
   // ---- conv cache update blocks (after the GEMM tiles) ----
-  if (!CONVT && (int64_t)blockIdx.x >= n_tiles) {
+  if (!CONVT && bid >= n_tiles) {
     const int64_t per_ent = (int64_t)a.L * a.cin;
     const int64_t total = (int64_t)a.n_ent * per_ent;
-    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kThreads + tid; j < total;
-         j += (int64_t)extra_blocks * kThreads) {
+    for (int64_t j = (bid - n_tiles) * kThreads + tid; j < total; j += (int64_t)extra_blocks * kThreads) {
       const int ei = (int)(j / per_ent);
       const int64_t rem = j % per_ent;
       const int64_t i = rem / a.cin;
@@ -220,15 +215,13 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
     }
     return;
   }
-  const int mt = (int)(blockIdx.x % n_mt);
-  const int64_t nt = blockIdx.x / n_mt;
+  const int mt = (int)(bid % n_mt);
+  const int64_t nt = bid / n_mt;
   const int m0 = mt * MT;
   const int64_t n0 = nt * NT;
 
-  // the column this thread gathers
-  const int my_col = tid % NT;
-  const int my_seg = tid / NT;
-  const Col gc = column<CONVT>(a, n0 + my_col, n_cols);
+  if (tid < NT) cols[tid] = make_col<CONVT>(a, n0 + tid, n_cols);
+  __syncthreads();
 
   const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
   const int row_bytes = Kpad * ES;
@@ -236,11 +229,8 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   const bool pre = a.pre_act != 0;
   const float qs = (PREC == 2) ? 1.0f / a.act_scale : 1.0f;
 
-  // A chunk: MT rows x 128 bytes = MT * 8 pieces of 16 B
-  constexpr int A_PIECES = MT * 8 / kThreads;
-  static_assert(A_PIECES == 1 || A_PIECES == 2, "MT of 32 or 64");
-  uint4 areg0, areg1;   // this thread's 16-byte pieces of the A chunk (registers)
-  float breg[SE];
+  uint4 areg0, areg1;   // this thread's 16-byte pieces of the A chunk
+  f4 breg[B_PIECES];    // this thread's raw FP32 pieces of the B chunk
 
   auto load_chunk = [&](int c) __attribute__((always_inline)) {
     {
@@ -250,9 +240,11 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
         areg1 = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r + 32) * row_bytes + c * kChunkBytes + seg * 16);
     }
 #pragma unroll
-    for (int g = 0; g < SE / 8; ++g) {
-      const int kk = c * KC + my_seg * SE + g * 8;
-      gather8<CONVT>(a, gc, kk, Kreal, half_pad, breg + g * 8);
+    for (int p = 0; p < B_PIECES; ++p) {
+      const int u = tid + p * kThreads;          // consecutive threads: consecutive pieces of a column
+      const int col = u / PPC, pp = u % PPC;
+      const float* src = src4<CONVT>(a, cols[col], c * KC + pp * 4, Kreal, half_pad);
+      breg[p] = src ? *reinterpret_cast<const f4*>(src) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
   auto store_chunk = [&](int buf) __attribute__((always_inline)) {
@@ -262,15 +254,17 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
       if constexpr (A_PIECES == 2) *reinterpret_cast<uint4*>(&lds_a[buf][(r + 32) * kRowStride + seg * 16]) = areg1;
     }
 #pragma unroll
-    for (int g = 0; g < SE / 8; ++g) {
-      float v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        float x = breg[g * 8 + i];
-        if (pre) x = lrelu(x);
-        v[i] = x * qs;
+    for (int p = 0; p < B_PIECES; ++p) {
+      const int u = tid + p * kThreads;
+      const int col = u / PPC, pp = u % PPC;
+      f4 v = breg[p];
+      if (pre) {
+        v.x = lrelu(v.x);
+        v.y = lrelu(v.y);
+        v.z = lrelu(v.z);
+        v.w = lrelu(v.w);
       }
-      store8<PREC>(&lds_b[buf][my_col * kRowStride + (my_seg * SE + g * 8) * ES], v);
+      store4<PREC>(&lds_b[buf][col * kRowStride + pp * 4 * ES], v.x * qs, v.y * qs, v.z * qs, v.w * qs);
     }
   };
 
@@ -283,22 +277,14 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   f4 acc[2][2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const float* carry = nullptr;
-    if (CONVT) {
-      const int64_t n = n0 + wn * 32 + j * 16 + lr;
-      if (n < n_cols) {
-        const int ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 1);
-        const Entry& e = a.ents[ei];
-        if (n - at_rate(e.off, a.in_num, a.in_den) - ei == 0)
-          carry = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-      }
-    }
+    const ColInfo& cj = cols[wn * 32 + j * 16 + lr];
+    const bool from_carry = CONVT && cj.ei >= 0 && cj.t == 0 && cj.Tin > 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       // the lane's rows of this 16-row block: m .. m + 3
       const int m = m0 + wm * 32 + i * 16 + lg * 4;
       f4 cv = {0.f, 0.f, 0.f, 0.f};
-      if (carry && m < Mreal) cv = *reinterpret_cast<const f4*>(carry + m);
+      if (from_carry && m < Mreal) cv = *reinterpret_cast<const f4*>(cj.cache + m);
       acc[i][j] = cv;
     }
   }
@@ -331,10 +317,10 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   // ---- epilogue: lane holds rows m..m+3 of column n for each (i, j) ----
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int64_t n = n0 + wn * 32 + j * 16 + lr;
-    if (n >= n_cols) continue;
-    const Col c = column<CONVT>(a, n, n_cols);
+    const ColInfo& c = cols[wn * 32 + j * 16 + lr];
+    if (c.ei < 0) continue;
     const Entry& e = a.ents[c.ei];
+    const int64_t n = n0 + wn * 32 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int m = m0 + wm * 32 + i * 16 + lg * 4;
@@ -345,27 +331,26 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
         v = v * (ws * a.act_scale);
       }
       if (CONVT) {
-        const int co = m % a.cout;
-        const int phi = m / a.cout;
         if (c.t >= c.Tin) {
-          // carry column: FP32 partial sums of the next buffer's first frame
+          // carry column: FP32 partial sums of the next buffer's first frame,
+          // kept in accumulator units (before the FP8 dequantization)
           float* carry_out = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
           *reinterpret_cast<f4*>(carry_out + m) = acc[i][j];
           continue;
         }
-        const f4 b = *reinterpret_cast<const f4*>(a.B + co);
-        v = v + b;
-        const int64_t t = c.t * a.stride + phi;
+        const int co = m % a.cout;
+        const int phi = m / a.cout;
+        v = v + *reinterpret_cast<const f4*>(a.B + co);
+        const int64_t t = (int64_t)c.t * a.stride + phi;
         if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay)
           v = f4{0.f, 0.f, 0.f, 0.f};
-        *reinterpret_cast<f4*>(a.out_buf + (c.in_start * a.stride + c.t * a.stride) * a.cout + m) = v;
+        *reinterpret_cast<f4*>(a.out_buf + ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m) = v;
       } else {
-        const f4 b = *reinterpret_cast<const f4*>(a.B + m);
-        v = v + b;
+        v = v + *reinterpret_cast<const f4*>(a.B + m);
         if (a.residual) {
-          const int64_t row = c.t + a.skip_off;
-          const float* sp = row < a.L ? c.cache + row * a.cin
-                                      : a.in_buf + (c.in_start + row - a.L) * a.cin;
+          const int row = c.t + a.skip_off;
+          const float* sp = row < a.L ? c.cache + (int64_t)row * a.cin
+                                      : a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin;
           v = v + *reinterpret_cast<const f4*>(sp + m);
         }
         if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + c.t < a.delay)

@@ -1,9 +1,8 @@
 // FP32 wavefront-FMA kernels: the narrow layers (few channels) and the
-// FP32 path of any layer.  One lane per output value; consecutive lanes take
-// consecutive output channels so that weight reads (packed [tap][cin][cout])
-// coalesce and input reads broadcast.  Every sum is a fixed chain of fmaf in
+// FP32 path of any layer.  Every output value is a fixed chain of fmaf in
 // tap-major, channel-minor order that does not depend on where a frame sits
-// in its buffer, so results are bitwise independent of the buffer split.
+// in its buffer, so results are bitwise independent of the buffer split and
+// of the other streams in the step.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -13,6 +12,7 @@ namespace sc {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kNarrowLdsBytes = 48 * 1024;
 
 inline int grid_for(int64_t items) {
   int64_t g = (items + kBlock - 1) / kBlock;
@@ -28,76 +28,167 @@ struct Row {
   int64_t cs;
 };
 
-__device__ inline Row window_row(const LayerArgs& a, const Entry& e, int64_t in_start, int64_t Tin,
-                                 int64_t row, int32_t L, int64_t soff, int64_t slen, const float* buf,
-                                 int32_t C) {
+__device__ inline Row window_row(const Entry& e, int64_t in_start, int64_t Tin, int64_t row, int32_t L,
+                                 int64_t soff, int64_t slen, const float* buf, int32_t C) {
   if (row < L) return Row{e.state + soff + (int64_t)e.parity * slen + row * C, 1};
   const int64_t r = row - L;
   if (buf) return Row{buf + (in_start + r) * C, 1};
   return Row{e.in + r, Tin};  // user input, channel-major
 }
 
-__global__ void __launch_bounds__(kBlock) conv_valu_kernel(LayerArgs a) {
-  const int64_t n_items = a.n_out * a.cout;
+// New cache of a conv = window rows [Tin, Tin + L), into the other copy.
+__device__ inline void cache_item(const LayerArgs& a, int64_t j) {
   const int64_t per_ent = (int64_t)a.L * a.cin;
-  const int64_t total = n_items + (int64_t)a.n_ent * per_ent;
+  const int ei = (int)(j / per_ent);
+  const int64_t rem = j % per_ent;
+  const int64_t i = rem / a.cin;
+  const int ci = (int)(rem % a.cin);
+  const Entry e = a.ents[ei];
+  const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
+  const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
+  const Row rw = window_row(e, in_start, Tin, Tin + i, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
+  e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = rw.p[ci * rw.cs];
+}
+
+__device__ inline float finish(const LayerArgs& a, const Entry& e, int64_t t, float acc) {
+  if (a.post_act == 2) acc = tanhf(acc);
+  if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) acc = 0.f;
+  return acc;
+}
+
+// Per-item conv: one lane per output value (used when the LDS window of the
+// narrow kernel would not fit).  Grid-stride over outputs, then cache items.
+__global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a) {
+  const int64_t n_items = a.n_out * a.cout;
+  const int64_t total = n_items + (int64_t)a.n_ent * a.L * a.cin;
+  const float* W = static_cast<const float*>(a.W);
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * kBlock) {
-    if (idx < n_items) {
-      const int co = (int)(idx % a.cout);
-      const int64_t n = idx / a.cout;
-      const int ei = find_entry(a.ents, a.n_ent, n, a.out_num, a.out_den, 0);
-      const Entry e = a.ents[ei];
-      const int64_t out_start = at_rate(e.off, a.out_num, a.out_den);
-      const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-      const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-      const int64_t t = n - out_start;
-      const float* W = static_cast<const float*>(a.W);
-      float acc = a.B[co];
-      for (int kk = 0; kk < a.k; ++kk) {
-        const Row rw = window_row(a, e, in_start, Tin, t * a.stride + (int64_t)a.dil * kk, a.L,
-                                  a.state_off, a.state_len, a.in_buf, a.cin);
-        const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
-        if (a.pre_act) {
-          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], lrelu(rw.p[ci * rw.cs]), acc);
-        } else {
-          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], rw.p[ci * rw.cs], acc);
+    if (idx >= n_items) {
+      cache_item(a, idx - n_items);
+      continue;
+    }
+    const int co = (int)(idx % a.cout);
+    const int64_t n = idx / a.cout;
+    const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
+    const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
+    const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
+    const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
+    float acc = a.B[co];
+    for (int kk = 0; kk < a.k; ++kk) {
+      const Row rw = window_row(e, in_start, Tin, t * a.stride + (int64_t)a.dil * kk, a.L, a.state_off,
+                                a.state_len, a.in_buf, a.cin);
+      const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
+      for (int ci = 0; ci < a.cin; ++ci) {
+        float x = rw.p[ci * rw.cs];
+        if (a.pre_act) x = lrelu(x);
+        acc = fmaf(wp[(int64_t)ci * a.cout], x, acc);
+      }
+    }
+    if (a.residual) {
+      const Row rw = window_row(e, in_start, Tin, t + a.skip_off, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
+      acc = acc + rw.p[co * rw.cs];
+    }
+    acc = finish(a, e, t, acc);
+    if (a.out_buf) a.out_buf[n * a.cout + co] = acc;
+    else e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
+  }
+}
+
+// LDS-staged narrow conv.  A block owns `a.tile` consecutive output frames of
+// the step's packed frame space (possibly of several streams) and a tile of
+// output channels.  It stages the activated input rows
+// [n0*S - L, (n0 + F)*S) of the packed input once; output frame n, tap k
+// reads packed row n*S + d*k - L, which belongs to n's own stream exactly
+// when its window row t*S + d*k is >= L -- otherwise the row comes from the
+// stream's cache.  Blocks beyond the tiles copy caches.
+__global__ void __launch_bounds__(kBlock) conv_narrow_kernel(LayerArgs a, int n_ct, int co_tile, int64_t n_tiles,
+                                                             int extra_blocks) {
+  extern __shared__ float xs[];
+  const int tid = threadIdx.x;
+  if ((int64_t)blockIdx.x >= n_tiles) {
+    const int64_t total = (int64_t)a.n_ent * a.L * a.cin;
+    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += (int64_t)extra_blocks * kBlock)
+      cache_item(a, j);
+    return;
+  }
+  const int F = a.tile;
+  const int S = a.stride;
+  const int ct = (int)(blockIdx.x % n_ct);
+  const int64_t n0 = (int64_t)(blockIdx.x / n_ct) * F;
+  const int co0 = ct * co_tile;
+  const int co_n = min(co_tile, a.cout - co0);
+  const int rows = F * S + a.L;
+  const int stride = a.cin | 1;          // odd row stride: conflict-free column reads
+  const int64_t p0 = n0 * S - a.L;       // packed input row of LDS row 0
+
+  // stage activated input rows
+  if (a.in_buf) {
+    for (int idx = tid; idx < rows * a.cin; idx += kBlock) {
+      const int j = idx / a.cin, ci = idx - j * a.cin;
+      const int64_t p = p0 + j;
+      float v = 0.f;
+      if (p >= 0 && p < a.n_in) v = a.in_buf[p * a.cin + ci];
+      xs[j * stride + ci] = a.pre_act ? lrelu(v) : v;
+    }
+  } else {
+    for (int idx = tid; idx < rows * a.cin; idx += kBlock) {
+      const int ci = idx / rows, j = idx - ci * rows;   // time fastest: coalesced channel-major reads
+      const int64_t p = p0 + j;
+      float v = 0.f;
+      if (p >= 0 && p < a.n_in) {
+        const Entry& e = a.ents[entry_at(a.fent, p, a.in_num, a.in_den)];
+        const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
+        v = e.in[(int64_t)ci * at_rate(e.T, a.in_num, a.in_den) + (p - in_start)];
+      }
+      xs[j * stride + ci] = a.pre_act ? lrelu(v) : v;
+    }
+  }
+  __syncthreads();
+
+  const float* W = static_cast<const float*>(a.W);
+  const int items = F * co_n;
+  for (int it = tid; it < items; it += kBlock) {
+    const int i = it / co_n;
+    const int co = co0 + (it - i * co_n);
+    const int64_t n = n0 + i;
+    if (n >= a.n_out) continue;
+    const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
+    const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
+    float acc = a.B[co];
+    for (int kk = 0; kk < a.k; ++kk) {
+      const int64_t w = t * S + (int64_t)a.dil * kk;     // window row
+      const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
+      if (w >= a.L) {
+        const float* x = xs + (i * S + a.dil * kk) * stride;
+        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], x[ci], acc);
+      } else {
+        const float* x = e.state + a.state_off + (int64_t)e.parity * a.state_len + w * a.cin;
+        for (int ci = 0; ci < a.cin; ++ci) {
+          float v = x[ci];
+          if (a.pre_act) v = lrelu(v);
+          acc = fmaf(wp[(int64_t)ci * a.cout], v, acc);
         }
       }
-      if (a.residual) {
-        const Row rw = window_row(a, e, in_start, Tin, t + a.skip_off, a.L, a.state_off, a.state_len,
-                                  a.in_buf, a.cin);
-        acc = acc + rw.p[co * rw.cs];
-      }
-      if (a.post_act == 2) acc = tanhf(acc);
-      if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) acc = 0.f;
-      if (a.out_buf) {
-        a.out_buf[n * a.cout + co] = acc;
-      } else {
-        const int64_t Tout = at_rate(e.T, a.out_num, a.out_den);
-        e.out[(int64_t)co * Tout + t] = acc;
-      }
-    } else {
-      // cache update: new cache = window rows [Tin, Tin + L) into the other copy
-      const int64_t j = idx - n_items;
-      const int ei = (int)(j / per_ent);
-      const int64_t rem = j % per_ent;
-      const int64_t i = rem / a.cin;
-      const int ci = (int)(rem % a.cin);
-      const Entry e = a.ents[ei];
+    }
+    if (a.residual) {
       const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
       const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-      const Row rw = window_row(a, e, in_start, Tin, Tin + i, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
-      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = rw.p[ci * rw.cs];
+      const Row rw = window_row(e, in_start, Tin, t + a.skip_off, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
+      acc = acc + rw.p[co * rw.cs];
     }
+    acc = finish(a, e, t, acc);
+    if (a.out_buf) a.out_buf[n * a.cout + co] = acc;
+    else e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
   }
 }
 
 // Transposed conv, kernel 2r: output frame q*r + phi of a buffer is
 //   W[phi + r] . a[q-1] + W[phi] . a[q]   (+ bias),
-// accumulated in that order.  Column q = T of each entry holds only the
-// first half: it is the FP32 overlap carry that column q = 0 of the next
-// buffer starts from, so the chain of fmaf is the same for every frame.
+// accumulated in that order.  Columns [0, n_in) are the input frames q of all
+// streams; columns n_in + e hold, for stream e, only the first half of
+// q = T: that is the FP32 overlap carry that column q = 0 of the next buffer
+// starts from, so the chain of fmaf is the same for every frame.
 // Weights packed [h][phi][cin][cout], h = 0 -> tap phi + r, h = 1 -> tap phi.
 __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
   const int r = a.stride;
@@ -110,11 +201,11 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
     const int64_t rest = idx / a.cout;
     const int phi = (int)(rest % r);
     const int64_t c = rest / r;
-    const int ei = find_entry(a.ents, a.n_ent, c, a.in_num, a.in_den, 1);
+    const int ei = c < a.n_in ? entry_at(a.fent, c, a.in_num, a.in_den) : (int)(c - a.n_in);
     const Entry e = a.ents[ei];
     const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
     const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-    const int64_t q = c - in_start - ei;
+    const int64_t q = c < a.n_in ? c - in_start : Tin;
     const float* carry_in = e.state + a.state_off + (int64_t)e.parity * a.state_len;
     float acc = (q == 0) ? carry_in[phi * a.cout + co] : 0.f;
     for (int h = 0; h < 2; ++h) {
@@ -133,11 +224,8 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
       float v = acc + a.B[co];
       const int64_t t = q * r + phi;
       if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
-      if (a.out_buf) {
-        a.out_buf[(in_start * r + t) * a.cout + co] = v;
-      } else {
-        e.out[(int64_t)co * (Tin * r) + t] = v;
-      }
+      if (a.out_buf) a.out_buf[(in_start * r + t) * a.cout + co] = v;
+      else e.out[(int64_t)co * (Tin * r) + t] = v;
     } else {
       e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + phi * a.cout + co] = acc;
     }
@@ -156,13 +244,12 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a) {
     if (idx < n_items) {
       const int c = (int)(idx % C);
       const int64_t n = idx / C;
-      const int ei = find_entry(a.ents, a.n_ent, n, a.out_num, a.out_den, 0);
-      const Entry e = a.ents[ei];
+      const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
       const int64_t start = at_rate(e.off, a.out_num, a.out_den);
       const int64_t Tn = at_rate(e.T, a.out_num, a.out_den);
       const int64_t t = n - start;
-      const Row r0 = window_row(a, e, start, Tn, t, a.A0, a.state_off, a.state_len, a.in_buf, C);
-      const Row r1 = window_row(a, e, start, Tn, t, a.A1, a.state_off2, a.state_len2, a.in_buf2, C);
+      const Row r0 = window_row(e, start, Tn, t, a.A0, a.state_off, a.state_len, a.in_buf, C);
+      const Row r1 = window_row(e, start, Tn, t, a.A1, a.state_off2, a.state_len2, a.in_buf2, C);
       float v = r0.p[c * r0.cs] + r1.p[c * r1.cs];
       if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
       if (a.out_buf) a.out_buf[n * C + c] = v;
@@ -181,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a) {
       const int32_t A = second ? a.A1 : a.A0;
       const int64_t soff = second ? a.state_off2 : a.state_off;
       const int64_t slen = second ? a.state_len2 : a.state_len;
-      const Row rw = window_row(a, e, start, Tn, Tn + i, A, soff, slen, second ? a.in_buf2 : a.in_buf, C);
+      const Row rw = window_row(e, start, Tn, Tn + i, A, soff, slen, second ? a.in_buf2 : a.in_buf, C);
       e.state[soff + (int64_t)(1 - e.parity) * slen + i * C + c] = rw.p[c * rw.cs];
     }
   }
@@ -199,8 +286,7 @@ __global__ void __launch_bounds__(kBlock) amax_kernel(LayerArgs a, float* amax) 
     } else {
       const int ci = (int)(idx % a.cin);
       const int64_t n = idx / a.cin;
-      const int ei = find_entry(a.ents, a.n_ent, n, a.in_num, a.in_den, 0);
-      const Entry e = a.ents[ei];
+      const Entry e = a.ents[entry_at(a.fent, n, a.in_num, a.in_den)];
       const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
       v = e.in[(int64_t)ci * Tin + (n - at_rate(e.off, a.in_num, a.in_den))];
     }
@@ -222,14 +308,40 @@ __global__ void __launch_bounds__(kBlock) fill_zero_kernel(float* p, int64_t n) 
 
 }  // namespace
 
+int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint) {
+  (void)k;
+  (void)dil;
+  const int stride_f = cin | 1;
+  int F = 256;
+  while (F > 16 && (int64_t)(F * stride + L) * stride_f * 4 > kNarrowLdsBytes) F /= 2;
+  if ((int64_t)(F * stride + L) * stride_f * 4 > kNarrowLdsBytes) return 0;
+  // enough blocks to fill the chip when outputs are many channels wide
+  const int co_tile = cout < kBlock ? cout : kBlock;
+  const int n_ct = (cout + co_tile - 1) / co_tile;
+  while (F > 16 && n_out_hint > 0 && ((n_out_hint + F - 1) / F) * n_ct < 1024 && F * co_tile > 8 * kBlock) F /= 2;
+  return F;
+}
+
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
   return hipGetLastError();
 }
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
-  const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * a.L * a.cin;
-  hipLaunchKernelGGL(conv_valu_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
+  if (a.tile <= 0) {
+    const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * a.L * a.cin;
+    hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+  const int co_tile = a.cout < kBlock ? a.cout : kBlock;
+  const int n_ct = (a.cout + co_tile - 1) / co_tile;
+  const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile * n_ct;
+  const int64_t cache_items = (int64_t)a.n_ent * a.L * a.cin;
+  const int extra = (int)std::min<int64_t>((cache_items + kBlock - 1) / kBlock, 1024);
+  const size_t lds = (size_t)(a.tile * a.stride + a.L) * (a.cin | 1) * sizeof(float);
+  if (n_tiles + extra == 0) return hipSuccess;
+  hipLaunchKernelGGL(conv_narrow_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a, n_ct, co_tile,
+                     n_tiles, extra);
   return hipGetLastError();
 }
 

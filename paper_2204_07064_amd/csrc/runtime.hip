@@ -49,10 +49,11 @@ struct OpDev {
 };
 
 // A slot of the descriptor ring: pinned host staging + device copy + event.
+// Layout: n Entry records, then one int32 per input frame of the step (its entry).
 struct DescSlot {
-  Entry* host = nullptr;
-  Entry* dev = nullptr;
-  int cap = 0;
+  unsigned char* host = nullptr;
+  unsigned char* dev = nullptr;
+  size_t cap = 0;          // bytes
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -155,9 +156,11 @@ void free_model(sc_model* m) {
   delete m;
 }
 
-LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, int n_ent, int64_t total_T) {
+LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent, int n_ent,
+                     int64_t total_T) {
   LayerArgs a{};
   a.ents = dents;
+  a.fent = dfent;
   a.n_ent = n_ent;
   a.in_buf = op.in_buf >= 0 ? m->ws[op.in_buf] : nullptr;
   a.in_buf2 = op.in_buf2 >= 0 ? m->ws[op.in_buf2] : nullptr;
@@ -178,6 +181,9 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, int n_
   a.state_off2 = op.state_off2; a.state_len2 = op.state_len2;
   a.n_in = op.in_rate.of(total_T);
   a.n_out = op.out_rate.of(total_T);
+  a.tile = (op.kind == K_CONV && op.impl == IMPL_VALU)
+               ? narrow_conv_tile(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, a.n_out)
+               : 0;
   return a;
 }
 
@@ -276,14 +282,16 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     slot.pending = false;
   }
-  if (slot.cap < n) {
+  const size_t ent_bytes = (size_t)n * sizeof(Entry);
+  const size_t need = ent_bytes + (size_t)total * sizeof(int32_t);
+  if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
     slot.host = nullptr;
     slot.dev = nullptr;
-    const int cap = std::max(n, 64);
-    if (hipHostMalloc(reinterpret_cast<void**>(&slot.host), cap * sizeof(Entry), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&slot.dev), cap * sizeof(Entry)) != hipSuccess) {
+    const size_t cap = std::max<size_t>(need * 2, 64 * 1024);
+    if (hipHostMalloc(reinterpret_cast<void**>(&slot.host), cap, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&slot.dev), cap) != hipSuccess) {
       slot.cap = 0;
       return fail(SC_ENOMEM, "descriptor allocation failed");
     }
@@ -293,9 +301,11 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
+  Entry* hents = reinterpret_cast<Entry*>(slot.host);
+  int32_t* hfent = reinterpret_cast<int32_t*>(slot.host + ent_bytes);
   int32_t off = 0;
   for (int i = 0; i < n; ++i) {
-    Entry& en = slot.host[i];
+    Entry& en = hents[i];
     en.in = d_in[i];
     en.out = d_out[i];
     en.state = streams[i]->d_state;
@@ -304,18 +314,21 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     en.parity = streams[i]->parity;
     en.flags = (int32_t)streams[i]->flags;
     en.pos = streams[i]->pos;
+    for (int32_t f = 0; f < n_frames[i]; ++f) hfent[off + f] = i;
     off += n_frames[i];
   }
   if (m->has_last) {
     e = hipStreamWaitEvent(hs, m->last_done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  e = hipMemcpyAsync(slot.dev, slot.host, n * sizeof(Entry), hipMemcpyHostToDevice, hs);
+  e = hipMemcpyAsync(slot.dev, slot.host, need, hipMemcpyHostToDevice, hs);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  const Entry* dents = reinterpret_cast<const Entry*>(slot.dev);
+  const int32_t* dfent = reinterpret_cast<const int32_t*>(slot.dev + ent_bytes);
 
   // ---- launches ----
   for (const Op& op : m->plan.ops) {
-    const LayerArgs a = layer_args(m, op, slot.dev, n, total);
+    const LayerArgs a = layer_args(m, op, dents, dfent, n, total);
     if (m->amax_on && op.layer >= 0) {
       e = launch_amax(a, m->d_amax + op.layer, hs);
       if (e != hipSuccess) break;

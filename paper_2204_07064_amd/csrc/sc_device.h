@@ -24,16 +24,10 @@ struct Entry {
 // Frames of `rate` (num/den per input frame) for t input frames.
 __device__ __host__ inline int64_t at_rate(int64_t t, int64_t num, int64_t den) { return t * num / den; }
 
-// Largest entry e with start(e) <= x, start(e) = off_e * num / den + e * extra.
-__device__ inline int find_entry(const Entry* ents, int n, int64_t x, int64_t num, int64_t den,
-                                 int64_t extra) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int64_t st = at_rate(ents[mid].off, num, den) + (int64_t)mid * extra;
-    if (st <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// Entry of packed frame n at rate num/den: fent maps every input frame of the
+// step to its entry, and frame n of a layer lies in input frame n * den / num.
+__device__ inline int entry_at(const int32_t* fent, int64_t n, int64_t num, int64_t den) {
+  return fent[n * den / num];
 }
 
 __device__ inline float lrelu(float v) { return v >= 0.f ? v : 0.2f * v; }
