@@ -35,6 +35,9 @@ struct LayerArgs {
 int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint);
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
+// Channel-major user inputs of a step -> packed channels-last [frame][C].
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
+                             hipStream_t s);
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);
 hipError_t launch_delay_add(const LayerArgs& a, hipStream_t s);
 // max |pre_act(x)| over the step's new input frames of a layer -> atomic max into *amax

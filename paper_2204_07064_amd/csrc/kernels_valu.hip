@@ -13,6 +13,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kNarrowLdsBytes = 48 * 1024;
+constexpr int kChansC = 16;         // channel-parallel conv: cin and k bounds of the
+constexpr int kChansK = 4;          // register-resident weights
+
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 inline int grid_for(int64_t items) {
   int64_t g = (items + kBlock - 1) / kBlock;
@@ -95,16 +99,130 @@ __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a) {
   }
 }
 
-// LDS-staged narrow conv.  A block owns `a.tile` consecutive output frames of
-// the step's packed frame space (possibly of several streams) and a tile of
-// output channels.  It stages the activated input rows
+// ---- LDS-staged narrow convs ---------------------------------------------------
+// A block owns F consecutive output frames of the step's packed frame space
+// (possibly of several streams).  It stages the activated input rows
 // [n0*S - L, (n0 + F)*S) of the packed input once; output frame n, tap k
-// reads packed row n*S + d*k - L, which belongs to n's own stream exactly
-// when its window row t*S + d*k is >= L -- otherwise the row comes from the
-// stream's cache.  Blocks beyond the tiles copy caches.
-__global__ void __launch_bounds__(kBlock) conv_narrow_kernel(LayerArgs a, int n_ct, int co_tile, int64_t n_tiles,
-                                                             int extra_blocks) {
-  extern __shared__ float xs[];
+// reads packed row n*S + d*k - L, which belongs to n's own stream exactly when
+// its window row t*S + d*k is >= L -- otherwise the row comes from the
+// stream's cache.  Per-frame stream data is resolved once per block into LDS.
+// Blocks beyond the tiles copy caches.
+struct FrameInfo {
+  const float* cache;   // current cache copy of the frame's stream
+  float* out;           // user output: &out[t] of the stream (channel stride `tout`)
+  int32_t t;            // local output frame
+  int32_t tout;         // output frames of the stream in this step
+  int32_t masked;       // warm-up mask applies
+  int32_t ei;
+};
+
+constexpr int kStageUnroll = 8;
+
+// Stages rows [p0, p0 + rows) x cin (activated) into xs with row stride `ld`.
+__device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int rows, int ld) {
+  const int tid = threadIdx.x;
+  if (a.in_buf && (a.cin & 3) == 0) {
+    // the rows are one contiguous range of the packed buffer: float4 copies,
+    // several loads in flight per thread before the LDS writes
+    const int64_t base = p0 * a.cin;
+    const int64_t lim = a.n_in * a.cin;
+    const int total4 = rows * a.cin / 4;
+    for (int v0 = 0; v0 < total4; v0 += kBlock * kStageUnroll) {
+      f4v buf[kStageUnroll];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) {
+        const int v = v0 + u * kBlock + tid;
+        const int64_t g = base + (int64_t)v * 4;
+        buf[u] = (v < total4 && g >= 0 && g < lim) ? *reinterpret_cast<const f4v*>(a.in_buf + g) : f4v{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) {
+        const int v = v0 + u * kBlock + tid;
+        if (v >= total4) break;
+        const int e0 = v * 4;
+        const int j = e0 / a.cin, ci = e0 - j * a.cin;
+        float* d = xs + j * ld + ci;
+        const f4v x = buf[u];
+        d[0] = a.pre_act ? lrelu(x.x) : x.x;
+        d[1] = a.pre_act ? lrelu(x.y) : x.y;
+        d[2] = a.pre_act ? lrelu(x.z) : x.z;
+        d[3] = a.pre_act ? lrelu(x.w) : x.w;
+      }
+    }
+    return;
+  }
+  const int total = rows * a.cin;
+  for (int v0 = 0; v0 < total; v0 += kBlock * kStageUnroll) {
+    float buf[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int idx = v0 + u * kBlock + tid;
+      float v = 0.f;
+      if (idx < total) {
+        // time fastest: coalesced reads of channel-major user input
+        const int ci = idx / rows, j = idx - ci * rows;
+        const int64_t p = p0 + j;
+        if (p >= 0 && p < a.n_in) {
+          if (a.in_buf) {
+            v = a.in_buf[p * a.cin + ci];
+          } else {
+            const Entry& e = a.ents[entry_at(a.fent, p, a.in_num, a.in_den)];
+            v = e.in[(int64_t)ci * at_rate(e.T, a.in_num, a.in_den) + (p - at_rate(e.off, a.in_num, a.in_den))];
+          }
+        }
+      }
+      buf[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int idx = v0 + u * kBlock + tid;
+      if (idx >= total) break;
+      const int ci = idx / rows, j = idx - ci * rows;
+      xs[j * ld + ci] = a.pre_act ? lrelu(buf[u]) : buf[u];
+    }
+  }
+}
+
+__device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int64_t n0, int F) {
+  for (int i = threadIdx.x; i < F; i += kBlock) {
+    FrameInfo f;
+    f.cache = nullptr;
+    f.out = nullptr;
+    f.t = 0;
+    f.tout = 0;
+    f.masked = 0;
+    f.ei = -1;
+    const int64_t n = n0 + i;
+    if (n < a.n_out) {
+      const int ei = entry_at(a.fent, n, a.out_num, a.out_den);
+      const Entry& e = a.ents[ei];
+      const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
+      f.ei = ei;
+      f.t = (int32_t)t;
+      f.tout = (int32_t)at_rate(e.T, a.out_num, a.out_den);
+      f.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+      f.out = e.out + t;
+      f.masked = (e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay;
+    }
+    fi[i] = f;
+  }
+}
+
+// Raw (not activated) skip value of window row t + skip_off, channel co.
+__device__ inline float skip_value(const LayerArgs& a, const FrameInfo& f, int co) {
+  const int64_t row = f.t + a.skip_off;
+  if (row < a.L) return f.cache[row * a.cin + co];
+  const Entry& e = a.ents[f.ei];
+  const int64_t r = row - a.L;
+  const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
+  if (a.in_buf) return a.in_buf[(in_start + r) * a.cin + co];
+  return e.in[(int64_t)co * at_rate(e.T, a.in_num, a.in_den) + r];
+}
+
+// Frame-parallel variant (few output channels): one lane per output frame,
+// looping over the output channels; weights staged in LDS.
+__global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int64_t n_tiles, int extra_blocks) {
+  extern __shared__ float smem[];
   const int tid = threadIdx.x;
   if ((int64_t)blockIdx.x >= n_tiles) {
     const int64_t total = (int64_t)a.n_ent * a.L * a.cin;
@@ -112,74 +230,122 @@ __global__ void __launch_bounds__(kBlock) conv_narrow_kernel(LayerArgs a, int n_
       cache_item(a, j);
     return;
   }
-  const int F = a.tile;
-  const int S = a.stride;
-  const int ct = (int)(blockIdx.x % n_ct);
-  const int64_t n0 = (int64_t)(blockIdx.x / n_ct) * F;
-  const int co0 = ct * co_tile;
-  const int co_n = min(co_tile, a.cout - co0);
+  const int F = a.tile, S = a.stride, ld = a.cin | 1;
   const int rows = F * S + a.L;
-  const int stride = a.cin | 1;          // odd row stride: conflict-free column reads
-  const int64_t p0 = n0 * S - a.L;       // packed input row of LDS row 0
-
-  // stage activated input rows
-  if (a.in_buf) {
-    for (int idx = tid; idx < rows * a.cin; idx += kBlock) {
-      const int j = idx / a.cin, ci = idx - j * a.cin;
-      const int64_t p = p0 + j;
-      float v = 0.f;
-      if (p >= 0 && p < a.n_in) v = a.in_buf[p * a.cin + ci];
-      xs[j * stride + ci] = a.pre_act ? lrelu(v) : v;
-    }
-  } else {
-    for (int idx = tid; idx < rows * a.cin; idx += kBlock) {
-      const int ci = idx / rows, j = idx - ci * rows;   // time fastest: coalesced channel-major reads
-      const int64_t p = p0 + j;
-      float v = 0.f;
-      if (p >= 0 && p < a.n_in) {
-        const Entry& e = a.ents[entry_at(a.fent, p, a.in_num, a.in_den)];
-        const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-        v = e.in[(int64_t)ci * at_rate(e.T, a.in_num, a.in_den) + (p - in_start)];
-      }
-      xs[j * stride + ci] = a.pre_act ? lrelu(v) : v;
-    }
-  }
-  __syncthreads();
-
+  const int nw = a.k * a.cin * a.cout;
+  float* ws = smem;                                   // [k][cin][cout]
+  FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem + ((nw + 3) & ~3));
+  float* xs = reinterpret_cast<float*>(fi + F);
+  const int64_t n0 = (int64_t)blockIdx.x * F;
   const float* W = static_cast<const float*>(a.W);
-  const int items = F * co_n;
-  for (int it = tid; it < items; it += kBlock) {
-    const int i = it / co_n;
-    const int co = co0 + (it - i * co_n);
-    const int64_t n = n0 + i;
-    if (n >= a.n_out) continue;
-    const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
-    const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
-    float acc = a.B[co];
-    for (int kk = 0; kk < a.k; ++kk) {
-      const int64_t w = t * S + (int64_t)a.dil * kk;     // window row
-      const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
-      if (w >= a.L) {
-        const float* x = xs + (i * S + a.dil * kk) * stride;
-        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], x[ci], acc);
-      } else {
-        const float* x = e.state + a.state_off + (int64_t)e.parity * a.state_len + w * a.cin;
-        for (int ci = 0; ci < a.cin; ++ci) {
-          float v = x[ci];
-          if (a.pre_act) v = lrelu(v);
-          acc = fmaf(wp[(int64_t)ci * a.cout], v, acc);
+  for (int i = tid; i < nw; i += kBlock) ws[i] = W[i];
+  frame_infos(a, fi, n0, F);
+  stage_rows(a, xs, n0 * S - a.L, rows, ld);
+  __syncthreads();
+  for (int i = tid; i < F; i += kBlock) {
+    const FrameInfo f = fi[i];
+    if (f.ei < 0) continue;
+    for (int co = 0; co < a.cout; ++co) {
+      float acc = a.B[co];
+      for (int kk = 0; kk < a.k; ++kk) {
+        const int w = f.t * S + a.dil * kk;       // window row
+        const float* wp = ws + kk * a.cin * a.cout + co;
+        if (w >= a.L) {
+          const float* x = xs + (i * S + a.dil * kk) * ld;
+          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
+        } else {
+          const float* x = f.cache + (int64_t)w * a.cin;
+          for (int ci = 0; ci < a.cin; ++ci) {
+            float v = x[ci];
+            if (a.pre_act) v = lrelu(v);
+            acc = fmaf(wp[ci * a.cout], v, acc);
+          }
         }
       }
+      if (a.residual) acc = acc + skip_value(a, f, co);
+      if (a.post_act == 2) acc = tanhf(acc);
+      if (f.masked) acc = 0.f;
+      if (a.out_buf) a.out_buf[(n0 + i) * a.cout + co] = acc;
+      else f.out[(int64_t)co * f.tout] = acc;
     }
-    if (a.residual) {
-      const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-      const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-      const Row rw = window_row(e, in_start, Tin, t + a.skip_off, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
-      acc = acc + rw.p[co * rw.cs];
+  }
+}
+
+// Channel-parallel variant (many output channels, short reductions): each lane
+// owns output channels co = tid, tid + 256, ... with their weights in
+// registers (cin <= CMAX, k <= KMAX) and walks the block's frames; input rows
+// are LDS broadcasts.
+template <int CMAX, int KMAX>
+__global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int64_t n_tiles, int extra_blocks) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x;
+  if ((int64_t)blockIdx.x >= n_tiles) {
+    const int64_t total = (int64_t)a.n_ent * a.L * a.cin;
+    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += (int64_t)extra_blocks * kBlock)
+      cache_item(a, j);
+    return;
+  }
+  const int F = a.tile, S = a.stride, ld = a.cin | 1;
+  const int rows = F * S + a.L;
+  FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem);
+  float* xs = reinterpret_cast<float*>(fi + F);
+  const int64_t n0 = (int64_t)blockIdx.x * F;
+  frame_infos(a, fi, n0, F);
+  stage_rows(a, xs, n0 * S - a.L, rows, ld);
+  __syncthreads();
+  const float* W = static_cast<const float*>(a.W);
+  for (int co = tid; co < a.cout; co += kBlock) {
+    float wr[KMAX][CMAX];
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk)
+#pragma unroll
+      for (int ci = 0; ci < CMAX; ++ci)
+        wr[kk][ci] = (kk < a.k && ci < a.cin) ? W[((int64_t)kk * a.cin + ci) * a.cout + co] : 0.f;
+    const float bias = a.B[co];
+    for (int i = 0; i < F; ++i) {
+      const FrameInfo f = fi[i];
+      if (f.ei < 0) break;
+      float acc = bias;
+#pragma unroll
+      for (int kk = 0; kk < KMAX; ++kk) {
+        if (kk >= a.k) break;
+        const int w = f.t * S + a.dil * kk;
+        if (w >= a.L) {
+          const float* x = xs + (i * S + a.dil * kk) * ld;
+#pragma unroll
+          for (int ci = 0; ci < CMAX; ++ci)
+            if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
+        } else {
+          const float* x = f.cache + (int64_t)w * a.cin;
+#pragma unroll
+          for (int ci = 0; ci < CMAX; ++ci) {
+            if (ci < a.cin) {
+              float v = x[ci];
+              if (a.pre_act) v = lrelu(v);
+              acc = fmaf(wr[kk][ci], v, acc);
+            }
+          }
+        }
+      }
+      if (a.residual) acc = acc + skip_value(a, f, co);
+      if (a.post_act == 2) acc = tanhf(acc);
+      if (f.masked) acc = 0.f;
+      if (a.out_buf) a.out_buf[(n0 + i) * a.cout + co] = acc;
+      else f.out[(int64_t)co * f.tout] = acc;
     }
-    acc = finish(a, e, t, acc);
-    if (a.out_buf) a.out_buf[n * a.cout + co] = acc;
-    else e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
+  }
+}
+
+// Channel-major user input [C][T] of every stream -> packed channels-last
+// [frame][C] for the step.
+__global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, int32_t C,
+                                                           int64_t n_frames, float* out) {
+  const int64_t total = n_frames * C;
+  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+    const int64_t f = idx % n_frames;   // frame fastest: coalesced reads of each channel row
+    const int c = (int)(idx / n_frames);
+    const Entry& e = ents[fent[f]];
+    out[f * C + c] = e.in[(int64_t)c * e.T + (f - e.off)];
   }
 }
 
@@ -308,17 +474,31 @@ __global__ void __launch_bounds__(kBlock) fill_zero_kernel(float* p, int64_t n) 
 
 }  // namespace
 
+// Narrow-conv kernel choice: 1 = channel-parallel, 2 = frame-parallel, 0 = per item.
+static int narrow_kind(int cin, int cout, int k) {
+  if (cout >= 32 && cin <= kChansC && k <= kChansK) return 1;
+  if (cout <= 16 && k * cin * cout <= 4096) return 2;
+  return 0;
+}
+
+static size_t narrow_lds(int kind, int F, int cin, int cout, int k, int stride, int L) {
+  size_t b = (size_t)(F * stride + L) * (cin | 1) * sizeof(float) + (size_t)F * sizeof(FrameInfo);
+  if (kind == 2) b += (size_t)((k * cin * cout + 3) & ~3) * sizeof(float);
+  return b;
+}
+
 int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint) {
-  (void)k;
   (void)dil;
-  const int stride_f = cin | 1;
+  const int kind = narrow_kind(cin, cout, k);
+  if (kind == 0) return 0;
   int F = 256;
-  while (F > 16 && (int64_t)(F * stride + L) * stride_f * 4 > kNarrowLdsBytes) F /= 2;
-  if ((int64_t)(F * stride + L) * stride_f * 4 > kNarrowLdsBytes) return 0;
-  // enough blocks to fill the chip when outputs are many channels wide
-  const int co_tile = cout < kBlock ? cout : kBlock;
-  const int n_ct = (cout + co_tile - 1) / co_tile;
-  while (F > 16 && n_out_hint > 0 && ((n_out_hint + F - 1) / F) * n_ct < 1024 && F * co_tile > 8 * kBlock) F /= 2;
+  while (F > 8 && narrow_lds(kind, F, cin, cout, k, stride, L) > kNarrowLdsBytes) F /= 2;
+  if (narrow_lds(kind, F, cin, cout, k, stride, L) > kNarrowLdsBytes) return 0;
+  // channel-parallel: lanes walk the frames serially, so use short tiles and
+  // many blocks
+  if (kind == 1) {
+    while (F > 8 && n_out_hint > 0 && (n_out_hint + F - 1) / F < 2048) F /= 2;
+  }
   return F;
 }
 
@@ -328,20 +508,30 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
-  if (a.tile <= 0) {
+  const int kind = narrow_kind(a.cin, a.cout, a.k);
+  if (a.tile <= 0 || kind == 0) {
     const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * a.L * a.cin;
     hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   }
-  const int co_tile = a.cout < kBlock ? a.cout : kBlock;
-  const int n_ct = (a.cout + co_tile - 1) / co_tile;
-  const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile * n_ct;
+  const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile;
   const int64_t cache_items = (int64_t)a.n_ent * a.L * a.cin;
   const int extra = (int)std::min<int64_t>((cache_items + kBlock - 1) / kBlock, 1024);
-  const size_t lds = (size_t)(a.tile * a.stride + a.L) * (a.cin | 1) * sizeof(float);
+  const size_t lds = narrow_lds(kind, a.tile, a.cin, a.cout, a.k, a.stride, a.L);
   if (n_tiles + extra == 0) return hipSuccess;
-  hipLaunchKernelGGL(conv_narrow_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a, n_ct, co_tile,
-                     n_tiles, extra);
+  if (kind == 1)
+    hipLaunchKernelGGL((conv_chans_kernel<kChansC, kChansK>), dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds,
+                       s, a, n_tiles, extra);
+  else
+    hipLaunchKernelGGL(conv_frames_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a, n_tiles,
+                       extra);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n_frames * C)), dim3(kBlock), 0, s, ents, fent, C, n_frames,
+                     out);
   return hipGetLastError();
 }
 

@@ -230,14 +230,17 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
   }
   std::vector<int32_t> buf_of(n, -1);
   std::vector<bool> busy;
+  // the model input is packed channels-last into a workspace buffer first
+  if (last_use[0] >= 0) {
+    plan.buf_floats.push_back(Frac(chans[0], 1));
+    busy.push_back(true);
+    buf_of[0] = 0;
+    plan.input_buf = 0;
+  }
   for (int o = 0; o < (int)plan.ops.size(); ++o) {
     Op& op = plan.ops[o];
-    if (op.kind == K_DELAY_ADD && (op.src == 0 || op.src2 == 0)) {
-      err = "a branch sum that reads the model input directly is not supported";
-      return SC_EUNSUPPORTED;
-    }
-    op.in_buf = (op.src == 0) ? -1 : buf_of[op.src];
-    op.in_buf2 = (op.src2 <= 0) ? -1 : buf_of[op.src2];
+    op.in_buf = buf_of[op.src];
+    op.in_buf2 = (op.src2 < 0) ? -1 : buf_of[op.src2];
     if (op.node != out_node) {
       const Frac need = plan.rate[op.node].mul(chans[op.node]);
       const double need_d = (double)need.num / need.den;
@@ -258,7 +261,7 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
       op.out_buf = best;
     }
     // release buffers whose last reader is this op
-    for (int i = 1; i < n; ++i)
+    for (int i = 0; i < n; ++i)
       if (last_use[i] == o && buf_of[i] >= 0 && i != op.node) busy[buf_of[i]] = false;
   }
   return SC_OK;

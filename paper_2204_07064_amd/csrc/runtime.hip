@@ -327,6 +327,13 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   const int32_t* dfent = reinterpret_cast<const int32_t*>(slot.dev + ent_bytes);
 
   // ---- launches ----
+  if (m->plan.input_buf >= 0) {
+    e = launch_pack_input(dents, dfent, m->plan.in_channels, total, m->ws[m->plan.input_buf], hs);
+    if (e != hipSuccess) {
+      for (int i = 0; i < n; ++i) streams[i]->bad = true;
+      return hip_fail(e, "kernel launch");
+    }
+  }
   for (const Op& op : m->plan.ops) {
     const LayerArgs a = layer_args(m, op, dents, dfent, n, total);
     if (m->amax_on && op.layer >= 0) {

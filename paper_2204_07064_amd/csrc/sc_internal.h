@@ -49,7 +49,7 @@ struct Op {
   int64_t out_delay = 0;      // lag of the output stream, in its own frames
   int64_t state_off = 0, state_len = 0;     // floats; copies at off and off + len
   int64_t state_off2 = 0, state_len2 = 0;   // second delay line of a delay-add
-  int32_t in_buf = -1, in_buf2 = -1, out_buf = -1;  // -1: user input / user output
+  int32_t in_buf = -1, in_buf2 = -1, out_buf = -1;  // workspace buffers; out -1: user output
   int32_t layer = -1;         // index among conv/convt nodes
   int64_t w_off = 0, b_off = 0;             // offsets into the FP32 weight array
 };
@@ -61,6 +61,7 @@ struct Plan {
   std::vector<Frac> rate;
   std::vector<int32_t> layer_node;   // conv/convt node of each layer
   std::vector<Frac> buf_floats;      // floats per input frame of each workspace buffer
+  int32_t input_buf = -1;            // buffer holding the packed model input
   int32_t in_channels = 0, out_channels = 0;
   int32_t input_multiple = 1;
   Frac out_rate;

@@ -14,9 +14,10 @@ import torch
 from oracle import offline
 
 
-def mfma_layer(nd, is_last, reads_input):
-    """Mirror of the library's rule for which layers run on MFMA."""
-    if is_last or reads_input:
+def mfma_layer(nd, is_last, reads_input=False):
+    """Mirror of the library's rule for which layers run on MFMA (every layer
+    reads a packed workspace buffer; the last one writes the user's output)."""
+    if is_last:
         return False
     if nd["op"] == "conv":
         return (nd["stride"] == 1 and nd["cin"] % 8 == 0 and nd["cout"] % 16 == 0 and nd["cin"] >= 32

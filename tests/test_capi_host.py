@@ -80,8 +80,8 @@ def test_planner_rejects_malformed_graphs():
     assert _plan_status([inp, _node(k=5, pad_l=0, pad_r=0)])[0] == -7   # cannot stream
     # a residual conv of the input fuses (its skip is a window row of the input) ...
     assert _plan_status([inp, _node(), _node(op=3, src=1, src2=0)])[0] == 0
-    # ... but an unfusable sum that reads the model input directly is refused
-    assert _plan_status([inp, _node(), _node(src=1), _node(op=3, src=2, src2=0)])[0] == -7
+    # ... and an unfusable sum reads the packed model input through a delay line
+    assert _plan_status([inp, _node(), _node(src=1), _node(op=3, src=2, src2=0)])[0] == 0
     st, _ = _plan_status([inp])
     assert st == -1
     assert sc.lib().sc_last_error().decode()
