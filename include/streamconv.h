@@ -125,8 +125,11 @@ sc_status sc_plan(const sc_node* nodes, int32_t n_nodes, sc_model_info* out);
 enum {
   SC_MODEL_NO_FUSION = 1u,  /* run residual sums as explicit delay-line + add kernels
                                instead of the fused centre-tap skip */
-  SC_MODEL_NO_MFMA = 2u     /* run every layer on the FP32 wavefront-FMA kernels
+  SC_MODEL_NO_MFMA = 2u,    /* run every layer on the FP32 wavefront-FMA kernels
                                (precision must be SC_FP32) */
+  SC_MODEL_NO_TWIN = 4u     /* MFMA layers activate and round their input on load
+                               instead of reading the copy their producer wrote in
+                               operand form (same results; for testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,

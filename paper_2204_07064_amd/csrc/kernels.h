@@ -29,6 +29,13 @@ struct LayerArgs {
   int64_t n_in;            // total input frames of the step at the input rate
   int64_t n_out;           // total output frames of the step at the output rate
   int32_t tile;            // frames per block of the narrow conv kernel (0: per-item kernel)
+  // operand twins (see finalize_plan): element type 0 FP32, 1 BF16, 2 FP8 e4m3
+  const void* in_twin;     // consumer: pre-activated, pre-rounded input, or null
+  void* out_twin;          // producer: twin of the output to write, or null
+  float twin_qs;           // producer: scale applied before rounding (FP8: 448 / amax)
+  int32_t twin_pre;        // producer: pre-activation of the consumer
+  int32_t twin_prec;
+  int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
 };
 
 // Frames per block for the LDS-staged narrow conv (0 if its window does not fit).
@@ -37,7 +44,7 @@ int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, i
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
 // Channel-major user inputs of a step -> packed channels-last [frame][C].
 hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
-                             hipStream_t s);
+                             void* twin, int32_t twin_prec, int32_t twin_pre, float twin_qs, hipStream_t s);
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);
 hipError_t launch_delay_add(const LayerArgs& a, hipStream_t s);
 // max |pre_act(x)| over the step's new input frames of a layer -> atomic max into *amax

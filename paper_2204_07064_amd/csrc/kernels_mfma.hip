@@ -46,9 +46,9 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 
 template <int PREC> struct Prec;
-template <> struct Prec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; };
-template <> struct Prec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; };
-template <> struct Prec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; };
+template <> struct Prec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; typedef float Elem; };
+template <> struct Prec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; typedef uint16_t Elem; };
+template <> struct Prec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; typedef uint8_t Elem; };
 
 // ---- operand conversion ------------------------------------------------------
 __device__ inline uint32_t pack_bf16(float lo, float hi) {
@@ -57,8 +57,6 @@ __device__ inline uint32_t pack_bf16(float lo, float hi) {
   __builtin_memcpy(&u, &v, 4);
   return u;
 }
-
-__device__ inline float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
 
 __device__ inline uint32_t pack_fp8x4(float a, float b, float c, float d) {
   int v = 0;
@@ -101,6 +99,7 @@ __device__ inline f4 mfma_chunk(const Frag& a, const Frag& b, f4 acc) {
 // Per-column context of a tile, staged in LDS once per tile.
 struct ColInfo {
   const float* cache;   // conv: current cache copy of the column's stream (raw FP32 [L][cin])
+  const unsigned char* tcache;   // conv: current twin cache copy (operand type [L][cin])
   int32_t ei;           // entry (stream) index; -1 for a padding column
   int32_t t;            // conv: local output frame; convt: q (== Tin for a carry column)
   int32_t in_start;     // first packed input frame of the stream
@@ -111,6 +110,7 @@ template <bool CONVT>
 __device__ inline ColInfo make_col(const LayerArgs& a, int64_t n, int64_t n_cols) {
   ColInfo c;
   c.cache = nullptr;
+  c.tcache = nullptr;
   c.ei = -1;
   c.t = 0;
   c.in_start = 0;
@@ -129,6 +129,7 @@ __device__ inline ColInfo make_col(const LayerArgs& a, int64_t n, int64_t n_cols
   } else {
     c.t = (int32_t)(n - at_rate(e.off, a.out_num, a.out_den));
     c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+    c.tcache = reinterpret_cast<const unsigned char*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len);
   }
   return c;
 }
@@ -168,17 +169,27 @@ __device__ inline void store4(unsigned char* dst, float v0, float v1, float v2, 
   }
 }
 
-template <int PREC, int MT, int NT, bool CONVT>
+// Writes the operand twin of 4 consecutive output elements (element index o).
+template <int PREC>
+__device__ inline void store_twin4(const LayerArgs& a, int64_t o, f4 v) {
+  if (a.twin_pre) {
+    v.x = lrelu(v.x);
+    v.y = lrelu(v.y);
+    v.z = lrelu(v.z);
+    v.w = lrelu(v.w);
+  }
+  const float q = a.twin_qs;
+  store4<PREC>(static_cast<unsigned char*>(a.out_twin) + o * Prec<PREC>::kEsize, v.x * q, v.y * q, v.z * q, v.w * q);
+}
+
+template <int PREC, int MT, int NT, bool CONVT, bool INTWIN>
 __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_cols, int n_mt, int n_nt,
                                                         int Kpad, int Kreal, int half_pad, int Mreal,
                                                         int extra_blocks) {
   constexpr int KC = Prec<PREC>::kKc;
   constexpr int ES = Prec<PREC>::kEsize;
-  constexpr int PPC = KC / 4;                   // 4-element pieces per column per chunk
-  constexpr int B_PIECES = NT * PPC / kThreads; // pieces each thread gathers per chunk
   constexpr int WM = MT / 32;                   // waves along M
   static_assert(WM * (NT / 32) == 4, "4 waves of 32x32");
-  static_assert(B_PIECES >= 1 && NT * PPC % kThreads == 0, "whole pieces per thread");
   constexpr int A_PIECES = MT * 8 / kThreads;
   static_assert(A_PIECES == 1 || A_PIECES == 2, "MT of 32 or 64");
 
@@ -212,6 +223,14 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
       if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + row * a.cin + ci];
       else v = a.in_buf[(at_rate(e.off, a.in_num, a.in_den) + row - a.L) * a.cin + ci];
       e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = v;
+      if (INTWIN) {
+        typedef typename Prec<PREC>::Elem T;
+        const T* src = row < a.L
+            ? reinterpret_cast<const T*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len) + row * a.cin + ci
+            : static_cast<const T*>(a.in_twin) + (at_rate(e.off, a.in_num, a.in_den) + row - a.L) * a.cin + ci;
+        T* dst = reinterpret_cast<T*>(e.state + a.tstate_off + (int64_t)(1 - e.parity) * a.tstate_len);
+        dst[i * a.cin + ci] = *src;
+      }
     }
     return;
   }
@@ -230,7 +249,50 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   const float qs = (PREC == 2) ? 1.0f / a.act_scale : 1.0f;
 
   uint4 areg0, areg1;   // this thread's 16-byte pieces of the A chunk
-  f4 breg[B_PIECES];    // this thread's raw FP32 pieces of the B chunk
+
+  // B operand.  With a twin input every 16-byte piece is a plain copy of
+  // pre-activated, pre-rounded operands; otherwise raw FP32 pieces are
+  // activated and rounded on the way into LDS.
+  constexpr int EPP = INTWIN ? 16 / ES : 4;             // elements per piece
+  constexpr int PPCOL = KC / EPP;                       // pieces per column per chunk
+  constexpr int B_PIECES = NT * PPCOL / kThreads;       // pieces per thread per chunk
+  static_assert(B_PIECES >= 1 && NT * PPCOL % kThreads == 0 && kThreads % PPCOL == 0, "piece mapping");
+  const int my_pp = tid % PPCOL;                        // piece index within a column chunk (fixed)
+  const int my_col0 = tid / PPCOL;                      // first column; then + kThreads / PPCOL
+  uint4 tb[INTWIN ? B_PIECES : 1];
+  f4 rb[INTWIN ? 1 : B_PIECES];
+  // K position of this thread's piece, advanced chunk by chunk without division
+  int k_tap = 0, k_ci = 0;
+  {
+    const int kk0 = my_pp * EPP;
+    if (!CONVT) {
+      k_tap = kk0 / a.cin;
+      k_ci = kk0 - k_tap * a.cin;
+    }
+  }
+  auto piece_src = [&](const ColInfo& cc, int c, int& off_ok) __attribute__((always_inline)) -> int64_t {
+    // returns the element offset of the piece in the twin / raw source and sets
+    // off_ok: 0 = zero piece, 1 = input buffer, 2 = cache
+    off_ok = 0;
+    if (cc.ei < 0) return 0;
+    if (CONVT) {
+      const int kk = c * KC + my_pp * EPP;
+      const int h = kk >= half_pad;
+      const int ci = kk - h * half_pad;
+      const int row = cc.t - 1 + h;
+      if (ci >= a.cin || row < 0 || row >= cc.Tin) return 0;
+      off_ok = 1;
+      return ((int64_t)cc.in_start + row) * a.cin + ci;
+    }
+    if (c * KC + my_pp * EPP >= Kreal) return 0;
+    const int row = cc.t + a.dil * k_tap;
+    if (row < a.L) {
+      off_ok = 2;
+      return (int64_t)row * a.cin + k_ci;
+    }
+    off_ok = 1;
+    return ((int64_t)cc.in_start + row - a.L) * a.cin + k_ci;
+  };
 
   auto load_chunk = [&](int c) __attribute__((always_inline)) {
     {
@@ -241,10 +303,23 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
     }
 #pragma unroll
     for (int p = 0; p < B_PIECES; ++p) {
-      const int u = tid + p * kThreads;          // consecutive threads: consecutive pieces of a column
-      const int col = u / PPC, pp = u % PPC;
-      const float* src = src4<CONVT>(a, cols[col], c * KC + pp * 4, Kreal, half_pad);
-      breg[p] = src ? *reinterpret_cast<const f4*>(src) : f4{0.f, 0.f, 0.f, 0.f};
+      const ColInfo& cc = cols[my_col0 + p * (kThreads / PPCOL)];
+      int where;
+      const int64_t off = piece_src(cc, c, where);
+      if constexpr (INTWIN) {
+        const unsigned char* base = where == 2 ? cc.tcache : static_cast<const unsigned char*>(a.in_twin);
+        tb[p] = where ? *reinterpret_cast<const uint4*>(base + off * ES) : uint4{0u, 0u, 0u, 0u};
+      } else {
+        const float* base = where == 2 ? cc.cache : a.in_buf;
+        rb[p] = where ? *reinterpret_cast<const f4*>(base + off) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    if (!CONVT) {
+      k_ci += KC;
+      while (k_ci >= a.cin) {
+        k_ci -= a.cin;
+        ++k_tap;
+      }
     }
   };
   auto store_chunk = [&](int buf) __attribute__((always_inline)) {
@@ -255,16 +330,20 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
     }
 #pragma unroll
     for (int p = 0; p < B_PIECES; ++p) {
-      const int u = tid + p * kThreads;
-      const int col = u / PPC, pp = u % PPC;
-      f4 v = breg[p];
-      if (pre) {
-        v.x = lrelu(v.x);
-        v.y = lrelu(v.y);
-        v.z = lrelu(v.z);
-        v.w = lrelu(v.w);
+      const int col = my_col0 + p * (kThreads / PPCOL);
+      unsigned char* dst = &lds_b[buf][col * kRowStride + my_pp * EPP * ES];
+      if constexpr (INTWIN) {
+        *reinterpret_cast<uint4*>(dst) = tb[p];
+      } else {
+        f4 v = rb[p];
+        if (pre) {
+          v.x = lrelu(v.x);
+          v.y = lrelu(v.y);
+          v.z = lrelu(v.z);
+          v.w = lrelu(v.w);
+        }
+        store4<PREC>(dst, v.x * qs, v.y * qs, v.z * qs, v.w * qs);
       }
-      store4<PREC>(&lds_b[buf][col * kRowStride + pp * 4 * ES], v.x * qs, v.y * qs, v.z * qs, v.w * qs);
     }
   };
 
@@ -344,7 +423,9 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
         const int64_t t = (int64_t)c.t * a.stride + phi;
         if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay)
           v = f4{0.f, 0.f, 0.f, 0.f};
-        *reinterpret_cast<f4*>(a.out_buf + ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m) = v;
+        const int64_t o = ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m;
+        *reinterpret_cast<f4*>(a.out_buf + o) = v;
+        if (a.out_twin) store_twin4<PREC>(a, o, v);
       } else {
         v = v + *reinterpret_cast<const f4*>(a.B + m);
         if (a.residual) {
@@ -356,6 +437,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
         if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + c.t < a.delay)
           v = f4{0.f, 0.f, 0.f, 0.f};
         *reinterpret_cast<f4*>(a.out_buf + n * a.cout + m) = v;
+        if (a.out_twin) store_twin4<PREC>(a, n * a.cout + m, v);
       }
     }
   }
@@ -432,7 +514,7 @@ void tile_for(int M, int& MT, int& NT) {
   else { MT = 64; NT = 64; }
 }
 
-template <int PREC, int MT, int NT, bool CONVT>
+template <int PREC, int MT, int NT, bool CONVT, bool INTWIN>
 hipError_t launch_t(const LayerArgs& a, int64_t n_cols, int Kpad, int Kreal, int half_pad, int M,
                     hipStream_t s) {
   const int n_mt = (M + MT - 1) / MT;
@@ -444,7 +526,7 @@ hipError_t launch_t(const LayerArgs& a, int64_t n_cols, int Kpad, int Kreal, int
   }
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT>), dim3((unsigned)grid), dim3(kThreads), 0, s, a, n_cols,
+  hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT, INTWIN>), dim3((unsigned)grid), dim3(kThreads), 0, s, a, n_cols,
                      n_mt, (int)n_nt, Kpad, Kreal, half_pad, M, extra);
   return hipGetLastError();
 }
@@ -454,8 +536,11 @@ hipError_t dispatch(const LayerArgs& a, int prec, int64_t n_cols, int Kpad, int 
                     hipStream_t s) {
   int MT, NT;
   tile_for(M, MT, NT);
-#define SC_CASE(P, A, B)                                                                       \
-  if (prec == P && MT == A && NT == B) return launch_t<P, A, B, CONVT>(a, n_cols, Kpad, Kreal, half_pad, M, s);
+#define SC_CASE(P, A, B)                                                                                   \
+  if (prec == P && MT == A && NT == B) {                                                                   \
+    if (a.in_twin) return launch_t<P, A, B, CONVT, true>(a, n_cols, Kpad, Kreal, half_pad, M, s);         \
+    return launch_t<P, A, B, CONVT, false>(a, n_cols, Kpad, Kreal, half_pad, M, s);                       \
+  }
   SC_CASE(0, 32, 128) SC_CASE(0, 64, 64)
   SC_CASE(1, 32, 128) SC_CASE(1, 64, 64)
   SC_CASE(2, 32, 128) SC_CASE(2, 64, 64)
@@ -467,12 +552,16 @@ hipError_t dispatch(const LayerArgs& a, int prec, int64_t n_cols, int Kpad, int 
 
 bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec) {
   (void)k;
-  return stride == 1 && cin % 8 == 0 && cout % 16 == 0 && cin >= 32 && cout >= 32 && prec >= 0 && prec <= 2;
+  // 16-byte operand pieces never straddle two taps: cin * element size % 16 == 0
+  const int es = esize(prec);
+  return stride == 1 && (cin * es) % 16 == 0 && cin % 8 == 0 && cout % 16 == 0 && cin >= 32 && cout >= 32 &&
+         prec >= 0 && prec <= 2;
 }
 
 bool convt_mfma_supported(int cin, int cout, int r, int prec) {
-  return cin % 8 == 0 && cout % 4 == 0 && cin >= 32 && r * cout >= 32 && (r * cout) % 16 == 0 && prec >= 0 &&
-         prec <= 2;
+  const int es = esize(prec);
+  return (cin * es) % 16 == 0 && cin % 8 == 0 && cout % 4 == 0 && cin >= 32 && r * cout >= 32 &&
+         (r * cout) % 16 == 0 && prec >= 0 && prec <= 2;
 }
 
 void pack_conv_mfma(const float* w, int cout, int cin, int k, int prec, std::vector<uint8_t>& out,

@@ -94,8 +94,12 @@ __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a) {
       acc = acc + rw.p[co * rw.cs];
     }
     acc = finish(a, e, t, acc);
-    if (a.out_buf) a.out_buf[n * a.cout + co] = acc;
-    else e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
+    if (a.out_buf) {
+      a.out_buf[n * a.cout + co] = acc;
+      if (a.out_twin) store_twin1(a.out_twin, n * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+    } else {
+      e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
+    }
   }
 }
 
@@ -265,8 +269,12 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int64_
       if (a.residual) acc = acc + skip_value(a, f, co);
       if (a.post_act == 2) acc = tanhf(acc);
       if (f.masked) acc = 0.f;
-      if (a.out_buf) a.out_buf[(n0 + i) * a.cout + co] = acc;
-      else f.out[(int64_t)co * f.tout] = acc;
+      if (a.out_buf) {
+        a.out_buf[(n0 + i) * a.cout + co] = acc;
+        if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+      } else {
+        f.out[(int64_t)co * f.tout] = acc;
+      }
     }
   }
 }
@@ -330,8 +338,12 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int64_t
       if (a.residual) acc = acc + skip_value(a, f, co);
       if (a.post_act == 2) acc = tanhf(acc);
       if (f.masked) acc = 0.f;
-      if (a.out_buf) a.out_buf[(n0 + i) * a.cout + co] = acc;
-      else f.out[(int64_t)co * f.tout] = acc;
+      if (a.out_buf) {
+        a.out_buf[(n0 + i) * a.cout + co] = acc;
+        if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+      } else {
+        f.out[(int64_t)co * f.tout] = acc;
+      }
     }
   }
 }
@@ -339,13 +351,16 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int64_t
 // Channel-major user input [C][T] of every stream -> packed channels-last
 // [frame][C] for the step.
 __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, int32_t C,
-                                                           int64_t n_frames, float* out) {
+                                                           int64_t n_frames, float* out, void* twin, int32_t twin_prec,
+                                                           int32_t twin_pre, float twin_qs) {
   const int64_t total = n_frames * C;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
     const int64_t f = idx % n_frames;   // frame fastest: coalesced reads of each channel row
     const int c = (int)(idx / n_frames);
     const Entry& e = ents[fent[f]];
-    out[f * C + c] = e.in[(int64_t)c * e.T + (f - e.off)];
+    const float v = e.in[(int64_t)c * e.T + (f - e.off)];
+    out[f * C + c] = v;
+    if (twin) store_twin1(twin, f * C + c, twin_prec, twin_pre, twin_qs, v);
   }
 }
 
@@ -390,8 +405,13 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
       float v = acc + a.B[co];
       const int64_t t = q * r + phi;
       if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
-      if (a.out_buf) a.out_buf[(in_start * r + t) * a.cout + co] = v;
-      else e.out[(int64_t)co * (Tin * r) + t] = v;
+      if (a.out_buf) {
+        a.out_buf[(in_start * r + t) * a.cout + co] = v;
+        if (a.out_twin)
+          store_twin1(a.out_twin, (in_start * r + t) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, v);
+      } else {
+        e.out[(int64_t)co * (Tin * r) + t] = v;
+      }
     } else {
       e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + phi * a.cout + co] = acc;
     }
@@ -418,8 +438,12 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a) {
       const Row r1 = window_row(e, start, Tn, t, a.A1, a.state_off2, a.state_len2, a.in_buf2, C);
       float v = r0.p[c * r0.cs] + r1.p[c * r1.cs];
       if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
-      if (a.out_buf) a.out_buf[n * C + c] = v;
-      else e.out[(int64_t)c * Tn + t] = v;
+      if (a.out_buf) {
+        a.out_buf[n * C + c] = v;
+        if (a.out_twin) store_twin1(a.out_twin, n * C + c, a.twin_prec, a.twin_pre, a.twin_qs, v);
+      } else {
+        e.out[(int64_t)c * Tn + t] = v;
+      }
     } else {
       const int64_t j = idx - n_items;
       const int ei = (int)(j / per_ent);
@@ -529,9 +553,9 @@ hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
-                             hipStream_t s) {
+                             void* twin, int32_t twin_prec, int32_t twin_pre, float twin_qs, hipStream_t s) {
   hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n_frames * C)), dim3(kBlock), 0, s, ents, fent, C, n_frames,
-                     out);
+                     out, twin, twin_prec, twin_pre, twin_qs);
   return hipGetLastError();
 }
 

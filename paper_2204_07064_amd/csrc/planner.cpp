@@ -208,20 +208,6 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
     plan.ops.push_back(op);
   }
 
-  // ---- state layout (double-buffered copies) ----------------------------------
-  // every region starts on a 16-float (64-byte) boundary for vector access
-  auto align16 = [](int64_t x) { return (x + 15) / 16 * 16; };
-  int64_t soff = 0, one = 0;
-  for (auto& op : plan.ops) {
-    op.state_off = soff;
-    soff = align16(soff + 2 * op.state_len);
-    op.state_off2 = soff;
-    soff = align16(soff + 2 * op.state_len2);
-    one += op.state_len + op.state_len2;
-  }
-  plan.state_floats = one;
-  plan.state_alloc_floats = soff;
-
   // ---- workspace buffers with reuse after the last reader ---------------------
   std::vector<int32_t> last_use(n, -1);
   for (int o = 0; o < (int)plan.ops.size(); ++o) {
@@ -264,7 +250,65 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
     for (int i = 0; i < n; ++i)
       if (last_use[i] == o && buf_of[i] >= 0 && i != op.node) busy[buf_of[i]] = false;
   }
+  finalize_plan(plan, false, 4);
   return SC_OK;
+}
+
+void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
+  const int n = (int)plan.nodes.size();
+  // ---- operand twins ----
+  plan.twin_elems.clear();
+  plan.input_twin = -1;
+  for (auto& op : plan.ops) {
+    op.in_twin = op.out_twin = -1;
+    op.tstate_len = 0;
+  }
+  if (twins) {
+    std::vector<int> producer(n, -1);
+    for (int o = 0; o < (int)plan.ops.size(); ++o) producer[plan.ops[o].node] = o;
+    for (int s = 0; s < n; ++s) {
+      int reader = -1, n_mfma = 0;
+      for (int o = 0; o < (int)plan.ops.size(); ++o) {
+        const Op& op = plan.ops[o];
+        if (op.impl == IMPL_MFMA && op.src == s) { reader = o; ++n_mfma; }
+      }
+      if (n_mfma != 1) continue;
+      const bool from_input = (s == 0 && plan.input_buf >= 0);
+      if (!from_input && (producer[s] < 0 || plan.ops[producer[s]].out_buf < 0)) continue;
+      const int t = (int)plan.twin_elems.size();
+      const int chans = from_input ? plan.in_channels : plan.ops[producer[s]].cout;
+      plan.twin_elems.push_back(plan.rate[s].mul(chans));
+      Op& rd = plan.ops[reader];
+      rd.in_twin = t;
+      if (from_input) {
+        plan.input_twin = t;
+        plan.input_twin_pre = rd.pre_act;
+        plan.input_twin_layer = rd.layer;
+      } else {
+        Op& pr = plan.ops[producer[s]];
+        pr.out_twin = t;
+        pr.twin_pre = rd.pre_act;
+        pr.twin_layer = rd.layer;
+      }
+      if (rd.kind == K_CONV && rd.cache_len > 0)
+        rd.tstate_len = ((int64_t)rd.cache_len * rd.cin * elem_bytes + 3) / 4;
+    }
+  }
+  // ---- state layout: double-buffered copies, every region on a 16-float
+  // (64-byte) boundary for vector access ----
+  auto align16 = [](int64_t x) { return (x + 15) / 16 * 16; };
+  int64_t soff = 0, one = 0;
+  for (auto& op : plan.ops) {
+    op.state_off = soff;
+    soff = align16(soff + 2 * op.state_len);
+    op.state_off2 = soff;
+    soff = align16(soff + 2 * op.state_len2);
+    op.tstate_off = soff;
+    soff = align16(soff + 2 * op.tstate_len);
+    one += op.state_len + op.state_len2;
+  }
+  plan.state_floats = one;
+  plan.state_alloc_floats = soff;
 }
 
 }  // namespace sc

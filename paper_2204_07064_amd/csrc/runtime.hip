@@ -71,6 +71,8 @@ struct sc_model {
   int64_t weight_bytes = 0;
   // workspace
   std::vector<float*> ws;
+  std::vector<void*> tw;           // operand twins
+  int tw_esize = 4;
   int64_t ws_cap = 0;              // input frames
   // descriptors
   DescSlot ring[kRing];
@@ -145,6 +147,7 @@ void free_model(sc_model* m) {
     hipFree(o.wscale);
   }
   for (float* p : m->ws) hipFree(p);
+  for (void* p : m->tw) hipFree(p);
   for (hipEvent_t ev : m->prof_events) hipEventDestroy(ev);
   for (auto& s : m->ring) {
     if (s.host) hipHostFree(s.host);
@@ -154,6 +157,13 @@ void free_model(sc_model* m) {
   if (m->last_done) hipEventDestroy(m->last_done);
   hipFree(m->d_amax);
   delete m;
+}
+
+// Scale applied before rounding a twin read by `layer`: the reciprocal of that
+// layer's FP8 activation scale (amax / 448), computed as the MFMA kernel does.
+float twin_scale(const sc_model* m, int layer) {
+  if (m->prec != SC_FP8E4M3 || layer < 0 || !m->have_scales) return 1.0f;
+  return 1.0f / (m->act_scales[layer] / 448.0f);
 }
 
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent, int n_ent,
@@ -184,6 +194,13 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.tile = (op.kind == K_CONV && op.impl == IMPL_VALU)
                ? narrow_conv_tile(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, a.n_out)
                : 0;
+  a.in_twin = op.in_twin >= 0 ? m->tw[op.in_twin] : nullptr;
+  a.out_twin = op.out_twin >= 0 ? m->tw[op.out_twin] : nullptr;
+  a.twin_prec = m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2);
+  a.twin_pre = op.twin_pre;
+  a.twin_qs = twin_scale(m, op.twin_layer);
+  a.tstate_off = op.tstate_off;
+  a.tstate_len = op.tstate_len;
   return a;
 }
 
@@ -195,7 +212,17 @@ sc_status ensure_workspace(sc_model* m, int64_t frames) {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   for (float*& p : m->ws) { hipFree(p); p = nullptr; }
+  for (void*& p : m->tw) { hipFree(p); p = nullptr; }
   m->ws.assign(m->plan.buf_floats.size(), nullptr);
+  m->tw.assign(m->plan.twin_elems.size(), nullptr);
+  for (size_t t = 0; t < m->plan.twin_elems.size(); ++t) {
+    const int64_t bytes = m->plan.twin_elems[t].of(cap) * m->tw_esize + 64;
+    e = hipMalloc(&m->tw[t], (size_t)bytes);
+    if (e != hipSuccess) {
+      m->ws_cap = 0;
+      return fail(SC_ENOMEM, "workspace allocation failed");
+    }
+  }
   for (size_t b = 0; b < m->plan.buf_floats.size(); ++b) {
     const int64_t n = m->plan.buf_floats[b].of(cap) + 1;
     e = hipMalloc(reinterpret_cast<void**>(&m->ws[b]), (size_t)n * sizeof(float));
@@ -328,7 +355,11 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
 
   // ---- launches ----
   if (m->plan.input_buf >= 0) {
-    e = launch_pack_input(dents, dfent, m->plan.in_channels, total, m->ws[m->plan.input_buf], hs);
+    const Plan& pl = m->plan;
+    e = launch_pack_input(dents, dfent, pl.in_channels, total, m->ws[pl.input_buf],
+                          pl.input_twin >= 0 ? m->tw[pl.input_twin] : nullptr,
+                          m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2), pl.input_twin_pre,
+                          twin_scale(m, pl.input_twin_layer), hs);
     if (e != hipSuccess) {
       for (int i = 0; i < n; ++i) streams[i]->bad = true;
       return hip_fail(e, "kernel launch");
@@ -498,6 +529,8 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     m->weight_bytes += (int64_t)op.cout * 4;
     if (e != hipSuccess) { free_model(m); return hip_fail(e, "weight upload"); }
   }
+  m->tw_esize = prec_id == 0 ? 4 : (prec_id == 1 ? 2 : 1);
+  finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN), m->tw_esize);
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
   if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }

@@ -32,4 +32,22 @@ __device__ inline int entry_at(const int32_t* fent, int64_t n, int64_t num, int6
 
 __device__ inline float lrelu(float v) { return v >= 0.f ? v : 0.2f * v; }
 
+__device__ inline float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
+
+// One operand element: act(v) * qs rounded to the twin type, stored at
+// element index `idx` of `base` (0 FP32, 1 BF16 RNE, 2 OCP FP8 e4m3 RNE saturating).
+__device__ inline void store_twin1(void* base, int64_t idx, int prec, int pre, float qs, float v) {
+  if (pre) v = lrelu(v);
+  v *= qs;
+  if (prec == 0) {
+    static_cast<float*>(base)[idx] = v;
+  } else if (prec == 1) {
+    __bf16 h = (__bf16)v;
+    static_cast<__bf16*>(base)[idx] = h;
+  } else {
+    const int q = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v), 0.f, 0, false);
+    static_cast<unsigned char*>(base)[idx] = (unsigned char)(q & 0xff);
+  }
+}
+
 }  // namespace sc

@@ -52,6 +52,13 @@ struct Op {
   int32_t in_buf = -1, in_buf2 = -1, out_buf = -1;  // workspace buffers; out -1: user output
   int32_t layer = -1;         // index among conv/convt nodes
   int64_t w_off = 0, b_off = 0;             // offsets into the FP32 weight array
+  // operand twins: pre-activated, pre-rounded copies of an activation in the
+  // MFMA operand type, written by the producer for its single MFMA consumer
+  int32_t in_twin = -1;       // consumer: twin buffer of the input
+  int32_t out_twin = -1;      // producer: twin buffer it writes
+  int32_t twin_pre = 0;       // producer: the consumer's pre-activation
+  int32_t twin_layer = -1;    // producer: the consumer's layer (FP8 activation scale)
+  int64_t tstate_off = 0, tstate_len = 0;   // consumer conv: twin cache (floats)
 };
 
 struct Plan {
@@ -62,6 +69,9 @@ struct Plan {
   std::vector<int32_t> layer_node;   // conv/convt node of each layer
   std::vector<Frac> buf_floats;      // floats per input frame of each workspace buffer
   int32_t input_buf = -1;            // buffer holding the packed model input
+  int32_t input_twin = -1;           // twin of the packed model input
+  int32_t input_twin_pre = 0, input_twin_layer = -1;
+  std::vector<Frac> twin_elems;      // elements per input frame of each twin buffer
   int32_t in_channels = 0, out_channels = 0;
   int32_t input_multiple = 1;
   Frac out_rate;
@@ -74,6 +84,12 @@ struct Plan {
 // Builds the streaming plan (post-training reconfiguration) of a node list.
 sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& plan,
                      std::string& err);
+
+// After the runtime has chosen each op's kernel family: assigns operand twins
+// (when `twins`) for inputs of MFMA ops that have exactly one MFMA reader and
+// a producer that can write them, and lays out the per-stream state (caches,
+// carries, delay lines, twin caches of `elem_bytes`-byte operands).
+void finalize_plan(Plan& plan, bool twins, int elem_bytes);
 
 void set_error(const std::string& msg);
 

@@ -14,17 +14,19 @@ import torch
 from oracle import offline
 
 
-def mfma_layer(nd, is_last, reads_input=False):
+def mfma_layer(nd, is_last, reads_input=False, precision="bf16"):
     """Mirror of the library's rule for which layers run on MFMA (every layer
     reads a packed workspace buffer; the last one writes the user's output)."""
     if is_last:
         return False
+    es = {"fp32": 4, "bf16": 2, "fp8": 1}[precision]
     if nd["op"] == "conv":
-        return (nd["stride"] == 1 and nd["cin"] % 8 == 0 and nd["cout"] % 16 == 0 and nd["cin"] >= 32
-                and nd["cout"] >= 32)
+        return (nd["stride"] == 1 and nd["cin"] * es % 16 == 0 and nd["cin"] % 8 == 0 and nd["cout"] % 16 == 0
+                and nd["cin"] >= 32 and nd["cout"] >= 32)
     if nd["op"] == "convt":
         m = nd["stride"] * nd["cout"]
-        return nd["cin"] % 8 == 0 and nd["cout"] % 4 == 0 and nd["cin"] >= 32 and m >= 32 and m % 16 == 0
+        return (nd["cin"] * es % 16 == 0 and nd["cin"] % 8 == 0 and nd["cout"] % 4 == 0 and nd["cin"] >= 32
+                and m >= 32 and m % 16 == 0)
     return False
 
 
@@ -53,7 +55,7 @@ def forward(model, weights, x, precision, act_scales=None):
         layer += 1
         w, b = params[i]
         u = offline.apply_pre(nd, outs[nd["src"]])
-        if precision != "fp32" and mfma_layer(nd, i == len(nodes) - 1, nd["src"] == 0):
+        if precision != "fp32" and mfma_layer(nd, i == len(nodes) - 1, nd["src"] == 0, precision):
             if nd.get("pre_act", 0) == 1:
                 # the kernel applies LeakyReLU in FP32 before rounding
                 x32 = np.asarray(outs[nd["src"]], np.float32)

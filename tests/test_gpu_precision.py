@@ -35,6 +35,22 @@ def _fp8_scales(sc, m, w, channels):
     return calibrate.act_scales(sc, m, w, cal)
 
 
+@pytest.mark.parametrize("name", ["rave_b", "wide"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_operand_twins_bitwise(name, prec):
+    """MFMA layers reading the operand copy written by their producer give
+    bitwise the same stream as layers that activate and round on load."""
+    sc = _sc()
+    m, w = weights_for(name)
+    c = m["in_channels"]
+    scales = _fp8_scales(sc, m, w, c) if prec == "fp8" else None
+    x = scgen.stream_latents(c, 40, 2)
+    splits = [1, 3, 16, 8, 12]
+    a = run_stream(sc.Model(m, w, prec, act_scales=scales), x, splits)
+    b = run_stream(sc.Model(m, w, prec, act_scales=scales, options=4), x, splits)
+    assert np.array_equal(a, b)
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     sc = _sc()
     m, w = weights_for("rave_b")
