@@ -44,6 +44,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int i8v __attribute__((ext_vector_type(8)));
+// native 16-byte vector (HIP's uint4 is a union-based class that defeats
+// register promotion of arrays of it)
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; typedef float Elem; };
@@ -67,7 +70,7 @@ __device__ inline uint32_t pack_fp8x4(float a, float b, float c, float d) {
 
 // 32-byte fragment of one lane (its slice of a 128-byte chunk row).
 struct Frag {
-  uint4 lo, hi;
+  u4 lo, hi;
 };
 
 template <int PREC>
@@ -239,113 +242,128 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   const int m0 = mt * MT;
   const int64_t n0 = nt * NT;
 
-  if (tid < NT) cols[tid] = make_col<CONVT>(a, n0 + tid, n_cols);
-  __syncthreads();
-
   const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
   const int row_bytes = Kpad * ES;
   const int n_chunks = Kpad / KC;
   const bool pre = a.pre_act != 0;
   const float qs = (PREC == 2) ? 1.0f / a.act_scale : 1.0f;
 
-  uint4 areg0, areg1;   // this thread's 16-byte pieces of the A chunk
-
-  // B operand.  With a twin input every 16-byte piece is a plain copy of
-  // pre-activated, pre-rounded operands; otherwise raw FP32 pieces are
-  // activated and rounded on the way into LDS.
-  constexpr int EPP = INTWIN ? 16 / ES : 4;             // elements per piece
+  // Register pipeline: chunk c + STAGES is in flight while chunk c is
+  // multiplied, so a chunk's memory latency overlaps STAGES chunks of work.
+  constexpr int STAGES = INTWIN ? 4 : 2;
+  static_assert(STAGES == 2 || STAGES == 4, "stages are written out for 2 or 4");
+  constexpr int EPP = INTWIN ? 16 / ES : 4;             // elements per B piece
   constexpr int PPCOL = KC / EPP;                       // pieces per column per chunk
   constexpr int B_PIECES = NT * PPCOL / kThreads;       // pieces per thread per chunk
   static_assert(B_PIECES >= 1 && NT * PPCOL % kThreads == 0 && kThreads % PPCOL == 0, "piece mapping");
   const int my_pp = tid % PPCOL;                        // piece index within a column chunk (fixed)
   const int my_col0 = tid / PPCOL;                      // first column; then + kThreads / PPCOL
-  uint4 tb[INTWIN ? B_PIECES : 1];
-  f4 rb[INTWIN ? 1 : B_PIECES];
-  // K position of this thread's piece, advanced chunk by chunk without division
-  int k_tap = 0, k_ci = 0;
-  {
-    const int kk0 = my_pp * EPP;
-    if (!CONVT) {
-      k_tap = kk0 / a.cin;
-      k_ci = kk0 - k_tap * a.cin;
-    }
-  }
-  auto piece_src = [&](const ColInfo& cc, int c, int& off_ok) __attribute__((always_inline)) -> int64_t {
-    // returns the element offset of the piece in the twin / raw source and sets
-    // off_ok: 0 = zero piece, 1 = input buffer, 2 = cache
-    off_ok = 0;
-    if (cc.ei < 0) return 0;
-    if (CONVT) {
-      const int kk = c * KC + my_pp * EPP;
-      const int h = kk >= half_pad;
-      const int ci = kk - h * half_pad;
-      const int row = cc.t - 1 + h;
-      if (ci >= a.cin || row < 0 || row >= cc.Tin) return 0;
-      off_ok = 1;
-      return ((int64_t)cc.in_start + row) * a.cin + ci;
-    }
-    if (c * KC + my_pp * EPP >= Kreal) return 0;
-    const int row = cc.t + a.dil * k_tap;
-    if (row < a.L) {
-      off_ok = 2;
-      return (int64_t)row * a.cin + k_ci;
-    }
-    off_ok = 1;
-    return ((int64_t)cc.in_start + row - a.L) * a.cin + k_ci;
-  };
+  u4 ar0[STAGES], ar1[STAGES];                       // A pieces (16 B) per stage
+  u4 tb[STAGES][INTWIN ? B_PIECES : 1];              // B twin pieces
+  f4 rb[STAGES][INTWIN ? 1 : B_PIECES];                 // B raw FP32 pieces
 
-  auto load_chunk = [&](int c) __attribute__((always_inline)) {
-    {
-      const int r = tid >> 3, seg = tid & 7;
-      areg0 = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r) * row_bytes + c * kChunkBytes + seg * 16);
-      if constexpr (A_PIECES == 2)
-        areg1 = *reinterpret_cast<const uint4*>(Wb + (int64_t)(m0 + r + 32) * row_bytes + c * kChunkBytes + seg * 16);
-    }
-#pragma unroll
-    for (int p = 0; p < B_PIECES; ++p) {
-      const ColInfo& cc = cols[my_col0 + p * (kThreads / PPCOL)];
-      int where;
-      const int64_t off = piece_src(cc, c, where);
-      if constexpr (INTWIN) {
-        const unsigned char* base = where == 2 ? cc.tcache : static_cast<const unsigned char*>(a.in_twin);
-        tb[p] = where ? *reinterpret_cast<const uint4*>(base + off * ES) : uint4{0u, 0u, 0u, 0u};
-      } else {
-        const float* base = where == 2 ? cc.cache : a.in_buf;
-        rb[p] = where ? *reinterpret_cast<const f4*>(base + off) : f4{0.f, 0.f, 0.f, 0.f};
-      }
-    }
-    if (!CONVT) {
-      k_ci += KC;
-      while (k_ci >= a.cin) {
-        k_ci -= a.cin;
-        ++k_tap;
-      }
-    }
-  };
-  auto store_chunk = [&](int buf) __attribute__((always_inline)) {
-    {
-      const int r = tid >> 3, seg = tid & 7;
-      *reinterpret_cast<uint4*>(&lds_a[buf][r * kRowStride + seg * 16]) = areg0;
-      if constexpr (A_PIECES == 2) *reinterpret_cast<uint4*>(&lds_a[buf][(r + 32) * kRowStride + seg * 16]) = areg1;
-    }
-#pragma unroll
-    for (int p = 0; p < B_PIECES; ++p) {
-      const int col = my_col0 + p * (kThreads / PPCOL);
-      unsigned char* dst = &lds_b[buf][col * kRowStride + my_pp * EPP * ES];
-      if constexpr (INTWIN) {
-        *reinterpret_cast<uint4*>(dst) = tb[p];
-      } else {
-        f4 v = rb[p];
-        if (pre) {
-          v.x = lrelu(v.x);
-          v.y = lrelu(v.y);
-          v.z = lrelu(v.z);
-          v.w = lrelu(v.w);
-        }
-        store4<PREC>(dst, v.x * qs, v.y * qs, v.z * qs, v.w * qs);
-      }
-    }
-  };
+  // ---- pipeline stage operations (macros: the stage registers must stay
+  // in VGPRs, which lambdas over arrays defeat) ----
+#define SC_LOAD_A(C, ST)                                                                                     \
+  {                                                                                                          \
+    const int r_ = tid >> 3, seg_ = tid & 7;                                                                 \
+    ar0[ST] = *reinterpret_cast<const u4*>(Wb + (int64_t)(m0 + r_) * row_bytes + (C) * kChunkBytes + seg_ * 16); \
+    if constexpr (A_PIECES == 2)                                                                             \
+      ar1[ST] = *reinterpret_cast<const u4*>(Wb + (int64_t)(m0 + r_ + 32) * row_bytes + (C) * kChunkBytes +      \
+                                                seg_ * 16);                                                  \
+  }
+#define SC_LOAD_B(C, ST)                                                                                     \
+  {                                                                                                          \
+    _Pragma("unroll") for (int p_ = 0; p_ < B_PIECES; ++p_) {                                                \
+      const ColInfo& cc_ = cols[my_col0 + p_ * (kThreads / PPCOL)];                                          \
+      int where_ = 0;                                                                                        \
+      int64_t off_ = 0;                                                                                      \
+      if (cc_.ei >= 0) {                                                                                     \
+        if (CONVT) {                                                                                         \
+          const int kk_ = (C) * KC + my_pp * EPP;                                                            \
+          const int h_ = kk_ >= half_pad;                                                                    \
+          const int ci_ = kk_ - h_ * half_pad;                                                               \
+          const int row_ = cc_.t - 1 + h_;                                                                   \
+          if (ci_ < a.cin && row_ >= 0 && row_ < cc_.Tin) {                                                  \
+            where_ = 1;                                                                                      \
+            off_ = ((int64_t)cc_.in_start + row_) * a.cin + ci_;                                             \
+          }                                                                                                  \
+        } else if ((C) * KC + my_pp * EPP < Kreal) {                                                         \
+          const int row_ = cc_.t + a.dil * k_tap;                                                            \
+          if (row_ < a.L) {                                                                                  \
+            where_ = 2;                                                                                      \
+            off_ = (int64_t)row_ * a.cin + k_ci;                                                             \
+          } else {                                                                                           \
+            where_ = 1;                                                                                      \
+            off_ = ((int64_t)cc_.in_start + row_ - a.L) * a.cin + k_ci;                                      \
+          }                                                                                                  \
+        }                                                                                                    \
+      }                                                                                                      \
+      if constexpr (INTWIN) {                                                                                \
+        const unsigned char* base_ = where_ == 2 ? cc_.tcache : static_cast<const unsigned char*>(a.in_twin); \
+        tb[ST][p_] = where_ ? *reinterpret_cast<const u4*>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};    \
+      } else {                                                                                               \
+        const float* base_ = where_ == 2 ? cc_.cache : a.in_buf;                                             \
+        rb[ST][p_] = where_ ? *reinterpret_cast<const f4*>(base_ + off_) : f4{0.f, 0.f, 0.f, 0.f};           \
+      }                                                                                                      \
+    }                                                                                                        \
+    if (!CONVT) {                                                                                            \
+      k_ci += KC;                                                                                            \
+      while (k_ci >= a.cin) {                                                                                \
+        k_ci -= a.cin;                                                                                       \
+        ++k_tap;                                                                                             \
+      }                                                                                                      \
+    }                                                                                                        \
+  }
+#define SC_STORE(BUF, ST)                                                                                    \
+  {                                                                                                          \
+    const int r_ = tid >> 3, seg_ = tid & 7;                                                                 \
+    *reinterpret_cast<u4*>(&lds_a[BUF][r_ * kRowStride + seg_ * 16]) = ar0[ST];                           \
+    if constexpr (A_PIECES == 2) *reinterpret_cast<u4*>(&lds_a[BUF][(r_ + 32) * kRowStride + seg_ * 16]) = ar1[ST]; \
+    _Pragma("unroll") for (int p_ = 0; p_ < B_PIECES; ++p_) {                                                \
+      const int col_ = my_col0 + p_ * (kThreads / PPCOL);                                                    \
+      unsigned char* dst_ = &lds_b[BUF][col_ * kRowStride + my_pp * EPP * ES];                               \
+      if constexpr (INTWIN) {                                                                                \
+        *reinterpret_cast<u4*>(dst_) = tb[ST][p_];                                                        \
+      } else {                                                                                               \
+        f4 v_ = rb[ST][p_];                                                                                  \
+        if (pre) {                                                                                           \
+          v_.x = lrelu(v_.x);                                                                                \
+          v_.y = lrelu(v_.y);                                                                                \
+          v_.z = lrelu(v_.z);                                                                                \
+          v_.w = lrelu(v_.w);                                                                                \
+        }                                                                                                    \
+        store4<PREC>(dst_, v_.x * qs, v_.y * qs, v_.z * qs, v_.w * qs);                                      \
+      }                                                                                                      \
+    }                                                                                                        \
+  }
+
+  // the weight pieces do not depend on the columns: start them first
+  // (stages written out: the stage registers need compile-time indices)
+  SC_LOAD_A(0, 0)
+  if (1 < n_chunks) SC_LOAD_A(1, 1)
+  if constexpr (STAGES > 2) {
+    if (2 < n_chunks) SC_LOAD_A(2, 2)
+    if (3 < n_chunks) SC_LOAD_A(3, 3)
+  }
+
+  if (tid < NT) cols[tid] = make_col<CONVT>(a, n0 + tid, n_cols);
+  __syncthreads();
+
+  // K position of this thread's B piece, advanced chunk by chunk without
+  // division (chunks are gathered in increasing order)
+  int k_tap = 0, k_ci = 0;
+  if (!CONVT) {
+    const int kk0 = my_pp * EPP;
+    k_tap = kk0 / a.cin;
+    k_ci = kk0 - k_tap * a.cin;
+  }
+  SC_LOAD_B(0, 0)
+  if (1 < n_chunks) SC_LOAD_B(1, 1)
+  if constexpr (STAGES > 2) {
+    if (2 < n_chunks) SC_LOAD_B(2, 2)
+    if (3 < n_chunks) SC_LOAD_B(3, 3)
+  }
 
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -368,30 +386,45 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
     }
   }
 
-  load_chunk(0);
-  for (int c = 0; c < n_chunks; ++c) {
-    const int buf = c & 1;
-    store_chunk(buf);
-    __syncthreads();
-    if (c + 1 < n_chunks) load_chunk(c + 1);
-    Frag fa[2], fb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const unsigned char* p = &lds_a[buf][(wm * 32 + i * 16 + lr) * kRowStride + lg * 32];
-      fa[i].lo = *reinterpret_cast<const uint4*>(p);
-      fa[i].hi = *reinterpret_cast<const uint4*>(p + 16);
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const unsigned char* p = &lds_b[buf][(wn * 32 + j * 16 + lr) * kRowStride + lg * 32];
-      fb[j].lo = *reinterpret_cast<const uint4*>(p);
-      fb[j].hi = *reinterpret_cast<const uint4*>(p + 16);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_chunk<PREC>(fa[i], fb[j], acc[i][j]);
+#define SC_STAGE(ST)                                                                                         \
+  {                                                                                                          \
+    const int c = c0 + (ST);                                                                                 \
+    if (c < n_chunks) {                                                                                      \
+      const int buf = c & 1;                                                                                 \
+      SC_STORE(buf, ST)                                                                                      \
+      __syncthreads();                                                                                       \
+      if (c + STAGES < n_chunks) {                                                                           \
+        SC_LOAD_A(c + STAGES, ST)                                                                            \
+        SC_LOAD_B(c + STAGES, ST)                                                                            \
+      }                                                                                                      \
+      Frag fa[2], fb[2];                                                                                     \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                        \
+        const unsigned char* p = &lds_a[buf][(wm * 32 + i * 16 + lr) * kRowStride + lg * 32];               \
+        fa[i].lo = *reinterpret_cast<const u4*>(p);                                                       \
+        fa[i].hi = *reinterpret_cast<const u4*>(p + 16);                                                  \
+      }                                                                                                      \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                                        \
+        const unsigned char* p = &lds_b[buf][(wn * 32 + j * 16 + lr) * kRowStride + lg * 32];               \
+        fb[j].lo = *reinterpret_cast<const u4*>(p);                                                       \
+        fb[j].hi = *reinterpret_cast<const u4*>(p + 16);                                                  \
+      }                                                                                                      \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i)                                                          \
+        _Pragma("unroll") for (int j = 0; j < 2; ++j) acc[i][j] = mfma_chunk<PREC>(fa[i], fb[j], acc[i][j]); \
+    }                                                                                                        \
   }
+  for (int c0 = 0; c0 < n_chunks; c0 += STAGES) {
+    SC_STAGE(0)
+    SC_STAGE(1)
+    if constexpr (STAGES > 2) {
+      SC_STAGE(2)
+      SC_STAGE(3)
+    }
+  }
+#undef SC_STAGE
+
+#undef SC_LOAD_A
+#undef SC_LOAD_B
+#undef SC_STORE
 
   // ---- epilogue: lane holds rows m..m+3 of column n for each (i, j) ----
 #pragma unroll
