@@ -23,7 +23,8 @@ struct LayerArgs {
   float act_scale;         // FP8: static activation scale (amax / 448)
   int32_t cin, cout, k, dil, stride, L, pre_act, post_act, residual, skip_off;
   int32_t A0, A1;
-  int64_t in_num, in_den, out_num, out_den;
+  uint32_t in_num, in_den, out_num, out_den;   // frames per input frame of input / output
+  FastDiv fd_in_num, fd_in_den, fd_out_num, fd_out_den, fd_cin, fd_cout;
   int64_t delay;           // output lag (frames at the output rate) for the warm-up mask
   int64_t state_off, state_len, state_off2, state_len2;
   int64_t n_in;            // total input frames of the step at the input rate
@@ -37,6 +38,19 @@ struct LayerArgs {
   int32_t twin_prec;
   int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
 };
+
+// ---- rate arithmetic without run-time division ----
+// frames of the input / output rate for x input frames of the step
+__device__ inline int32_t in_frames(const LayerArgs& a, int32_t x) { return (int32_t)fdiv(a.fd_in_den, (uint32_t)x * a.in_num); }
+__device__ inline int32_t out_frames(const LayerArgs& a, int32_t x) { return (int32_t)fdiv(a.fd_out_den, (uint32_t)x * a.out_num); }
+// stream (entry) of packed frame n at the input / output rate
+__device__ inline int entry_of_in(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_in_num, (uint32_t)n * a.in_den)]; }
+__device__ inline int entry_of_out(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_out_num, (uint32_t)n * a.out_den)]; }
+// warm-up mask of local output frame t of stream e: pos*num/den + t < delay,
+// compared exactly as pos*num + t*den < delay*den
+__device__ inline bool masked(const LayerArgs& a, const Entry& e, int64_t t) {
+  return (e.flags & SC_FLAG_WARMUP_MASK) && ((int64_t)e.pos * a.out_num + t * a.out_den < a.delay * (int64_t)a.out_den);
+}
 
 // Frames per block for the LDS-staged narrow conv (0 if its window does not fit).
 int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint);

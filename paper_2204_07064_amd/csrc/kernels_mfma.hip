@@ -110,7 +110,7 @@ struct ColInfo {
 };
 
 template <bool CONVT>
-__device__ inline ColInfo make_col(const LayerArgs& a, int64_t n, int64_t n_cols) {
+__device__ inline ColInfo make_col(const LayerArgs& a, int32_t n, int32_t n_cols) {
   ColInfo c;
   c.cache = nullptr;
   c.tcache = nullptr;
@@ -120,42 +120,20 @@ __device__ inline ColInfo make_col(const LayerArgs& a, int64_t n, int64_t n_cols
   c.Tin = 0;
   if (n >= n_cols) return c;
   int ei;
-  if (CONVT) ei = n < a.n_in ? entry_at(a.fent, n, a.in_num, a.in_den) : (int)(n - a.n_in);
-  else ei = entry_at(a.fent, n, a.out_num, a.out_den);
+  if (CONVT) ei = n < a.n_in ? entry_of_in(a, n) : n - (int32_t)a.n_in;
+  else ei = entry_of_out(a, n);
   const Entry& e = a.ents[ei];
   c.ei = ei;
-  c.in_start = (int32_t)at_rate(e.off, a.in_num, a.in_den);
-  c.Tin = (int32_t)at_rate(e.T, a.in_num, a.in_den);
+  c.in_start = in_frames(a, e.off);
+  c.Tin = in_frames(a, e.T);
+  c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;   // conv cache / convt carry copy
   if (CONVT) {
-    c.t = n < a.n_in ? (int32_t)(n - c.in_start) : c.Tin;
-    c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;   // carry copy
+    c.t = n < a.n_in ? n - c.in_start : c.Tin;
   } else {
-    c.t = (int32_t)(n - at_rate(e.off, a.out_num, a.out_den));
-    c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+    c.t = n - out_frames(a, e.off);
     c.tcache = reinterpret_cast<const unsigned char*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len);
   }
   return c;
-}
-
-// Source of 4 consecutive K elements (kk .. kk + 3) of a column: raw FP32
-// input channels, or null for padding / absent frames.
-template <bool CONVT>
-__device__ inline const float* src4(const LayerArgs& a, const ColInfo& c, int kk, int Kreal, int half_pad) {
-  if (c.ei < 0) return nullptr;
-  if (CONVT) {
-    // K layout: [h = 0: half_pad][h = 1: half_pad], real channels first in each half
-    const int h = kk >= half_pad;
-    const int ci = kk - h * half_pad;
-    const int row = c.t - 1 + h;
-    if (ci >= a.cin || row < 0 || row >= c.Tin) return nullptr;
-    return a.in_buf + ((int64_t)c.in_start + row) * a.cin + ci;
-  }
-  if (kk >= Kreal) return nullptr;
-  const int tap = kk / a.cin;
-  const int ci = kk - tap * a.cin;
-  const int row = c.t + a.dil * tap;
-  if (row < a.L) return c.cache + (int64_t)row * a.cin + ci;
-  return a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin + ci;
 }
 
 template <int PREC>
@@ -186,9 +164,9 @@ __device__ inline void store_twin4(const LayerArgs& a, int64_t o, f4 v) {
 }
 
 template <int PREC, int MT, int NT, bool CONVT, bool INTWIN>
-__global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_cols, int n_mt, int n_nt,
+__global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_cols, int n_mt, int n_nt,
                                                         int Kpad, int Kreal, int half_pad, int Mreal,
-                                                        int extra_blocks) {
+                                                        int extra_blocks, FastDiv fd_per_ent) {
   constexpr int KC = Prec<PREC>::kKc;
   constexpr int ES = Prec<PREC>::kEsize;
   constexpr int WM = MT / 32;                   // waves along M
@@ -201,46 +179,46 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   __shared__ ColInfo cols[NT];
 
   const int tid = threadIdx.x;
-  const int64_t n_tiles = (int64_t)n_mt * n_nt;
+  const int32_t n_tiles = n_mt * n_nt;
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs; remap so
   // that the M tiles of one column tile (which share B) run on one XCD's L2.
-  int64_t bid = blockIdx.x;
+  int32_t bid = blockIdx.x;
   {
-    const int64_t G = n_tiles;
-    const int64_t full = G / 8 * 8;
+    const int32_t full = n_tiles / 8 * 8;
     if (bid < full) bid = (bid % 8) * (full / 8) + bid / 8;
   }
   // ---- conv cache update blocks (after the GEMM tiles) ----
   if (!CONVT && bid >= n_tiles) {
-    const int64_t per_ent = (int64_t)a.L * a.cin;
-    const int64_t total = (int64_t)a.n_ent * per_ent;
-    for (int64_t j = (bid - n_tiles) * kThreads + tid; j < total; j += (int64_t)extra_blocks * kThreads) {
-      const int ei = (int)(j / per_ent);
-      const int64_t rem = j % per_ent;
-      const int64_t i = rem / a.cin;
-      const int ci = (int)(rem % a.cin);
+    const int32_t per_ent = a.L * a.cin;
+    const int32_t total = a.n_ent * per_ent;
+    for (int32_t j = (bid - n_tiles) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
+      const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
+      const int32_t rem = j - ei * per_ent;
+      const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
+      const int ci = rem - i * a.cin;
       const Entry& e = a.ents[ei];
-      const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-      const int64_t row = Tin + i;
+      const int32_t Tin = in_frames(a, e.T);
+      const int32_t row = Tin + i;
+      const int64_t src_in = ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
       float v;
-      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + row * a.cin + ci];
-      else v = a.in_buf[(at_rate(e.off, a.in_num, a.in_den) + row - a.L) * a.cin + ci];
-      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = v;
+      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci];
+      else v = a.in_buf[src_in];
+      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = v;
       if (INTWIN) {
         typedef typename Prec<PREC>::Elem T;
         const T* src = row < a.L
-            ? reinterpret_cast<const T*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len) + row * a.cin + ci
-            : static_cast<const T*>(a.in_twin) + (at_rate(e.off, a.in_num, a.in_den) + row - a.L) * a.cin + ci;
+            ? reinterpret_cast<const T*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len) + (int64_t)row * a.cin + ci
+            : static_cast<const T*>(a.in_twin) + src_in;
         T* dst = reinterpret_cast<T*>(e.state + a.tstate_off + (int64_t)(1 - e.parity) * a.tstate_len);
-        dst[i * a.cin + ci] = *src;
+        dst[(int64_t)i * a.cin + ci] = *src;
       }
     }
     return;
   }
-  const int mt = (int)(bid % n_mt);
-  const int64_t nt = bid / n_mt;
+  const int mt = (int)((uint32_t)bid % (uint32_t)n_mt);
+  const int32_t nt = (int32_t)((uint32_t)bid / (uint32_t)n_mt);
   const int m0 = mt * MT;
-  const int64_t n0 = nt * NT;
+  const int32_t n0 = nt * NT;
 
   const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
   const int row_bytes = Kpad * ES;
@@ -355,7 +333,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
   int k_tap = 0, k_ci = 0;
   if (!CONVT) {
     const int kk0 = my_pp * EPP;
-    k_tap = kk0 / a.cin;
+    k_tap = (int)fdiv(a.fd_cin, (uint32_t)kk0);
     k_ci = kk0 - k_tap * a.cin;
   }
   SC_LOAD_B(0, 0)
@@ -432,7 +410,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
     const ColInfo& c = cols[wn * 32 + j * 16 + lr];
     if (c.ei < 0) continue;
     const Entry& e = a.ents[c.ei];
-    const int64_t n = n0 + wn * 32 + j * 16 + lr;
+    const int32_t n = n0 + wn * 32 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int m = m0 + wm * 32 + i * 16 + lg * 4;
@@ -450,12 +428,11 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
           *reinterpret_cast<f4*>(carry_out + m) = acc[i][j];
           continue;
         }
-        const int co = m % a.cout;
-        const int phi = m / a.cout;
+        const int phi = (int)fdiv(a.fd_cout, (uint32_t)m);
+        const int co = m - phi * a.cout;
         v = v + *reinterpret_cast<const f4*>(a.B + co);
-        const int64_t t = (int64_t)c.t * a.stride + phi;
-        if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay)
-          v = f4{0.f, 0.f, 0.f, 0.f};
+        const int32_t t = c.t * a.stride + phi;
+        if (masked(a, e, t)) v = f4{0.f, 0.f, 0.f, 0.f};
         const int64_t o = ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m;
         *reinterpret_cast<f4*>(a.out_buf + o) = v;
         if (a.out_twin) store_twin4<PREC>(a, o, v);
@@ -467,10 +444,9 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int64_t n_c
                                       : a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin;
           v = v + *reinterpret_cast<const f4*>(sp + m);
         }
-        if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + c.t < a.delay)
-          v = f4{0.f, 0.f, 0.f, 0.f};
-        *reinterpret_cast<f4*>(a.out_buf + n * a.cout + m) = v;
-        if (a.out_twin) store_twin4<PREC>(a, n * a.cout + m, v);
+        if (masked(a, e, c.t)) v = f4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f4*>(a.out_buf + (int64_t)n * a.cout + m) = v;
+        if (a.out_twin) store_twin4<PREC>(a, (int64_t)n * a.cout + m, v);
       }
     }
   }
@@ -559,8 +535,9 @@ hipError_t launch_t(const LayerArgs& a, int64_t n_cols, int Kpad, int Kreal, int
   }
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT, INTWIN>), dim3((unsigned)grid), dim3(kThreads), 0, s, a, n_cols,
-                     n_mt, (int)n_nt, Kpad, Kreal, half_pad, M, extra);
+  hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT, INTWIN>), dim3((unsigned)grid), dim3(kThreads), 0, s, a,
+                     (int32_t)n_cols, n_mt, (int)n_nt, Kpad, Kreal, half_pad, M, extra,
+                     make_fastdiv((uint32_t)std::max(a.L * a.cin, 1)));
   return hipGetLastError();
 }
 

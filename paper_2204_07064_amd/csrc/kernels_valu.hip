@@ -32,56 +32,56 @@ struct Row {
   int64_t cs;
 };
 
-__device__ inline Row window_row(const Entry& e, int64_t in_start, int64_t Tin, int64_t row, int32_t L,
+__device__ inline Row window_row(const Entry& e, int32_t in_start, int32_t Tin, int32_t row, int32_t L,
                                  int64_t soff, int64_t slen, const float* buf, int32_t C) {
-  if (row < L) return Row{e.state + soff + (int64_t)e.parity * slen + row * C, 1};
-  const int64_t r = row - L;
-  if (buf) return Row{buf + (in_start + r) * C, 1};
+  if (row < L) return Row{e.state + soff + (int64_t)e.parity * slen + (int64_t)row * C, 1};
+  const int32_t r = row - L;
+  if (buf) return Row{buf + ((int64_t)in_start + r) * C, 1};
   return Row{e.in + r, Tin};  // user input, channel-major
 }
 
 // New cache of a conv = window rows [Tin, Tin + L), into the other copy.
-__device__ inline void cache_item(const LayerArgs& a, int64_t j) {
-  const int64_t per_ent = (int64_t)a.L * a.cin;
-  const int ei = (int)(j / per_ent);
-  const int64_t rem = j % per_ent;
-  const int64_t i = rem / a.cin;
-  const int ci = (int)(rem % a.cin);
-  const Entry e = a.ents[ei];
-  const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-  const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
+// Item j of the step's cache items: entry j / (L*cin), row, channel.
+__device__ inline void cache_item(const LayerArgs& a, const FastDiv& fd_per_ent, int32_t j) {
+  const int32_t per_ent = a.L * a.cin;
+  const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
+  const int32_t rem = j - ei * per_ent;
+  const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
+  const int ci = rem - i * a.cin;
+  const Entry& e = a.ents[ei];
+  const int32_t in_start = in_frames(a, e.off);
+  const int32_t Tin = in_frames(a, e.T);
   const Row rw = window_row(e, in_start, Tin, Tin + i, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
-  e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + i * a.cin + ci] = rw.p[ci * rw.cs];
+  e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = rw.p[ci * rw.cs];
 }
 
-__device__ inline float finish(const LayerArgs& a, const Entry& e, int64_t t, float acc) {
+__device__ inline float finish(const LayerArgs& a, const Entry& e, int32_t t, float acc) {
   if (a.post_act == 2) acc = tanhf(acc);
-  if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) acc = 0.f;
+  if (masked(a, e, t)) acc = 0.f;
   return acc;
 }
 
 // Per-item conv: one lane per output value (used when the LDS window of the
 // narrow kernel would not fit).  Grid-stride over outputs, then cache items.
-__global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a) {
-  const int64_t n_items = a.n_out * a.cout;
-  const int64_t total = n_items + (int64_t)a.n_ent * a.L * a.cin;
+__global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a, FastDiv fd_per_ent) {
+  const int32_t n_items = (int32_t)a.n_out * a.cout;
+  const int32_t total = n_items + a.n_ent * a.L * a.cin;
   const float* W = static_cast<const float*>(a.W);
-  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kBlock) {
+  for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     if (idx >= n_items) {
-      cache_item(a, idx - n_items);
+      cache_item(a, fd_per_ent, idx - n_items);
       continue;
     }
-    const int co = (int)(idx % a.cout);
-    const int64_t n = idx / a.cout;
-    const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
-    const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-    const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-    const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
+    const int32_t n = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
+    const int co = idx - n * a.cout;
+    const Entry& e = a.ents[entry_of_out(a, n)];
+    const int32_t in_start = in_frames(a, e.off);
+    const int32_t Tin = in_frames(a, e.T);
+    const int32_t t = n - out_frames(a, e.off);
     float acc = a.B[co];
     for (int kk = 0; kk < a.k; ++kk) {
-      const Row rw = window_row(e, in_start, Tin, t * a.stride + (int64_t)a.dil * kk, a.L, a.state_off,
-                                a.state_len, a.in_buf, a.cin);
+      const Row rw = window_row(e, in_start, Tin, t * a.stride + a.dil * kk, a.L, a.state_off, a.state_len,
+                                a.in_buf, a.cin);
       const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
       for (int ci = 0; ci < a.cin; ++ci) {
         float x = rw.p[ci * rw.cs];
@@ -95,10 +95,10 @@ __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a) {
     }
     acc = finish(a, e, t, acc);
     if (a.out_buf) {
-      a.out_buf[n * a.cout + co] = acc;
-      if (a.out_twin) store_twin1(a.out_twin, n * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+      a.out_buf[(int64_t)n * a.cout + co] = acc;
+      if (a.out_twin) store_twin1(a.out_twin, (int64_t)n * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
     } else {
-      e.out[(int64_t)co * at_rate(e.T, a.out_num, a.out_den) + t] = acc;
+      e.out[(int64_t)co * out_frames(a, e.T) + t] = acc;
     }
   }
 }
@@ -144,7 +144,7 @@ __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int
         const int v = v0 + u * kBlock + tid;
         if (v >= total4) break;
         const int e0 = v * 4;
-        const int j = e0 / a.cin, ci = e0 - j * a.cin;
+        const int j = (int)fdiv(a.fd_cin, (uint32_t)e0), ci = e0 - j * a.cin;
         float* d = xs + j * ld + ci;
         const f4v x = buf[u];
         d[0] = a.pre_act ? lrelu(x.x) : x.x;
@@ -163,17 +163,9 @@ __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int
       const int idx = v0 + u * kBlock + tid;
       float v = 0.f;
       if (idx < total) {
-        // time fastest: coalesced reads of channel-major user input
-        const int ci = idx / rows, j = idx - ci * rows;
+        const int j = (int)fdiv(a.fd_cin, (uint32_t)idx), ci = idx - j * a.cin;
         const int64_t p = p0 + j;
-        if (p >= 0 && p < a.n_in) {
-          if (a.in_buf) {
-            v = a.in_buf[p * a.cin + ci];
-          } else {
-            const Entry& e = a.ents[entry_at(a.fent, p, a.in_num, a.in_den)];
-            v = e.in[(int64_t)ci * at_rate(e.T, a.in_num, a.in_den) + (p - at_rate(e.off, a.in_num, a.in_den))];
-          }
-        }
+        if (p >= 0 && p < a.n_in) v = a.in_buf[p * a.cin + ci];
       }
       buf[u] = v;
     }
@@ -181,13 +173,13 @@ __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int
     for (int u = 0; u < kStageUnroll; ++u) {
       const int idx = v0 + u * kBlock + tid;
       if (idx >= total) break;
-      const int ci = idx / rows, j = idx - ci * rows;
+      const int j = (int)fdiv(a.fd_cin, (uint32_t)idx), ci = idx - j * a.cin;
       xs[j * ld + ci] = a.pre_act ? lrelu(buf[u]) : buf[u];
     }
   }
 }
 
-__device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int64_t n0, int F) {
+__device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int32_t n0, int F) {
   for (int i = threadIdx.x; i < F; i += kBlock) {
     FrameInfo f;
     f.cache = nullptr;
@@ -196,17 +188,17 @@ __device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int64_t n0
     f.tout = 0;
     f.masked = 0;
     f.ei = -1;
-    const int64_t n = n0 + i;
+    const int32_t n = n0 + i;
     if (n < a.n_out) {
-      const int ei = entry_at(a.fent, n, a.out_num, a.out_den);
+      const int ei = entry_of_out(a, n);
       const Entry& e = a.ents[ei];
-      const int64_t t = n - at_rate(e.off, a.out_num, a.out_den);
+      const int32_t t = n - out_frames(a, e.off);
       f.ei = ei;
-      f.t = (int32_t)t;
-      f.tout = (int32_t)at_rate(e.T, a.out_num, a.out_den);
+      f.t = t;
+      f.tout = out_frames(a, e.T);
       f.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
       f.out = e.out + t;
-      f.masked = (e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay;
+      f.masked = masked(a, e, t);
     }
     fi[i] = f;
   }
@@ -214,24 +206,22 @@ __device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int64_t n0
 
 // Raw (not activated) skip value of window row t + skip_off, channel co.
 __device__ inline float skip_value(const LayerArgs& a, const FrameInfo& f, int co) {
-  const int64_t row = f.t + a.skip_off;
-  if (row < a.L) return f.cache[row * a.cin + co];
+  const int32_t row = f.t + a.skip_off;
+  if (row < a.L) return f.cache[(int64_t)row * a.cin + co];
   const Entry& e = a.ents[f.ei];
-  const int64_t r = row - a.L;
-  const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-  if (a.in_buf) return a.in_buf[(in_start + r) * a.cin + co];
-  return e.in[(int64_t)co * at_rate(e.T, a.in_num, a.in_den) + r];
+  return a.in_buf[((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + co];
 }
 
 // Frame-parallel variant (few output channels): one lane per output frame,
 // looping over the output channels; weights staged in LDS.
-__global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int64_t n_tiles, int extra_blocks) {
+__global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_t n_tiles, int extra_blocks,
+                                                             FastDiv fd_per_ent) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
-  if ((int64_t)blockIdx.x >= n_tiles) {
-    const int64_t total = (int64_t)a.n_ent * a.L * a.cin;
-    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += (int64_t)extra_blocks * kBlock)
-      cache_item(a, j);
+  if ((int32_t)blockIdx.x >= n_tiles) {
+    const int32_t total = a.n_ent * a.L * a.cin;
+    for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
+      cache_item(a, fd_per_ent, j);
     return;
   }
   const int F = a.tile, S = a.stride, ld = a.cin | 1;
@@ -240,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int64_
   float* ws = smem;                                   // [k][cin][cout]
   FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem + ((nw + 3) & ~3));
   float* xs = reinterpret_cast<float*>(fi + F);
-  const int64_t n0 = (int64_t)blockIdx.x * F;
+  const int32_t n0 = (int32_t)blockIdx.x * F;
   const float* W = static_cast<const float*>(a.W);
   for (int i = tid; i < nw; i += kBlock) ws[i] = W[i];
   frame_infos(a, fi, n0, F);
@@ -284,20 +274,21 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int64_
 // registers (cin <= CMAX, k <= KMAX) and walks the block's frames; input rows
 // are LDS broadcasts.
 template <int CMAX, int KMAX>
-__global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int64_t n_tiles, int extra_blocks) {
+__global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t n_tiles, int extra_blocks,
+                                                            FastDiv fd_per_ent) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
-  if ((int64_t)blockIdx.x >= n_tiles) {
-    const int64_t total = (int64_t)a.n_ent * a.L * a.cin;
-    for (int64_t j = ((int64_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += (int64_t)extra_blocks * kBlock)
-      cache_item(a, j);
+  if ((int32_t)blockIdx.x >= n_tiles) {
+    const int32_t total = a.n_ent * a.L * a.cin;
+    for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
+      cache_item(a, fd_per_ent, j);
     return;
   }
   const int F = a.tile, S = a.stride, ld = a.cin | 1;
   const int rows = F * S + a.L;
   FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem);
   float* xs = reinterpret_cast<float*>(fi + F);
-  const int64_t n0 = (int64_t)blockIdx.x * F;
+  const int32_t n0 = (int32_t)blockIdx.x * F;
   frame_infos(a, fi, n0, F);
   stage_rows(a, xs, n0 * S - a.L, rows, ld);
   __syncthreads();
@@ -351,16 +342,17 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int64_t
 // Channel-major user input [C][T] of every stream -> packed channels-last
 // [frame][C] for the step.
 __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, int32_t C,
-                                                           int64_t n_frames, float* out, void* twin, int32_t twin_prec,
-                                                           int32_t twin_pre, float twin_qs) {
-  const int64_t total = n_frames * C;
-  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
-    const int64_t f = idx % n_frames;   // frame fastest: coalesced reads of each channel row
-    const int c = (int)(idx / n_frames);
+                                                           int32_t n_frames, FastDiv fd_frames, float* out,
+                                                           void* twin, int32_t twin_prec, int32_t twin_pre,
+                                                           float twin_qs) {
+  const int32_t total = n_frames * C;
+  for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
+    const int c = (int)fdiv(fd_frames, (uint32_t)idx);   // frame fastest: coalesced reads of each channel row
+    const int32_t f = idx - c * n_frames;
     const Entry& e = ents[fent[f]];
     const float v = e.in[(int64_t)c * e.T + (f - e.off)];
-    out[f * C + c] = v;
-    if (twin) store_twin1(twin, f * C + c, twin_prec, twin_pre, twin_qs, v);
+    out[(int64_t)f * C + c] = v;
+    if (twin) store_twin1(twin, (int64_t)f * C + c, twin_prec, twin_pre, twin_qs, v);
   }
 }
 
@@ -371,44 +363,42 @@ __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, c
 // q = T: that is the FP32 overlap carry that column q = 0 of the next buffer
 // starts from, so the chain of fmaf is the same for every frame.
 // Weights packed [h][phi][cin][cout], h = 0 -> tap phi + r, h = 1 -> tap phi.
-__global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
+__global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv fd_r) {
   const int r = a.stride;
-  const int64_t n_cols = a.n_in + a.n_ent;
-  const int64_t total = n_cols * r * a.cout;
+  const int32_t n_cols = (int32_t)a.n_in + a.n_ent;
+  const int32_t total = n_cols * r * a.cout;
   const float* W = static_cast<const float*>(a.W);
-  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kBlock) {
-    const int co = (int)(idx % a.cout);
-    const int64_t rest = idx / a.cout;
-    const int phi = (int)(rest % r);
-    const int64_t c = rest / r;
-    const int ei = c < a.n_in ? entry_at(a.fent, c, a.in_num, a.in_den) : (int)(c - a.n_in);
-    const Entry e = a.ents[ei];
-    const int64_t in_start = at_rate(e.off, a.in_num, a.in_den);
-    const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-    const int64_t q = c < a.n_in ? c - in_start : Tin;
+  for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
+    const int32_t rest = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
+    const int co = idx - rest * a.cout;
+    const int32_t c = (int32_t)fdiv(fd_r, (uint32_t)rest);
+    const int phi = rest - c * r;
+    const int ei = c < a.n_in ? entry_of_in(a, c) : c - (int32_t)a.n_in;
+    const Entry& e = a.ents[ei];
+    const int32_t in_start = in_frames(a, e.off);
+    const int32_t Tin = in_frames(a, e.T);
+    const int32_t q = c < a.n_in ? c - in_start : Tin;
     const float* carry_in = e.state + a.state_off + (int64_t)e.parity * a.state_len;
     float acc = (q == 0) ? carry_in[phi * a.cout + co] : 0.f;
     for (int h = 0; h < 2; ++h) {
-      const int64_t row = q - 1 + h;
+      const int32_t row = q - 1 + h;
       if (row < 0 || row >= Tin) continue;
-      const float* x = a.in_buf ? a.in_buf + (in_start + row) * a.cin : e.in + row;
-      const int64_t xs = a.in_buf ? 1 : Tin;
+      const float* x = a.in_buf + ((int64_t)in_start + row) * a.cin;
       const float* wp = W + ((int64_t)(h * r + phi) * a.cin) * a.cout + co;
       if (a.pre_act) {
-        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], lrelu(x[ci * xs]), acc);
+        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], lrelu(x[ci]), acc);
       } else {
-        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], x[ci * xs], acc);
+        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[(int64_t)ci * a.cout], x[ci], acc);
       }
     }
     if (q < Tin) {
       float v = acc + a.B[co];
-      const int64_t t = q * r + phi;
-      if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
+      const int32_t t = q * r + phi;
+      if (masked(a, e, t)) v = 0.f;
       if (a.out_buf) {
-        a.out_buf[(in_start * r + t) * a.cout + co] = v;
-        if (a.out_twin)
-          store_twin1(a.out_twin, (in_start * r + t) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, v);
+        const int64_t o = ((int64_t)in_start * r + t) * a.cout + co;
+        a.out_buf[o] = v;
+        if (a.out_twin) store_twin1(a.out_twin, o, a.twin_prec, a.twin_pre, a.twin_qs, v);
       } else {
         e.out[(int64_t)co * (Tin * r) + t] = v;
       }
@@ -420,46 +410,45 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a) {
 
 // Sum of two branches, branch j delayed by A_j frames through a delay line
 // (Eq. 3).  Window of branch j: [line_j (A_j frames) | new frames].
-__global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a) {
+__global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a, FastDiv fd_per_ent) {
   const int C = a.cout;
-  const int64_t n_items = a.n_out * C;
-  const int64_t per_ent = (int64_t)(a.A0 + a.A1) * C;
-  const int64_t total = n_items + (int64_t)a.n_ent * per_ent;
-  for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kBlock) {
+  const int32_t n_items = (int32_t)a.n_out * C;
+  const int32_t per_ent = (a.A0 + a.A1) * C;
+  const int32_t total = n_items + a.n_ent * per_ent;
+  for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     if (idx < n_items) {
-      const int c = (int)(idx % C);
-      const int64_t n = idx / C;
-      const Entry e = a.ents[entry_at(a.fent, n, a.out_num, a.out_den)];
-      const int64_t start = at_rate(e.off, a.out_num, a.out_den);
-      const int64_t Tn = at_rate(e.T, a.out_num, a.out_den);
-      const int64_t t = n - start;
+      const int32_t n = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
+      const int c = idx - n * C;
+      const Entry& e = a.ents[entry_of_out(a, n)];
+      const int32_t start = out_frames(a, e.off);
+      const int32_t Tn = out_frames(a, e.T);
+      const int32_t t = n - start;
       const Row r0 = window_row(e, start, Tn, t, a.A0, a.state_off, a.state_len, a.in_buf, C);
       const Row r1 = window_row(e, start, Tn, t, a.A1, a.state_off2, a.state_len2, a.in_buf2, C);
       float v = r0.p[c * r0.cs] + r1.p[c * r1.cs];
-      if ((e.flags & SC_FLAG_WARMUP_MASK) && at_rate(e.pos, a.out_num, a.out_den) + t < a.delay) v = 0.f;
+      if (masked(a, e, t)) v = 0.f;
       if (a.out_buf) {
-        a.out_buf[n * C + c] = v;
-        if (a.out_twin) store_twin1(a.out_twin, n * C + c, a.twin_prec, a.twin_pre, a.twin_qs, v);
+        a.out_buf[(int64_t)n * C + c] = v;
+        if (a.out_twin) store_twin1(a.out_twin, (int64_t)n * C + c, a.twin_prec, a.twin_pre, a.twin_qs, v);
       } else {
         e.out[(int64_t)c * Tn + t] = v;
       }
     } else {
-      const int64_t j = idx - n_items;
-      const int ei = (int)(j / per_ent);
-      int64_t rem = j % per_ent;
-      const Entry e = a.ents[ei];
-      const int64_t start = at_rate(e.off, a.out_num, a.out_den);
-      const int64_t Tn = at_rate(e.T, a.out_num, a.out_den);
-      const bool second = rem >= (int64_t)a.A0 * C;
-      if (second) rem -= (int64_t)a.A0 * C;
-      const int64_t i = rem / C;
-      const int c = (int)(rem % C);
+      const int32_t j = idx - n_items;
+      const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
+      int32_t rem = j - ei * per_ent;
+      const Entry& e = a.ents[ei];
+      const int32_t start = out_frames(a, e.off);
+      const int32_t Tn = out_frames(a, e.T);
+      const bool second = rem >= a.A0 * C;
+      if (second) rem -= a.A0 * C;
+      const int32_t i = (int32_t)fdiv(a.fd_cout, (uint32_t)rem);
+      const int c = rem - i * C;
       const int32_t A = second ? a.A1 : a.A0;
       const int64_t soff = second ? a.state_off2 : a.state_off;
       const int64_t slen = second ? a.state_len2 : a.state_len;
       const Row rw = window_row(e, start, Tn, Tn + i, A, soff, slen, second ? a.in_buf2 : a.in_buf, C);
-      e.state[soff + (int64_t)(1 - e.parity) * slen + i * C + c] = rw.p[c * rw.cs];
+      e.state[soff + (int64_t)(1 - e.parity) * slen + (int64_t)i * C + c] = rw.p[c * rw.cs];
     }
   }
 }
@@ -470,16 +459,7 @@ __global__ void __launch_bounds__(kBlock) amax_kernel(LayerArgs a, float* amax) 
   const int64_t total = a.n_in * a.cin;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * kBlock) {
-    float v;
-    if (a.in_buf) {
-      v = a.in_buf[idx];
-    } else {
-      const int ci = (int)(idx % a.cin);
-      const int64_t n = idx / a.cin;
-      const Entry e = a.ents[entry_at(a.fent, n, a.in_num, a.in_den)];
-      const int64_t Tin = at_rate(e.T, a.in_num, a.in_den);
-      v = e.in[(int64_t)ci * Tin + (n - at_rate(e.off, a.in_num, a.in_den))];
-    }
+    float v = a.in_buf[idx];
     if (a.pre_act) v = lrelu(v);
     m = fmaxf(m, fabsf(v));
   }
@@ -535,7 +515,8 @@ hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
   const int kind = narrow_kind(a.cin, a.cout, a.k);
   if (a.tile <= 0 || kind == 0) {
     const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * a.L * a.cin;
-    hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a,
+                       make_fastdiv((uint32_t)std::max(a.L * a.cin, 1)));
     return hipGetLastError();
   }
   const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile;
@@ -543,31 +524,35 @@ hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
   const int extra = (int)std::min<int64_t>((cache_items + kBlock - 1) / kBlock, 1024);
   const size_t lds = narrow_lds(kind, a.tile, a.cin, a.cout, a.k, a.stride, a.L);
   if (n_tiles + extra == 0) return hipSuccess;
+  const FastDiv fpe = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
   if (kind == 1)
     hipLaunchKernelGGL((conv_chans_kernel<kChansC, kChansK>), dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds,
-                       s, a, n_tiles, extra);
+                       s, a, (int32_t)n_tiles, extra, fpe);
   else
-    hipLaunchKernelGGL(conv_frames_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a, n_tiles,
-                       extra);
+    hipLaunchKernelGGL(conv_frames_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a,
+                       (int32_t)n_tiles, extra, fpe);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
                              void* twin, int32_t twin_prec, int32_t twin_pre, float twin_qs, hipStream_t s) {
-  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n_frames * C)), dim3(kBlock), 0, s, ents, fent, C, n_frames,
-                     out, twin, twin_prec, twin_pre, twin_qs);
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n_frames * C)), dim3(kBlock), 0, s, ents, fent, C,
+                     (int32_t)n_frames, make_fastdiv((uint32_t)std::max<int64_t>(n_frames, 1)), out, twin, twin_prec,
+                     twin_pre, twin_qs);
   return hipGetLastError();
 }
 
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s) {
   const int64_t items = (a.n_in + a.n_ent) * a.stride * a.cout;
-  hipLaunchKernelGGL(convt_valu_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(convt_valu_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a,
+                     make_fastdiv((uint32_t)a.stride));
   return hipGetLastError();
 }
 
 hipError_t launch_delay_add(const LayerArgs& a, hipStream_t s) {
   const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * (a.A0 + a.A1) * a.cout;
-  hipLaunchKernelGGL(delay_add_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(delay_add_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a,
+                     make_fastdiv((uint32_t)std::max((a.A0 + a.A1) * a.cout, 1)));
   return hipGetLastError();
 }
 

@@ -184,8 +184,14 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.L = op.cache_len; a.pre_act = op.pre_act; a.post_act = op.post_act;
   a.residual = op.residual; a.skip_off = op.skip_off;
   a.A0 = op.A0; a.A1 = op.A1;
-  a.in_num = op.in_rate.num; a.in_den = op.in_rate.den;
-  a.out_num = op.out_rate.num; a.out_den = op.out_rate.den;
+  a.in_num = (uint32_t)op.in_rate.num; a.in_den = (uint32_t)op.in_rate.den;
+  a.out_num = (uint32_t)op.out_rate.num; a.out_den = (uint32_t)op.out_rate.den;
+  a.fd_in_num = make_fastdiv(a.in_num);
+  a.fd_in_den = make_fastdiv(a.in_den);
+  a.fd_out_num = make_fastdiv(a.out_num);
+  a.fd_out_den = make_fastdiv(a.out_den);
+  a.fd_cin = make_fastdiv((uint32_t)std::max(op.cin, 1));
+  a.fd_cout = make_fastdiv((uint32_t)std::max(op.cout, 1));
   a.delay = op.out_delay;
   a.state_off = op.state_off; a.state_len = op.state_len;
   a.state_off2 = op.state_off2; a.state_len2 = op.state_len2;

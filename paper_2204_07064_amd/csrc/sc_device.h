@@ -21,13 +21,36 @@ struct Entry {
   int64_t pos;       // input frames processed before this buffer
 };
 
-// Frames of `rate` (num/den per input frame) for t input frames.
-__device__ __host__ inline int64_t at_rate(int64_t t, int64_t num, int64_t den) { return t * num / den; }
+// Frames of `rate` (num/den per input frame) for t input frames (host side).
+__host__ __device__ inline int64_t at_rate(int64_t t, int64_t num, int64_t den) { return t * num / den; }
 
-// Entry of packed frame n at rate num/den: fent maps every input frame of the
-// step to its entry, and frame n of a layer lies in input frame n * den / num.
-__device__ inline int entry_at(const int32_t* fent, int64_t n, int64_t num, int64_t den) {
-  return fent[n * den / num];
+// Unsigned 32-bit division by a run-time invariant d as a multiply-high, add
+// and shift (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d)
+// + 1, n / d = (mulhi(n, m) + n) >> l for every 32-bit n (the add is done in 64
+// bits).  Device code never divides by a run-time value otherwise.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  f.s = l;
+  f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+  return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(const FastDiv& f, uint32_t n) {
+  if (f.d == 1) return n;
+#ifdef __HIP_DEVICE_COMPILE__
+  const uint32_t t = __umulhi(n, f.m);
+#else
+  const uint32_t t = (uint32_t)(((uint64_t)n * f.m) >> 32);
+#endif
+  return (uint32_t)(((uint64_t)t + n) >> f.s);
 }
 
 __device__ inline float lrelu(float v) { return v >= 0.f ? v : 0.2f * v; }
