@@ -25,6 +25,7 @@ struct LayerArgs {
   int32_t A0, A1;
   uint32_t in_num, in_den, out_num, out_den;   // frames per input frame of input / output
   FastDiv fd_in_num, fd_in_den, fd_out_num, fd_out_den, fd_cin, fd_cout;
+  FastDiv fd_per_ent_narrow;   // L * cin
   int64_t delay;           // output lag (frames at the output rate) for the warm-up mask
   int64_t state_off, state_len, state_off2, state_len2;
   int64_t n_in;            // total input frames of the step at the input rate

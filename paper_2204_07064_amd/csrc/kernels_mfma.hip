@@ -390,6 +390,31 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
         _Pragma("unroll") for (int j = 0; j < 2; ++j) acc[i][j] = mfma_chunk<PREC>(fa[i], fb[j], acc[i][j]); \
     }                                                                                                        \
   }
+  // epilogue operands (bias, FP8 row scales, residual skip rows) are fetched
+  // now so that their latency hides behind the K loop
+  f4 ep_bias[2], ep_ws[2], ep_skip[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = m0 + wm * 32 + i * 16 + lg * 4;
+    const bool ok = m < Mreal;
+    const int co = CONVT ? m - (int)fdiv(a.fd_cout, (uint32_t)m) * a.cout : m;
+    ep_bias[i] = ok ? *reinterpret_cast<const f4*>(a.B + co) : f4{0.f, 0.f, 0.f, 0.f};
+    ep_ws[i] = (PREC == 2 && ok) ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      ep_skip[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      if (!CONVT && ok && a.residual) {
+        const ColInfo& c = cols[wn * 32 + j * 16 + lr];
+        if (c.ei >= 0) {
+          const int row = c.t + a.skip_off;
+          const float* sp = row < a.L ? c.cache + (int64_t)row * a.cin
+                                      : a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin;
+          ep_skip[i][j] = *reinterpret_cast<const f4*>(sp + m);
+        }
+      }
+    }
+  }
+
   for (int c0 = 0; c0 < n_chunks; c0 += STAGES) {
     SC_STAGE(0)
     SC_STAGE(1)
@@ -416,10 +441,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
       const int m = m0 + wm * 32 + i * 16 + lg * 4;
       if (m >= Mreal) continue;
       f4 v = acc[i][j];
-      if (PREC == 2) {
-        const f4 ws = *reinterpret_cast<const f4*>(a.wscale + m);
-        v = v * (ws * a.act_scale);
-      }
+      if (PREC == 2) v = v * (ep_ws[i] * a.act_scale);
       if (CONVT) {
         if (c.t >= c.Tin) {
           // carry column: FP32 partial sums of the next buffer's first frame,
@@ -429,21 +451,15 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
           continue;
         }
         const int phi = (int)fdiv(a.fd_cout, (uint32_t)m);
-        const int co = m - phi * a.cout;
-        v = v + *reinterpret_cast<const f4*>(a.B + co);
+        v = v + ep_bias[i];
         const int32_t t = c.t * a.stride + phi;
         if (masked(a, e, t)) v = f4{0.f, 0.f, 0.f, 0.f};
         const int64_t o = ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m;
         *reinterpret_cast<f4*>(a.out_buf + o) = v;
         if (a.out_twin) store_twin4<PREC>(a, o, v);
       } else {
-        v = v + *reinterpret_cast<const f4*>(a.B + m);
-        if (a.residual) {
-          const int row = c.t + a.skip_off;
-          const float* sp = row < a.L ? c.cache + (int64_t)row * a.cin
-                                      : a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin;
-          v = v + *reinterpret_cast<const f4*>(sp + m);
-        }
+        v = v + ep_bias[i];
+        if (a.residual) v = v + ep_skip[i][j];
         if (masked(a, e, c.t)) v = f4{0.f, 0.f, 0.f, 0.f};
         *reinterpret_cast<f4*>(a.out_buf + (int64_t)n * a.cout + m) = v;
         if (a.out_twin) store_twin4<PREC>(a, (int64_t)n * a.cout + m, v);

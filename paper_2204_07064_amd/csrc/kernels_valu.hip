@@ -121,6 +121,25 @@ struct FrameInfo {
 };
 
 constexpr int kStageUnroll = 8;
+// Streams of a tile whose cache rows are staged in LDS (a tile spans
+// consecutive streams; beyond this many, later ones read their cache directly).
+constexpr int kCacheSlots = 8;
+
+// Stages the activated cache rows [0, L) of the tile's first kCacheSlots
+// streams e_first, e_first + 1, ... into cs (row stride ld).
+__device__ inline void stage_cache(const LayerArgs& a, float* cs, int e_first, int e_last, int ld) {
+  const int slots = min(e_last - e_first + 1, kCacheSlots);
+  const int per = a.L * a.cin;
+  for (int idx = threadIdx.x; idx < slots * per; idx += kBlock) {
+    const int s = (int)fdiv(a.fd_per_ent_narrow, (uint32_t)idx);
+    const int rem = idx - s * per;
+    const int w = (int)fdiv(a.fd_cin, (uint32_t)rem);
+    const int ci = rem - w * a.cin;
+    const Entry& e = a.ents[e_first + s];
+    const float v = e.state[a.state_off + (int64_t)e.parity * a.state_len + rem];
+    cs[(s * a.L + w) * ld + ci] = a.pre_act ? lrelu(v) : v;
+  }
+}
 
 // Stages rows [p0, p0 + rows) x cin (activated) into xs with row stride `ld`.
 __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int rows, int ld) {
@@ -230,11 +249,15 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   float* ws = smem;                                   // [k][cin][cout]
   FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem + ((nw + 3) & ~3));
   float* xs = reinterpret_cast<float*>(fi + F);
+  float* cs = xs + rows * ld;                          // cache rows of the tile's streams
   const int32_t n0 = (int32_t)blockIdx.x * F;
   const float* W = static_cast<const float*>(a.W);
+  const int e_first = entry_of_out(a, n0);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
   for (int i = tid; i < nw; i += kBlock) ws[i] = W[i];
   frame_infos(a, fi, n0, F);
-  stage_rows(a, xs, n0 * S - a.L, rows, ld);
+  stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
+  stage_cache(a, cs, e_first, e_last, ld);
   __syncthreads();
   for (int i = tid; i < F; i += kBlock) {
     const FrameInfo f = fi[i];
@@ -246,6 +269,9 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
         const float* wp = ws + kk * a.cin * a.cout + co;
         if (w >= a.L) {
           const float* x = xs + (i * S + a.dil * kk) * ld;
+          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
+        } else if (f.ei - e_first < kCacheSlots) {
+          const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
           for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
         } else {
           const float* x = f.cache + (int64_t)w * a.cin;
@@ -288,9 +314,13 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
   const int rows = F * S + a.L;
   FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem);
   float* xs = reinterpret_cast<float*>(fi + F);
+  float* cs = xs + rows * ld;                          // cache rows of the tile's streams
   const int32_t n0 = (int32_t)blockIdx.x * F;
+  const int e_first = entry_of_out(a, n0);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
   frame_infos(a, fi, n0, F);
-  stage_rows(a, xs, n0 * S - a.L, rows, ld);
+  stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
+  stage_cache(a, cs, e_first, e_last, ld);
   __syncthreads();
   const float* W = static_cast<const float*>(a.W);
   for (int co = tid; co < a.cout; co += kBlock) {
@@ -311,6 +341,11 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
         const int w = f.t * S + a.dil * kk;
         if (w >= a.L) {
           const float* x = xs + (i * S + a.dil * kk) * ld;
+#pragma unroll
+          for (int ci = 0; ci < CMAX; ++ci)
+            if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
+        } else if (f.ei - e_first < kCacheSlots) {
+          const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
 #pragma unroll
           for (int ci = 0; ci < CMAX; ++ci)
             if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
@@ -487,6 +522,7 @@ static int narrow_kind(int cin, int cout, int k) {
 
 static size_t narrow_lds(int kind, int F, int cin, int cout, int k, int stride, int L) {
   size_t b = (size_t)(F * stride + L) * (cin | 1) * sizeof(float) + (size_t)F * sizeof(FrameInfo);
+  b += (size_t)kCacheSlots * L * (cin | 1) * sizeof(float);
   if (kind == 2) b += (size_t)((k * cin * cout + 3) & ~3) * sizeof(float);
   return b;
 }

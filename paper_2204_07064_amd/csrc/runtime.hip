@@ -192,6 +192,7 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.fd_out_den = make_fastdiv(a.out_den);
   a.fd_cin = make_fastdiv((uint32_t)std::max(op.cin, 1));
   a.fd_cout = make_fastdiv((uint32_t)std::max(op.cout, 1));
+  a.fd_per_ent_narrow = make_fastdiv((uint32_t)std::max(op.cache_len * op.cin, 1));
   a.delay = op.out_delay;
   a.state_off = op.state_off; a.state_len = op.state_len;
   a.state_off2 = op.state_off2; a.state_len2 = op.state_len2;
