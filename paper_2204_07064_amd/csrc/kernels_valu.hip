@@ -295,13 +295,16 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   }
 }
 
-// Channel-parallel variant (many output channels, short reductions): each lane
-// owns output channels co = tid, tid + 256, ... with their weights in
-// registers (cin <= CMAX, k <= KMAX) and walks the block's frames; input rows
-// are LDS broadcasts.
+// Channel-parallel variant (many output channels, short reductions): a block
+// owns a tile of F frames and kChansCo output channels; the tile's weights are
+// staged in LDS with vector loads, then each lane keeps the weights of its
+// channel in registers (cin <= CMAX, k <= KMAX) and walks half of the frames;
+// input rows are LDS broadcasts.
+constexpr int kChansCo = 128;
+
 template <int CMAX, int KMAX>
 __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t n_tiles, int extra_blocks,
-                                                            FastDiv fd_per_ent) {
+                                                            FastDiv fd_per_ent, int n_ct) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   if ((int32_t)blockIdx.x >= n_tiles) {
@@ -312,64 +315,152 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
   }
   const int F = a.tile, S = a.stride, ld = a.cin | 1;
   const int rows = F * S + a.L;
-  FrameInfo* fi = reinterpret_cast<FrameInfo*>(smem);
+  const int kin = a.k * a.cin;
+  const int ct = (int)((uint32_t)blockIdx.x % (uint32_t)n_ct);
+  const int32_t n0 = (int32_t)((uint32_t)blockIdx.x / (uint32_t)n_ct) * F;
+  const int co0 = ct * kChansCo;
+  float* wsm = smem;                                   // [kin][kChansCo]
+  FrameInfo* fi = reinterpret_cast<FrameInfo*>(wsm + kin * kChansCo);
   float* xs = reinterpret_cast<float*>(fi + F);
   float* cs = xs + rows * ld;                          // cache rows of the tile's streams
-  const int32_t n0 = (int32_t)blockIdx.x * F;
   const int e_first = entry_of_out(a, n0);
   const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
+  {
+    // weight tile: rows q of W[q][cout] (q = tap * cin + ci), columns co0..co0+127
+    const float* W = static_cast<const float*>(a.W);
+    const int n4 = kin * (kChansCo / 4);
+    for (int v = tid; v < n4; v += kBlock) {
+      const int q = v >> 5, c4 = (v & 31) * 4;        // kChansCo / 4 == 32 vectors per row
+      f4v w = {0.f, 0.f, 0.f, 0.f};
+      if (co0 + c4 < a.cout) w = *reinterpret_cast<const f4v*>(W + (int64_t)q * a.cout + co0 + c4);
+      *reinterpret_cast<f4v*>(wsm + q * kChansCo + c4) = w;
+    }
+  }
   frame_infos(a, fi, n0, F);
   stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
   stage_cache(a, cs, e_first, e_last, ld);
   __syncthreads();
-  const float* W = static_cast<const float*>(a.W);
-  for (int co = tid; co < a.cout; co += kBlock) {
-    float wr[KMAX][CMAX];
+  const int cl = tid & (kChansCo - 1);
+  const int co = co0 + cl;
+  if (co >= a.cout) return;
+  float wr[KMAX][CMAX];
 #pragma unroll
-    for (int kk = 0; kk < KMAX; ++kk)
+  for (int kk = 0; kk < KMAX; ++kk)
 #pragma unroll
-      for (int ci = 0; ci < CMAX; ++ci)
-        wr[kk][ci] = (kk < a.k && ci < a.cin) ? W[((int64_t)kk * a.cin + ci) * a.cout + co] : 0.f;
-    const float bias = a.B[co];
-    for (int i = 0; i < F; ++i) {
-      const FrameInfo f = fi[i];
-      if (f.ei < 0) break;
-      float acc = bias;
+    for (int ci = 0; ci < CMAX; ++ci)
+      wr[kk][ci] = (kk < a.k && ci < a.cin) ? wsm[(kk * a.cin + ci) * kChansCo + cl] : 0.f;
+  const float bias = a.B[co];
+  for (int i = tid >> 7; i < F; i += kBlock / kChansCo) {
+    const FrameInfo f = fi[i];
+    if (f.ei < 0) break;
+    float acc = bias;
 #pragma unroll
-      for (int kk = 0; kk < KMAX; ++kk) {
-        if (kk >= a.k) break;
-        const int w = f.t * S + a.dil * kk;
-        if (w >= a.L) {
-          const float* x = xs + (i * S + a.dil * kk) * ld;
+    for (int kk = 0; kk < KMAX; ++kk) {
+      if (kk >= a.k) break;
+      const int w = f.t * S + a.dil * kk;
+      if (w >= a.L) {
+        const float* x = xs + (i * S + a.dil * kk) * ld;
 #pragma unroll
-          for (int ci = 0; ci < CMAX; ++ci)
-            if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
-        } else if (f.ei - e_first < kCacheSlots) {
-          const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
+        for (int ci = 0; ci < CMAX; ++ci)
+          if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
+      } else if (f.ei - e_first < kCacheSlots) {
+        const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
 #pragma unroll
-          for (int ci = 0; ci < CMAX; ++ci)
-            if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
-        } else {
-          const float* x = f.cache + (int64_t)w * a.cin;
+        for (int ci = 0; ci < CMAX; ++ci)
+          if (ci < a.cin) acc = fmaf(wr[kk][ci], x[ci], acc);
+      } else {
+        const float* x = f.cache + (int64_t)w * a.cin;
 #pragma unroll
-          for (int ci = 0; ci < CMAX; ++ci) {
-            if (ci < a.cin) {
-              float v = x[ci];
-              if (a.pre_act) v = lrelu(v);
-              acc = fmaf(wr[kk][ci], v, acc);
-            }
+        for (int ci = 0; ci < CMAX; ++ci) {
+          if (ci < a.cin) {
+            float v = x[ci];
+            if (a.pre_act) v = lrelu(v);
+            acc = fmaf(wr[kk][ci], v, acc);
           }
         }
       }
-      if (a.residual) acc = acc + skip_value(a, f, co);
-      if (a.post_act == 2) acc = tanhf(acc);
-      if (f.masked) acc = 0.f;
-      if (a.out_buf) {
-        a.out_buf[(n0 + i) * a.cout + co] = acc;
-        if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
-      } else {
-        f.out[(int64_t)co * f.tout] = acc;
+    }
+    if (a.residual) acc = acc + skip_value(a, f, co);
+    if (a.post_act == 2) acc = tanhf(acc);
+    if (f.masked) acc = 0.f;
+    if (a.out_buf) {
+      a.out_buf[(int64_t)(n0 + i) * a.cout + co] = acc;
+      if (a.out_twin) store_twin1(a.out_twin, (int64_t)(n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+    } else {
+      f.out[(int64_t)co * f.tout] = acc;
+    }
+  }
+}
+
+// One-output-channel conv with compile-time input width (the decoder's output
+// conv): one lane per frame, taps and channels fully unrolled over 16-byte LDS
+// reads (rows padded to CIN + 4 floats), weights broadcast from LDS.
+template <int CIN, int KMAX>
+__global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t n_tiles, int extra_blocks,
+                                                           FastDiv fd_per_ent) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x;
+  if ((int32_t)blockIdx.x >= n_tiles) {
+    const int32_t total = a.n_ent * a.L * a.cin;
+    for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
+      cache_item(a, fd_per_ent, j);
+    return;
+  }
+  constexpr int LD = CIN + 4;
+  const int F = a.tile;
+  const int rows = F + a.L;
+  float* ws = smem;                                    // [KMAX][CIN] (taps >= k are zero)
+  FrameInfo* fi = reinterpret_cast<FrameInfo*>(ws + KMAX * CIN);
+  float* xs = reinterpret_cast<float*>(fi + F);        // [rows][LD]
+  float* cs = xs + rows * LD;                          // [kCacheSlots][L][LD]
+  const int32_t n0 = (int32_t)blockIdx.x * F;
+  const int e_first = entry_of_out(a, n0);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
+  const float* W = static_cast<const float*>(a.W);
+  for (int q = tid; q < KMAX * CIN; q += kBlock) ws[q] = q < a.k * CIN ? W[q] : 0.f;
+  frame_infos(a, fi, n0, F);
+  stage_rows(a, xs, (int64_t)n0 - a.L, rows, LD);
+  stage_cache(a, cs, e_first, e_last, LD);
+  __syncthreads();
+  for (int i = tid; i < F; i += kBlock) {
+    const FrameInfo f = fi[i];
+    if (f.ei < 0) break;
+    float acc = a.B[0];
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+      if (kk < a.k) {
+        const int w = f.t + a.dil * kk;
+        const float* x;
+        if (w >= a.L) x = xs + (i + a.dil * kk) * LD;
+        else if (f.ei - e_first < kCacheSlots) x = cs + ((f.ei - e_first) * a.L + w) * LD;
+        else x = nullptr;
+        if (x) {
+#pragma unroll
+          for (int c4 = 0; c4 < CIN; c4 += 4) {
+            const f4v xv = *reinterpret_cast<const f4v*>(x + c4);
+            const f4v wv = *reinterpret_cast<const f4v*>(ws + kk * CIN + c4);
+            acc = fmaf(wv.x, xv.x, acc);
+            acc = fmaf(wv.y, xv.y, acc);
+            acc = fmaf(wv.z, xv.z, acc);
+            acc = fmaf(wv.w, xv.w, acc);
+          }
+        } else {
+          const float* xg = f.cache + (int64_t)w * CIN;
+          for (int ci = 0; ci < CIN; ++ci) {
+            float v = xg[ci];
+            if (a.pre_act) v = lrelu(v);
+            acc = fmaf(ws[kk * CIN + ci], v, acc);
+          }
+        }
       }
+    }
+    if (a.post_act == 2) acc = tanhf(acc);
+    if (f.masked) acc = 0.f;
+    if (a.out_buf) {
+      a.out_buf[n0 + i] = acc;
+      if (a.out_twin) store_twin1(a.out_twin, n0 + i, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+    } else {
+      f.out[0] = acc;
     }
   }
 }
@@ -513,31 +604,39 @@ __global__ void __launch_bounds__(kBlock) fill_zero_kernel(float* p, int64_t n) 
 
 }  // namespace
 
-// Narrow-conv kernel choice: 1 = channel-parallel, 2 = frame-parallel, 0 = per item.
-static int narrow_kind(int cin, int cout, int k) {
-  if (cout >= 32 && cin <= kChansC && k <= kChansK) return 1;
+// Narrow-conv kernel choice: 1 = channel-parallel, 2 = frame-parallel,
+// 3 = one-output-channel with compile-time width, 0 = per item.
+static int narrow_kind(int cin, int cout, int k, int stride, int residual) {
+  if (cout == 1 && stride == 1 && !residual && k <= 8 && (cin == 16 || cin == 32 || cin == 48)) return 3;
+  if (cout >= 32 && cout % 4 == 0 && cin <= kChansC && k <= kChansK) return 1;
   if (cout <= 16 && k * cin * cout <= 4096) return 2;
   return 0;
 }
 
 static size_t narrow_lds(int kind, int F, int cin, int cout, int k, int stride, int L) {
+  if (kind == 3) {
+    const int ld = cin + 4;
+    return (size_t)(8 * cin + (F + L) * ld + kCacheSlots * L * ld) * sizeof(float) + (size_t)F * sizeof(FrameInfo);
+  }
   size_t b = (size_t)(F * stride + L) * (cin | 1) * sizeof(float) + (size_t)F * sizeof(FrameInfo);
   b += (size_t)kCacheSlots * L * (cin | 1) * sizeof(float);
   if (kind == 2) b += (size_t)((k * cin * cout + 3) & ~3) * sizeof(float);
+  if (kind == 1) b += (size_t)k * cin * kChansCo * sizeof(float);
   return b;
 }
 
 int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint) {
   (void)dil;
-  const int kind = narrow_kind(cin, cout, k);
+  const int kind = narrow_kind(cin, cout, k, stride, 0);
   if (kind == 0) return 0;
   int F = 256;
   while (F > 8 && narrow_lds(kind, F, cin, cout, k, stride, L) > kNarrowLdsBytes) F /= 2;
   if (narrow_lds(kind, F, cin, cout, k, stride, L) > kNarrowLdsBytes) return 0;
-  // channel-parallel: lanes walk the frames serially, so use short tiles and
-  // many blocks
   if (kind == 1) {
-    while (F > 8 && n_out_hint > 0 && (n_out_hint + F - 1) / F < 2048) F /= 2;
+    // channel-parallel: two frames per lane pass; keep tiles short enough to
+    // give every CU a few blocks
+    const int n_ct = (cout + kChansCo - 1) / kChansCo;
+    while (F > 8 && n_out_hint > 0 && (n_out_hint + F - 1) / F * n_ct < 1024) F /= 2;
   }
   return F;
 }
@@ -548,25 +647,33 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
-  const int kind = narrow_kind(a.cin, a.cout, a.k);
-  if (a.tile <= 0 || kind == 0) {
+  const int kind = a.tile > 0 ? narrow_kind(a.cin, a.cout, a.k, a.stride, a.residual) : 0;
+  const FastDiv fpe = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
+  if (kind == 0) {
     const int64_t items = a.n_out * a.cout + (int64_t)a.n_ent * a.L * a.cin;
-    hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a,
-                       make_fastdiv((uint32_t)std::max(a.L * a.cin, 1)));
+    hipLaunchKernelGGL(conv_item_kernel, dim3(grid_for(items)), dim3(kBlock), 0, s, a, fpe);
     return hipGetLastError();
   }
-  const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile;
+  const int n_ct = kind == 1 ? (a.cout + kChansCo - 1) / kChansCo : 1;
+  const int64_t n_tiles = (a.n_out + a.tile - 1) / a.tile * n_ct;
   const int64_t cache_items = (int64_t)a.n_ent * a.L * a.cin;
   const int extra = (int)std::min<int64_t>((cache_items + kBlock - 1) / kBlock, 1024);
   const size_t lds = narrow_lds(kind, a.tile, a.cin, a.cout, a.k, a.stride, a.L);
   if (n_tiles + extra == 0) return hipSuccess;
-  const FastDiv fpe = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
-  if (kind == 1)
-    hipLaunchKernelGGL((conv_chans_kernel<kChansC, kChansK>), dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds,
-                       s, a, (int32_t)n_tiles, extra, fpe);
-  else
-    hipLaunchKernelGGL(conv_frames_kernel, dim3((unsigned)(n_tiles + extra)), dim3(kBlock), lds, s, a,
-                       (int32_t)n_tiles, extra, fpe);
+  const dim3 grid((unsigned)(n_tiles + extra));
+  if (kind == 1) {
+    hipLaunchKernelGGL((conv_chans_kernel<kChansC, kChansK>), grid, dim3(kBlock), lds, s, a, (int32_t)n_tiles, extra,
+                       fpe, n_ct);
+  } else if (kind == 3) {
+    if (a.cin == 16)
+      hipLaunchKernelGGL((conv_out1_kernel<16, 8>), grid, dim3(kBlock), lds, s, a, (int32_t)n_tiles, extra, fpe);
+    else if (a.cin == 32)
+      hipLaunchKernelGGL((conv_out1_kernel<32, 8>), grid, dim3(kBlock), lds, s, a, (int32_t)n_tiles, extra, fpe);
+    else
+      hipLaunchKernelGGL((conv_out1_kernel<48, 8>), grid, dim3(kBlock), lds, s, a, (int32_t)n_tiles, extra, fpe);
+  } else {
+    hipLaunchKernelGGL(conv_frames_kernel, grid, dim3(kBlock), lds, s, a, (int32_t)n_tiles, extra, fpe);
+  }
   return hipGetLastError();
 }
 
