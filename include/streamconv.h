@@ -53,7 +53,8 @@ typedef enum {
                            multiple of the model's total stride */
   SC_EDEVICE = -5,      /* a HIP call or kernel launch failed */
   SC_ESTATE = -6,       /* the stream saw a device error; call stream_reset */
-  SC_EUNSUPPORTED = -7  /* valid model that this build cannot stream */
+  SC_EUNSUPPORTED = -7, /* valid model that this build cannot stream */
+  SC_PENDING = 1        /* sc_server_poll: the buffer is not processed yet */
 } sc_status;
 
 typedef enum {
@@ -197,6 +198,52 @@ sc_status sc_model_profile(sc_model* model, int32_t enable);
 /* Synchronizes, then fills up to `max_ops` records (one per launch of a
  * step, in launch order) and sets *n_ops to the number of launches per step. */
 sc_status sc_model_profile_read(sc_model* model, sc_op_profile* out, int32_t max_ops, int32_t* n_ops);
+
+/* ---- serving: continuous batching of many live streams ----
+ * A server holds a reference to its model and owns one worker thread and one
+ * HIP stream.  Other processing calls on the same model stay legal and are
+ * ordered with the server's steps; while a server that replays graphs lives,
+ * a call whose step needs a larger workspace than the server's (max_streams *
+ * max_buffer_frames input frames) fails with SC_ELENGTH.  Buffers submitted for any number of streams
+ * are queued; every step the worker takes the next buffer of each admitted
+ * stream (merging further queued buffers of the same stream up to
+ * max_buffer_frames, which the split invariance of the method makes exact),
+ * runs them as one batched step, and stamps each buffer's latency from
+ * submission to completion.  Buffers arriving while a step runs join the
+ * next one.  Streams are admitted first come first served while a slot and
+ * the HBM budget (per-stream state, fixed workspace and staging) allow; the
+ * others wait until a stream is closed.  Results are bitwise those of
+ * processing each stream alone. */
+typedef struct sc_server sc_server;
+typedef struct {
+  int32_t max_streams;        /* slots: streams admitted at once */
+  int32_t max_buffer_frames;  /* per stream per step (also the largest buffer accepted) */
+  int64_t hbm_budget_bytes;   /* device memory the server may use (0: no limit) */
+  int32_t use_graph;          /* 1: replay one captured hipGraph per step context */
+  uint32_t stream_flags;      /* SC_FLAG_* applied to every stream */
+} sc_server_config;
+typedef struct {
+  int64_t steps, buffers, merged_buffers, frames_in, samples_out;
+  int32_t admitted, waiting, max_admitted, queued;
+  int64_t fixed_bytes, per_stream_bytes;
+} sc_server_stats;
+
+sc_status sc_server_create(sc_model* model, const sc_server_config* config, sc_server** out);
+/* Queue one buffer (host memory [in_channels][n_frames], copied) of stream
+ * `stream_id`; the stream is opened on first use.  Sets *ticket. */
+sc_status sc_server_submit(sc_server* server, int64_t stream_id, const float* host_in, int32_t n_frames,
+                           int64_t* ticket);
+/* SC_OK: done -- copies the output ([out_channels][n_frames * out_num / out_den])
+ * to host_out (may be NULL) and the submit-to-completion latency in seconds
+ * to *latency_s (may be NULL), and forgets the ticket.  SC_PENDING: not yet. */
+sc_status sc_server_poll(sc_server* server, int64_t ticket, float* host_out, double* latency_s);
+/* No more buffers for this stream: its slot is freed once its queued buffers
+ * are done (a later submit with the same id opens a new stream). */
+sc_status sc_server_close_stream(sc_server* server, int64_t stream_id);
+/* Blocks until every queued buffer is processed. */
+sc_status sc_server_drain(sc_server* server);
+sc_status sc_server_stats_get(sc_server* server, sc_server_stats* out);
+void sc_server_destroy(sc_server* server);
 
 const char* sc_last_error(void);
 

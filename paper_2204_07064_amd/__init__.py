@@ -17,7 +17,7 @@ import numpy as np
 from . import _native
 from ._native import ScError, check, lib, nodes_array  # noqa: F401
 
-__all__ = ["Model", "Stream", "process_batch", "plan", "ScError", "lib"]
+__all__ = ["Model", "Stream", "Server", "process_batch", "plan", "ScError", "lib"]
 
 
 _EXITING = [False]
@@ -171,3 +171,60 @@ def process_batch(model, streams, xs, outs=None, hip_stream=None):
     tf = (ctypes.c_int32 * n)(*[int(x.shape[-1]) for x in xs])
     check(lib().sc_process_batch(model.handle, n, sh, ins, tf, ous, _stream_handle(hip_stream)))
     return outs
+
+
+class Server:
+    """Continuous-batching server over one model (see sc_server_* in the
+    header).  Inputs and outputs are host numpy arrays; the server copies them."""
+
+    def __init__(self, model, max_streams, max_buffer_frames, hbm_budget_bytes=0, use_graph=True,
+                 warmup_mask=False):
+        cfg = _native.ScServerConfig(int(max_streams), int(max_buffer_frames), int(hbm_budget_bytes),
+                                     int(bool(use_graph)),
+                                     _native.SC_FLAG_WARMUP_MASK if warmup_mask else 0)
+        h = ctypes.c_void_p()
+        check(lib().sc_server_create(model.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.model = model
+        self.cin = model.info["in_channels"]
+        self.cout = model.info["out_channels"]
+
+    def submit(self, stream_id, x):
+        """x: float32 [in_channels][frames] (host).  Returns a ticket."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = ctypes.c_int64()
+        check(lib().sc_server_submit(self.handle, int(stream_id), x.ctypes.data_as(_native.c_fp), x.shape[-1],
+                                     ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, frames):
+        """(output [out_channels][frames*rate], latency_s) when done, else None."""
+        out = np.empty((self.cout, self.model.out_frames(frames)), np.float32)
+        lat = ctypes.c_double()
+        st = lib().sc_server_poll(self.handle, int(ticket), out.ctypes.data_as(_native.c_fp), ctypes.byref(lat))
+        if st == _native.SC_PENDING:
+            return None
+        check(st)
+        return out, lat.value
+
+    def close_stream(self, stream_id):
+        check(lib().sc_server_close_stream(self.handle, int(stream_id)))
+
+    def drain(self):
+        check(lib().sc_server_drain(self.handle))
+
+    def stats(self):
+        st = _native.ScServerStats()
+        check(lib().sc_server_stats_get(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _native.ScServerStats._fields_}
+
+    def close(self):
+        if self.handle and not _EXITING[0]:
+            lib().sc_server_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -32,7 +32,10 @@ EXPORTS = [
     "sc_model_set_act_scales", "sc_model_read_amax", "sc_model_enable_amax", "sc_model_destroy",
     "stream_create", "stream_process", "stream_reset", "stream_position", "stream_destroy",
     "sc_process_batch", "sc_last_error", "sc_model_profile", "sc_model_profile_read",
+    "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
+    "sc_server_stats_get", "sc_server_destroy",
 ]
+SC_PENDING = 1
 
 
 class ScNode(ctypes.Structure):
@@ -55,6 +58,17 @@ class ScOpProfile(ctypes.Structure):
                 ("rate_in_num", c_i32), ("rate_in_den", c_i32), ("rate_out_num", c_i32),
                 ("rate_out_den", c_i32), ("ms", ctypes.c_double), ("launches", c_i64),
                 ("frames_in", c_i64), ("frames_out", c_i64), ("entries", c_i64)]
+
+
+class ScServerConfig(ctypes.Structure):
+    _fields_ = [("max_streams", c_i32), ("max_buffer_frames", c_i32), ("hbm_budget_bytes", c_i64),
+                ("use_graph", c_i32), ("stream_flags", c_u32)]
+
+
+class ScServerStats(ctypes.Structure):
+    _fields_ = [("steps", c_i64), ("buffers", c_i64), ("merged_buffers", c_i64), ("frames_in", c_i64),
+                ("samples_out", c_i64), ("admitted", c_i32), ("waiting", c_i32), ("max_admitted", c_i32),
+                ("queued", c_i32), ("fixed_bytes", c_i64), ("per_stream_bytes", c_i64)]
 
 
 class ScError(RuntimeError):
@@ -98,6 +112,13 @@ def lib():
     _sig(L, "sc_last_error", ctypes.c_char_p, [])
     _sig(L, "sc_model_profile", c_i32, [c_vp, c_i32])
     _sig(L, "sc_model_profile_read", c_i32, [c_vp, P(ScOpProfile), c_i32, P(c_i32)])
+    _sig(L, "sc_server_create", c_i32, [c_vp, P(ScServerConfig), P(c_vp)])
+    _sig(L, "sc_server_submit", c_i32, [c_vp, c_i64, c_fp, c_i32, P(c_i64)])
+    _sig(L, "sc_server_poll", c_i32, [c_vp, c_i64, c_fp, P(ctypes.c_double)])
+    _sig(L, "sc_server_close_stream", c_i32, [c_vp, c_i64])
+    _sig(L, "sc_server_drain", c_i32, [c_vp])
+    _sig(L, "sc_server_stats_get", c_i32, [c_vp, P(ScServerStats)])
+    _sig(L, "sc_server_destroy", None, [c_vp])
     _LIB = L
     return L
 

@@ -13,7 +13,9 @@ namespace sc {
 struct LayerArgs {
   const Entry* ents;
   const int32_t* fent;     // entry of every input frame of the step
-  int32_t n_ent;
+  const int32_t* hdr;      // device step header: [0] streams, [1] input frames of the step
+  int32_t n_ent;           // host: upper bounds used to size grids (the header has the
+                           // actual values, so a captured launch serves any smaller step)
   const float* in_buf;     // packed [frames][cin] at the input rate, or null: user input
   const float* in_buf2;    // delay-add second branch
   float* out_buf;          // packed [frames][cout] at the output rate, or null: user output
@@ -40,6 +42,10 @@ struct LayerArgs {
   int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
 };
 
+// ---- the step's actual size (device header) ----
+__device__ inline int32_t step_ents(const LayerArgs& a) { return a.hdr[0]; }
+__device__ inline int32_t step_frames(const LayerArgs& a) { return a.hdr[1]; }
+
 // ---- rate arithmetic without run-time division ----
 // frames of the input / output rate for x input frames of the step
 __device__ inline int32_t in_frames(const LayerArgs& a, int32_t x) { return (int32_t)fdiv(a.fd_in_den, (uint32_t)x * a.in_num); }
@@ -53,13 +59,17 @@ __device__ inline bool masked(const LayerArgs& a, const Entry& e, int64_t t) {
   return (e.flags & SC_FLAG_WARMUP_MASK) && ((int64_t)e.pos * a.out_num + t * a.out_den < a.delay * (int64_t)a.out_den);
 }
 
+__device__ inline int32_t step_in(const LayerArgs& a) { return in_frames(a, step_frames(a)); }
+__device__ inline int32_t step_out(const LayerArgs& a) { return out_frames(a, step_frames(a)); }
+
 // Frames per block for the LDS-staged narrow conv (0 if its window does not fit).
 int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, int64_t n_out_hint);
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
 // Channel-major user inputs of a step -> packed channels-last [frame][C].
-hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
-                             void* twin, int32_t twin_prec, int32_t twin_pre, float twin_qs, hipStream_t s);
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, const int32_t* hdr, int32_t C,
+                             int64_t max_frames, float* out, void* twin, int32_t twin_prec, int32_t twin_pre,
+                             float twin_qs, hipStream_t s);
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);
 hipError_t launch_delay_add(const LayerArgs& a, hipStream_t s);
 // max |pre_act(x)| over the step's new input frames of a layer -> atomic max into *amax

@@ -120,7 +120,7 @@ __device__ inline ColInfo make_col(const LayerArgs& a, int32_t n, int32_t n_cols
   c.Tin = 0;
   if (n >= n_cols) return c;
   int ei;
-  if (CONVT) ei = n < a.n_in ? entry_of_in(a, n) : n - (int32_t)a.n_in;
+  if (CONVT) ei = n < step_in(a) ? entry_of_in(a, n) : n - (int32_t)step_in(a);
   else ei = entry_of_out(a, n);
   const Entry& e = a.ents[ei];
   c.ei = ei;
@@ -128,7 +128,7 @@ __device__ inline ColInfo make_col(const LayerArgs& a, int32_t n, int32_t n_cols
   c.Tin = in_frames(a, e.T);
   c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;   // conv cache / convt carry copy
   if (CONVT) {
-    c.t = n < a.n_in ? n - c.in_start : c.Tin;
+    c.t = n < step_in(a) ? n - c.in_start : c.Tin;
   } else {
     c.t = n - out_frames(a, e.off);
     c.tcache = reinterpret_cast<const unsigned char*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len);
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
   // ---- conv cache update blocks (after the GEMM tiles) ----
   if (!CONVT && bid >= n_tiles) {
     const int32_t per_ent = a.L * a.cin;
-    const int32_t total = a.n_ent * per_ent;
+    const int32_t total = step_ents(a) * per_ent;
     for (int32_t j = (bid - n_tiles) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
       const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
       const int32_t rem = j - ei * per_ent;
@@ -219,6 +219,9 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
   const int32_t nt = (int32_t)((uint32_t)bid / (uint32_t)n_mt);
   const int m0 = mt * MT;
   const int32_t n0 = nt * NT;
+  // the grid may be sized for a larger step than this one (captured launches)
+  n_cols = CONVT ? step_in(a) + step_ents(a) : step_out(a);
+  if (n0 >= n_cols) return;
 
   const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
   const int row_bytes = Kpad * ES;

@@ -64,8 +64,8 @@ __device__ inline float finish(const LayerArgs& a, const Entry& e, int32_t t, fl
 // Per-item conv: one lane per output value (used when the LDS window of the
 // narrow kernel would not fit).  Grid-stride over outputs, then cache items.
 __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a, FastDiv fd_per_ent) {
-  const int32_t n_items = (int32_t)a.n_out * a.cout;
-  const int32_t total = n_items + a.n_ent * a.L * a.cin;
+  const int32_t n_items = (int32_t)step_out(a) * a.cout;
+  const int32_t total = n_items + step_ents(a) * a.L * a.cin;
   const float* W = static_cast<const float*>(a.W);
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     if (idx >= n_items) {
@@ -148,7 +148,7 @@ __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int
     // the rows are one contiguous range of the packed buffer: float4 copies,
     // several loads in flight per thread before the LDS writes
     const int64_t base = p0 * a.cin;
-    const int64_t lim = a.n_in * a.cin;
+    const int64_t lim = step_in(a) * a.cin;
     const int total4 = rows * a.cin / 4;
     for (int v0 = 0; v0 < total4; v0 += kBlock * kStageUnroll) {
       f4v buf[kStageUnroll];
@@ -184,7 +184,7 @@ __device__ inline void stage_rows(const LayerArgs& a, float* xs, int64_t p0, int
       if (idx < total) {
         const int j = (int)fdiv(a.fd_cin, (uint32_t)idx), ci = idx - j * a.cin;
         const int64_t p = p0 + j;
-        if (p >= 0 && p < a.n_in) v = a.in_buf[p * a.cin + ci];
+        if (p >= 0 && p < step_in(a)) v = a.in_buf[p * a.cin + ci];
       }
       buf[u] = v;
     }
@@ -208,7 +208,7 @@ __device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int32_t n0
     f.masked = 0;
     f.ei = -1;
     const int32_t n = n0 + i;
-    if (n < a.n_out) {
+    if (n < step_out(a)) {
       const int ei = entry_of_out(a, n);
       const Entry& e = a.ents[ei];
       const int32_t t = n - out_frames(a, e.off);
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   if ((int32_t)blockIdx.x >= n_tiles) {
-    const int32_t total = a.n_ent * a.L * a.cin;
+    const int32_t total = step_ents(a) * a.L * a.cin;
     for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
       cache_item(a, fd_per_ent, j);
     return;
@@ -251,9 +251,10 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   float* xs = reinterpret_cast<float*>(fi + F);
   float* cs = xs + rows * ld;                          // cache rows of the tile's streams
   const int32_t n0 = (int32_t)blockIdx.x * F;
+  if (n0 >= step_out(a)) return;                       // grid sized for the largest step
   const float* W = static_cast<const float*>(a.W);
   const int e_first = entry_of_out(a, n0);
-  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)step_out(a)) - 1);
   for (int i = tid; i < nw; i += kBlock) ws[i] = W[i];
   frame_infos(a, fi, n0, F);
   stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
@@ -308,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   if ((int32_t)blockIdx.x >= n_tiles) {
-    const int32_t total = a.n_ent * a.L * a.cin;
+    const int32_t total = step_ents(a) * a.L * a.cin;
     for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
       cache_item(a, fd_per_ent, j);
     return;
@@ -318,13 +319,14 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
   const int kin = a.k * a.cin;
   const int ct = (int)((uint32_t)blockIdx.x % (uint32_t)n_ct);
   const int32_t n0 = (int32_t)((uint32_t)blockIdx.x / (uint32_t)n_ct) * F;
+  if (n0 >= step_out(a)) return;                       // grid sized for the largest step
   const int co0 = ct * kChansCo;
   float* wsm = smem;                                   // [kin][kChansCo]
   FrameInfo* fi = reinterpret_cast<FrameInfo*>(wsm + kin * kChansCo);
   float* xs = reinterpret_cast<float*>(fi + F);
   float* cs = xs + rows * ld;                          // cache rows of the tile's streams
   const int e_first = entry_of_out(a, n0);
-  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)step_out(a)) - 1);
   {
     // weight tile: rows q of W[q][cout] (q = tap * cin + ci), columns co0..co0+127
     const float* W = static_cast<const float*>(a.W);
@@ -401,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   if ((int32_t)blockIdx.x >= n_tiles) {
-    const int32_t total = a.n_ent * a.L * a.cin;
+    const int32_t total = step_ents(a) * a.L * a.cin;
     for (int32_t j = ((int32_t)blockIdx.x - n_tiles) * kBlock + tid; j < total; j += extra_blocks * kBlock)
       cache_item(a, fd_per_ent, j);
     return;
@@ -414,8 +416,9 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
   float* xs = reinterpret_cast<float*>(fi + F);        // [rows][LD]
   float* cs = xs + rows * LD;                          // [kCacheSlots][L][LD]
   const int32_t n0 = (int32_t)blockIdx.x * F;
+  if (n0 >= step_out(a)) return;                       // grid sized for the largest step
   const int e_first = entry_of_out(a, n0);
-  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)a.n_out) - 1);
+  const int e_last = entry_of_out(a, min((int32_t)(n0 + F), (int32_t)step_out(a)) - 1);
   const float* W = static_cast<const float*>(a.W);
   for (int q = tid; q < KMAX * CIN; q += kBlock) ws[q] = q < a.k * CIN ? W[q] : 0.f;
   frame_infos(a, fi, n0, F);
@@ -467,13 +470,13 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
 
 // Channel-major user input [C][T] of every stream -> packed channels-last
 // [frame][C] for the step.
-__global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, int32_t C,
-                                                           int32_t n_frames, FastDiv fd_frames, float* out,
-                                                           void* twin, int32_t twin_prec, int32_t twin_pre,
-                                                           float twin_qs) {
+__global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, const int32_t* hdr,
+                                                           int32_t C, float* out, void* twin, int32_t twin_prec,
+                                                           int32_t twin_pre, float twin_qs) {
+  const int32_t n_frames = hdr[1];
   const int32_t total = n_frames * C;
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
-    const int c = (int)fdiv(fd_frames, (uint32_t)idx);   // frame fastest: coalesced reads of each channel row
+    const int c = idx / n_frames;   // frame fastest: coalesced reads of each channel row
     const int32_t f = idx - c * n_frames;
     const Entry& e = ents[fent[f]];
     const float v = e.in[(int64_t)c * e.T + (f - e.off)];
@@ -491,7 +494,7 @@ __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, c
 // Weights packed [h][phi][cin][cout], h = 0 -> tap phi + r, h = 1 -> tap phi.
 __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv fd_r) {
   const int r = a.stride;
-  const int32_t n_cols = (int32_t)a.n_in + a.n_ent;
+  const int32_t n_cols = (int32_t)step_in(a) + step_ents(a);
   const int32_t total = n_cols * r * a.cout;
   const float* W = static_cast<const float*>(a.W);
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
@@ -499,11 +502,11 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv
     const int co = idx - rest * a.cout;
     const int32_t c = (int32_t)fdiv(fd_r, (uint32_t)rest);
     const int phi = rest - c * r;
-    const int ei = c < a.n_in ? entry_of_in(a, c) : c - (int32_t)a.n_in;
+    const int ei = c < step_in(a) ? entry_of_in(a, c) : c - (int32_t)step_in(a);
     const Entry& e = a.ents[ei];
     const int32_t in_start = in_frames(a, e.off);
     const int32_t Tin = in_frames(a, e.T);
-    const int32_t q = c < a.n_in ? c - in_start : Tin;
+    const int32_t q = c < step_in(a) ? c - in_start : Tin;
     const float* carry_in = e.state + a.state_off + (int64_t)e.parity * a.state_len;
     float acc = (q == 0) ? carry_in[phi * a.cout + co] : 0.f;
     for (int h = 0; h < 2; ++h) {
@@ -538,9 +541,9 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv
 // (Eq. 3).  Window of branch j: [line_j (A_j frames) | new frames].
 __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a, FastDiv fd_per_ent) {
   const int C = a.cout;
-  const int32_t n_items = (int32_t)a.n_out * C;
+  const int32_t n_items = (int32_t)step_out(a) * C;
   const int32_t per_ent = (a.A0 + a.A1) * C;
-  const int32_t total = n_items + a.n_ent * per_ent;
+  const int32_t total = n_items + step_ents(a) * per_ent;
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     if (idx < n_items) {
       const int32_t n = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
@@ -582,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a, FastDiv 
 __global__ void __launch_bounds__(kBlock) amax_kernel(LayerArgs a, float* amax) {
   __shared__ float red[kBlock];
   float m = 0.f;
-  const int64_t total = a.n_in * a.cin;
+  const int64_t total = step_in(a) * a.cin;
   for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * kBlock) {
     float v = a.in_buf[idx];
@@ -677,11 +680,11 @@ hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t C, int64_t n_frames, float* out,
-                             void* twin, int32_t twin_prec, int32_t twin_pre, float twin_qs, hipStream_t s) {
-  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n_frames * C)), dim3(kBlock), 0, s, ents, fent, C,
-                     (int32_t)n_frames, make_fastdiv((uint32_t)std::max<int64_t>(n_frames, 1)), out, twin, twin_prec,
-                     twin_pre, twin_qs);
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, const int32_t* hdr, int32_t C,
+                             int64_t max_frames, float* out, void* twin, int32_t twin_prec, int32_t twin_pre,
+                             float twin_qs, hipStream_t s) {
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(max_frames * C)), dim3(kBlock), 0, s, ents, fent, hdr, C, out,
+                     twin, twin_prec, twin_pre, twin_qs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,106 @@
+// Internal model / stream objects shared by the runtime and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+#include "sc_internal.h"
+
+namespace sc {
+
+constexpr int kRing = 16;
+constexpr size_t kDescHeaderBytes = 64;   // step header: [0] streams, [1] input frames
+
+// Device copies of one op's weights.
+struct OpDev {
+  void* W = nullptr;        // packed weights (fp32 / bf16 / fp8 by impl)
+  float* B = nullptr;       // bias
+  float* wscale = nullptr;  // fp8 per-row scales
+  int prec = 0;             // precision of this op's kernel
+};
+
+// A slot of the descriptor ring: pinned host staging + device copy + event.
+// Layout: n Entry records, then one int32 per input frame of the step (its entry).
+struct DescSlot {
+  unsigned char* host = nullptr;
+  unsigned char* dev = nullptr;
+  size_t cap = 0;          // bytes
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+}  // namespace sc
+
+struct sc_model {
+  int device = 0;
+  sc_precision prec = SC_FP32;
+  uint32_t options = 0;
+  sc::Plan plan;
+  std::vector<sc::OpDev> opdev;
+  std::vector<float> act_scales;   // per layer (FP8)
+  bool have_scales = false;
+  int64_t weight_bytes = 0;
+  // workspace
+  std::vector<float*> ws;
+  std::vector<void*> tw;           // operand twins
+  int tw_esize = 4;
+  int64_t ws_cap = 0;              // input frames
+  int ws_pins = 0;                 // captured graphs holding the workspace's addresses
+  // descriptors
+  sc::DescSlot ring[sc::kRing];
+  int ring_next = 0;
+  // cross-stream ordering of steps
+  hipEvent_t last_done = nullptr;
+  bool has_last = false;
+  // calibration
+  float* d_amax = nullptr;
+  bool amax_on = false;
+  // lifetime: the model itself plus one reference per live stream
+  int refs = 1;
+  // tracing
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_events;        // pool, used in pairs
+  size_t prof_used = 0;                       // events recorded since the last fold
+  std::vector<int32_t> prof_op;               // op index of each recorded pair
+  std::vector<int64_t> prof_in, prof_out, prof_ent;  // per recorded pair
+  std::vector<sc_op_profile> prof;            // per op sums
+  std::mutex mu;
+};
+
+struct sc_stream {
+  sc_model* m = nullptr;
+  float* d_state = nullptr;
+  int32_t max_frames = 0;
+  uint32_t flags = 0;
+  int64_t pos = 0;
+  int parity = 0;
+  bool bad = false;
+};
+
+
+namespace sc {
+
+// Bytes of a step descriptor for n streams and `frames` input frames.
+inline size_t desc_bytes(int n, int64_t frames) {  // n: entry capacity
+  return kDescHeaderBytes + (size_t)n * sizeof(Entry) + (size_t)frames * sizeof(int32_t);
+}
+
+// Checks a step's arguments; sets *total to its input frames.  No state change.
+sc_status validate_step(const sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                        const int32_t* n_frames, float* const* d_out, int64_t* total);
+// Writes the step descriptor (header, entries, frame -> entry) into `host`;
+// the frame table starts after `ent_capacity` entries (>= n).
+void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* const* streams,
+                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total);
+// Enqueues the step's kernels on hs reading the descriptor at `dev`; grids are
+// sized for grid_n streams and grid_frames input frames (>= the actual step).
+hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs);
+sc_status ensure_workspace(sc_model* m, int64_t frames);
+// After a successful enqueue: advance positions and flip state copies.
+void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames);
+sc_status fail_status(sc_status st, const char* msg);
+
+}  // namespace sc

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "model_internal.h"
 #include "sc_internal.h"
 
 namespace sc {
@@ -28,8 +29,6 @@ using namespace sc;
 
 namespace {
 
-constexpr int kRing = 16;
-
 sc_status fail(sc_status st, const std::string& msg) {
   set_error(msg);
   return st;
@@ -40,70 +39,7 @@ sc_status hip_fail(hipError_t e, const char* what) {
   return SC_EDEVICE;
 }
 
-// Device copies of one op's weights.
-struct OpDev {
-  void* W = nullptr;        // packed weights (fp32 / bf16 / fp8 by impl)
-  float* B = nullptr;       // bias
-  float* wscale = nullptr;  // fp8 per-row scales
-  int prec = 0;             // precision of this op's kernel
-};
-
-// A slot of the descriptor ring: pinned host staging + device copy + event.
-// Layout: n Entry records, then one int32 per input frame of the step (its entry).
-struct DescSlot {
-  unsigned char* host = nullptr;
-  unsigned char* dev = nullptr;
-  size_t cap = 0;          // bytes
-  hipEvent_t done = nullptr;
-  bool pending = false;
-};
-
 }  // namespace
-
-struct sc_model {
-  int device = 0;
-  sc_precision prec = SC_FP32;
-  uint32_t options = 0;
-  Plan plan;
-  std::vector<OpDev> opdev;
-  std::vector<float> act_scales;   // per layer (FP8)
-  bool have_scales = false;
-  int64_t weight_bytes = 0;
-  // workspace
-  std::vector<float*> ws;
-  std::vector<void*> tw;           // operand twins
-  int tw_esize = 4;
-  int64_t ws_cap = 0;              // input frames
-  // descriptors
-  DescSlot ring[kRing];
-  int ring_next = 0;
-  // cross-stream ordering of steps
-  hipEvent_t last_done = nullptr;
-  bool has_last = false;
-  // calibration
-  float* d_amax = nullptr;
-  bool amax_on = false;
-  // lifetime: the model itself plus one reference per live stream
-  int refs = 1;
-  // tracing
-  bool prof_on = false;
-  std::vector<hipEvent_t> prof_events;        // pool, used in pairs
-  size_t prof_used = 0;                       // events recorded since the last fold
-  std::vector<int32_t> prof_op;               // op index of each recorded pair
-  std::vector<int64_t> prof_in, prof_out, prof_ent;  // per recorded pair
-  std::vector<sc_op_profile> prof;            // per op sums
-  std::mutex mu;
-};
-
-struct sc_stream {
-  sc_model* m = nullptr;
-  float* d_state = nullptr;
-  int32_t max_frames = 0;
-  uint32_t flags = 0;
-  int64_t pos = 0;
-  int parity = 0;
-  bool bad = false;
-};
 
 namespace {
 
@@ -166,11 +102,12 @@ float twin_scale(const sc_model* m, int layer) {
   return 1.0f / (m->act_scales[layer] / 448.0f);
 }
 
-LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent, int n_ent,
-                     int64_t total_T) {
+LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
+                     const int32_t* dhdr, int n_ent, int64_t total_T) {
   LayerArgs a{};
   a.ents = dents;
   a.fent = dfent;
+  a.hdr = dhdr;
   a.n_ent = n_ent;
   a.in_buf = op.in_buf >= 0 ? m->ws[op.in_buf] : nullptr;
   a.in_buf2 = op.in_buf2 >= 0 ? m->ws[op.in_buf2] : nullptr;
@@ -211,8 +148,12 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   return a;
 }
 
-sc_status ensure_workspace(sc_model* m, int64_t frames) {
+}  // namespace
+
+sc_status sc::ensure_workspace(sc_model* m, int64_t frames) {
   if (frames <= m->ws_cap) return SC_OK;
+  if (m->ws_pins > 0)
+    return fail(SC_ELENGTH, "step larger than the workspace that a server's captured graph holds");
   int64_t cap = std::max<int64_t>(frames, 2 * m->ws_cap);
   const int64_t mult = m->plan.input_multiple;
   cap = (cap + mult - 1) / mult * mult;
@@ -241,6 +182,8 @@ sc_status ensure_workspace(sc_model* m, int64_t frames) {
   m->ws_cap = cap;
   return SC_OK;
 }
+
+namespace {
 
 // Records the start event of a timed launch and hands out its end event.
 hipError_t prof_begin(sc_model* m, int oi, const LayerArgs& a, hipStream_t hs, hipEvent_t* ev_end) {
@@ -284,9 +227,14 @@ hipError_t prof_fold(sc_model* m) {
   return e;
 }
 
-sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
-                   const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
-  // ---- validation (no state change on failure) ----
+}  // namespace
+
+namespace sc {
+
+sc_status fail_status(sc_status st, const char* msg) { return fail(st, msg); }
+
+sc_status validate_step(const sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                        const int32_t* n_frames, float* const* d_out, int64_t* total_out) {
   if (n <= 0 || !streams || !d_in || !n_frames || !d_out) return fail(SC_EINVAL, "null argument or n <= 0");
   if (m->prec == SC_FP8E4M3 && !m->have_scales) return fail(SC_EINVAL, "FP8 model has no activation scales");
   int64_t total = 0;
@@ -302,10 +250,95 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (!d_in[i] || !d_out[i]) return fail(SC_EINVAL, "null device buffer");
     total += T;
   }
-  if (total > INT32_MAX / 2) return fail(SC_ELENGTH, "batch too large");
+  if (total > INT32_MAX / 4) return fail(SC_ELENGTH, "batch too large");
+  *total_out = total;
+  return SC_OK;
+}
+
+void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* const* streams,
+                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total) {
+  int32_t* hhdr = reinterpret_cast<int32_t*>(host);
+  hhdr[0] = n;
+  hhdr[1] = (int32_t)total;
+  Entry* hents = reinterpret_cast<Entry*>(host + kDescHeaderBytes);
+  int32_t* hfent = reinterpret_cast<int32_t*>(host + kDescHeaderBytes + (size_t)ent_capacity * sizeof(Entry));
+  int32_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    Entry& en = hents[i];
+    en.in = d_in[i];
+    en.out = d_out[i];
+    en.state = streams[i]->d_state;
+    en.T = n_frames[i];
+    en.off = off;
+    en.parity = streams[i]->parity;
+    en.flags = (int32_t)streams[i]->flags;
+    en.pos = streams[i]->pos;
+    for (int32_t f = 0; f < n_frames[i]; ++f) hfent[off + f] = i;
+    off += n_frames[i];
+  }
+}
+
+hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs) {
+  const int32_t* dhdr = reinterpret_cast<const int32_t*>(dev);
+  const Entry* dents = reinterpret_cast<const Entry*>(dev + kDescHeaderBytes);
+  const int32_t* dfent = reinterpret_cast<const int32_t*>(dev + kDescHeaderBytes + (size_t)grid_n * sizeof(Entry));
+  hipError_t e = hipSuccess;
+  if (m->plan.input_buf >= 0) {
+    const Plan& pl = m->plan;
+    e = launch_pack_input(dents, dfent, dhdr, pl.in_channels, grid_frames, m->ws[pl.input_buf],
+                          pl.input_twin >= 0 ? m->tw[pl.input_twin] : nullptr,
+                          m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2), pl.input_twin_pre,
+                          twin_scale(m, pl.input_twin_layer), hs);
+    if (e != hipSuccess) return e;
+  }
+  for (const Op& op : m->plan.ops) {
+    const LayerArgs a = layer_args(m, op, dents, dfent, dhdr, grid_n, grid_frames);
+    if (m->amax_on && op.layer >= 0) {
+      e = launch_amax(a, m->d_amax + op.layer, hs);
+      if (e != hipSuccess) return e;
+    }
+    const size_t oi = &op - &m->plan.ops[0];
+    const int prec = m->opdev[oi].prec;
+    hipEvent_t ev_end = nullptr;
+    if (m->prof_on) {
+      e = prof_begin(m, (int)oi, a, hs, &ev_end);
+      if (e != hipSuccess) return e;
+    }
+    if (op.kind == K_CONV) {
+      e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
+    } else if (op.kind == K_CONVT) {
+      e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, hs) : launch_convt_valu(a, hs);
+    } else {
+      e = launch_delay_add(a, hs);
+    }
+    if (e != hipSuccess) return e;
+    if (ev_end) {
+      e = hipEventRecord(ev_end, hs);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return e;
+}
+
+void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames) {
+  for (int i = 0; i < n; ++i) {
+    streams[i]->pos += n_frames[i];
+    streams[i]->parity ^= 1;
+  }
+}
+
+}  // namespace sc
+
+namespace {
+
+sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                   const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
+  int64_t total = 0;
+  sc_status st = validate_step(m, n, streams, d_in, n_frames, d_out, &total);
+  if (st != SC_OK) return st;
   hipError_t e = hipSetDevice(m->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  sc_status st = ensure_workspace(m, total);
+  st = ensure_workspace(m, total);
   if (st != SC_OK) return st;
 
   // ---- descriptors ----
@@ -316,8 +349,7 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     slot.pending = false;
   }
-  const size_t ent_bytes = (size_t)n * sizeof(Entry);
-  const size_t need = ent_bytes + (size_t)total * sizeof(int32_t);
+  const size_t need = desc_bytes(n, total);
   if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
@@ -335,69 +367,14 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
-  Entry* hents = reinterpret_cast<Entry*>(slot.host);
-  int32_t* hfent = reinterpret_cast<int32_t*>(slot.host + ent_bytes);
-  int32_t off = 0;
-  for (int i = 0; i < n; ++i) {
-    Entry& en = hents[i];
-    en.in = d_in[i];
-    en.out = d_out[i];
-    en.state = streams[i]->d_state;
-    en.T = n_frames[i];
-    en.off = off;
-    en.parity = streams[i]->parity;
-    en.flags = (int32_t)streams[i]->flags;
-    en.pos = streams[i]->pos;
-    for (int32_t f = 0; f < n_frames[i]; ++f) hfent[off + f] = i;
-    off += n_frames[i];
-  }
+  fill_descriptor(slot.host, n, n, streams, d_in, n_frames, d_out, total);
   if (m->has_last) {
     e = hipStreamWaitEvent(hs, m->last_done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
   e = hipMemcpyAsync(slot.dev, slot.host, need, hipMemcpyHostToDevice, hs);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-  const Entry* dents = reinterpret_cast<const Entry*>(slot.dev);
-  const int32_t* dfent = reinterpret_cast<const int32_t*>(slot.dev + ent_bytes);
-
-  // ---- launches ----
-  if (m->plan.input_buf >= 0) {
-    const Plan& pl = m->plan;
-    e = launch_pack_input(dents, dfent, pl.in_channels, total, m->ws[pl.input_buf],
-                          pl.input_twin >= 0 ? m->tw[pl.input_twin] : nullptr,
-                          m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2), pl.input_twin_pre,
-                          twin_scale(m, pl.input_twin_layer), hs);
-    if (e != hipSuccess) {
-      for (int i = 0; i < n; ++i) streams[i]->bad = true;
-      return hip_fail(e, "kernel launch");
-    }
-  }
-  for (const Op& op : m->plan.ops) {
-    const LayerArgs a = layer_args(m, op, dents, dfent, n, total);
-    if (m->amax_on && op.layer >= 0) {
-      e = launch_amax(a, m->d_amax + op.layer, hs);
-      if (e != hipSuccess) break;
-    }
-    const size_t oi = &op - &m->plan.ops[0];
-    const int prec = m->opdev[oi].prec;
-    hipEvent_t ev_end = nullptr;
-    if (m->prof_on) {
-      e = prof_begin(m, (int)oi, a, hs, &ev_end);
-      if (e != hipSuccess) break;
-    }
-    if (op.kind == K_CONV) {
-      e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
-    } else if (op.kind == K_CONVT) {
-      e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, hs) : launch_convt_valu(a, hs);
-    } else {
-      e = launch_delay_add(a, hs);
-    }
-    if (e != hipSuccess) break;
-    if (ev_end) {
-      e = hipEventRecord(ev_end, hs);
-      if (e != hipSuccess) break;
-    }
-  }
+  e = enqueue_kernels(m, slot.dev, n, total, hs);
   if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
   if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
   if (e != hipSuccess) {
@@ -406,10 +383,7 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   }
   slot.pending = true;
   m->has_last = true;
-  for (int i = 0; i < n; ++i) {
-    streams[i]->pos += n_frames[i];
-    streams[i]->parity ^= 1;
-  }
+  commit_step(n, streams, n_frames);
   return SC_OK;
 }
 

@@ -1,0 +1,128 @@
+"""GPU tests of the serving loop: continuous batching with hipGraph replays,
+admission by HBM budget, same-stream buffer merging, and each stream's result
+equal (bitwise) to processing it alone."""
+import numpy as np
+import pytest
+
+import scgen
+from gpu_helpers import log, run_stream, weights_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sc():
+    import paper_2204_07064_amd as sc
+    return sc
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _workload(n_streams, n_bufs, seed, max_buf=8):
+    rng = np.random.default_rng(seed)
+    lens = [list(rng.integers(1, max_buf + 1, size=n_bufs)) for _ in range(n_streams)]
+    xs = [scgen.stream_latents(16, int(sum(l)), 100 + i) for i, l in enumerate(lens)]
+    # an arrival order that keeps each stream's buffers in order
+    order = []
+    nxt = [0] * n_streams
+    while any(nxt[i] < n_bufs for i in range(n_streams)):
+        i = int(rng.integers(0, n_streams))
+        if nxt[i] < n_bufs:
+            order.append((i, nxt[i]))
+            nxt[i] += 1
+    return lens, xs, order
+
+
+def _serve(sc, mod, lens, xs, order, use_graph, budget=0, max_streams=None, close_after=True, max_buf=16):
+    n = len(lens)
+    srv = sc.Server(mod, max_streams or n, max_buf, hbm_budget_bytes=budget, use_graph=use_graph)
+    tickets = {}
+    starts = [np.concatenate([[0], np.cumsum(l)]) for l in lens]
+    for (i, b) in order:
+        a, e = int(starts[i][b]), int(starts[i][b + 1])
+        tickets[(i, b)] = srv.submit(i, xs[i][:, a:e])
+    if close_after:
+        for i in range(n):
+            srv.close_stream(i)
+    srv.drain()
+    outs = [[None] * len(l) for l in lens]
+    lat = []
+    for (i, b), t in tickets.items():
+        r = srv.poll(t, int(lens[i][b]))
+        assert r is not None
+        outs[i][b] = r[0]
+        lat.append(r[1])
+    st = srv.stats()
+    srv.close()
+    return [np.concatenate(o, axis=1).astype(np.float64) for o in outs], lat, st
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_served_equals_alone(prec, use_graph):
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, prec)
+    lens, xs, order = _workload(24, 6, 1)
+    outs, lat, st = _serve(sc, mod, lens, xs, order, use_graph)
+    log("%s graph=%s: steps %d buffers %d merged %d, latency p50 %.2f ms"
+        % (prec, use_graph, st["steps"], st["buffers"], st["merged_buffers"], 1e3 * np.median(lat)))
+    assert st["buffers"] == 24 * 6
+    assert min(lat) > 0
+    for i in range(len(lens)):
+        alone = run_stream(mod, xs[i], [int(v) for v in lens[i]])
+        assert np.array_equal(outs[i], alone), i
+
+
+def test_graph_replays_equal_eager():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "bf16")
+    lens, xs, order = _workload(12, 10, 2)
+    a, _, _ = _serve(sc, mod, lens, xs, order, True)
+    b, _, _ = _serve(sc, mod, lens, xs, order, False)
+    for i in range(len(lens)):
+        assert np.array_equal(a[i], b[i])
+
+
+def test_budget_admission_fifo():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "bf16")
+    probe = sc.Server(mod, 8, 16)
+    st0 = probe.stats()
+    probe.close()
+    budget = st0["fixed_bytes"] + int(3.5 * st0["per_stream_bytes"])
+    srv = sc.Server(mod, 8, 16, hbm_budget_bytes=budget)
+    assert srv.stats()["max_admitted"] == 3
+    lens, xs, _ = _workload(8, 3, 3)
+    starts = [np.concatenate([[0], np.cumsum(l)]) for l in lens]
+    tickets = {}
+    for i in range(8):                      # streams arrive in id order: FIFO admission
+        for b in range(3):
+            tickets[(i, b)] = srv.submit(i, xs[i][:, int(starts[i][b]):int(starts[i][b + 1])])
+    done_order = []
+    for i in range(8):
+        srv.close_stream(i)
+    srv.drain()
+    st = srv.stats()
+    assert st["buffers"] == 24 and st["admitted"] == 0 and st["waiting"] == 0
+    for i in range(8):
+        got = np.concatenate([srv.poll(tickets[(i, b)], int(lens[i][b]))[0] for b in range(3)], axis=1)
+        alone = run_stream(mod, xs[i], [int(v) for v in lens[i]])
+        assert np.array_equal(got.astype(np.float64), alone)
+        done_order.append(i)
+    srv.close()
+
+
+def test_budget_too_small_is_refused():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "bf16")
+    with pytest.raises(sc.ScError) as ei:
+        sc.Server(mod, 8, 16, hbm_budget_bytes=1024)
+    assert ei.value.status == -3
