@@ -40,6 +40,7 @@ struct Ticket {
   std::vector<float> out;   // [C_out][frames * rate]
   Clock::time_point t_submit, t_done;
   bool done = false;
+  bool failed = false;      // its step could not be enqueued
 };
 
 struct SStream {
@@ -122,7 +123,7 @@ void free_ctx(StepCtx& c) {
 
 // Copies a finished context's outputs to its tickets and releases streams
 // whose last buffer it held.  Called with srv->mu held.
-void finalize(sc_server* srv, StepCtx& c) {
+void finalize(sc_server* srv, StepCtx& c, bool failed = false) {
   const auto now = Clock::now();
   for (Part& p : c.parts) {
     int64_t t_off = 0;
@@ -135,6 +136,7 @@ void finalize(sc_server* srv, StepCtx& c) {
       t_off += Tt;
       t->t_done = now;
       t->done = true;
+      t->failed = failed;
       srv->queued--;
     }
     SStream* st = p.st;
@@ -197,24 +199,9 @@ void worker_main(sc_server* srv) {
     // finalize finished contexts
     for (auto& c : srv->ctx)
       if (c.busy && hipEventQuery(c.done) == hipSuccess) finalize(srv, c);
-    // the next step: one buffer per admitted stream, merging queued buffers
-    std::vector<Part> parts;
-    int64_t total = 0;
-    for (auto& kv : srv->streams) {
-      SStream* st = kv.second.get();
-      if (!st->admitted || st->queue.empty()) continue;
-      Part p;
-      p.st = st;
-      while (!st->queue.empty() && p.frames + st->queue.front()->frames <= srv->cfg.max_buffer_frames) {
-        p.frames += st->queue.front()->frames;
-        p.tickets.push_back(st->queue.front());
-        st->queue.pop_front();
-      }
-      total += p.frames;
-      parts.push_back(std::move(p));
-      if ((int)parts.size() == srv->cfg.max_streams) break;
-    }
-    if (parts.empty()) {
+    bool work = false;
+    for (auto& kv : srv->streams) work |= kv.second->admitted && !kv.second->queue.empty();
+    if (!work) {
       bool any_busy = false;
       for (auto& c : srv->ctx) any_busy |= c.busy;
       if (srv->stop && !any_busy && srv->queued == 0) break;
@@ -235,12 +222,34 @@ void worker_main(sc_server* srv) {
       continue;
     }
     StepCtx& c = srv->ctx[srv->next_ctx];
-    srv->next_ctx = (srv->next_ctx + 1) % kCtx;
     if (c.busy) {
+      // the ring is full: retire its oldest step first (this may free slots)
       lk.unlock();
       hipEventSynchronize(c.done);
       lk.lock();
       finalize(srv, c);
+      continue;
+    }
+    srv->next_ctx = (srv->next_ctx + 1) % kCtx;
+    // the next step: one buffer per admitted stream, merging queued buffers.
+    // A stream counts the step as in flight from here on, so that closing it
+    // cannot free it while the step is formed or running.
+    std::vector<Part> parts;
+    int64_t total = 0;
+    for (auto& kv : srv->streams) {
+      SStream* st = kv.second.get();
+      if (!st->admitted || st->queue.empty()) continue;
+      Part p;
+      p.st = st;
+      while (!st->queue.empty() && p.frames + st->queue.front()->frames <= srv->cfg.max_buffer_frames) {
+        p.frames += st->queue.front()->frames;
+        p.tickets.push_back(st->queue.front());
+        st->queue.pop_front();
+      }
+      st->inflight++;
+      total += p.frames;
+      parts.push_back(std::move(p));
+      if ((int)parts.size() == srv->cfg.max_streams) break;
     }
     // stage inputs (channel-major per stream, merged buffers back to back)
     const int n = (int)parts.size();
@@ -266,7 +275,6 @@ void worker_main(sc_server* srv) {
       nf[i] = p.frames;
       in_off += (int64_t)srv->cin * p.frames;
       out_off += (int64_t)srv->cout * out_frames_of(srv, p.frames);
-      p.st->inflight++;
     }
     const int cap = srv->cfg.use_graph ? srv->cfg.max_streams : n;
     fill_descriptor(c.desc_host, n, cap, ss.data(), din.data(), nf.data(), dout.data(), total);
@@ -299,7 +307,7 @@ void worker_main(sc_server* srv) {
       for (int i = 0; i < n; ++i) ss[i]->bad = true;
       // finalize the failed context so that waiting callers are released
       hipStreamSynchronize(srv->hs);
-      finalize(srv, c);
+      finalize(srv, c, true);
       continue;
     }
     srv->stats.steps++;
@@ -443,6 +451,10 @@ sc_status sc_server_poll(sc_server* srv, int64_t ticket, float* host_out, double
   if (!t->done) {
     if (!srv->worker_error.empty()) return srv_fail(SC_EDEVICE, srv->worker_error);
     return SC_PENDING;
+  }
+  if (t->failed) {
+    srv->tickets.erase(it);
+    return srv_fail(SC_EDEVICE, srv->worker_error);
   }
   if (host_out) std::memcpy(host_out, t->out.data(), t->out.size() * sizeof(float));
   if (latency_s) *latency_s = std::chrono::duration<double>(t->t_done - t->t_submit).count();
