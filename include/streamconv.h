@@ -233,6 +233,23 @@ sc_status sc_server_create(sc_model* model, const sc_server_config* config, sc_s
  * `stream_id`; the stream is opened on first use.  Sets *ticket. */
 sc_status sc_server_submit(sc_server* server, int64_t stream_id, const float* host_in, int32_t n_frames,
                            int64_t* ticket);
+/* Flags of sc_server_submit_batch. */
+enum {
+  SC_SUBMIT_DISCARD = 1u  /* keep no output: at completion the ticket is forgotten
+                             and (ticket, latency) goes to the latency log */
+};
+/* Queues n buffers in order (buffer i: stream stream_ids[i], host memory
+ * host_in[i] of [in_channels][n_frames[i]], copied) under one lock, which
+ * keeps the per-buffer cost low for load generators.  All buffers are checked
+ * first: on an error none is queued.  Sets tickets[i] (may be NULL with
+ * SC_SUBMIT_DISCARD). */
+sc_status sc_server_submit_batch(sc_server* server, int32_t n, const int64_t* stream_ids,
+                                 const float* const* host_in, const int32_t* n_frames, uint32_t flags,
+                                 int64_t* tickets);
+/* Moves up to `max` entries of the latency log (buffers submitted with
+ * SC_SUBMIT_DISCARD, in completion order) to tickets[] / latency_s[]
+ * (seconds from submission to completion) and sets *n to their number. */
+sc_status sc_server_latencies(sc_server* server, int64_t* tickets, double* latency_s, int64_t max, int64_t* n);
 /* SC_OK: done -- copies the output ([out_channels][n_frames * out_num / out_den])
  * to host_out (may be NULL) and the submit-to-completion latency in seconds
  * to *latency_s (may be NULL), and forgets the ticket.  SC_PENDING: not yet. */

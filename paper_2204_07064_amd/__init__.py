@@ -197,6 +197,35 @@ class Server:
                                      ctypes.byref(t)))
         return t.value
 
+    def submit_batch(self, stream_ids, ptrs, frames, discard=True):
+        """Queue len(stream_ids) buffers under one lock.  ptrs: host addresses
+        (int64/uint64 numpy array) of float32 [in_channels][frames[i]] buffers
+        that stay alive for the call.  Returns the tickets; with discard no
+        output is kept and (ticket, latency) goes to latencies()."""
+        ids = np.ascontiguousarray(stream_ids, dtype=np.int64)
+        p = np.ascontiguousarray(ptrs, dtype=np.uint64)
+        f = np.ascontiguousarray(frames, dtype=np.int32)
+        n = len(ids)
+        if len(p) != n or len(f) != n:
+            raise ValueError("stream_ids, ptrs and frames differ in length")
+        t = np.empty(n, np.int64)
+        check(lib().sc_server_submit_batch(
+            self.handle, n, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            p.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)), f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            _native.SC_SUBMIT_DISCARD if discard else 0,
+            t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return t
+
+    def latencies(self, max_n=1 << 20):
+        """(tickets, latency_s) of finished discarded buffers, completion order."""
+        t = np.empty(max_n, np.int64)
+        lat = np.empty(max_n, np.float64)
+        n = ctypes.c_int64()
+        check(lib().sc_server_latencies(self.handle, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), max_n,
+                                        ctypes.byref(n)))
+        return t[:n.value], lat[:n.value]
+
     def poll(self, ticket, frames):
         """(output [out_channels][frames*rate], latency_s) when done, else None."""
         out = np.empty((self.cout, self.model.out_frames(frames)), np.float32)

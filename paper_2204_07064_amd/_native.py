@@ -33,9 +33,10 @@ EXPORTS = [
     "stream_create", "stream_process", "stream_reset", "stream_position", "stream_destroy",
     "sc_process_batch", "sc_last_error", "sc_model_profile", "sc_model_profile_read",
     "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
-    "sc_server_stats_get", "sc_server_destroy",
+    "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
 ]
 SC_PENDING = 1
+SC_SUBMIT_DISCARD = 1
 
 
 class ScNode(ctypes.Structure):
@@ -119,6 +120,8 @@ def lib():
     _sig(L, "sc_server_drain", c_i32, [c_vp])
     _sig(L, "sc_server_stats_get", c_i32, [c_vp, P(ScServerStats)])
     _sig(L, "sc_server_destroy", None, [c_vp])
+    _sig(L, "sc_server_submit_batch", c_i32, [c_vp, c_i32, P(c_i64), P(c_vp), P(c_i32), c_u32, P(c_i64)])
+    _sig(L, "sc_server_latencies", c_i32, [c_vp, P(c_i64), P(ctypes.c_double), c_i64, P(c_i64)])
     _LIB = L
     return L
 

@@ -41,6 +41,7 @@ struct Ticket {
   Clock::time_point t_submit, t_done;
   bool done = false;
   bool failed = false;      // its step could not be enqueued
+  bool discard = false;     // SC_SUBMIT_DISCARD
 };
 
 struct SStream {
@@ -98,6 +99,7 @@ struct sc_server {
   bool stop = false;
   std::string worker_error;
   sc_server_stats stats{};
+  std::deque<std::pair<int64_t, double>> lat_log;   // (ticket, latency) of discarded buffers
 };
 
 namespace {
@@ -130,6 +132,14 @@ void finalize(sc_server* srv, StepCtx& c, bool failed = false) {
     const int64_t T = out_frames_of(srv, p.frames);
     for (Ticket* t : p.tickets) {
       const int64_t Tt = out_frames_of(srv, t->frames);
+      srv->queued--;
+      if (t->discard) {
+        if (!failed)
+          srv->lat_log.emplace_back(t->id, std::chrono::duration<double>(now - t->t_submit).count());
+        t_off += Tt;
+        srv->tickets.erase(t->id);
+        continue;
+      }
       t->out.resize((size_t)srv->cout * Tt);
       for (int co = 0; co < srv->cout; ++co)
         std::memcpy(&t->out[(size_t)co * Tt], c.out_host + p.out_off + (int64_t)co * T + t_off, Tt * sizeof(float));
@@ -137,7 +147,6 @@ void finalize(sc_server* srv, StepCtx& c, bool failed = false) {
       t->t_done = now;
       t->done = true;
       t->failed = failed;
-      srv->queued--;
     }
     SStream* st = p.st;
     st->inflight--;
@@ -346,6 +355,53 @@ sc_status alloc_ctx(sc_server* srv, StepCtx& c) {
 
 }  // namespace
 
+namespace {
+
+sc_status check_buffer(const sc_server* srv, const float* host_in, int32_t n_frames) {
+  if (!host_in) return srv_fail(SC_EINVAL, "null input buffer");
+  if (n_frames < 1 || n_frames > srv->cfg.max_buffer_frames || n_frames % srv->m->plan.input_multiple)
+    return srv_fail(SC_ELENGTH, "buffer length must be in [1, max_buffer_frames] and a multiple of the total stride");
+  return SC_OK;
+}
+
+// Whether a buffer for stream_id may be queued now.  Called with srv->mu held.
+sc_status check_stream(const sc_server* srv, int64_t stream_id) {
+  auto it = srv->streams.find(stream_id);
+  if (it != srv->streams.end() && it->second->closing)
+    return srv_fail(SC_ESTATE, "stream is closing; wait for its buffers");
+  return SC_OK;
+}
+
+// Queues one checked buffer.  Called with srv->mu held.
+int64_t enqueue_buffer(sc_server* srv, int64_t stream_id, const float* host_in, int32_t n_frames, bool discard,
+                       Clock::time_point now) {
+  std::unique_ptr<Ticket> t(new Ticket());
+  t->stream_id = stream_id;
+  t->frames = n_frames;
+  t->discard = discard;
+  t->in.assign(host_in, host_in + (size_t)srv->cin * n_frames);
+  t->t_submit = now;
+  auto it = srv->streams.find(stream_id);
+  SStream* st;
+  if (it == srv->streams.end()) {
+    std::unique_ptr<SStream> ns(new SStream());
+    ns->id = stream_id;
+    st = ns.get();
+    srv->streams[stream_id] = std::move(ns);
+    srv->waiting.push_back(st);
+  } else {
+    st = it->second.get();
+  }
+  t->id = srv->next_ticket++;
+  const int64_t id = t->id;
+  st->queue.push_back(t.get());
+  srv->queued++;
+  srv->tickets[id] = std::move(t);
+  return id;
+}
+
+}  // namespace
+
 extern "C" {
 
 sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server** out) {
@@ -407,38 +463,61 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   return SC_OK;
 }
 
+
 sc_status sc_server_submit(sc_server* srv, int64_t stream_id, const float* host_in, int32_t n_frames,
                            int64_t* ticket) {
-  if (!srv || !host_in || !ticket) return srv_fail(SC_EINVAL, "null argument");
-  if (n_frames < 1 || n_frames > srv->cfg.max_buffer_frames || n_frames % srv->m->plan.input_multiple)
-    return srv_fail(SC_ELENGTH, "buffer length must be in [1, max_buffer_frames] and a multiple of the total stride");
-  std::unique_ptr<Ticket> t(new Ticket());
-  t->stream_id = stream_id;
-  t->frames = n_frames;
-  t->in.assign(host_in, host_in + (size_t)srv->cin * n_frames);
-  t->t_submit = Clock::now();
+  if (!srv || !ticket) return srv_fail(SC_EINVAL, "null argument");
+  sc_status st = check_buffer(srv, host_in, n_frames);
+  if (st != SC_OK) return st;
   {
     std::lock_guard<std::mutex> g(srv->mu);
     if (!srv->worker_error.empty()) return srv_fail(SC_EDEVICE, srv->worker_error);
-    auto it = srv->streams.find(stream_id);
-    SStream* st;
-    if (it == srv->streams.end() || it->second->closing) {
-      if (it != srv->streams.end()) return srv_fail(SC_ESTATE, "stream is closing; wait for its buffers");
-      std::unique_ptr<SStream> ns(new SStream());
-      ns->id = stream_id;
-      st = ns.get();
-      srv->streams[stream_id] = std::move(ns);
-      srv->waiting.push_back(st);
-    } else {
-      st = it->second.get();
-    }
-    t->id = srv->next_ticket++;
-    *ticket = t->id;
-    st->queue.push_back(t.get());
-    srv->queued++;
-    srv->tickets[t->id] = std::move(t);
+    st = check_stream(srv, stream_id);
+    if (st != SC_OK) return st;
+    *ticket = enqueue_buffer(srv, stream_id, host_in, n_frames, false, Clock::now());
   }
   srv->cv.notify_one();
+  return SC_OK;
+}
+
+sc_status sc_server_submit_batch(sc_server* srv, int32_t n, const int64_t* stream_ids, const float* const* host_in,
+                                 const int32_t* n_frames, uint32_t flags, int64_t* tickets) {
+  if (!srv || n < 0 || (n > 0 && (!stream_ids || !host_in || !n_frames))) return srv_fail(SC_EINVAL, "null argument");
+  if (flags & ~(uint32_t)SC_SUBMIT_DISCARD) return srv_fail(SC_EINVAL, "unknown submit flags");
+  const bool discard = flags & SC_SUBMIT_DISCARD;
+  if (!tickets && !discard) return srv_fail(SC_EINVAL, "tickets may be NULL only with SC_SUBMIT_DISCARD");
+  for (int32_t i = 0; i < n; ++i) {
+    sc_status st = check_buffer(srv, host_in[i], n_frames[i]);
+    if (st != SC_OK) return st;
+  }
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (!srv->worker_error.empty()) return srv_fail(SC_EDEVICE, srv->worker_error);
+    for (int32_t i = 0; i < n; ++i) {
+      sc_status st = check_stream(srv, stream_ids[i]);
+      if (st != SC_OK) return st;
+    }
+    const auto now = Clock::now();
+    for (int32_t i = 0; i < n; ++i) {
+      const int64_t id = enqueue_buffer(srv, stream_ids[i], host_in[i], n_frames[i], discard, now);
+      if (tickets) tickets[i] = id;
+    }
+  }
+  srv->cv.notify_one();
+  return SC_OK;
+}
+
+sc_status sc_server_latencies(sc_server* srv, int64_t* tickets, double* latency_s, int64_t max, int64_t* n) {
+  if (!srv || !n || max < 0 || (max > 0 && (!tickets || !latency_s))) return srv_fail(SC_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(srv->mu);
+  int64_t k = 0;
+  while (k < max && !srv->lat_log.empty()) {
+    tickets[k] = srv->lat_log.front().first;
+    latency_s[k] = srv->lat_log.front().second;
+    srv->lat_log.pop_front();
+    ++k;
+  }
+  *n = k;
   return SC_OK;
 }
 

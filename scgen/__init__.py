@@ -20,4 +20,4 @@ from .models import (  # noqa: F401
 )
 from .weights import init_weights  # noqa: F401
 from .inputs import (  # noqa: F401
-    latents, stream_latents, buffer_lengths, split_lengths, random_split, STREAM_SEED_BASE)
+    latents, stream_latents, buffer_lengths, split_lengths, random_split, poisson_arrivals, STREAM_SEED_BASE)

@@ -51,3 +51,10 @@ def random_split(total, seed, max_buf, multiple=1):
         out.append(b * multiple)
         left -= b
     return out
+
+
+def poisson_arrivals(n, rate, seed):
+    """``n`` arrival times (seconds from 0) of a Poisson process of ``rate``
+    events per second: cumulative sums of exponential gaps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

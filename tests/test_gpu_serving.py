@@ -126,3 +126,38 @@ def test_budget_too_small_is_refused():
     with pytest.raises(sc.ScError) as ei:
         sc.Server(mod, 8, 16, hbm_budget_bytes=1024)
     assert ei.value.status == -3
+
+
+def test_submit_batch_and_latency_log():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, "bf16")
+    lens, xs, order = _workload(16, 5, 4)
+    starts = [np.concatenate([[0], np.cumsum(l)]) for l in lens]
+    bufs = []
+    for (i, b) in order:
+        bufs.append(np.ascontiguousarray(xs[i][:, int(starts[i][b]):int(starts[i][b + 1])], dtype=np.float32))
+    ids = np.array([i for i, _ in order], np.int64)
+    ptrs = np.array([x.ctypes.data for x in bufs], np.uint64)
+    fr = np.array([x.shape[1] for x in bufs], np.int32)
+    srv = sc.Server(mod, 16, 16)
+    half = len(order) // 2
+    t_keep = srv.submit_batch(ids[:half], ptrs[:half], fr[:half], discard=False)
+    t_disc = srv.submit_batch(ids[half:], ptrs[half:], fr[half:], discard=True)
+    srv.drain()
+    tick, lat = srv.latencies()
+    assert sorted(tick.tolist()) == sorted(t_disc.tolist())
+    assert np.all(lat > 0)
+    got = {}
+    for k in range(half):
+        got[order[k]] = srv.poll(int(t_keep[k]), int(fr[k]))[0]
+    srv.close()
+    # the kept outputs equal the first buffers of each stream processed alone
+    for i in range(16):
+        mine = [b for (j, b) in order[:half] if j == i]
+        if not mine:
+            continue
+        alone = run_stream(mod, xs[i], [int(v) for v in lens[i]])
+        n_out = sum(int(lens[i][b]) for b in mine) * 128
+        ref = alone[:, :n_out]
+        assert np.array_equal(np.concatenate([got[(i, b)] for b in mine], axis=1).astype(np.float64), ref)
