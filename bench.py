@@ -45,6 +45,29 @@ PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
 DTYPE = {0: "fp32", 1: "bf16", 2: "fp8e4m3"}
 
 
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (KiB per dispatch), each scaled by what the counter reads for a plain copy
+# of known size.  Valid only for the kernel sources it was taken with.
+MEASURED_TRAFFIC = {
+    "kernel": "conv_mfma node 25 (cin 32, cout 32, k 3, d 1)",
+    "sources_sha1": "aba1a37cae6d961b52992599fac9e0b9796726b2 5d38a60eb4fb637ab8214808638dfa6abbc7442f "
+                    "1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "fetch_kib": 32568.8, "write_kib": 64777.9,
+    "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
+}
+TRAFFIC_SOURCES = ("kernels_mfma.hip", "kernels.h", "sc_device.h")
+
+
+def measured_traffic(kernel):
+    import hashlib
+    d = os.path.join(ROOT, "paper_2204_07064_amd", "csrc")
+    sha = " ".join(hashlib.sha1(open(os.path.join(d, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES)
+    t = MEASURED_TRAFFIC
+    if kernel != t["kernel"] or sha != t["sources_sha1"]:
+        return None
+    return round(t["fetch_kib"] * t["fetch_bytes_per_kib"] + t["write_kib"] * t["write_bytes_per_kib"])
+
+
 def op_accounting(p):
     """Algorithmic FLOPs and HBM bytes of one op summed over its timed
     launches: inputs read once, outputs written once, state (caches, carries,
@@ -79,10 +102,12 @@ def roofline(prof):
         bound, ach, peak, unit = "hbm", byts / sec / 1e9, HBM_PEAK / 1e9, "GB/s"
     kname = {1: "conv", 2: "convt", 3: "delay_add"}[best["kind"]]
     impl = "mfma" if best["impl"] == 1 else "valu"
+    kernel = "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
+        kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": None,
-            "kernel": "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
-                kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"]),
+            "frac": round(ach / peak, 4), "traffic": measured_traffic(kernel),
+            "algorithmic_bytes_per_launch": round(byts / max(best["launches"], 1)),
+            "kernel": kernel,
             "avg_launch_us": round(best["ms"] * 1e3 / max(best["launches"], 1), 2),
             "share_of_step": round(best["ms"] / sum(p["ms"] for p in prof), 3)}
 
@@ -269,6 +294,79 @@ def cpu_baseline(budget_s=12.0):
                       "offline FP64 numpy, %.1f s" % (n, samples, dt)}
 
 
+def summarize(run_dir):
+    """Per-layer figures from rocprofv3 CSV output under run_dir (a kernel
+    trace and/or counter collections of one `bench.py --no-serving` run whose
+    JSON line is in run_dir/bench.json).  Dispatches are mapped to layers by
+    their position in each step: every step launches the same kernels in
+    plan order, optionally preceded by the input packing kernel."""
+    import csv
+    import glob
+    with open(os.path.join(run_dir, "bench.json")) as f:
+        bench = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    ops = bench["per_kernel"]
+    lines = []
+
+    def ours(name):
+        return "sc::" in name and "fill_zero" not in name and "amax" not in name
+
+    def per_op(rows, key):
+        rows = sorted(rows, key=lambda r: int(r["Start_Timestamp"]))
+        rows = [r for r in rows if ours(r["Kernel_Name"])]
+        K = len(ops) + (1 if rows and "pack_input" in rows[0]["Kernel_Name"] else 0)
+        if len(rows) % K:
+            raise SystemExit("dispatch count %d is not a multiple of %d launches per step" % (len(rows), K))
+        sums = np.zeros(K)
+        for i, r in enumerate(rows):
+            sums[i % K] += key(r)
+        return rows, K, sums / (len(rows) // K), len(rows) // K
+
+    for path in sorted(glob.glob(os.path.join(run_dir, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        rows, K, avg, steps = per_op(rows, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        lines.append("kernel trace: %d steps x %d launches (%s)" % (steps, K, os.path.relpath(path, run_dir)))
+        lines.append("%-5s %-6s %-5s %-5s %-5s %-3s %10s %10s  %s" % (
+            "node", "kind", "impl", "cin", "cout", "d", "rocprof_us", "events_us", "kernel"))
+        off = K - len(ops)
+        if off:
+            lines.append("%-5s %-6s %-5s %-5s %-5s %-3s %10.2f %10s  %s" % (
+                "-", "pack", "valu", "-", "-", "-", avg[0], "-", rows[0]["Kernel_Name"][:60]))
+        for j, o in enumerate(ops):
+            lines.append("%-5d %-6s %-5s %-5d %-5d %-3d %10.2f %10.2f  %s" % (
+                o["node"], {1: "conv", 2: "convt", 3: "add"}[o["kind"]], "mfma" if o["impl"] else "valu",
+                o["cin"], o["cout"], o["d"], avg[j + off], o["avg_us"], rows[j + off]["Kernel_Name"][:60]))
+        lines.append("step sum: rocprof %.1f us" % avg.sum())
+    for path in sorted(glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        for cname in sorted({r["Counter_Name"] for r in rows}):
+            sel = [r for r in rows if r["Counter_Name"] == cname]
+            sel, K, avg, steps = per_op(sel, lambda r: float(r["Counter_Value"]))
+            off = K - len(ops)
+            lines.append("%s per dispatch (%d steps, %s):" % (cname, steps, os.path.relpath(path, run_dir)))
+            for j, o in enumerate(ops):
+                lines.append("  node %-3d %-5s cin %-4d cout %-4d  %.1f" % (
+                    o["node"], "mfma" if o["impl"] else "valu", o["cin"], o["cout"], avg[j + off]))
+    print("\n".join(lines))
+
+
+def copy_probe_summary(run_dir, nbytes):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB) of the copy kernel of a
+    `--copy-probe` run, and the factor that turns each into bytes."""
+    import csv
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as f:
+            rows = [r for r in csv.DictReader(f) if int(r["Grid_Size"]) > 4096]
+        for cname in sorted({r["Counter_Name"] for r in rows}):
+            v = np.mean([float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == cname])
+            out.append("%s: %.1f KiB per copy of %d bytes -> factor %.4f (bytes per KiB counted)" % (
+                cname, v, nbytes, nbytes / v))
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +378,15 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--summarize", metavar="DIR", help="print per-layer figures from rocprofv3 CSVs under DIR")
+    ap.add_argument("--summarize-copy", metavar="DIR", help="print the copy-probe counter factors under DIR")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
+    if args.summarize_copy:
+        copy_probe_summary(args.summarize_copy, args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: streams are independent and the path has no cross-GPU "
               "step; run with --gpus 1", file=sys.stderr)
