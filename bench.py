@@ -43,6 +43,7 @@ HBM_PEAK = 8.0e12  # B/s
 PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
 PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
 DTYPE = {0: "fp32", 1: "bf16", 2: "fp8e4m3"}
+IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
@@ -93,15 +94,15 @@ def roofline(prof):
     best = max(prof, key=lambda p: p["ms"])
     flops, byts = op_accounting(best)
     sec = best["ms"] * 1e-3
-    peak_f = PEAK[best["precision"]] if best["impl"] == 1 else PEAK[0]
+    peak_f = PEAK[best["precision"]] if best["impl"] >= 1 else PEAK[0]
     ridge = peak_f / HBM_PEAK
     if flops / max(byts, 1.0) >= ridge:
-        bound = "mfma" if best["impl"] == 1 else "alu"
+        bound = "mfma" if best["impl"] >= 1 else "alu"
         ach, peak, unit = flops / sec / 1e12, peak_f / 1e12, "TFLOP/s"
     else:
         bound, ach, peak, unit = "hbm", byts / sec / 1e9, HBM_PEAK / 1e9, "GB/s"
     kname = {1: "conv", 2: "convt", 3: "delay_add"}[best["kind"]]
-    impl = "mfma" if best["impl"] == 1 else "valu"
+    impl = IMPL_NAME[best["impl"]]
     kernel = "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
         kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
@@ -334,7 +335,7 @@ def summarize(run_dir):
                 "-", "pack", "valu", "-", "-", "-", avg[0], "-", rows[0]["Kernel_Name"][:60]))
         for j, o in enumerate(ops):
             lines.append("%-5d %-6s %-5s %-5d %-5d %-3d %10.2f %10.2f  %s" % (
-                o["node"], {1: "conv", 2: "convt", 3: "add"}[o["kind"]], "mfma" if o["impl"] else "valu",
+                o["node"], {1: "conv", 2: "convt", 3: "add"}[o["kind"]], IMPL_NAME[o["impl"]],
                 o["cin"], o["cout"], o["d"], avg[j + off], o["avg_us"], rows[j + off]["Kernel_Name"][:60]))
         lines.append("step sum: rocprof %.1f us" % avg.sum())
     for path in sorted(glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)):
@@ -347,7 +348,7 @@ def summarize(run_dir):
             lines.append("%s per dispatch (%d steps, %s):" % (cname, steps, os.path.relpath(path, run_dir)))
             for j, o in enumerate(ops):
                 lines.append("  node %-3d %-5s cin %-4d cout %-4d  %.1f" % (
-                    o["node"], "mfma" if o["impl"] else "valu", o["cin"], o["cout"], avg[j + off]))
+                    o["node"], IMPL_NAME[o["impl"]], o["cin"], o["cout"], avg[j + off]))
     print("\n".join(lines))
 
 
@@ -415,7 +416,7 @@ def main():
     run = timed_run(sc, torch, model, args.warmup, args.steps)
     prof_run = timed_run(sc, torch, model, args.warmup, args.steps, profile=True)
     prof = prof_run["prof"]
-    used = sorted({p["precision"] for p in prof if p["impl"] == 1})
+    used = sorted({p["precision"] for p in prof if p["impl"] >= 1})
     value = run["samples"] / run["gpu_s"]
     out = {
         "metric": "output audio samples/sec at 256 streams (BF16/FP8 vs FP32); p99 buffer latency",

@@ -128,9 +128,13 @@ enum {
                                instead of the fused centre-tap skip */
   SC_MODEL_NO_MFMA = 2u,    /* run every layer on the FP32 wavefront-FMA kernels
                                (precision must be SC_FP32) */
-  SC_MODEL_NO_TWIN = 4u     /* MFMA layers activate and round their input on load
+  SC_MODEL_NO_TWIN = 4u,    /* MFMA layers activate and round their input on load
                                instead of reading the copy their producer wrote in
                                operand form (same results; for testing) */
+  SC_MODEL_NO_WIN = 8u      /* narrow stride-1 MFMA convs gather their operands
+                               chunk by chunk instead of staging each tile's
+                               [cache | new frames] window in LDS (same results;
+                               for testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,
@@ -178,7 +182,8 @@ sc_status sc_process_batch(sc_model* model, int32_t n, sc_stream* const* streams
 /* ---- tracing: per-launch timing with HIP events on the processing stream ---- */
 typedef struct {
   int32_t kind;        /* 1 conv (with fused skip if residual), 2 transposed conv, 3 delay-line sum */
-  int32_t impl;        /* 0 FP32 wavefront FMA, 1 MFMA implicit GEMM */
+  int32_t impl;        /* 0 FP32 wavefront FMA, 1 MFMA implicit GEMM (gathered
+                          operands), 2 MFMA with LDS-staged windows */
   int32_t precision;   /* sc_precision of this launch's operands */
   int32_t node;        /* node whose output the launch writes */
   int32_t cin, cout, k, dilation, stride, cache_len, residual;

@@ -79,6 +79,10 @@ hipError_t launch_amax(const LayerArgs& a, float* amax, hipStream_t s);
 hipError_t launch_conv_mfma(const LayerArgs& a, int prec, hipStream_t s);
 hipError_t launch_convt_mfma(const LayerArgs& a, int prec, hipStream_t s);
 bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec);
+// LDS-window MFMA conv: the window rows one tile needs at most (0 if the layer
+// does not qualify); min_frames = the fewest frames a stream brings to the layer.
+int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec);
+hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s);
 bool convt_mfma_supported(int cin, int cout, int r, int prec);
 // Host packing of weights into the MFMA kernels' tile order (and, for FP8,
 // per-output-row scales).  conv: W[cout][cin][k]; convt: W[cin][cout][2r].

@@ -1,0 +1,430 @@
+// LDS-window MFMA kernel for cached stride-1 convs with narrow inputs (gfx950).
+//
+// Cached padding (Sec. 2.2): output frame t of a stream reads rows
+// t + dil * tap of that stream's window [cache (L frames) | new frames].  A
+// workgroup computes output rows [m0, m0 + MT) for F consecutive frames of the
+// step's packed frame space.  Those frames may belong to a few streams; for
+// each of them the workgroup copies, once, the window rows its columns read
+// (the columns' own rows plus the L rows behind the first of them) into LDS as
+// raw FP32, back to back.  Column c then finds the row of tap `tap` at
+// colbase[c] + dil * tap, whatever stream it belongs to; the residual skip is
+// the row colbase[c] + skip_off of the same staged rows.  LeakyReLU and the
+// operand rounding (BF16 RNE, or FP8 e4m3 with the layer's static activation
+// scale) are applied on the way from LDS into the MFMA registers.
+//
+// Compared with the gather kernel this reads every input element from HBM
+// once per tile (plus the L-row halo), keeps all per-element address work out
+// of the K loop, and needs no pre-rounded operand copy from the producer.
+//
+// The reduction order over K is that of the gather kernel (same packed
+// weights, same 128-byte chunks, same MFMA instructions), so both kernels
+// produce the same bits for the same layer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace sc {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxStreams = 8;     // streams one tile may touch (the host guarantees it)
+constexpr int kStageBatch = 4;     // 16-byte staging loads in flight per thread
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct WPrec;
+// kMaxChunks: 128-byte K chunks held in registers (k = 3 taps of up to 64
+// channels in BF16 / FP8, 32 in FP32)
+template <> struct WPrec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; static constexpr int kMaxChunks = 3; };
+template <> struct WPrec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; static constexpr int kMaxChunks = 3; };
+template <> struct WPrec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; static constexpr int kMaxChunks = 2; };
+
+__device__ inline uint32_t wpack_bf16(float lo, float hi) {
+  bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return u;
+}
+
+__device__ inline uint32_t wpack_fp8x4(float a, float b, float c, float d) {
+  int v = 0;
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(a), sat448(b), v, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), v, true);
+  return (uint32_t)v;
+}
+
+__device__ inline float act(float v, bool pre) { return pre ? lrelu(v) : v; }
+
+__device__ inline int w_esize_dev(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
+
+// 16 bytes of operand (4 FP32, 8 BF16 or 16 FP8 values) from FP32 values in LDS
+// starting at p, with the pre-activation and the FP8 activation scale.
+template <int PREC>
+__device__ inline u4 operand16(const float* p, bool pre, float qs) {
+  u4 r;
+  if constexpr (PREC == 0) {
+    const f4 v = *reinterpret_cast<const f4*>(p);
+    r[0] = __float_as_uint(act(v.x, pre));
+    r[1] = __float_as_uint(act(v.y, pre));
+    r[2] = __float_as_uint(act(v.z, pre));
+    r[3] = __float_as_uint(act(v.w, pre));
+  } else if constexpr (PREC == 1) {
+    const f4 v0 = *reinterpret_cast<const f4*>(p);
+    const f4 v1 = *reinterpret_cast<const f4*>(p + 4);
+    r[0] = wpack_bf16(act(v0.x, pre), act(v0.y, pre));
+    r[1] = wpack_bf16(act(v0.z, pre), act(v0.w, pre));
+    r[2] = wpack_bf16(act(v1.x, pre), act(v1.y, pre));
+    r[3] = wpack_bf16(act(v1.z, pre), act(v1.w, pre));
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f4 v = *reinterpret_cast<const f4*>(p + 4 * q);
+      r[q] = wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
+    }
+  }
+  return r;
+}
+
+template <int PREC>
+__device__ inline f4 mfma32(const u4& alo, const u4& ahi, const u4& blo, const u4& bhi, f4 acc) {
+  if constexpr (PREC == 0) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(alo[0]), __uint_as_float(blo[0]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(alo[1]), __uint_as_float(blo[1]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(alo[2]), __uint_as_float(blo[2]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(alo[3]), __uint_as_float(blo[3]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ahi[0]), __uint_as_float(bhi[0]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ahi[1]), __uint_as_float(bhi[1]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ahi[2]), __uint_as_float(bhi[2]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(ahi[3]), __uint_as_float(bhi[3]), acc, 0, 0, 0);
+  } else if constexpr (PREC == 1) {
+    bf16x8 a0, a1, b0, b1;
+    __builtin_memcpy(&a0, &alo, 16);
+    __builtin_memcpy(&a1, &ahi, 16);
+    __builtin_memcpy(&b0, &blo, 16);
+    __builtin_memcpy(&b1, &bhi, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
+  } else {
+    i8v av, bv;
+    __builtin_memcpy(&av, &alo, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(&av) + 16, &ahi, 16);
+    __builtin_memcpy(&bv, &blo, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(&bv) + 16, &bhi, 16);
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+  }
+  return acc;
+}
+
+// Per-stream part of a tile (LDS).
+struct WinSeg {
+  const float* cache;     // current cache copy [L][cin]
+  int64_t pos;
+  int32_t in_start;       // first packed input frame of the stream
+  int32_t out_start;      // first packed output frame (equal for stride 1)
+  int32_t r0;             // first window row staged
+  int32_t base;           // first LDS row of this stream's rows
+  int32_t rows;
+  int32_t flags;
+};
+
+// MT x F tile, 4 waves: MT = 32 -> 2 x 2 waves of 16 x (F / 2); MT = 64 ->
+// 4 x 1 waves of 16 x F.  Either way a wave owns 4 column blocks of 16.
+template <int PREC, int MT>
+__global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
+                                                             int row_cap, int extra_blocks, FastDiv fd_per_ent,
+                                                             FastDiv fd_ppr) {
+  constexpr int F = MT == 32 ? 128 : 64;
+  constexpr int WM = MT / 16;
+  constexpr int WN = 4 / WM;
+  constexpr int NB = F / WN / 16;
+  static_assert(NB == 4, "four column blocks per wave");
+  constexpr int ES = WPrec<PREC>::kEsize;
+  constexpr int kMaxChunks = WPrec<PREC>::kMaxChunks;
+
+  extern __shared__ __attribute__((aligned(16))) float win[];   // [row_cap][cin + 4]
+  __shared__ WinSeg segs[kMaxStreams];
+  __shared__ int32_t colbase[F];
+  __shared__ int8_t colseg[F];
+  __shared__ int32_t tile_info[4];   // e_first, n_seg, total rows, ok
+
+  const int tid = threadIdx.x;
+  const int32_t n_tiles = n_mt * n_nt;
+  const int32_t bid = blockIdx.x;
+
+  // ---- cache update blocks (after the tiles): new cache = last L window rows ----
+  if (bid >= n_tiles) {
+    const int32_t per_ent = a.L * a.cin;
+    const int32_t total = step_ents(a) * per_ent;
+    for (int32_t j = (bid - n_tiles) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
+      const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
+      const int32_t rem = j - ei * per_ent;
+      const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
+      const int ci = rem - i * a.cin;
+      const Entry& e = a.ents[ei];
+      const int32_t row = in_frames(a, e.T) + i;
+      float v;
+      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci];
+      else v = a.in_buf[((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci];
+      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = v;
+    }
+    return;
+  }
+
+  const int mt = (int)((uint32_t)bid % (uint32_t)n_mt);
+  const int32_t nt = (int32_t)((uint32_t)bid / (uint32_t)n_mt);
+  const int m0 = mt * MT;
+  const int32_t f0 = nt * F;
+  const int32_t n_cols = step_out(a);   // the grid may be sized for a larger step
+  if (f0 >= n_cols) return;
+  const int32_t f_last = min(f0 + F, n_cols) - 1;
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int n_chunks = Kpad * ES / 128;
+  const bool pre = a.pre_act != 0;
+  const float qs = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
+  const int cin = a.cin;
+  const int rowf = cin + 4;               // LDS row stride (floats), padded against bank conflicts
+
+  // weights of the wave's 16 rows, all chunks (independent of the columns: issued first)
+  u4 alo[kMaxChunks], ahi[kMaxChunks];
+  {
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.W) +
+                                (int64_t)(m0 + wm * 16 + lr) * (Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) {
+      if (c < n_chunks) {
+        alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+        ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+      }
+    }
+  }
+  // epilogue operands of the lane's rows m .. m + 3
+  const int m = m0 + wm * 16 + lg * 4;
+  const bool m_ok = m < a.cout;
+  const f4 bias = m_ok ? *reinterpret_cast<const f4*>(a.B + m) : f4{0.f, 0.f, 0.f, 0.f};
+  const f4 wsc = (PREC == 2 && m_ok) ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+
+  // ---- the streams of the tile ----
+  if (tid == 0) {
+    const int e0 = entry_of_out(a, f0);
+    const int e1 = entry_of_out(a, f_last);
+    tile_info[0] = e0;
+    tile_info[1] = e1 - e0 + 1;
+  }
+  __syncthreads();
+  const int e_first = tile_info[0];
+  const int n_seg = tile_info[1];
+  if (tid < n_seg && tid < kMaxStreams) {
+    const Entry& e = a.ents[e_first + tid];
+    WinSeg g;
+    g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+    g.pos = e.pos;
+    g.flags = e.flags;
+    g.in_start = in_frames(a, e.off);
+    g.out_start = out_frames(a, e.off);
+    const int32_t T = out_frames(a, e.T);
+    const int32_t t_first = tid == 0 ? f0 - g.out_start : 0;
+    const int32_t t_last = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
+    g.r0 = t_first;
+    g.rows = t_last - t_first + 1 + a.L;
+    g.base = 0;
+    segs[tid] = g;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int32_t b = 0;
+    for (int s = 0; s < n_seg && s < kMaxStreams; ++s) {
+      segs[s].base = b;
+      b += segs[s].rows;
+    }
+    tile_info[2] = b;
+    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap) ? 1 : 0;
+  }
+  __syncthreads();
+  // the host sizes tiles so that this holds; never index LDS beyond it
+  if (!tile_info[3]) return;
+  const int32_t R = tile_info[2];
+
+  // column -> stream, and the LDS row of its window row t
+  if (tid < F) {
+    const int32_t f = f0 + tid;
+    int s = 0;
+    if (f <= f_last) {
+      while (s + 1 < n_seg && segs[s + 1].out_start <= f) ++s;
+      colbase[tid] = segs[s].base + (f - segs[s].out_start - segs[s].r0);
+    } else {
+      colbase[tid] = 0;
+      s = -1;
+    }
+    colseg[tid] = (int8_t)s;
+  }
+
+  // ---- stage the window rows (raw FP32) ----
+  {
+    const int ppr = cin >> 2;              // 16-byte pieces per row
+    const int32_t n_pieces = R * ppr;
+    for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * kStageBatch) {
+      f4 v[kStageBatch];
+      int32_t dst[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int32_t idx = i0 + u * kThreads + tid;
+        dst[u] = -1;
+        v[u] = f4{0.f, 0.f, 0.f, 0.f};
+        if (idx < n_pieces) {
+          const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
+          const int pc = idx - j * ppr;
+          int s = 0;
+          while (s + 1 < n_seg && segs[s + 1].base <= j) ++s;
+          const int32_t r = segs[s].r0 + (j - segs[s].base);
+          const float* src = r < a.L ? segs[s].cache + (int64_t)r * cin
+                                     : a.in_buf + ((int64_t)segs[s].in_start + r - a.L) * cin;
+          v[u] = *reinterpret_cast<const f4*>(src + pc * 4);
+          dst[u] = j * rowf + pc * 4;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (dst[u] >= 0) *reinterpret_cast<f4*>(&win[dst[u]]) = v[u];
+    }
+  }
+  __syncthreads();
+
+  // ---- K loop: B operands from the staged rows ----
+  int cb[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) cb[nb] = colbase[wn * (F / WN) + nb * 16 + lr];
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int c = 0; c < kMaxChunks; ++c) {
+    if (c < n_chunks) {
+      // the lane's two 16-byte pieces of this chunk: element kk -> (tap, ci)
+      int off[2];
+      bool live[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int kk = (c * 128 + lg * 32 + p * 16) / ES;
+        live[p] = kk < Kreal;
+        const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
+        off[p] = tap * a.dil * rowf + (kk - tap * cin);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float* rowp = &win[cb[nb] * rowf];
+        const u4 z = {0u, 0u, 0u, 0u};
+        const u4 blo = live[0] ? operand16<PREC>(rowp + off[0], pre, qs) : z;
+        const u4 bhi = live[1] ? operand16<PREC>(rowp + off[1], pre, qs) : z;
+        acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo, bhi, acc[nb]);
+      }
+    }
+  }
+
+  // ---- epilogue: lane holds rows m .. m + 3 of column col for each block ----
+  if (!m_ok) return;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = wn * (F / WN) + nb * 16 + lr;
+    const int s = colseg[col];
+    if (s < 0) continue;
+    const int32_t f = f0 + col;
+    const int32_t t = f - segs[s].out_start;
+    f4 v = acc[nb];
+    if (PREC == 2) v = v * (wsc * a.act_scale);
+    v = v + bias;
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(&win[(cb[nb] + a.skip_off) * rowf + m]);
+    if ((segs[s].flags & SC_FLAG_WARMUP_MASK) &&
+        (segs[s].pos * (int64_t)a.out_num + (int64_t)t * a.out_den < a.delay * (int64_t)a.out_den))
+      v = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t o = (int64_t)f * a.cout + m;
+    *reinterpret_cast<f4*>(a.out_buf + o) = v;
+    if (a.out_twin) {
+      f4 w = v;
+      if (a.twin_pre) {
+        w.x = lrelu(w.x);
+        w.y = lrelu(w.y);
+        w.z = lrelu(w.z);
+        w.w = lrelu(w.w);
+      }
+      const float q = a.twin_qs;
+      unsigned char* dst = static_cast<unsigned char*>(a.out_twin) + o * w_esize_dev(a.twin_prec);
+      if (a.twin_prec == 0) {
+        *reinterpret_cast<f4*>(dst) = w * q;
+      } else if (a.twin_prec == 1) {
+        uint2 u;
+        u.x = wpack_bf16(w.x * q, w.y * q);
+        u.y = wpack_bf16(w.z * q, w.w * q);
+        *reinterpret_cast<uint2*>(dst) = u;
+      } else {
+        *reinterpret_cast<uint32_t*>(dst) = wpack_fp8x4(w.x * q, w.y * q, w.z * q, w.w * q);
+      }
+    }
+  }
+}
+
+int w_esize(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
+int w_kchunk(int prec) { return prec == 0 ? 32 : (prec == 1 ? 64 : 128); }
+
+// Tile shape: the gather kernel's M tile (the packed weights are padded to it).
+int win_mt(int cout) { return cout <= 32 ? 32 : 64; }
+int win_f(int mt) { return mt == 32 ? 128 : 64; }
+
+}  // namespace
+
+int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec) {
+  if (!conv_mfma_supported(cin, cout, k, stride, prec)) return 0;
+  if (cin > 64 || cin % 16 != 0 || cout % 16 != 0 || min_frames < 1) return 0;
+  if (L != dil * (k - 1)) return 0;
+  const int kc = w_kchunk(prec);
+  const int Kpad = (k * cin + kc - 1) / kc * kc;
+  // K chunks held in registers: 3 (FP32, BF16) or 2 (FP8); more would cut occupancy
+  if (Kpad * w_esize(prec) / 128 > (prec == 2 ? 2 : 3)) return 0;
+  const int F = win_f(win_mt(cout));
+  const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
+  if (max_seg > kMaxStreams) return 0;
+  const int64_t rows = F + (int64_t)L * max_seg;
+  if (rows * (cin + 4) * 4 > 64 * 1024) return 0;
+  return (int32_t)rows;
+}
+
+hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s) {
+  const int MT = win_mt(a.cout);
+  const int F = win_f(MT);
+  const int n_mt = (a.cout + MT - 1) / MT;
+  const int64_t n_nt = (a.n_out + F - 1) / F;
+  const int kc = w_kchunk(prec);
+  const int Kreal = a.k * a.cin;
+  const int Kpad = (Kreal + kc - 1) / kc * kc;
+  const int64_t items = (int64_t)a.n_ent * a.L * a.cin;
+  const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
+  const int64_t grid = (int64_t)n_mt * n_nt + extra;
+  if (grid <= 0) return hipSuccess;
+  const size_t lds = (size_t)row_cap * (a.cin + 4) * sizeof(float);
+  const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
+  const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
+#define SC_WIN(P, M)                                                                                      \
+  if (prec == P && MT == M) {                                                                             \
+    hipLaunchKernelGGL((conv_win_kernel<P, M>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, n_mt,    \
+                       (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                       \
+    return hipGetLastError();                                                                             \
+  }
+  SC_WIN(0, 32) SC_WIN(0, 64)
+  SC_WIN(1, 32) SC_WIN(1, 64)
+  SC_WIN(2, 32) SC_WIN(2, 64)
+#undef SC_WIN
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sc

@@ -20,6 +20,7 @@ struct OpDev {
   float* B = nullptr;       // bias
   float* wscale = nullptr;  // fp8 per-row scales
   int prec = 0;             // precision of this op's kernel
+  int32_t win_rows = 0;     // IMPL_WIN: LDS window rows per tile
 };
 
 // A slot of the descriptor ring: pinned host staging + device copy + event.

@@ -305,7 +305,8 @@ hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, in
       if (e != hipSuccess) return e;
     }
     if (op.kind == K_CONV) {
-      e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
+      if (op.impl == IMPL_WIN) e = launch_conv_win(a, prec, m->opdev[oi].win_rows, hs);
+      else e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
     } else if (op.kind == K_CONVT) {
       e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, hs) : launch_convt_valu(a, hs);
     } else {
@@ -492,6 +493,11 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     }
     op.impl = mfma ? IMPL_MFMA : IMPL_VALU;
     od.prec = mfma ? prec_id : 0;
+    if (mfma && op.kind == K_CONV && !(options & SC_MODEL_NO_WIN)) {
+      const int64_t min_frames = op.in_rate.of(m->plan.input_multiple);
+      od.win_rows = conv_win_rows(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, min_frames, prec_id);
+      if (od.win_rows > 0) op.impl = IMPL_WIN;
+    }
     if (mfma) {
       std::vector<uint8_t> packed;
       std::vector<float> wscale;

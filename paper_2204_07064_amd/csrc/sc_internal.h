@@ -28,7 +28,9 @@ struct Frac {
 enum OpKind : int32_t { K_CONV = 1, K_CONVT = 2, K_DELAY_ADD = 3 };
 
 // Which kernel family runs an op.
-enum Impl : int32_t { IMPL_VALU = 0, IMPL_MFMA = 1 };
+// IMPL_MFMA gathers each K chunk of the operands from HBM; IMPL_WIN stages
+// each tile's window rows in LDS once (stride-1 convs with narrow inputs).
+enum Impl : int32_t { IMPL_VALU = 0, IMPL_MFMA = 1, IMPL_WIN = 2 };
 
 // One launch of a processing step (a conv with optional fused residual, a
 // transposed conv, or a delay-line sum).

@@ -51,6 +51,52 @@ def test_operand_twins_bitwise(name, prec):
     assert np.array_equal(a, b)
 
 
+def _batched_streams(sc, mod, xs, lens):
+    """Steps of len(xs) streams; step j gives stream i lens[i][j] frames.
+    Returns each stream's concatenated output (numpy float64)."""
+    streams = [sc.Stream(mod, int(max(l))) for l in lens]
+    xd = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda() for x in xs]
+    pos = [0] * len(xs)
+    outs = [[] for _ in xs]
+    for j in range(len(lens[0])):
+        ins = []
+        for i in range(len(xs)):
+            n = int(lens[i][j])
+            ins.append(xd[i][:, pos[i]:pos[i] + n].contiguous())
+            pos[i] += n
+        for i, o in enumerate(sc.process_batch(mod, streams, ins)):
+            outs[i].append(o)
+    torch.cuda.synchronize()
+    return [torch.cat(o, dim=1).cpu().double().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("name", ["rave_b", "wide"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_window_kernel_bitwise(name, prec):
+    """Narrow stride-1 MFMA convs that stage each tile's [cache | new frames]
+    window in LDS give bitwise the same streams as the chunk-gathering kernel,
+    in a batch whose tiles span several streams of uneven buffers."""
+    sc = _sc()
+    m, w = weights_for(name)
+    c = m["in_channels"]
+    scales = _fp8_scales(sc, m, w, c) if prec == "fp8" else None
+    rng = np.random.default_rng(5)
+    n_str, n_steps = (9, 4) if name == "rave_b" else (5, 3)
+    lens = [[int(v) for v in rng.choice([1, 2, 3, 5, 8], size=n_steps)] for _ in range(n_str)]
+    xs = [scgen.stream_latents(c, sum(l), 30 + i) for i, l in enumerate(lens)]
+    win = sc.Model(m, w, prec, act_scales=scales)
+    win.profile(True)
+    a = _batched_streams(sc, win, xs, lens)
+    impls = {p["node"]: p["impl"] for p in win.profile_read()}
+    win.profile(False)
+    # the window kernel ran (FP32 holds at most 3 K chunks: none of the wide
+    # decoder's 48- and 96-channel layers qualify)
+    assert (2 in impls.values()) == ((name, prec) != ("wide", "fp32")), impls
+    b = _batched_streams(sc, sc.Model(m, w, prec, act_scales=scales, options=8), xs, lens)
+    for i in range(n_str):
+        assert np.array_equal(a[i], b[i]), i
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     sc = _sc()
     m, w = weights_for("rave_b")
