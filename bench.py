@@ -122,12 +122,20 @@ class Workload:
         self.streams = [sc.Stream(model, max(BUF_CHOICES)) for _ in range(N_STREAMS)]
         self.lens = np.array([scgen.buffer_lengths(steps, BUF_CHOICES, seed * 100003 + i)
                               for i in range(N_STREAMS)], dtype=np.int64)   # [stream][step]
-        self.inputs = []
+        # every buffer contiguous ([16][n]) in one host array, copied to HBM at once
+        sizes = self.lens * LATENT                                            # [stream][step]
+        offs = np.concatenate([[0], np.cumsum(sizes.ravel())[:-1]]).reshape(sizes.shape)
+        host = np.empty(int(sizes.sum()), np.float32)
         for i in range(N_STREAMS):
-            tot = int(self.lens[i].sum())
-            x = torch.from_numpy(scgen.stream_latents(LATENT, tot, i)).cuda()
-            cuts = np.concatenate([[0], np.cumsum(self.lens[i])])
-            self.inputs.append([x[:, cuts[j]:cuts[j + 1]].contiguous() for j in range(steps)])
+            x = scgen.stream_latents(LATENT, int(self.lens[i].sum()), i)
+            a = 0
+            for j in range(steps):
+                n = int(self.lens[i, j])
+                host[offs[i, j]:offs[i, j] + LATENT * n] = x[:, a:a + n].ravel()
+                a += n
+        flat = torch.from_numpy(host).cuda()
+        self.inputs = [[flat[offs[i, j]:offs[i, j] + sizes[i, j]].view(LATENT, int(self.lens[i, j]))
+                        for j in range(steps)] for i in range(N_STREAMS)]
         self.outs = [torch.empty((1, max(BUF_CHOICES) * SPF), device="cuda") for _ in range(N_STREAMS)]
         self.step_i = 0
         torch.cuda.synchronize()

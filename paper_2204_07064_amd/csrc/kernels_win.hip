@@ -125,17 +125,21 @@ __device__ inline f4 mfma32(const u4& alo, const u4& ahi, const u4& blo, const u
 // Per-stream part of a tile (LDS).
 struct WinSeg {
   const float* cache;     // current cache copy [L][cin]
-  int64_t pos;
+  int64_t mask_x;         // warm-up mask: local output frame t is zeroed iff t * out_den < mask_x
   int32_t in_start;       // first packed input frame of the stream
   int32_t out_start;      // first packed output frame (equal for stride 1)
   int32_t r0;             // first window row staged
   int32_t base;           // first LDS row of this stream's rows
   int32_t rows;
-  int32_t flags;
+  int32_t t_lo, t_hi;     // local output frames of the stream inside the tile
 };
 
 // MT x F tile, 4 waves: MT = 32 -> 2 x 2 waves of 16 x (F / 2); MT = 64 ->
 // 4 x 1 waves of 16 x F.  Either way a wave owns 4 column blocks of 16.
+//
+// LDS: the staged window rows in operand form (activated and rounded once,
+// row stride cin * ES + 16 bytes), then, for a fused residual, each column's
+// skip row as raw FP32 ([F][cin + 4]).
 template <int PREC, int MT>
 __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
   constexpr int ES = WPrec<PREC>::kEsize;
   constexpr int kMaxChunks = WPrec<PREC>::kMaxChunks;
 
-  extern __shared__ __attribute__((aligned(16))) float win[];   // [row_cap][cin + 4]
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
@@ -193,7 +197,10 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
   const bool pre = a.pre_act != 0;
   const float qs = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
   const int cin = a.cin;
-  const int rowf = cin + 4;               // LDS row stride (floats), padded against bank conflicts
+  const int rowb = cin * ES + 16;         // operand row stride (bytes), padded against bank conflicts
+  const int skipf = cin + 4;              // skip row stride (floats)
+  unsigned char* wop = lds;
+  float* wskip = reinterpret_cast<float*>(lds + row_cap * rowb);
 
   // weights of the wave's 16 rows, all chunks (independent of the columns: issued first)
   u4 alo[kMaxChunks], ahi[kMaxChunks];
@@ -228,15 +235,16 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
     const Entry& e = a.ents[e_first + tid];
     WinSeg g;
     g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-    g.pos = e.pos;
-    g.flags = e.flags;
+    g.mask_x = (e.flags & SC_FLAG_WARMUP_MASK)
+                   ? a.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
+                   : INT64_MIN;
     g.in_start = in_frames(a, e.off);
     g.out_start = out_frames(a, e.off);
     const int32_t T = out_frames(a, e.T);
-    const int32_t t_first = tid == 0 ? f0 - g.out_start : 0;
-    const int32_t t_last = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
-    g.r0 = t_first;
-    g.rows = t_last - t_first + 1 + a.L;
+    g.t_lo = tid == 0 ? f0 - g.out_start : 0;
+    g.t_hi = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
+    g.r0 = g.t_lo;
+    g.rows = g.t_hi - g.t_lo + 1 + a.L;
     g.base = 0;
     segs[tid] = g;
   }
@@ -269,17 +277,17 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
     colseg[tid] = (int8_t)s;
   }
 
-  // ---- stage the window rows (raw FP32) ----
+  // ---- stage the window rows: operand form, plus the raw skip rows ----
   {
-    const int ppr = cin >> 2;              // 16-byte pieces per row
+    const int ppr = cin >> 2;              // 16-byte FP32 source pieces per row
     const int32_t n_pieces = R * ppr;
     for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * kStageBatch) {
       f4 v[kStageBatch];
-      int32_t dst[kStageBatch];
+      int32_t jj[kStageBatch], pp[kStageBatch], ss[kStageBatch];
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int32_t idx = i0 + u * kThreads + tid;
-        dst[u] = -1;
+        jj[u] = -1;
         v[u] = f4{0.f, 0.f, 0.f, 0.f};
         if (idx < n_pieces) {
           const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
@@ -290,20 +298,45 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
           const float* src = r < a.L ? segs[s].cache + (int64_t)r * cin
                                      : a.in_buf + ((int64_t)segs[s].in_start + r - a.L) * cin;
           v[u] = *reinterpret_cast<const f4*>(src + pc * 4);
-          dst[u] = j * rowf + pc * 4;
+          jj[u] = j;
+          pp[u] = pc;
+          ss[u] = s;
         }
       }
 #pragma unroll
-      for (int u = 0; u < kStageBatch; ++u)
-        if (dst[u] >= 0) *reinterpret_cast<f4*>(&win[dst[u]]) = v[u];
+      for (int u = 0; u < kStageBatch; ++u) {
+        if (jj[u] < 0) continue;
+        const int32_t j = jj[u];
+        const int pc = pp[u];
+        const f4 x = v[u];
+        unsigned char* dst = wop + j * rowb + pc * 4 * ES;
+        if constexpr (PREC == 0) {
+          *reinterpret_cast<f4*>(dst) = f4{act(x.x, pre), act(x.y, pre), act(x.z, pre), act(x.w, pre)};
+        } else if constexpr (PREC == 1) {
+          uint2 w;
+          w.x = wpack_bf16(act(x.x, pre), act(x.y, pre));
+          w.y = wpack_bf16(act(x.z, pre), act(x.w, pre));
+          *reinterpret_cast<uint2*>(dst) = w;
+        } else {
+          *reinterpret_cast<uint32_t*>(dst) =
+              wpack_fp8x4(act(x.x, pre) * qs, act(x.y, pre) * qs, act(x.z, pre) * qs, act(x.w, pre) * qs);
+        }
+        if (a.residual) {
+          // the row is the skip row of local output frame t = window row - skip_off
+          const WinSeg& g = segs[ss[u]];
+          const int32_t t = g.r0 + (j - g.base) - a.skip_off;
+          if (t >= g.t_lo && t <= g.t_hi)
+            *reinterpret_cast<f4*>(&wskip[(g.out_start + t - f0) * skipf + pc * 4]) = x;
+        }
+      }
     }
   }
   __syncthreads();
 
-  // ---- K loop: B operands from the staged rows ----
+  // ---- K loop: B operands read straight from the staged rows ----
   int cb[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) cb[nb] = colbase[wn * (F / WN) + nb * 16 + lr];
+  for (int nb = 0; nb < NB; ++nb) cb[nb] = colbase[wn * (F / WN) + nb * 16 + lr] * rowb;
   f4 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -319,14 +352,13 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
         const int kk = (c * 128 + lg * 32 + p * 16) / ES;
         live[p] = kk < Kreal;
         const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
-        off[p] = tap * a.dil * rowf + (kk - tap * cin);
+        off[p] = tap * a.dil * rowb + (kk - tap * cin) * ES;
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const float* rowp = &win[cb[nb] * rowf];
         const u4 z = {0u, 0u, 0u, 0u};
-        const u4 blo = live[0] ? operand16<PREC>(rowp + off[0], pre, qs) : z;
-        const u4 bhi = live[1] ? operand16<PREC>(rowp + off[1], pre, qs) : z;
+        const u4 blo = live[0] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]) : z;
+        const u4 bhi = live[1] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]) : z;
         acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo, bhi, acc[nb]);
       }
     }
@@ -344,10 +376,8 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
     f4 v = acc[nb];
     if (PREC == 2) v = v * (wsc * a.act_scale);
     v = v + bias;
-    if (a.residual) v = v + *reinterpret_cast<const f4*>(&win[(cb[nb] + a.skip_off) * rowf + m]);
-    if ((segs[s].flags & SC_FLAG_WARMUP_MASK) &&
-        (segs[s].pos * (int64_t)a.out_num + (int64_t)t * a.out_den < a.delay * (int64_t)a.out_den))
-      v = f4{0.f, 0.f, 0.f, 0.f};
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
+    if ((int64_t)t * a.out_den < segs[s].mask_x) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     *reinterpret_cast<f4*>(a.out_buf + o) = v;
     if (a.out_twin) {
@@ -380,6 +410,10 @@ int w_kchunk(int prec) { return prec == 0 ? 32 : (prec == 1 ? 64 : 128); }
 // Tile shape: the gather kernel's M tile (the packed weights are padded to it).
 int win_mt(int cout) { return cout <= 32 ? 32 : 64; }
 int win_f(int mt) { return mt == 32 ? 128 : 64; }
+// operand rows plus the skip rows (allocated whether or not the layer has a skip)
+int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
+  return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4;
+}
 
 }  // namespace
 
@@ -395,7 +429,7 @@ int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int6
   const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
   if (max_seg > kMaxStreams) return 0;
   const int64_t rows = F + (int64_t)L * max_seg;
-  if (rows * (cin + 4) * 4 > 64 * 1024) return 0;
+  if (win_lds_bytes(rows, cin, prec, F) > 64 * 1024) return 0;
   return (int32_t)rows;
 }
 
@@ -411,7 +445,7 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  const size_t lds = (size_t)row_cap * (a.cin + 4) * sizeof(float);
+  const size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
   const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
 #define SC_WIN(P, M)                                                                                      \
