@@ -116,9 +116,12 @@ def roofline(prof):
 class Workload:
     """256 streams, pre-drawn buffer lengths and device-resident inputs."""
 
-    def __init__(self, sc, torch, model, steps, seed=7):
+    def __init__(self, sc, torch, model, steps, seed=7, graph=False):
         self.sc, self.torch = sc, torch
         self.model = model
+        model.reserve(N_STREAMS * max(BUF_CHOICES))   # no workspace growth inside the timed steps
+        model.enable_graph(N_STREAMS if graph else 0)  # optional: one graph replay per step
+        # every step's arguments are prebuilt (BatchCall), so issuing a step is one library call
         self.streams = [sc.Stream(model, max(BUF_CHOICES)) for _ in range(N_STREAMS)]
         self.lens = np.array([scgen.buffer_lengths(steps, BUF_CHOICES, seed * 100003 + i)
                               for i in range(N_STREAMS)], dtype=np.int64)   # [stream][step]
@@ -137,6 +140,10 @@ class Workload:
         self.inputs = [[flat[offs[i, j]:offs[i, j] + sizes[i, j]].view(LATENT, int(self.lens[i, j]))
                         for j in range(steps)] for i in range(N_STREAMS)]
         self.outs = [torch.empty((1, max(BUF_CHOICES) * SPF), device="cuda") for _ in range(N_STREAMS)]
+        out_ptrs = [o.data_ptr() for o in self.outs]
+        self.calls = [sc.BatchCall(model, self.streams, [self.inputs[i][j].data_ptr() for i in range(N_STREAMS)],
+                                   self.lens[:, j], out_ptrs) for j in range(steps)]
+        self.hs = torch.cuda.current_stream().cuda_stream
         self.step_i = 0
         torch.cuda.synchronize()
 
@@ -144,15 +151,12 @@ class Workload:
         return int(self.lens[:, j].sum()) * SPF
 
     def step(self):
-        j = self.step_i
-        xs = [self.inputs[i][j] for i in range(N_STREAMS)]
-        outs = [self.outs[i][:, :int(self.lens[i, j]) * SPF] for i in range(N_STREAMS)]
-        self.sc.process_batch(self.model, self.streams, xs, outs)
+        self.calls[self.step_i].run(self.hs)
         self.step_i += 1
 
 
-def timed_run(sc, torch, model, warmup, steps, profile=False):
-    wl = Workload(sc, torch, model, warmup + steps)
+def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False):
+    wl = Workload(sc, torch, model, warmup + steps, graph=graph)
     for _ in range(warmup):
         wl.step()
     torch.cuda.synchronize()
@@ -346,6 +350,16 @@ def summarize(run_dir):
                 o["node"], {1: "conv", 2: "convt", 3: "add"}[o["kind"]], IMPL_NAME[o["impl"]],
                 o["cin"], o["cout"], o["d"], avg[j + off], o["avg_us"], rows[j + off]["Kernel_Name"][:60]))
         lines.append("step sum: rocprof %.1f us" % avg.sum())
+        # time between launches: inside a step, and from one step's last kernel to the next step's first
+        t0 = np.array([int(r["Start_Timestamp"]) for r in rows], dtype=np.float64) * 1e-3
+        t1 = np.array([int(r["End_Timestamp"]) for r in rows], dtype=np.float64) * 1e-3
+        span = np.array([t1[(k + 1) * K - 1] - t0[k * K] for k in range(steps)])
+        inner = np.array([np.sum(t0[k * K + 1:(k + 1) * K] - t1[k * K:(k + 1) * K - 1]) for k in range(steps)])
+        between = np.array([t0[(k + 1) * K] - t1[(k + 1) * K - 1] for k in range(steps - 1)])
+        lines.append("step span: median %.1f us, mean %.1f us; gaps inside a step: median %.1f us; "
+                     "between steps: median %.1f us, max %.1f us" % (
+                         np.median(span), span.mean(), np.median(inner), np.median(between),
+                         between.max() if len(between) else 0.0))
     for path in sorted(glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)):
         with open(path) as f:
             rows = list(csv.DictReader(f))
@@ -385,6 +399,8 @@ def main():
     ap.add_argument("--compare", default="fp32,fp8", help="other precisions timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay one captured graph per step (measured slower than one-by-one launches here)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--summarize", metavar="DIR", help="print per-layer figures from rocprofv3 CSVs under DIR")
@@ -421,7 +437,7 @@ def main():
         return sc.Model(m, w, prec, act_scales=scales)
 
     model = make(args.precision)
-    run = timed_run(sc, torch, model, args.warmup, args.steps)
+    run = timed_run(sc, torch, model, args.warmup, args.steps, graph=args.graph)
     prof_run = timed_run(sc, torch, model, args.warmup, args.steps, profile=True)
     prof = prof_run["prof"]
     used = sorted({p["precision"] for p in prof if p["impl"] >= 1})
@@ -451,7 +467,7 @@ def main():
     for prec in [c for c in args.compare.split(",") if c and c != args.precision]:
         try:
             mod2 = make(prec)
-            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4))
+            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4), graph=args.graph)
             comp[prec] = round(r2["samples"] / r2["gpu_s"], 1)
             mod2.close()
         except Exception as e:  # report, do not hide

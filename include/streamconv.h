@@ -142,6 +142,22 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
 sc_status sc_model_info_get(const sc_model* model, sc_model_info* out);
 /* Number of CONV/CONVT nodes (the length of an act_scales array). */
 int32_t sc_model_n_layers(const sc_model* model);
+/* Sizes the model's activation workspace for steps of up to `max_step_frames`
+ * input frames (summed over the streams of a step).  The workspace otherwise
+ * grows on the first step that needs more, which synchronizes the device
+ * and reallocates; reserving up front keeps every later step free of that.
+ * Errors: SC_EINVAL, SC_ENOMEM, SC_ELENGTH (a server that replays graphs
+ * holds the workspace). */
+sc_status sc_model_reserve(sc_model* model, int64_t max_step_frames);
+/* Steps of up to `max_streams` streams (0: off, the default) replay one
+ * hipGraph of the step's kernels instead of launching them one by one.  The
+ * graph is captured on first use for the current workspace (grids sized for
+ * max_streams streams and the workspace's frames; the kernels read each
+ * step's actual size from its descriptor) and captured again after the
+ * workspace grows, so reserve the workspace first.  Results are bitwise
+ * those of one-by-one launches.  Steps with profiling or calibration enabled
+ * launch one by one.  Errors: SC_EINVAL. */
+sc_status sc_model_enable_graph(sc_model* model, int32_t max_streams);
 /* Replace the static FP8 activation scales (host array, sc_model_n_layers
  * values).  Only between processing calls. */
 sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);

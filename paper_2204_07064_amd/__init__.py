@@ -17,7 +17,7 @@ import numpy as np
 from . import _native
 from ._native import ScError, check, lib, nodes_array  # noqa: F401
 
-__all__ = ["Model", "Stream", "Server", "process_batch", "plan", "ScError", "lib"]
+__all__ = ["Model", "Stream", "Server", "BatchCall", "process_batch", "plan", "ScError", "lib"]
 
 
 _EXITING = [False]
@@ -102,6 +102,14 @@ class Model:
         check(lib().sc_model_profile_read(self.handle, arr, n.value, ctypes.byref(n)))
         return [{f: getattr(arr[i], f) for f, _ in _native.ScOpProfile._fields_} for i in range(n.value)]
 
+    def enable_graph(self, max_streams):
+        """Replay one captured graph per step of up to max_streams streams (0: off)."""
+        check(lib().sc_model_enable_graph(self.handle, int(max_streams)))
+
+    def reserve(self, max_step_frames):
+        """Size the workspace for steps of up to max_step_frames input frames."""
+        check(lib().sc_model_reserve(self.handle, int(max_step_frames)))
+
     def close(self):
         if self.handle and not _EXITING[0]:
             lib().sc_model_destroy(self.handle)
@@ -171,6 +179,27 @@ def process_batch(model, streams, xs, outs=None, hip_stream=None):
     tf = (ctypes.c_int32 * n)(*[int(x.shape[-1]) for x in xs])
     check(lib().sc_process_batch(model.handle, n, sh, ins, tf, ous, _stream_handle(hip_stream)))
     return outs
+
+
+class BatchCall:
+    """Prebuilt arguments of one batched step (streams, device input and
+    output addresses, frames), so that issuing the step costs one library
+    call.  The buffers behind the addresses must stay alive."""
+
+    def __init__(self, model, streams, in_ptrs, frames, out_ptrs):
+        n = len(streams)
+        if not (len(in_ptrs) == len(frames) == len(out_ptrs) == n):
+            raise ValueError("streams, inputs, frames and outputs differ in length")
+        self.model = model
+        self.n = n
+        self.sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+        self.ins = (ctypes.c_void_p * n)(*[int(p) for p in in_ptrs])
+        self.tf = (ctypes.c_int32 * n)(*[int(f) for f in frames])
+        self.ous = (ctypes.c_void_p * n)(*[int(p) for p in out_ptrs])
+
+    def run(self, hip_stream=None):
+        check(lib().sc_process_batch(self.model.handle, self.n, self.sh, self.ins, self.tf, self.ous,
+                                     _stream_handle(hip_stream)))
 
 
 class Server:

@@ -35,6 +35,7 @@ EXPORTS = [
     "sc_process_batch", "sc_last_error", "sc_model_profile", "sc_model_profile_read",
     "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
     "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
+    "sc_model_reserve", "sc_model_enable_graph",
 ]
 SC_PENDING = 1
 SC_SUBMIT_DISCARD = 1
@@ -101,6 +102,8 @@ def lib():
     _sig(L, "sc_model_create", c_i32, [P(ScNode), c_i32, c_fp, c_size, c_i32, c_fp, c_u32, c_i32, P(c_vp)])
     _sig(L, "sc_model_info_get", c_i32, [c_vp, P(ScModelInfo)])
     _sig(L, "sc_model_n_layers", c_i32, [c_vp])
+    _sig(L, "sc_model_reserve", c_i32, [c_vp, c_i64])
+    _sig(L, "sc_model_enable_graph", c_i32, [c_vp, c_i32])
     _sig(L, "sc_model_set_act_scales", c_i32, [c_vp, c_fp])
     _sig(L, "sc_model_read_amax", c_i32, [c_vp, c_fp, c_i32])
     _sig(L, "sc_model_enable_amax", c_i32, [c_vp, c_i32])

@@ -179,14 +179,8 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
   __shared__ ColInfo cols[NT];
 
   const int tid = threadIdx.x;
-  const int32_t n_tiles = n_mt * n_nt;
-  // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs; remap so
-  // that the M tiles of one column tile (which share B) run on one XCD's L2.
+  const int32_t n_tiles = n_mt * n_nt;   // tiles of the grid (sized for the largest step)
   int32_t bid = blockIdx.x;
-  {
-    const int32_t full = n_tiles / 8 * 8;
-    if (bid < full) bid = (bid % 8) * (full / 8) + bid / 8;
-  }
   // ---- conv cache update blocks (after the GEMM tiles) ----
   if (!CONVT && bid >= n_tiles) {
     const int32_t per_ent = a.L * a.cin;
@@ -215,13 +209,21 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
     }
     return;
   }
+  // the grid may be sized for a larger step than this one (captured launches):
+  // the step's own tiles are the first ones
+  n_cols = CONVT ? step_in(a) + step_ents(a) : step_out(a);
+  const int32_t step_tiles = n_mt * ((n_cols + NT - 1) / NT);
+  if (bid >= step_tiles) return;
+  // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs; remap so
+  // that the M tiles of one column tile (which share B) run on one XCD's L2
+  {
+    const int32_t full = step_tiles / 8 * 8;
+    if (bid < full) bid = (bid % 8) * (full / 8) + bid / 8;
+  }
   const int mt = (int)((uint32_t)bid % (uint32_t)n_mt);
   const int32_t nt = (int32_t)((uint32_t)bid / (uint32_t)n_mt);
   const int m0 = mt * MT;
   const int32_t n0 = nt * NT;
-  // the grid may be sized for a larger step than this one (captured launches)
-  n_cols = CONVT ? step_in(a) + step_ents(a) : step_out(a);
-  if (n0 >= n_cols) return;
 
   const unsigned char* Wb = static_cast<const unsigned char*>(a.W);
   const int row_bytes = Kpad * ES;

@@ -49,7 +49,17 @@ struct sc_model {
   std::vector<void*> tw;           // operand twins
   int tw_esize = 4;
   int64_t ws_cap = 0;              // input frames
-  int ws_pins = 0;                 // captured graphs holding the workspace's addresses
+  int ws_pins = 0;                 // server graphs holding the workspace's addresses
+  // step graph (sc_model_enable_graph): the kernels of one step captured once,
+  // sized for graph_streams streams and the whole workspace, reading the
+  // descriptor at graph_desc; replayed by every step that fits
+  int32_t graph_streams = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_frames = 0;        // workspace capacity it was captured for
+  unsigned char* graph_desc = nullptr;
+  size_t graph_desc_bytes = 0;
+  hipStream_t capture_stream = nullptr;
+  uint64_t step_gen = 0;           // duplicate-stream check of a step
   // descriptors
   sc::DescSlot ring[sc::kRing];
   int ring_next = 0;
@@ -79,6 +89,7 @@ struct sc_stream {
   int64_t pos = 0;
   int parity = 0;
   bool bad = false;
+  uint64_t seen = 0;               // step_gen of the last step that listed it
 };
 
 
@@ -89,8 +100,9 @@ inline size_t desc_bytes(int n, int64_t frames) {  // n: entry capacity
   return kDescHeaderBytes + (size_t)n * sizeof(Entry) + (size_t)frames * sizeof(int32_t);
 }
 
-// Checks a step's arguments; sets *total to its input frames.  No state change.
-sc_status validate_step(const sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+// Checks a step's arguments; sets *total to its input frames.  No stream state
+// changes (only the duplicate-check marks).
+sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                         const int32_t* n_frames, float* const* d_out, int64_t* total);
 // Writes the step descriptor (header, entries, frame -> entry) into `host`;
 // the frame table starts after `ent_capacity` entries (>= n).

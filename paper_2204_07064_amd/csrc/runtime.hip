@@ -91,6 +91,9 @@ void free_model(sc_model* m) {
     if (s.done) hipEventDestroy(s.done);
   }
   if (m->last_done) hipEventDestroy(m->last_done);
+  if (m->graph_exec) hipGraphExecDestroy(m->graph_exec);
+  hipFree(m->graph_desc);
+  if (m->capture_stream) hipStreamDestroy(m->capture_stream);
   hipFree(m->d_amax);
   delete m;
 }
@@ -159,6 +162,10 @@ sc_status sc::ensure_workspace(sc_model* m, int64_t frames) {
   cap = (cap + mult - 1) / mult * mult;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if (m->graph_exec) {   // captured with the old addresses
+    hipGraphExecDestroy(m->graph_exec);
+    m->graph_exec = nullptr;
+  }
   for (float*& p : m->ws) { hipFree(p); p = nullptr; }
   for (void*& p : m->tw) { hipFree(p); p = nullptr; }
   m->ws.assign(m->plan.buf_floats.size(), nullptr);
@@ -233,16 +240,17 @@ namespace sc {
 
 sc_status fail_status(sc_status st, const char* msg) { return fail(st, msg); }
 
-sc_status validate_step(const sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                         const int32_t* n_frames, float* const* d_out, int64_t* total_out) {
   if (n <= 0 || !streams || !d_in || !n_frames || !d_out) return fail(SC_EINVAL, "null argument or n <= 0");
   if (m->prec == SC_FP8E4M3 && !m->have_scales) return fail(SC_EINVAL, "FP8 model has no activation scales");
   int64_t total = 0;
-  std::unordered_set<const sc_stream*> seen;
+  const uint64_t gen = ++m->step_gen;
   for (int i = 0; i < n; ++i) {
-    const sc_stream* s = streams[i];
+    sc_stream* s = streams[i];
     if (!s || s->m != m) return fail(SC_EINVAL, "stream is null or belongs to another model");
-    if (!seen.insert(s).second) return fail(SC_EINVAL, "a stream appears twice in one batch");
+    if (s->seen == gen) return fail(SC_EINVAL, "a stream appears twice in one batch");
+    s->seen = gen;
     if (s->bad) return fail(SC_ESTATE, "stream saw a device error; call stream_reset");
     const int32_t T = n_frames[i];
     if (T < 1 || T > s->max_frames || T % m->plan.input_multiple != 0)
@@ -332,6 +340,47 @@ void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames) {
 
 namespace {
 
+// Captures the step graph for the current workspace if it is missing or
+// stale.  Its descriptor buffer is reallocated only with the device idle (the
+// workspace has just grown, or the graph was just enabled).
+sc_status ensure_graph(sc_model* m) {
+  if (m->graph_exec && m->graph_frames == m->ws_cap) return SC_OK;
+  hipError_t e;
+  if (m->graph_exec) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipGraphExecDestroy(m->graph_exec);
+    m->graph_exec = nullptr;
+  }
+  const size_t bytes = desc_bytes(m->graph_streams, m->ws_cap);
+  if (m->graph_desc_bytes < bytes) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(m->graph_desc);
+    m->graph_desc = nullptr;
+    m->graph_desc_bytes = 0;
+    e = hipMalloc(reinterpret_cast<void**>(&m->graph_desc), bytes);
+    if (e != hipSuccess) return fail(SC_ENOMEM, "step graph descriptor allocation failed");
+    m->graph_desc_bytes = bytes;
+  }
+  if (!m->capture_stream) {
+    e = hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const hipError_t le = enqueue_kernels(m, m->graph_desc, m->graph_streams, m->ws_cap, m->capture_stream);
+  e = hipStreamEndCapture(m->capture_stream, &g);
+  if (le != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(le, "step capture"); }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&m->graph_exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) { m->graph_exec = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
+  m->graph_frames = m->ws_cap;
+  return SC_OK;
+}
+
 sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                    const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
   int64_t total = 0;
@@ -342,6 +391,11 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   st = ensure_workspace(m, total);
   if (st != SC_OK) return st;
 
+  // the step graph serves steps of up to graph_streams streams (and any size
+  // up to the workspace); timed or calibrating steps launch one by one
+  const bool graph = m->graph_streams >= n && !m->prof_on && !m->amax_on;
+  const int cap = graph ? m->graph_streams : n;
+
   // ---- descriptors ----
   DescSlot& slot = m->ring[m->ring_next];
   m->ring_next = (m->ring_next + 1) % kRing;
@@ -350,7 +404,7 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     slot.pending = false;
   }
-  const size_t need = desc_bytes(n, total);
+  const size_t need = desc_bytes(cap, total);
   if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
@@ -368,14 +422,18 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
-  fill_descriptor(slot.host, n, n, streams, d_in, n_frames, d_out, total);
+  fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total);
+  if (graph) {
+    st = ensure_graph(m);
+    if (st != SC_OK) return st;
+  }
   if (m->has_last) {
     e = hipStreamWaitEvent(hs, m->last_done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  e = hipMemcpyAsync(slot.dev, slot.host, need, hipMemcpyHostToDevice, hs);
+  e = hipMemcpyAsync(graph ? m->graph_desc : slot.dev, slot.host, need, hipMemcpyHostToDevice, hs);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-  e = enqueue_kernels(m, slot.dev, n, total, hs);
+  e = graph ? hipGraphLaunch(m->graph_exec, hs) : enqueue_kernels(m, slot.dev, n, total, hs);
   if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
   if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
   if (e != hipSuccess) {
@@ -536,12 +594,42 @@ sc_status sc_model_info_get(const sc_model* m, sc_model_info* out) {
 
 int32_t sc_model_n_layers(const sc_model* m) { return m ? (int32_t)m->plan.layer_node.size() : -1; }
 
+sc_status sc_model_enable_graph(sc_model* m, int32_t max_streams) {
+  if (!m || max_streams < 0) return fail(SC_EINVAL, "null model or negative stream count");
+  std::lock_guard<std::mutex> g(m->mu);
+  hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (m->graph_exec) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipGraphExecDestroy(m->graph_exec);
+    m->graph_exec = nullptr;
+  }
+  m->graph_streams = max_streams;
+  return SC_OK;
+}
+
+sc_status sc_model_reserve(sc_model* m, int64_t max_step_frames) {
+  if (!m || max_step_frames < 1 || max_step_frames > INT32_MAX / 4)
+    return fail(SC_EINVAL, "null model or step size out of range");
+  std::lock_guard<std::mutex> g(m->mu);
+  const hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return ensure_workspace(m, max_step_frames);
+}
+
 sc_status sc_model_set_act_scales(sc_model* m, const float* s) {
   if (!m || !s) return fail(SC_EINVAL, "null argument");
   std::lock_guard<std::mutex> g(m->mu);
   const int n = (int)m->plan.layer_node.size();
   for (int i = 0; i < n; ++i)
     if (!(s[i] > 0.f) || !std::isfinite(s[i])) return fail(SC_EINVAL, "activation scales must be positive and finite");
+  if (m->graph_exec) {   // the captured launches hold the old scales
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipGraphExecDestroy(m->graph_exec);
+    m->graph_exec = nullptr;
+  }
   m->act_scales.assign(s, s + n);
   m->have_scales = true;
   return SC_OK;

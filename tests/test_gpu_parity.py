@@ -116,6 +116,39 @@ def test_batch_equals_alone_bitwise():
         assert np.array_equal(got, alone[i]), i
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_step_graph_replays_bitwise(prec):
+    """Steps replaying the captured step graph equal one-by-one launches, step
+    by step, with eager device work and synchronizations between replays; a
+    step larger than the reserved workspace grows it and recaptures."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    g = sc.Model(m, w, prec)
+    e = sc.Model(m, w, prec)
+    g.reserve(24)
+    g.enable_graph(6)
+    rng = np.random.default_rng(9)
+    steps = [[int(v) for v in rng.integers(1, 5, size=5)] for _ in range(5)]
+    steps.insert(3, [8, 8, 8, 8, 8])            # 40 frames > 24 reserved: grows and recaptures
+    xs = [scgen.stream_latents(16, sum(st[i] for st in steps), 60 + i) for i in range(5)]
+    sg = [sc.Stream(g, 8) for _ in range(5)]
+    se = [sc.Stream(e, 8) for _ in range(5)]
+    pos = [0] * 5
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for k, st in enumerate(steps):
+        ins = [torch.from_numpy(np.ascontiguousarray(xs[i][:, pos[i]:pos[i] + st[i]])).cuda() for i in range(5)]
+        for i in range(5):
+            pos[i] += st[i]
+        yg = sc.process_batch(g, sg, ins)
+        scratch.mul_(0.5).add_(float(k))        # eager work between replays
+        torch.cuda.synchronize()
+        ye = sc.process_batch(e, se, ins)
+        torch.cuda.synchronize()
+        for i in range(5):
+            assert torch.equal(yg[i], ye[i]), (k, i)
+    log("step graph: %d steps bitwise equal (%s)" % (len(steps), prec))
+
+
 def test_bad_length_changes_nothing():
     sc = _sc()
     m, w = weights_for("rave_b")
