@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxStreams = 8;     // streams one tile may touch (the host guarantees it)
-constexpr int kStageBatch = 4;     // 16-byte staging loads in flight per thread
+constexpr int kStageBatch = 8;     // 16-byte staging loads in flight per thread (one round trip for a tile)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -40,11 +40,9 @@ typedef int i8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct WPrec;
-// kMaxChunks: 128-byte K chunks held in registers (k = 3 taps of up to 64
-// channels in BF16 / FP8, 32 in FP32)
-template <> struct WPrec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; static constexpr int kMaxChunks = 3; };
-template <> struct WPrec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; static constexpr int kMaxChunks = 3; };
-template <> struct WPrec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; static constexpr int kMaxChunks = 2; };
+template <> struct WPrec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; };
+template <> struct WPrec<1> { static constexpr int kEsize = 2; static constexpr int kKc = 64; };
+template <> struct WPrec<2> { static constexpr int kEsize = 1; static constexpr int kKc = 128; };
 
 __device__ inline uint32_t wpack_bf16(float lo, float hi) {
   bf16x2 v = {(__bf16)lo, (__bf16)hi};
@@ -135,22 +133,21 @@ struct WinSeg {
 };
 
 // MT x F tile, 4 waves: MT = 32 -> 2 x 2 waves of 16 x (F / 2); MT = 64 ->
-// 4 x 1 waves of 16 x F.  Either way a wave owns 4 column blocks of 16.
+// 4 x 1 waves of 16 x F.  A wave owns NB column blocks of 16, so F = 16 NB WN;
+// all KCM 128-byte K chunks of its weight rows stay in registers.
 //
 // LDS: the staged window rows in operand form (activated and rounded once,
 // row stride cin * ES + 16 bytes), then, for a fused residual, each column's
 // skip row as raw FP32 ([F][cin + 4]).
-template <int PREC, int MT>
-__global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
+template <int PREC, int MT, int NB, int KCM>
+__global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
                                                              FastDiv fd_ppr) {
-  constexpr int F = MT == 32 ? 128 : 64;
   constexpr int WM = MT / 16;
   constexpr int WN = 4 / WM;
-  constexpr int NB = F / WN / 16;
-  static_assert(NB == 4, "four column blocks per wave");
+  constexpr int F = NB * 16 * WN;
   constexpr int ES = WPrec<PREC>::kEsize;
-  constexpr int kMaxChunks = WPrec<PREC>::kMaxChunks;
+  constexpr int kMaxChunks = KCM;
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
@@ -282,12 +279,13 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
     const int ppr = cin >> 2;              // 16-byte FP32 source pieces per row
     const int32_t n_pieces = R * ppr;
     for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * kStageBatch) {
+      // all loads of the batch first (one round trip), then the LDS stores;
+      // the piece's row and stream are recomputed for the stores to keep
+      // registers for the loads only
       f4 v[kStageBatch];
-      int32_t jj[kStageBatch], pp[kStageBatch], ss[kStageBatch];
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int32_t idx = i0 + u * kThreads + tid;
-        jj[u] = -1;
         v[u] = f4{0.f, 0.f, 0.f, 0.f};
         if (idx < n_pieces) {
           const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
@@ -298,16 +296,14 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
           const float* src = r < a.L ? segs[s].cache + (int64_t)r * cin
                                      : a.in_buf + ((int64_t)segs[s].in_start + r - a.L) * cin;
           v[u] = *reinterpret_cast<const f4*>(src + pc * 4);
-          jj[u] = j;
-          pp[u] = pc;
-          ss[u] = s;
         }
       }
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
-        if (jj[u] < 0) continue;
-        const int32_t j = jj[u];
-        const int pc = pp[u];
+        const int32_t idx = i0 + u * kThreads + tid;
+        if (idx >= n_pieces) continue;
+        const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
+        const int pc = idx - j * ppr;
         const f4 x = v[u];
         unsigned char* dst = wop + j * rowb + pc * 4 * ES;
         if constexpr (PREC == 0) {
@@ -323,7 +319,9 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
         }
         if (a.residual) {
           // the row is the skip row of local output frame t = window row - skip_off
-          const WinSeg& g = segs[ss[u]];
+          int sg = 0;
+          while (sg + 1 < n_seg && segs[sg + 1].base <= j) ++sg;
+          const WinSeg& g = segs[sg];
           const int32_t t = g.r0 + (j - g.base) - a.skip_off;
           if (t >= g.t_lo && t <= g.t_hi)
             *reinterpret_cast<f4*>(&wskip[(g.out_start + t - f0) * skipf + pc * 4]) = x;
@@ -407,9 +405,13 @@ __global__ void __launch_bounds__(kThreads) conv_win_kernel(LayerArgs a, int n_m
 int w_esize(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
 int w_kchunk(int prec) { return prec == 0 ? 32 : (prec == 1 ? 64 : 128); }
 
-// Tile shape: the gather kernel's M tile (the packed weights are padded to it).
+// Tile shape: the gather kernel's M tile (the packed weights are padded to
+// it); 64 frames per wave for inputs of up to 64 channels, 32 for 128.
 int win_mt(int cout) { return cout <= 32 ? 32 : 64; }
-int win_f(int mt) { return mt == 32 ? 128 : 64; }
+int win_nb(int cin) { return cin <= 64 ? 4 : 2; }
+int win_f(int mt, int nb) { return nb * 16 * (4 / (mt / 16)); }
+// K chunks the kernel holds in registers
+int win_kcm(int prec, int cin) { return prec == 0 ? 3 : (cin <= 64 ? (prec == 1 ? 3 : 2) : (prec == 1 ? 6 : 3)); }
 // operand rows plus the skip rows (allocated whether or not the layer has a skip)
 int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
   return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4;
@@ -419,13 +421,17 @@ int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
 
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec) {
   if (!conv_mfma_supported(cin, cout, k, stride, prec)) return 0;
+  // up to 64 input channels: measured slower than the gathering kernel at 128
+  // (32-frame tiles re-stage too large a halo per output)
   if (cin > 64 || cin % 16 != 0 || cout % 16 != 0 || min_frames < 1) return 0;
+  if (prec == 0 && cin > 32) return 0;
   if (L != dil * (k - 1)) return 0;
   const int kc = w_kchunk(prec);
   const int Kpad = (k * cin + kc - 1) / kc * kc;
-  // K chunks held in registers: 3 (FP32, BF16) or 2 (FP8); more would cut occupancy
-  if (Kpad * w_esize(prec) / 128 > (prec == 2 ? 2 : 3)) return 0;
-  const int F = win_f(win_mt(cout));
+  if (Kpad * w_esize(prec) / 128 > win_kcm(prec, cin)) return 0;
+  const int mt = win_mt(cout);
+  if (win_nb(cin) == 2 && mt != 64) return 0;
+  const int F = win_f(mt, win_nb(cin));
   const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
   if (max_seg > kMaxStreams) return 0;
   const int64_t rows = F + (int64_t)L * max_seg;
@@ -435,7 +441,9 @@ int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int6
 
 hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s) {
   const int MT = win_mt(a.cout);
-  const int F = win_f(MT);
+  const int NB = win_nb(a.cin);
+  const int F = win_f(MT, NB);
+  const int KCM = win_kcm(prec, a.cin);
   const int n_mt = (a.cout + MT - 1) / MT;
   const int64_t n_nt = (a.n_out + F - 1) / F;
   const int kc = w_kchunk(prec);
@@ -448,15 +456,15 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   const size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
   const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
-#define SC_WIN(P, M)                                                                                      \
-  if (prec == P && MT == M) {                                                                             \
-    hipLaunchKernelGGL((conv_win_kernel<P, M>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, n_mt,    \
-                       (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                       \
-    return hipGetLastError();                                                                             \
+#define SC_WIN(P, M, N, K)                                                                                  \
+  if (prec == P && MT == M && NB == N && KCM == K) {                                                       \
+    hipLaunchKernelGGL((conv_win_kernel<P, M, N, K>), dim3((unsigned)grid), dim3(kThreads), lds, s, a,     \
+                       n_mt, (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                  \
+    return hipGetLastError();                                                                              \
   }
-  SC_WIN(0, 32) SC_WIN(0, 64)
-  SC_WIN(1, 32) SC_WIN(1, 64)
-  SC_WIN(2, 32) SC_WIN(2, 64)
+  SC_WIN(0, 32, 4, 3) SC_WIN(0, 64, 4, 3)
+  SC_WIN(1, 32, 4, 3) SC_WIN(1, 64, 4, 3) SC_WIN(1, 64, 2, 6)
+  SC_WIN(2, 32, 4, 2) SC_WIN(2, 64, 4, 2) SC_WIN(2, 64, 2, 3)
 #undef SC_WIN
   return hipErrorInvalidValue;
 }
