@@ -185,6 +185,26 @@ sc_status stream_process(sc_stream* stream, const float* d_in, int32_t n_frames,
 sc_status stream_reset(sc_stream* stream, void* hip_stream);
 /* Input frames processed since creation / the last reset. */
 int64_t stream_position(const sc_stream* stream);
+
+/* ---- stream state export / import (checkpoint, resume, migration) ----
+ * A stream's whole streaming state (every layer's cache, transposed-conv
+ * carry and delay line, its position and buffer parity; Sec. 2.2: the cached
+ * padding is the only state the method carries between buffers) as a
+ * self-describing host byte string.  Importing it into a stream of a model
+ * with the same graph and precision (this or another model object, on this
+ * or another device) continues the stream bitwise as if the original had
+ * processed the following buffers. */
+/* Bytes of an exported state for streams of `model`. */
+int64_t sc_stream_state_bytes(const sc_model* model);
+/* Waits for the stream's queued steps, then writes its state to host memory
+ * `host` (`bytes` >= sc_stream_state_bytes).  Errors: SC_EINVAL (null, too
+ * small), SC_ESTATE (the stream saw a device error), SC_EDEVICE. */
+sc_status stream_export(sc_stream* stream, void* host, int64_t bytes);
+/* Replaces the stream's state with an exported one; the stream's own flags
+ * and maximum buffer length stay.  Waits for its queued steps first.
+ * Errors: SC_EINVAL (null, wrong size, or state of another graph or
+ * precision; the stream is left unchanged), SC_EDEVICE. */
+sc_status stream_import(sc_stream* stream, const void* host, int64_t bytes);
 void stream_destroy(sc_stream* stream);
 
 /* Process one buffer for each of n streams of the same model in one batched

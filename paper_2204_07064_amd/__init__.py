@@ -154,6 +154,18 @@ class Stream:
     def position(self):
         return lib().stream_position(self.handle)
 
+    def export_state(self):
+        """The stream's whole state as bytes (after its queued steps)."""
+        n = lib().sc_stream_state_bytes(self.model.handle)
+        buf = ctypes.create_string_buffer(n)
+        check(lib().stream_export(self.handle, buf, n))
+        return buf.raw
+
+    def import_state(self, state):
+        """Continue from an exported state (same graph and precision)."""
+        b = bytes(state)
+        check(lib().stream_import(self.handle, ctypes.c_char_p(b), len(b)))
+
     def close(self):
         if self.handle and not _EXITING[0]:
             lib().stream_destroy(self.handle)

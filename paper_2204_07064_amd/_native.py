@@ -35,7 +35,7 @@ EXPORTS = [
     "sc_process_batch", "sc_last_error", "sc_model_profile", "sc_model_profile_read",
     "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
     "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
-    "sc_model_reserve", "sc_model_enable_graph",
+    "sc_model_reserve", "sc_model_enable_graph", "sc_stream_state_bytes", "stream_export", "stream_import",
 ]
 SC_PENDING = 1
 SC_SUBMIT_DISCARD = 1
@@ -104,6 +104,9 @@ def lib():
     _sig(L, "sc_model_n_layers", c_i32, [c_vp])
     _sig(L, "sc_model_reserve", c_i32, [c_vp, c_i64])
     _sig(L, "sc_model_enable_graph", c_i32, [c_vp, c_i32])
+    _sig(L, "sc_stream_state_bytes", c_i64, [c_vp])
+    _sig(L, "stream_export", c_i32, [c_vp, c_vp, c_i64])
+    _sig(L, "stream_import", c_i32, [c_vp, c_vp, c_i64])
     _sig(L, "sc_model_set_act_scales", c_i32, [c_vp, c_fp])
     _sig(L, "sc_model_read_amax", c_i32, [c_vp, c_fp, c_i32])
     _sig(L, "sc_model_enable_amax", c_i32, [c_vp, c_i32])

@@ -730,6 +730,87 @@ sc_status stream_create(sc_model* m, int32_t max_frames, uint32_t flags, void* h
   return SC_OK;
 }
 
+namespace {
+// Exported state: header, then the device state allocation (both copies).
+struct StateHeader {
+  uint32_t magic;             // 'SCST'
+  uint32_t version;
+  int64_t state_alloc_floats;
+  int64_t latency, warmup;
+  int32_t precision, n_ops;
+  int32_t in_channels, out_channels;
+  int64_t pos;
+  int32_t parity, reserved;
+};
+constexpr uint32_t kStateMagic = 0x54534353u;   // "SCST" little-endian
+
+StateHeader state_header(const sc_model* m) {
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.version = 1;
+  h.state_alloc_floats = std::max<int64_t>(m->plan.state_alloc_floats, 1);
+  h.latency = m->plan.latency;
+  h.warmup = m->plan.warmup;
+  h.precision = (int32_t)m->prec;
+  h.n_ops = (int32_t)m->plan.ops.size();
+  h.in_channels = m->plan.in_channels;
+  h.out_channels = m->plan.out_channels;
+  return h;
+}
+}  // namespace
+
+int64_t sc_stream_state_bytes(const sc_model* m) {
+  if (!m) return -1;
+  return (int64_t)sizeof(StateHeader) + std::max<int64_t>(m->plan.state_alloc_floats, 1) * (int64_t)sizeof(float);
+}
+
+sc_status stream_export(sc_stream* s, void* host, int64_t bytes) {
+  if (!s || !host) return fail(SC_EINVAL, "null argument");
+  sc_model* m = s->m;
+  if (bytes < sc_stream_state_bytes(m)) return fail(SC_EINVAL, "buffer smaller than sc_stream_state_bytes");
+  std::lock_guard<std::mutex> g(m->mu);
+  if (s->bad) return fail(SC_ESTATE, "stream saw a device error; call stream_reset");
+  hipError_t e = hipSetDevice(m->device);
+  if (e == hipSuccess && m->has_last) e = hipEventSynchronize(m->last_done);
+  StateHeader h = state_header(m);
+  h.pos = s->pos;
+  h.parity = s->parity;
+  std::memcpy(host, &h, sizeof(h));
+  if (e == hipSuccess)
+    e = hipMemcpy(static_cast<unsigned char*>(host) + sizeof(h), s->d_state,
+                  (size_t)h.state_alloc_floats * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "state export");
+  return SC_OK;
+}
+
+sc_status stream_import(sc_stream* s, const void* host, int64_t bytes) {
+  if (!s || !host) return fail(SC_EINVAL, "null argument");
+  sc_model* m = s->m;
+  if (bytes != sc_stream_state_bytes(m)) return fail(SC_EINVAL, "size differs from sc_stream_state_bytes");
+  StateHeader h;
+  std::memcpy(&h, host, sizeof(h));
+  StateHeader want = state_header(m);
+  if (h.magic != want.magic || h.version != want.version || h.state_alloc_floats != want.state_alloc_floats ||
+      h.latency != want.latency || h.warmup != want.warmup || h.precision != want.precision ||
+      h.n_ops != want.n_ops || h.in_channels != want.in_channels || h.out_channels != want.out_channels ||
+      h.pos < 0 || (h.parity != 0 && h.parity != 1))
+    return fail(SC_EINVAL, "state of another graph or precision");
+  std::lock_guard<std::mutex> g(m->mu);
+  hipError_t e = hipSetDevice(m->device);
+  if (e == hipSuccess && m->has_last) e = hipEventSynchronize(m->last_done);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->d_state, static_cast<const unsigned char*>(host) + sizeof(h),
+                  (size_t)h.state_alloc_floats * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    s->bad = true;
+    return hip_fail(e, "state import");
+  }
+  s->pos = h.pos;
+  s->parity = h.parity;
+  s->bad = false;
+  return SC_OK;
+}
+
 sc_status stream_process(sc_stream* s, const float* d_in, int32_t n_frames, float* d_out, void* hip_stream) {
   if (!s) return fail(SC_EINVAL, "null stream");
   std::lock_guard<std::mutex> g(s->m->mu);

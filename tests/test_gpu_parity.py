@@ -149,6 +149,44 @@ def test_step_graph_replays_bitwise(prec):
     log("step graph: %d steps bitwise equal (%s)" % (len(steps), prec))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_state_export_import_continues_bitwise(prec):
+    """A stream checkpointed after some buffers and resumed in a fresh stream
+    (of the same model object, or of a second model object: migration)
+    continues bitwise as the uninterrupted stream."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, prec)
+    x = scgen.stream_latents(16, 24, 41)
+    whole = run_stream(mod, x, [5, 7, 3, 9])
+    a = sc.Stream(mod, 9)
+    first = run_stream(mod, x[:, :12], [5, 7], stream=a)
+    state = a.export_state()
+    assert len(state) == sc.lib().sc_stream_state_bytes(mod.handle)
+    for target in (mod, sc.Model(m, w, prec)):
+        b = sc.Stream(target, 9)
+        b.import_state(state)
+        assert b.position == 12
+        rest = run_stream(target, x[:, 12:], [3, 9], stream=b)
+        assert np.array_equal(np.concatenate([first, rest], axis=1), whole)
+
+
+def test_state_import_rejects_other_graph():
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    a = sc.Stream(sc.Model(m, w, "fp32"), 8)
+    state = a.export_state()
+    b = sc.Stream(sc.Model(m, w, "bf16"), 8)
+    with pytest.raises(sc.ScError):
+        b.import_state(state)                     # another precision
+    with pytest.raises(sc.ScError):
+        a.import_state(state[:-4])                # wrong size
+    m3, w3 = weights_for("stack3")
+    c = sc.Stream(sc.Model(m3, w3, "fp32"), 8)
+    with pytest.raises(sc.ScError):
+        c.import_state(state)                     # another graph
+
+
 def test_bad_length_changes_nothing():
     sc = _sc()
     m, w = weights_for("rave_b")
