@@ -46,27 +46,47 @@ DTYPE = {0: "fp32", 1: "bf16", 2: "fp8e4m3"}
 IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 
 
-# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (KiB per dispatch), each scaled by what the counter reads for a plain copy
-# of known size.  Valid only for the kernel sources it was taken with.
+# HBM traffic per launch of every layer of the BF16 256-stream workload from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled by what
+# the counter reads for a plain copy of known size.  Valid only for the kernel
+# sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "kernel": "conv_mfma node 25 (cin 32, cout 32, k 3, d 1)",
-    "sources_sha1": "aba1a37cae6d961b52992599fac9e0b9796726b2 5d38a60eb4fb637ab8214808638dfa6abbc7442f "
-                    "1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
-    "fetch_kib": 32568.8, "write_kib": 64777.9,
+    "sources_sha1": "e39183e741dde5c3a3f0ed1aa1965f849b72be6d 467ddbb1db5e93ee81ed100394f71277d3c028ea e509de939f5812d55aeb8e86719a9902dbc0a2e7 c2e77a1f210e1a1a75ed7f2890e7e5c6f45229df 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
+    # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    "by_node": {
+        1: ('valu', 897.6, 8117.2),
+        2: ('mfma', 10491.9, 17194.8),
+        4: ('mfma', 10331.2, 16938.5),
+        6: ('mfma', 11319.7, 18474.5),
+        8: ('mfma', 14223.4, 23082.5),
+        9: ('mfma', 5242.5, 32858.7),
+        11: ('mfma', 17135.8, 32725.0),
+        13: ('mfma', 17638.4, 33493.0),
+        15: ('mfma', 19122.6, 35797.6),
+        16: ('mfma', 6204.3, 43377.2),
+        18: ('mfma_win', 22718.0, 43249.2),
+        20: ('mfma_win', 24203.6, 43505.2),
+        22: ('mfma_win', 28741.1, 65833.9),
+        23: ('mfma', 10997.0, 43185.2),
+        25: ('mfma_win', 22251.1, 43185.2),
+        27: ('mfma_win', 22993.7, 43313.2),
+        29: ('mfma_win', 25206.6, 43697.2),
+        30: ('valu', 23427.1, 1539.5),
+    },
 }
-TRAFFIC_SOURCES = ("kernels_mfma.hip", "kernels.h", "sc_device.h")
+TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
 
 
-def measured_traffic(kernel):
+def measured_traffic(best):
     import hashlib
     d = os.path.join(ROOT, "paper_2204_07064_amd", "csrc")
     sha = " ".join(hashlib.sha1(open(os.path.join(d, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES)
     t = MEASURED_TRAFFIC
-    if kernel != t["kernel"] or sha != t["sources_sha1"]:
+    rec = t["by_node"].get(best["node"])
+    if sha != t["sources_sha1"] or rec is None or rec[0] != IMPL_NAME[best["impl"]] or best["precision"] != 1:
         return None
-    return round(t["fetch_kib"] * t["fetch_bytes_per_kib"] + t["write_kib"] * t["write_bytes_per_kib"])
+    return round(rec[1] * t["fetch_bytes_per_kib"] + rec[2] * t["write_bytes_per_kib"])
 
 
 def op_accounting(p):
@@ -106,7 +126,7 @@ def roofline(prof):
     kernel = "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
         kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": measured_traffic(kernel),
+            "frac": round(ach / peak, 4), "traffic": measured_traffic(best),
             "algorithmic_bytes_per_launch": round(byts / max(best["launches"], 1)),
             "kernel": kernel,
             "avg_launch_us": round(best["ms"] * 1e3 / max(best["launches"], 1), 2),
