@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
     if (a.residual) v = v + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
     if ((int64_t)t * a.out_den < segs[s].mask_x) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
-    *reinterpret_cast<f4*>(a.out_buf + o) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
     if (a.out_twin) {
       f4 w = v;
       if (a.twin_pre) {

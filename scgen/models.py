@@ -124,6 +124,25 @@ def branch_unit():
     return {"name": "branch", "nodes": nodes, "in_channels": 4, "out_channels": 8}
 
 
+def branch3_unit():
+    """Four parallel branches of one input, summed by three adds (Sec. 3.2,
+    Eq. 3 beyond two branches): (k3, d1); (k5, d2) then (k3, d1); (k7, d3);
+    and a rate excursion, a transposed conv (ratio 2) followed by a strided
+    conv (K4, S2, pads 1/1) back to the input rate (Eq. 2 inside a branch).
+    Post-reconfiguration delays 1, 5, 9 and 1 frames."""
+    nodes = [_input(4),
+             _conv(0, 4, 8, 3, 1),                                    # 1: D 1
+             _conv(0, 4, 8, 5, 2),                                    # 2: D 4
+             _conv(2, 8, 8, 3, 1, pre_act=ACT_LRELU),                 # 3: D 5
+             _add(1, 3),                                              # 4: D 5
+             _conv(0, 4, 8, 7, 3),                                    # 5: D 9
+             _add(4, 5),                                              # 6: D 9
+             _convt(0, 4, 8, 2, pre_act=ACT_NONE),                    # 7: rate 2, D 1
+             _conv(7, 8, 8, 4, 1, stride=2, pad_l=1, pad_r=1, pre_act=ACT_LRELU),   # 8: rate 1, D 1
+             _add(6, 8)]                                              # 9: D 9
+    return {"name": "branch3", "nodes": nodes, "in_channels": 4, "out_channels": 8}
+
+
 def encoder(name="encoder", ratios=(4, 4, 4, 2), widths=(16, 32, 64, 128, 256), latent=16):
     """RAVE-style strided-conv encoder: Conv k7 1->widths[0], then per ratio
     r: LeakyReLU -> Conv(k=2r+1, stride r, pads r/r), then LeakyReLU -> Conv k3
@@ -140,7 +159,7 @@ def model_by_name(name):
     table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder,
              "strided": lambda: strided_unit(False),
              "strided_aligned": lambda: strided_unit(True),
-             "branch": branch_unit, "encoder": encoder}
+             "branch": branch_unit, "branch3": branch3_unit, "encoder": encoder}
     return table[name]()
 
 

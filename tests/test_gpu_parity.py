@@ -35,6 +35,7 @@ def _need_gpu():
     ("strided", 256, 8, 0),             # Eq. 2 alignment delay D_a = 1
     ("strided_aligned", 256, 6, 0),
     ("branch", 300, 7, 0),              # Eq. 3 branch delays (3, 0)
+    ("branch3", 301, 5, 0),             # four branches, three adds, a rate excursion
     ("encoder", 128 * 40, 128 * 3, 0),  # strided encoder, buffers multiple of 128
 ])
 def test_fp32_parity(name, frames, buf, options):

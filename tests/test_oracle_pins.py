@@ -149,7 +149,7 @@ def torch_forward(model, weights, x):
 
 
 @pytest.mark.parametrize("name,frames", [("stack3", 300), ("rave_b", 12), ("strided", 40),
-                                         ("branch", 50), ("encoder", 256)])
+                                         ("branch", 50), ("branch3", 50), ("encoder", 256)])
 def test_forward_vs_torch_graph(name, frames):
     m = scgen.model_by_name(name)
     w = scgen.init_weights(m, 0, "kaiming" if name == "stack3" else "calibrated")
@@ -228,7 +228,7 @@ def _golden_delays():
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["stack3", "rave_b", "wide", "strided", "strided_aligned", "branch"])
+@pytest.mark.parametrize("name", ["stack3", "rave_b", "wide", "strided", "strided_aligned", "branch", "branch3"])
 def test_latency_and_warmup_closed_form(name):
     g = _golden_delays()[name]
     m = scgen.model_by_name(name)
@@ -239,7 +239,7 @@ def test_latency_and_warmup_closed_form(name):
 
 @pytest.mark.parametrize("name,frames,buf", [("stack3", 2048, 64), ("rave_b", 48, 5),
                                              ("strided", 64, 6), ("strided_aligned", 64, 4),
-                                             ("branch", 60, 7)])
+                                             ("branch", 60, 7), ("branch3", 61, 5)])
 def test_latency_and_warmup_empirical(name, frames, buf):
     """Brute-force search: the only lag at which the streamed output matches
     the offline one over the tail is D, and the last mismatching offline index
@@ -295,7 +295,7 @@ def _stream_vs_offline(name, frames, splits, **kw):
 
 @pytest.mark.parametrize("name,frames,mult", [("stack3", 1500, 1), ("rave_b", 40, 1),
                                               ("strided", 60, 2), ("branch", 77, 1),
-                                              ("encoder", 512, 128)])
+                                              ("branch3", 83, 1), ("encoder", 512, 128)])
 def test_offline_parity_and_split_invariance(name, frames, mult):
     outs = []
     for seed in range(3):
@@ -325,9 +325,9 @@ def test_negative_control_no_stride_alignment():
     assert err > 1e-2
 
 
-@pytest.mark.parametrize("name", ["branch", "rave_b"])
+@pytest.mark.parametrize("name", ["branch", "branch3", "rave_b"])
 def test_negative_control_unaligned_branches(name):
-    frames = 77 if name == "branch" else 24
+    frames = 24 if name == "rave_b" else 77
     s, y, so, err = _stream_vs_offline(name, frames, [frames], align_branches=False)
     assert err > 1e-2
 
