@@ -177,11 +177,13 @@ class Workload:
 
 def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False):
     wl = Workload(sc, torch, model, warmup + steps, graph=graph)
+    if profile:
+        model.profile(True)    # the warm-up steps also create the event pool
     for _ in range(warmup):
         wl.step()
     torch.cuda.synchronize()
     if profile:
-        model.profile(True)
+        model.profile(True)    # clears the sums: only the timed steps count
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     evs[0].record()

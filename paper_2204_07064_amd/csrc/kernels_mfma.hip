@@ -163,8 +163,11 @@ __device__ inline void store_twin4(const LayerArgs& a, int64_t o, f4 v) {
   store4<PREC>(static_cast<unsigned char*>(a.out_twin) + o * Prec<PREC>::kEsize, v.x * q, v.y * q, v.z * q, v.w * q);
 }
 
+// A 2-chunk register pipeline; kernels reading operand twins ask for 4 waves
+// per SIMD (3 for FP8), measured faster than 4 chunks in flight at 3 waves;
+// the others keep the default register budget (they would spill).
 template <int PREC, int MT, int NT, bool CONVT, bool INTWIN>
-__global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_cols, int n_mt, int n_nt,
+__global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) gemm_kernel(LayerArgs a, int32_t n_cols, int n_mt, int n_nt,
                                                         int Kpad, int Kreal, int half_pad, int Mreal,
                                                         int extra_blocks, FastDiv fd_per_ent) {
   constexpr int KC = Prec<PREC>::kKc;
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(LayerArgs a, int32_t n_c
 
   // Register pipeline: chunk c + STAGES is in flight while chunk c is
   // multiplied, so a chunk's memory latency overlaps STAGES chunks of work.
-  constexpr int STAGES = INTWIN ? 4 : 2;
+  constexpr int STAGES = 2;
   static_assert(STAGES == 2 || STAGES == 4, "stages are written out for 2 or 4");
   constexpr int EPP = INTWIN ? 16 / ES : 4;             // elements per B piece
   constexpr int PPCOL = KC / EPP;                       // pieces per column per chunk
