@@ -411,7 +411,10 @@ int win_mt(int cout) { return cout <= 32 ? 32 : 64; }
 int win_nb(int cin) { return cin <= 64 ? 4 : 2; }
 int win_f(int mt, int nb) { return nb * 16 * (4 / (mt / 16)); }
 // K chunks the kernel holds in registers
-int win_kcm(int prec, int cin) { return prec == 0 ? 3 : (cin <= 64 ? (prec == 1 ? 3 : 2) : (prec == 1 ? 6 : 3)); }
+int win_kcm(int prec, int cin) {
+  if (prec == 0) return cin <= 32 ? 3 : 6;
+  return cin <= 64 ? (prec == 1 ? 3 : 2) : (prec == 1 ? 6 : 3);
+}
 // operand rows plus the skip rows (allocated whether or not the layer has a skip)
 int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
   return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4;
@@ -424,7 +427,6 @@ int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int6
   // up to 64 input channels: measured slower than the gathering kernel at 128
   // (32-frame tiles re-stage too large a halo per output)
   if (cin > 64 || cin % 16 != 0 || cout % 16 != 0 || min_frames < 1) return 0;
-  if (prec == 0 && cin > 32) return 0;
   if (L != dil * (k - 1)) return 0;
   const int kc = w_kchunk(prec);
   const int Kpad = (k * cin + kc - 1) / kc * kc;
@@ -462,7 +464,7 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
                        n_mt, (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                  \
     return hipGetLastError();                                                                              \
   }
-  SC_WIN(0, 32, 4, 3) SC_WIN(0, 64, 4, 3)
+  SC_WIN(0, 32, 4, 3) SC_WIN(0, 64, 4, 3) SC_WIN(0, 64, 4, 6)
   SC_WIN(1, 32, 4, 3) SC_WIN(1, 64, 4, 3) SC_WIN(1, 64, 2, 6)
   SC_WIN(2, 32, 4, 2) SC_WIN(2, 64, 4, 2) SC_WIN(2, 64, 2, 3)
 #undef SC_WIN
