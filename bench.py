@@ -51,27 +51,27 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "e39183e741dde5c3a3f0ed1aa1965f849b72be6d 467ddbb1db5e93ee81ed100394f71277d3c028ea e509de939f5812d55aeb8e86719a9902dbc0a2e7 c2e77a1f210e1a1a75ed7f2890e7e5c6f45229df 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "16283b4f90559ab493f9d0d15f9eaf7e3ba6d711 617dafaded7a8330ae2c05e6d9cc904adc3f23df e509de939f5812d55aeb8e86719a9902dbc0a2e7 c2e77a1f210e1a1a75ed7f2890e7e5c6f45229df 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
         1: ('valu', 897.6, 8117.2),
-        2: ('mfma', 10491.9, 17194.8),
-        4: ('mfma', 10331.2, 16938.5),
-        6: ('mfma', 11319.7, 18474.5),
-        8: ('mfma', 14223.4, 23082.5),
-        9: ('mfma', 5242.5, 32858.7),
-        11: ('mfma', 17135.8, 32725.0),
-        13: ('mfma', 17638.4, 33493.0),
-        15: ('mfma', 19122.6, 35797.6),
-        16: ('mfma', 6204.3, 43377.2),
-        18: ('mfma_win', 22718.0, 43249.2),
-        20: ('mfma_win', 24203.6, 43505.2),
-        22: ('mfma_win', 28741.1, 65833.9),
-        23: ('mfma', 10997.0, 43185.2),
-        25: ('mfma_win', 22251.1, 43185.2),
-        27: ('mfma_win', 22993.7, 43313.2),
-        29: ('mfma_win', 25206.6, 43697.2),
+        2: ('mfma', 10430.2, 22399.0),
+        4: ('mfma', 10303.7, 22081.2),
+        6: ('mfma', 11288.5, 23405.6),
+        8: ('mfma', 14131.1, 27341.3),
+        9: ('mfma', 5216.6, 42315.2),
+        11: ('mfma', 16977.7, 40088.1),
+        13: ('mfma', 17500.6, 40885.6),
+        15: ('mfma', 19003.0, 43024.7),
+        16: ('mfma', 6179.9, 58793.9),
+        18: ('mfma_win', 22650.5, 58324.5),
+        20: ('mfma_win', 24122.2, 57259.7),
+        22: ('mfma_win', 28601.3, 80176.8),
+        23: ('mfma', 10974.4, 57848.2),
+        25: ('mfma_win', 22211.7, 58411.8),
+        27: ('mfma_win', 22945.2, 58050.2),
+        29: ('mfma_win', 25145.1, 58518.0),
         30: ('valu', 23427.1, 1539.5),
     },
 }
