@@ -234,7 +234,8 @@ typedef struct {
 
 /* Enable (1) or disable (0) per-launch timing; enabling clears the sums.
  * While enabled every launch is bracketed by two hipEventRecord calls on the
- * processing stream. */
+ * processing stream, and each step first waits on the host for the previous
+ * step's timings (the event pool then holds one step's worth). */
 sc_status sc_model_profile(sc_model* model, int32_t enable);
 /* Synchronizes, then fills up to `max_ops` records (one per launch of a
  * step, in launch order) and sets *n_ops to the number of launches per step. */

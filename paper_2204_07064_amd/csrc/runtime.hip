@@ -390,6 +390,12 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   st = ensure_workspace(m, total);
   if (st != SC_OK) return st;
+  if (m->prof_on && m->prof_used > 0) {
+    // fold the previous step's launch timings, so that one step's worth of
+    // events is reused (the host waits for that step: profiling only)
+    e = prof_fold(m);
+    if (e != hipSuccess) return hip_fail(e, "profile fold");
+  }
 
   // the step graph serves steps of up to graph_streams streams (and any size
   // up to the workspace); timed or calibrating steps launch one by one
