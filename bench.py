@@ -39,6 +39,20 @@ BUF_CHOICES = (1, 2, 4, 8, 16, 32)
 N_STREAMS = 256
 LATENT = 16
 SPF = 128          # output samples per latent frame
+
+
+class Shape:
+    """A closed-loop workload: a decoder, its stream count and buffer mix."""
+
+    def __init__(self, name, model_fn, streams, choices, latent, spf):
+        self.name, self.model_fn, self.streams = name, model_fn, streams
+        self.choices, self.latent, self.spf = tuple(choices), latent, spf
+
+
+HEADLINE = Shape("rave_b", scgen.rave_decoder_b, N_STREAMS, BUF_CHOICES, LATENT, SPF)
+# the wide decoder (128 latent channels, 512 samples per frame) with 1024
+# streams of uneven 1..8-frame buffers
+WIDE = Shape("wide", scgen.wide_decoder, 1024, range(1, 9), 128, 512)
 HBM_PEAK = 8.0e12  # B/s
 PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
 PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
@@ -51,28 +65,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "16283b4f90559ab493f9d0d15f9eaf7e3ba6d711 617dafaded7a8330ae2c05e6d9cc904adc3f23df e509de939f5812d55aeb8e86719a9902dbc0a2e7 c2e77a1f210e1a1a75ed7f2890e7e5c6f45229df 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "16283b4f90559ab493f9d0d15f9eaf7e3ba6d711 617dafaded7a8330ae2c05e6d9cc904adc3f23df 9c5b01c64c454d87da90bad86645835e5fcdd2aa e0543016740a123080c38c42a0fc2741dfd862f2 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('valu', 897.6, 8117.2),
-        2: ('mfma', 10430.2, 22399.0),
-        4: ('mfma', 10303.7, 22081.2),
-        6: ('mfma', 11288.5, 23405.6),
-        8: ('mfma', 14131.1, 27341.3),
-        9: ('mfma', 5216.6, 42315.2),
-        11: ('mfma', 16977.7, 40088.1),
-        13: ('mfma', 17500.6, 40885.6),
-        15: ('mfma', 19003.0, 43024.7),
-        16: ('mfma', 6179.9, 58793.9),
-        18: ('mfma_win', 22650.5, 58324.5),
-        20: ('mfma_win', 24122.2, 57259.7),
-        22: ('mfma_win', 28601.3, 80176.8),
-        23: ('mfma', 10974.4, 57848.2),
-        25: ('mfma_win', 22211.7, 58411.8),
-        27: ('mfma_win', 22945.2, 58050.2),
-        29: ('mfma_win', 25145.1, 58518.0),
-        30: ('valu', 23427.1, 1539.5),
+        1: ('valu', 895.1, 8117.2),
+        2: ('mfma', 10430.3, 22400.3),
+        4: ('mfma', 10303.7, 22084.3),
+        6: ('mfma', 11288.9, 23402.3),
+        8: ('mfma', 14131.8, 27320.7),
+        9: ('mfma', 5216.6, 42293.0),
+        11: ('mfma', 16976.6, 40112.5),
+        13: ('mfma', 17499.3, 40893.7),
+        15: ('mfma', 19004.5, 43023.9),
+        16: ('mfma', 6179.9, 58810.3),
+        18: ('mfma_win', 22650.4, 58339.5),
+        20: ('mfma_win', 24122.3, 57332.6),
+        22: ('mfma_win', 28599.9, 80215.3),
+        23: ('mfma', 10974.4, 57986.3),
+        25: ('mfma_win', 22211.6, 58642.9),
+        27: ('mfma_win', 22945.4, 58400.0),
+        29: ('mfma_win', 25145.1, 58910.9),
+        30: ('valu', 23428.7, 1539.5),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
@@ -134,49 +148,55 @@ def roofline(prof):
 
 
 class Workload:
-    """256 streams, pre-drawn buffer lengths and device-resident inputs."""
+    """The shape's streams, pre-drawn buffer lengths and device-resident inputs."""
 
-    def __init__(self, sc, torch, model, steps, seed=7, graph=False):
+    def __init__(self, sc, torch, model, steps, seed=7, graph=False, shape=HEADLINE):
         self.sc, self.torch = sc, torch
         self.model = model
-        model.reserve(N_STREAMS * max(BUF_CHOICES))   # no workspace growth inside the timed steps
-        model.enable_graph(N_STREAMS if graph else 0)  # optional: one graph replay per step
+        S, C, top = shape.streams, shape.latent, max(shape.choices)
+        self.spf = shape.spf
+        model.reserve(S * top)                 # no workspace growth inside the timed steps
+        model.enable_graph(S if graph else 0)  # optional: one graph replay per step
         # every step's arguments are prebuilt (BatchCall), so issuing a step is one library call
-        self.streams = [sc.Stream(model, max(BUF_CHOICES)) for _ in range(N_STREAMS)]
-        self.lens = np.array([scgen.buffer_lengths(steps, BUF_CHOICES, seed * 100003 + i)
-                              for i in range(N_STREAMS)], dtype=np.int64)   # [stream][step]
-        # every buffer contiguous ([16][n]) in one host array, copied to HBM at once
-        sizes = self.lens * LATENT                                            # [stream][step]
+        self.streams = [sc.Stream(model, top) for _ in range(S)]
+        self.lens = np.array([scgen.buffer_lengths(steps, shape.choices, seed * 100003 + i)
+                              for i in range(S)], dtype=np.int64)   # [stream][step]
+        # every buffer contiguous ([C][n]) in one host array, copied to HBM at once
+        sizes = self.lens * C                                        # [stream][step]
         offs = np.concatenate([[0], np.cumsum(sizes.ravel())[:-1]]).reshape(sizes.shape)
         host = np.empty(int(sizes.sum()), np.float32)
-        for i in range(N_STREAMS):
-            x = scgen.stream_latents(LATENT, int(self.lens[i].sum()), i)
+        for i in range(S):
+            x = scgen.stream_latents(C, int(self.lens[i].sum()), i)
             a = 0
             for j in range(steps):
                 n = int(self.lens[i, j])
-                host[offs[i, j]:offs[i, j] + LATENT * n] = x[:, a:a + n].ravel()
+                host[offs[i, j]:offs[i, j] + C * n] = x[:, a:a + n].ravel()
                 a += n
         flat = torch.from_numpy(host).cuda()
-        self.inputs = [[flat[offs[i, j]:offs[i, j] + sizes[i, j]].view(LATENT, int(self.lens[i, j]))
-                        for j in range(steps)] for i in range(N_STREAMS)]
-        self.outs = [torch.empty((1, max(BUF_CHOICES) * SPF), device="cuda") for _ in range(N_STREAMS)]
+        self.inputs = [[flat[offs[i, j]:offs[i, j] + sizes[i, j]].view(C, int(self.lens[i, j]))
+                        for j in range(steps)] for i in range(S)]
+        self.outs = [torch.empty((1, top * shape.spf), device="cuda") for _ in range(S)]
         out_ptrs = [o.data_ptr() for o in self.outs]
-        self.calls = [sc.BatchCall(model, self.streams, [self.inputs[i][j].data_ptr() for i in range(N_STREAMS)],
+        self.calls = [sc.BatchCall(model, self.streams, [self.inputs[i][j].data_ptr() for i in range(S)],
                                    self.lens[:, j], out_ptrs) for j in range(steps)]
         self.hs = torch.cuda.current_stream().cuda_stream
         self.step_i = 0
         torch.cuda.synchronize()
 
     def samples(self, j):
-        return int(self.lens[:, j].sum()) * SPF
+        return int(self.lens[:, j].sum()) * self.spf
+
+    def close(self):
+        for st in self.streams:
+            st.close()
 
     def step(self):
         self.calls[self.step_i].run(self.hs)
         self.step_i += 1
 
 
-def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False):
-    wl = Workload(sc, torch, model, warmup + steps, graph=graph)
+def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False, shape=HEADLINE):
+    wl = Workload(sc, torch, model, warmup + steps, graph=graph, shape=shape)
     if profile:
         model.profile(True)    # the warm-up steps also create the event pool
     for _ in range(warmup):
@@ -192,6 +212,8 @@ def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False):
         samples += wl.samples(warmup + k)
         wl.step()
         evs[k + 1].record()
+    frames_in = int(wl.lens[:, warmup:].sum())
+    buffers = int(wl.lens[:, warmup:].size)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
@@ -199,7 +221,113 @@ def timed_run(sc, torch, model, warmup, steps, profile=False, graph=False):
     prof = model.profile_read() if profile else None
     if profile:
         model.profile(False)
-    return {"samples": samples, "gpu_s": gpu_s, "wall_s": wall, "step_ms": step_ms, "prof": prof}
+    wl.close()
+    return {"samples": samples, "gpu_s": gpu_s, "wall_s": wall, "step_ms": step_ms, "prof": prof,
+            "frames_in": frames_in, "buffers": buffers,
+            "algorithmic_bytes": 4.0 * (samples + frames_in * shape.latent)
+            + 2.0 * buffers * model.info["state_bytes_per_stream"]}
+
+
+def step_roofline(run, value, prec):
+    """The whole step against the chip, from a profiled run: FLOPs per output
+    sample summed over every launch (op_accounting).  Algorithmic bytes per
+    sample: the step's input and output plus every stream's state read and
+    written once per buffer; the roofline min(MFMA peak / FLOP, HBM / bytes)
+    in samples/s at the step's precision, and the value as a fraction of it.
+    The layer-by-layer figures (every layer's input and output through HBM,
+    op_accounting) are the design's own roofline, given beside it."""
+    prof, samples = run["prof"], run["samples"]
+    flops = sum(op_accounting(p)[0] for p in prof) / samples
+    byts = run["algorithmic_bytes"] / samples
+    lbl = sum(op_accounting(p)[1] for p in prof) / samples
+    by_f, by_b = PEAK[prec] / flops, HBM_PEAK / byts
+    roof = min(by_f, by_b)
+    roof_lbl = min(by_f, HBM_PEAK / lbl)
+    return {"flop_per_sample": round(flops, 1), "bytes_per_sample": round(byts, 1),
+            "bound": "mfma" if by_f <= by_b else "hbm", "roofline_samples_per_s": round(roof, 1),
+            "frac": round(value / roof, 5),
+            "layer_by_layer": {"bytes_per_sample": round(lbl, 1), "roofline_samples_per_s": round(roof_lbl, 1),
+                               "frac": round(value / roof_lbl, 5)}}
+
+
+def wide_runs(sc, torch, precisions=("fp8", "bf16", "fp32"), warmup=3, steps=10):
+    """The wide decoder with 1024 streams (closed loop, buffers uniform over
+    1..8 frames) at each precision: samples/s and its step roofline."""
+    m = WIDE.model_fn()
+    w = scgen.init_weights(m)
+    out = {"workload": "wide decoder (128 latent ch, widths 768->384->192->96->48, ratios [8,8,4,2], "
+                       "dilations 1/3/9/27): 1024 streams, buffers uniform over 1..8 latent frames, closed loop"}
+    for prec in precisions:
+        scales = calibrate(sc, torch, m, w, latent=WIDE.latent) if prec == "fp8" else None
+        mod = sc.Model(m, w, prec, act_scales=scales)
+        r = timed_run(sc, torch, mod, warmup, steps, shape=WIDE)
+        p = timed_run(sc, torch, mod, warmup, steps, profile=True, shape=WIDE)
+        v = r["samples"] / r["gpu_s"]
+        out[prec] = {"samples_per_s": round(v, 1), "ms_per_step": round(r["gpu_s"] * 1e3 / steps, 3),
+                     "step_roofline": step_roofline(p, v, PREC_NAME[prec])}
+        mod.close()
+    return out
+
+
+def single_stream_sweep(sc, torch, model, sizes=(1, 2, 4, 8, 16, 32, 64, 128, 256), n_buf=32, reps=16):
+    """One stream, buffer by buffer (the paper's real-time setting): per buffer
+    size, the GPU time per buffer when buffers are issued back to back and the
+    latency of one buffer issued alone (host call to output ready), and the
+    real-time factor (time per buffer / buffer duration at 44.1 kHz)."""
+    top = max(sizes)
+    x = torch.from_numpy(scgen.stream_latents(LATENT, top * (n_buf + 4), 99)).cuda()
+    out = torch.empty((1, top * SPF), device="cuda")
+    res = []
+    for n in sizes:
+        st = sc.Stream(model, top)
+        views = [x[:, k * n:(k + 1) * n].contiguous() for k in range(n_buf + 4)]
+        for k in range(4):
+            st.process_into(views[k], out, n)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(n_buf):
+            st.process_into(views[4 + k], out, n)
+        e1.record()
+        torch.cuda.synchronize()
+        per = e0.elapsed_time(e1) * 1e3 / n_buf
+        lat = []
+        for k in range(reps):
+            t0 = time.perf_counter()
+            st.process_into(views[k % n_buf], out, n)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e6)
+        st.close()
+        dur = n * SPF / 44100.0 * 1e6
+        res.append({"frames": n, "us_per_buffer": round(per, 1), "latency_us_p50": round(float(np.median(lat)), 1),
+                    "rtf": round(per / dur, 5)})
+    return res
+
+
+def stack_buffer_us(sc, torch, n_buf=32, buf=512):
+    """The plain three-layer cached conv stack (1 -> 16 -> 16 -> 16 channels,
+    dilations 1/2/4), FP32, one stream of 512-sample buffers: GPU time per
+    buffer issued back to back."""
+    m = scgen.stack3()
+    w = scgen.init_weights(m)
+    mod = sc.Model(m, w, "fp32")
+    st = sc.Stream(mod, buf)
+    x = torch.from_numpy(scgen.latents(1, buf * (n_buf + 4), 5)).cuda()
+    views = [x[:, k * buf:(k + 1) * buf].contiguous() for k in range(n_buf + 4)]
+    out = torch.empty((16, buf), device="cuda")
+    for k in range(4):
+        st.process_into(views[k], out, buf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(n_buf):
+        st.process_into(views[4 + k], out, buf)
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) * 1e3 / n_buf
+    st.close()
+    mod.close()
+    return {"us_per_buffer": round(per, 1), "rtf": round(per / (buf / 44100.0 * 1e6), 5)}
 
 
 class ServingLoad:
@@ -236,6 +364,16 @@ def serve(srv, load, times):
     seconds after the start; returns latency (server latency + the driver's
     lag behind the schedule) per buffer, wall time and the server's step
     counters over the run."""
+    import gc
+    gc.collect()
+    gc.disable()    # a collector pause would show up as driver lag
+    try:
+        return _serve(srv, load, times)
+    finally:
+        gc.enable()
+
+
+def _serve(srv, load, times):
     order = np.lexsort((load.buf, times))                         # by time; a stream's buffers stay in order
     ids, ptrs, fr, tt = load.stream[order], load.ptrs[order], load.frames[order], times[order]
     st0 = srv.stats()
@@ -272,7 +410,7 @@ def serving_runs(sc, model, seed=11, budget=4 << 30):
     """One server (graph replay, HBM budget) for all runs: a warm-up, the
     serving capacity (every buffer queued at once and drained), then open-loop
     Poisson buffer arrivals at the real-time rate of 256 live streams and at
-    50% / 80% of that capacity."""
+    50% / 80% / 95% of that capacity."""
     srv = sc.Server(model, N_STREAMS, max(BUF_CHOICES), hbm_budget_bytes=budget, use_graph=True)
     st = srv.stats()
     out = {"admission": {"hbm_budget_bytes": budget, "max_admitted": st["max_admitted"],
@@ -286,7 +424,8 @@ def serving_runs(sc, model, seed=11, budget=4 << 30):
     out["capacity_steps"] = r["steps"]
     out["capacity_merged_buffers"] = r["merged"]
     mean_samples = float(np.mean(BUF_CHOICES)) * SPF
-    points = [("realtime", N_STREAMS * 44100.0, 1.5), ("load50", 0.5 * cap, 0.6), ("load80", 0.8 * cap, 0.6)]
+    points = [("realtime", N_STREAMS * 44100.0, 1.5), ("load50", 0.5 * cap, 0.6), ("load80", 0.8 * cap, 0.6),
+              ("load95", 0.95 * cap, 0.6)]
     for name, offered, dur in points:
         lam = offered / N_STREAMS / mean_samples                    # buffers per second per stream
         B = max(int(np.ceil(lam * dur)), 4)
@@ -325,6 +464,7 @@ def cpu_baseline(budget_s=12.0):
         n += 1
     dt = time.perf_counter() - t0
     return {"value": round(samples / dt, 1), "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+            "rtf": round(44100.0 / (samples / dt), 4),
             "sample": "%d streams x 64 latent frames (%d output samples) of the same decoder, "
                       "offline FP64 numpy, %.1f s" % (n, samples, dt)}
 
@@ -334,7 +474,8 @@ def summarize(run_dir):
     trace and/or counter collections of one `bench.py --no-serving` run whose
     JSON line is in run_dir/bench.json).  Dispatches are mapped to layers by
     their position in each step: every step launches the same kernels in
-    plan order, optionally preceded by the input packing kernel."""
+    plan order, preceded by the descriptor upload and, optionally, the input
+    packing kernel."""
     import csv
     import glob
     with open(os.path.join(run_dir, "bench.json")) as f:
@@ -348,7 +489,11 @@ def summarize(run_dir):
     def per_op(rows, key):
         rows = sorted(rows, key=lambda r: int(r["Start_Timestamp"]))
         rows = [r for r in rows if ours(r["Kernel_Name"])]
-        K = len(ops) + (1 if rows and "pack_input" in rows[0]["Kernel_Name"] else 0)
+        # per-step launches before the layers: descriptor upload, input packing
+        lead = 0
+        while lead < len(rows) and any(k in rows[lead]["Kernel_Name"] for k in ("upload_kernel", "pack_input")):
+            lead += 1
+        K = len(ops) + lead
         if len(rows) % K:
             raise SystemExit("dispatch count %d is not a multiple of %d launches per step" % (len(rows), K))
         sums = np.zeros(K)
@@ -364,9 +509,10 @@ def summarize(run_dir):
         lines.append("%-5s %-6s %-5s %-5s %-5s %-3s %10s %10s  %s" % (
             "node", "kind", "impl", "cin", "cout", "d", "rocprof_us", "events_us", "kernel"))
         off = K - len(ops)
-        if off:
+        for j in range(off):
+            kind = "upload" if "upload_kernel" in rows[j]["Kernel_Name"] else "pack"
             lines.append("%-5s %-6s %-5s %-5s %-5s %-3s %10.2f %10s  %s" % (
-                "-", "pack", "valu", "-", "-", "-", avg[0], "-", rows[0]["Kernel_Name"][:60]))
+                "-", kind, "valu", "-", "-", "-", avg[j], "-", rows[j]["Kernel_Name"][:60]))
         for j, o in enumerate(ops):
             lines.append("%-5d %-6s %-5s %-5d %-5d %-3d %10.2f %10.2f  %s" % (
                 o["node"], {1: "conv", 2: "convt", 3: "add"}[o["kind"]], IMPL_NAME[o["impl"]],
@@ -421,6 +567,8 @@ def main():
     ap.add_argument("--compare", default="fp32,fp8", help="other precisions timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-stream buffer sweep and the wide-decoder 1024-stream runs")
     ap.add_argument("--graph", action="store_true",
                     help="replay one captured graph per step (measured slower than one-by-one launches here)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -481,6 +629,7 @@ def main():
                     "p99": round(float(np.percentile(run["step_ms"], 99)), 4)},
         "rtf": round(1.0 / (value / N_STREAMS / 44100.0), 6),
         "roofline": roofline(prof),
+        "step_roofline": step_roofline(prof_run, value, PREC_NAME[args.precision]),
         "per_kernel": [{"node": p["node"], "kind": p["kind"], "impl": p["impl"], "prec": p["precision"],
                         "cin": p["cin"], "cout": p["cout"], "d": p["dilation"],
                         "avg_us": round(p["ms"] * 1e3 / max(p["launches"], 1), 2)} for p in prof],
@@ -495,6 +644,10 @@ def main():
         except Exception as e:  # report, do not hide
             comp[prec] = "failed: %s" % e
     out["compare_samples_per_s"] = comp
+    if not args.no_extra:
+        out["single_stream"] = {"decoder": single_stream_sweep(sc, torch, model),
+                                "stack3_512": stack_buffer_us(sc, torch)}
+        out["wide_1024_streams"] = wide_runs(sc, torch)
     if not args.no_serving:
         srv = serving_runs(sc, model)
         out["serving"] = srv
@@ -507,10 +660,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def calibrate(sc, torch, m, w, frames=64, n_streams=4):
+def calibrate(sc, torch, m, w, frames=64, n_streams=4, latent=LATENT):
     """Static FP8 activation scales from four seeded calibration streams."""
     from paper_2204_07064_amd import calibrate as cal
-    return cal.act_scales(sc, m, w, [scgen.latents(LATENT, frames, 1 + i) for i in range(n_streams)])
+    return cal.act_scales(sc, m, w, [scgen.latents(latent, frames, 1 + i) for i in range(n_streams)])
 
 
 if __name__ == "__main__":

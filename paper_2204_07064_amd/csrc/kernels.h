@@ -94,5 +94,8 @@ void pack_convt_mfma(const float* w, int cin, int cout, int r, int prec, std::ve
 // Zero n floats (a kernel rather than a memset so that it is safe to capture
 // into a HIP graph).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+// Copies bytes from src (device-visible pinned host memory or device memory)
+// to device memory dst; both 16-byte aligned.
+hipError_t launch_upload(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace sc

@@ -605,6 +605,16 @@ __global__ void __launch_bounds__(kBlock) fill_zero_kernel(float* p, int64_t n) 
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0.f;
 }
 
+// 16-byte pieces, then the last bytes % 16 bytes one by one (16-byte aligned ends)
+__global__ void __launch_bounds__(kBlock) upload_kernel(const unsigned char* __restrict__ src,
+                                                       unsigned char* __restrict__ dst, int64_t bytes) {
+  const int64_t n = bytes / 16;
+  const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int64_t i = first; i < n; i += (int64_t)gridDim.x * kBlock)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+  if (first < bytes - n * 16) dst[n * 16 + first] = src[n * 16 + first];
+}
+
 }  // namespace
 
 // Narrow-conv kernel choice: 1 = channel-parallel, 2 = frame-parallel,
@@ -646,6 +656,15 @@ int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, i
 
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_upload(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(upload_kernel, dim3(grid_for((int64_t)(bytes + 15) / 16)), dim3(kBlock), 0, s,
+                     static_cast<const unsigned char*>(src), static_cast<unsigned char*>(dst), (int64_t)bytes);
   return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ struct OpDev {
 // A slot of the descriptor ring: pinned host staging + device copy + event.
 // Layout: n Entry records, then one int32 per input frame of the step (its entry).
 struct DescSlot {
-  unsigned char* host = nullptr;
+  unsigned char* host = nullptr;            // coherent pinned memory
+  const unsigned char* host_dev = nullptr;  // its device address
   unsigned char* dev = nullptr;
   size_t cap = 0;          // bytes
   hipEvent_t done = nullptr;
@@ -64,8 +65,12 @@ struct sc_model {
   sc::DescSlot ring[sc::kRing];
   int ring_next = 0;
   // cross-stream ordering of steps
+  // the event recorded after the model's newest work (every piece of work
+  // waits for the previous one, so it covers all of it); not owned: it is a
+  // ring slot's, own_done, or a server context's
   hipEvent_t last_done = nullptr;
   bool has_last = false;
+  hipEvent_t own_done = nullptr;              // recorded after a state reset
   // calibration
   float* d_amax = nullptr;
   bool amax_on = false;

@@ -90,7 +90,7 @@ void free_model(sc_model* m) {
     if (s.dev) hipFree(s.dev);
     if (s.done) hipEventDestroy(s.done);
   }
-  if (m->last_done) hipEventDestroy(m->last_done);
+  if (m->own_done) hipEventDestroy(m->own_done);
   if (m->graph_exec) hipGraphExecDestroy(m->graph_exec);
   hipFree(m->graph_desc);
   if (m->capture_stream) hipStreamDestroy(m->capture_stream);
@@ -415,13 +415,20 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
     slot.host = nullptr;
+    slot.host_dev = nullptr;
     slot.dev = nullptr;
     const size_t cap = std::max<size_t>(need * 2, 64 * 1024);
-    if (hipHostMalloc(reinterpret_cast<void**>(&slot.host), cap, hipHostMallocDefault) != hipSuccess ||
+    // coherent: the upload kernel reads the host's latest writes, never a
+    // cached copy of this slot's previous use
+    void* hd = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&slot.host), cap, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer(&hd, slot.host, 0) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&slot.dev), cap) != hipSuccess) {
       slot.cap = 0;
       return fail(SC_ENOMEM, "descriptor allocation failed");
     }
+    slot.host_dev = static_cast<const unsigned char*>(hd);
     slot.cap = cap;
   }
   if (!slot.done) {
@@ -437,16 +444,18 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     e = hipStreamWaitEvent(hs, m->last_done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  e = hipMemcpyAsync(graph ? m->graph_desc : slot.dev, slot.host, need, hipMemcpyHostToDevice, hs);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  // a kernel reads the descriptor over PCIe: one short launch instead of a DMA
+  // copy and its engine hand-off before the step's first kernel
+  e = launch_upload(slot.host_dev, graph ? m->graph_desc : slot.dev, need, hs);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   e = graph ? hipGraphLaunch(m->graph_exec, hs) : enqueue_kernels(m, slot.dev, n, total, hs);
   if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
-  if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
   if (e != hipSuccess) {
     for (int i = 0; i < n; ++i) streams[i]->bad = true;
     return hip_fail(e, "kernel launch");
   }
   slot.pending = true;
+  m->last_done = slot.done;   // one event per step: the slot's also orders later work
   m->has_last = true;
   commit_step(n, streams, n_frames);
   return SC_OK;
@@ -480,8 +489,9 @@ sc_status zero_state(sc_stream* s, hipStream_t hs) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
   e = launch_fill_zero(s->d_state, std::max<int64_t>(m->plan.state_alloc_floats, 1), hs);
-  if (e == hipSuccess) e = hipEventRecord(m->last_done, hs);
+  if (e == hipSuccess) e = hipEventRecord(m->own_done, hs);
   if (e != hipSuccess) return hip_fail(e, "state reset");
+  m->last_done = m->own_done;
   m->has_last = true;
   s->pos = 0;
   s->parity = 0;
@@ -533,7 +543,7 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
   m->prec = precision;
   m->options = options;
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->last_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->own_done, hipEventDisableTiming);
   if (e != hipSuccess) { delete m; return hip_fail(e, "device setup"); }
   const int n_layers = (int)m->plan.layer_node.size();
   if (act_scales) {

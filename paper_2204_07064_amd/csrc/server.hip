@@ -62,8 +62,10 @@ struct Part {               // one stream's share of a step
 
 struct StepCtx {
   unsigned char* desc_host = nullptr;
+  const unsigned char* desc_hdev = nullptr;   // device address of desc_host
   unsigned char* desc_dev = nullptr;
   float* in_host = nullptr;
+  const float* in_hdev = nullptr;             // device address of in_host
   float* in_dev = nullptr;
   float* out_host = nullptr;
   float* out_dev = nullptr;
@@ -297,15 +299,16 @@ void worker_main(sc_server* srv) {
     {
       std::lock_guard<std::mutex> g(m->mu);
       e = m->has_last ? hipStreamWaitEvent(srv->hs, m->last_done, 0) : hipSuccess;
-      if (e == hipSuccess) e = hipMemcpyAsync(c.desc_dev, c.desc_host, desc_bytes(cap, total), hipMemcpyHostToDevice, srv->hs);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(c.in_dev, c.in_host, in_off * sizeof(float), hipMemcpyHostToDevice, srv->hs);
+      // descriptor and input are read over PCIe by kernels (no DMA hand-off
+      // before the step); the output goes back by DMA
+      if (e == hipSuccess) e = launch_upload(c.desc_hdev, c.desc_dev, desc_bytes(cap, total), srv->hs);
+      if (e == hipSuccess) e = launch_upload(c.in_hdev, c.in_dev, in_off * sizeof(float), srv->hs);
       if (e == hipSuccess) e = launch_step(srv, c, n, total);
       if (e == hipSuccess)
         e = hipMemcpyAsync(c.out_host, c.out_dev, out_off * sizeof(float), hipMemcpyDeviceToHost, srv->hs);
       if (e == hipSuccess) e = hipEventRecord(c.done, srv->hs);
-      if (e == hipSuccess) e = hipEventRecord(m->last_done, srv->hs);
       if (e == hipSuccess) {
+        m->last_done = c.done;
         m->has_last = true;
         commit_step(n, ss.data(), nf.data());
       }
@@ -342,14 +345,22 @@ sc_status alloc_ctx(sc_server* srv, StepCtx& c) {
   const int64_t in_f = srv->max_frames * srv->cin;
   const int64_t out_f = out_frames_of(srv, srv->max_frames) * srv->cout;
   const size_t db = desc_bytes(srv->cfg.max_streams, srv->max_frames);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c.desc_host), db, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c.in_host), in_f * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+  // descriptor and input staging: coherent, read by the upload kernel
+  const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent;
+  void* dh = nullptr;
+  void* ih = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c.desc_host), db, flags) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c.in_host), in_f * sizeof(float), flags) != hipSuccess ||
+      hipHostGetDevicePointer(&dh, c.desc_host, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&ih, c.in_host, 0) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c.out_host), out_f * sizeof(float), hipHostMallocDefault) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c.desc_dev), db) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c.in_dev), in_f * sizeof(float)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c.out_dev), out_f * sizeof(float)) != hipSuccess ||
       hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess)
     return srv_fail(SC_ENOMEM, "server staging allocation failed");
+  c.desc_hdev = static_cast<const unsigned char*>(dh);
+  c.in_hdev = static_cast<const float*>(ih);
   return SC_OK;
 }
 
@@ -597,6 +608,15 @@ void sc_server_destroy(sc_server* srv) {
   hipStreamSynchronize(srv->hs);
   for (auto& kv : srv->streams)
     if (kv.second->s) stream_destroy(kv.second->s);
+  {
+    // the model must not keep a context's event as its last one (its work is done)
+    std::lock_guard<std::mutex> g(srv->m->mu);
+    for (auto& c : srv->ctx)
+      if (c.done && srv->m->last_done == c.done) {
+        srv->m->last_done = nullptr;
+        srv->m->has_last = false;
+      }
+  }
   for (auto& c : srv->ctx) free_ctx(c);
   hipStreamDestroy(srv->hs);
   unpin(srv);
