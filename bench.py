@@ -269,12 +269,17 @@ def wide_runs(sc, torch, precisions=("fp8", "bf16", "fp32"), warmup=3, steps=10)
     return out
 
 
-def single_stream_sweep(sc, torch, model, sizes=(1, 2, 4, 8, 16, 32, 64, 128, 256), n_buf=32, reps=16):
+def single_stream_sweep(sc, torch, model, sizes=(1, 2, 4, 8, 16, 32, 64, 128, 256), n_buf=32, reps=16,
+                        graph=False):
     """One stream, buffer by buffer (the paper's real-time setting): per buffer
     size, the GPU time per buffer when buffers are issued back to back and the
     latency of one buffer issued alone (host call to output ready), and the
-    real-time factor (time per buffer / buffer duration at 44.1 kHz)."""
+    real-time factor (time per buffer / buffer duration at 44.1 kHz).  With
+    graph, each buffer replays one captured graph (sized for one stream of
+    the largest buffer) instead of launching the kernels one by one."""
     top = max(sizes)
+    model.reserve(top)
+    model.enable_graph(1 if graph else 0)
     x = torch.from_numpy(scgen.stream_latents(LATENT, top * (n_buf + 4), 99)).cuda()
     out = torch.empty((1, top * SPF), device="cuda")
     res = []
@@ -645,8 +650,11 @@ def main():
             comp[prec] = "failed: %s" % e
     out["compare_samples_per_s"] = comp
     if not args.no_extra:
-        out["single_stream"] = {"decoder": single_stream_sweep(sc, torch, model),
+        solo = make(args.precision)   # its own workspace and graph, sized for one stream
+        out["single_stream"] = {"decoder": single_stream_sweep(sc, torch, solo),
+                                "decoder_graph": single_stream_sweep(sc, torch, solo, graph=True),
                                 "stack3_512": stack_buffer_us(sc, torch)}
+        solo.close()
         out["wide_1024_streams"] = wide_runs(sc, torch)
     if not args.no_serving:
         srv = serving_runs(sc, model)
