@@ -572,6 +572,9 @@ def main():
     ap.add_argument("--compare", default="fp32,fp8", help="other precisions timed on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
+    ap.add_argument("--no-split", action="store_true",
+                    help="run every step as one launch sequence (per-layer kernel traces map launches to layers "
+                         "by position; the per-launch profile always runs unsplit)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-stream buffer sweep and the wide-decoder 1024-stream runs")
     ap.add_argument("--graph", action="store_true",
@@ -605,11 +608,13 @@ def main():
     m = scgen.rave_decoder_b()
     w = scgen.init_weights(m)
 
+    options = sc._native.SC_MODEL_NO_SPLIT if args.no_split else 0
+
     def make(prec):
         scales = None
         if prec == "fp8":
             scales = calibrate(sc, torch, m, w)
-        return sc.Model(m, w, prec, act_scales=scales)
+        return sc.Model(m, w, prec, act_scales=scales, options=options)
 
     model = make(args.precision)
     run = timed_run(sc, torch, model, args.warmup, args.steps, graph=args.graph)

@@ -131,10 +131,16 @@ enum {
   SC_MODEL_NO_TWIN = 4u,    /* MFMA layers activate and round their input on load
                                instead of reading the copy their producer wrote in
                                operand form (same results; for testing) */
-  SC_MODEL_NO_WIN = 8u      /* narrow stride-1 MFMA convs gather their operands
+  SC_MODEL_NO_WIN = 8u,     /* narrow stride-1 MFMA convs gather their operands
                                chunk by chunk instead of staging each tile's
                                [cache | new frames] window in LDS (same results;
                                for testing) */
+  SC_MODEL_NO_SPLIT = 16u   /* run every step as one launch sequence; by default a
+                               step of at least 32 streams and 512 input frames runs
+                               as two halves of its streams at once, the second on
+                               an internal HIP stream joined back into the caller's
+                               stream before the step ends (same results; for
+                               testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,

@@ -71,6 +71,10 @@ struct sc_model {
   hipEvent_t last_done = nullptr;
   bool has_last = false;
   hipEvent_t own_done = nullptr;              // recorded after a state reset
+  // a large step runs as two halves of its streams at once: the first on the
+  // caller's stream, the second on `side`, joined before the step's event
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // calibration
   float* d_amax = nullptr;
   bool amax_on = false;
@@ -115,7 +119,10 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
                      const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total);
 // Enqueues the step's kernels on hs reading the descriptor at `dev`; grids are
 // sized for grid_n streams and grid_frames input frames (>= the actual step).
-hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs);
+// `base`: the input-frame offset at which this launch set's frames sit in the
+// workspace (a step's halves use disjoint ranges).
+hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
+                           int64_t base = 0);
 sc_status ensure_workspace(sc_model* m, int64_t frames);
 // After a successful enqueue: advance positions and flip state copies.
 void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames);

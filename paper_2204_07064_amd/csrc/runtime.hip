@@ -91,6 +91,12 @@ void free_model(sc_model* m) {
     if (s.done) hipEventDestroy(s.done);
   }
   if (m->own_done) hipEventDestroy(m->own_done);
+  if (m->side) {
+    hipStreamSynchronize(m->side);
+    hipStreamDestroy(m->side);
+  }
+  if (m->fork_ev) hipEventDestroy(m->fork_ev);
+  if (m->join_ev) hipEventDestroy(m->join_ev);
   if (m->graph_exec) hipGraphExecDestroy(m->graph_exec);
   hipFree(m->graph_desc);
   if (m->capture_stream) hipStreamDestroy(m->capture_stream);
@@ -105,16 +111,24 @@ float twin_scale(const sc_model* m, int layer) {
   return 1.0f / (m->act_scales[layer] / 448.0f);
 }
 
+// Workspace buffer b / operand twin t from input frame `base` on.
+float* ws_at(const sc_model* m, int b, int64_t base) {
+  return b >= 0 ? m->ws[b] + m->plan.buf_floats[b].of(base) : nullptr;
+}
+void* tw_at(const sc_model* m, int t, int64_t base) {
+  return t >= 0 ? static_cast<unsigned char*>(m->tw[t]) + m->plan.twin_elems[t].of(base) * m->tw_esize : nullptr;
+}
+
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
-                     const int32_t* dhdr, int n_ent, int64_t total_T) {
+                     const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base) {
   LayerArgs a{};
   a.ents = dents;
   a.fent = dfent;
   a.hdr = dhdr;
   a.n_ent = n_ent;
-  a.in_buf = op.in_buf >= 0 ? m->ws[op.in_buf] : nullptr;
-  a.in_buf2 = op.in_buf2 >= 0 ? m->ws[op.in_buf2] : nullptr;
-  a.out_buf = op.out_buf >= 0 ? m->ws[op.out_buf] : nullptr;
+  a.in_buf = ws_at(m, op.in_buf, base);
+  a.in_buf2 = ws_at(m, op.in_buf2, base);
+  a.out_buf = ws_at(m, op.out_buf, base);
   const size_t oi = &op - &m->plan.ops[0];
   a.W = m->opdev[oi].W;
   a.B = m->opdev[oi].B;
@@ -141,8 +155,8 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.tile = (op.kind == K_CONV && op.impl == IMPL_VALU)
                ? narrow_conv_tile(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, a.n_out)
                : 0;
-  a.in_twin = op.in_twin >= 0 ? m->tw[op.in_twin] : nullptr;
-  a.out_twin = op.out_twin >= 0 ? m->tw[op.out_twin] : nullptr;
+  a.in_twin = tw_at(m, op.in_twin, base);
+  a.out_twin = tw_at(m, op.out_twin, base);
   a.twin_prec = m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2);
   a.twin_pre = op.twin_pre;
   a.twin_qs = twin_scale(m, op.twin_layer);
@@ -286,21 +300,22 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
   }
 }
 
-hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs) {
+hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
+                           int64_t base) {
   const int32_t* dhdr = reinterpret_cast<const int32_t*>(dev);
   const Entry* dents = reinterpret_cast<const Entry*>(dev + kDescHeaderBytes);
   const int32_t* dfent = reinterpret_cast<const int32_t*>(dev + kDescHeaderBytes + (size_t)grid_n * sizeof(Entry));
   hipError_t e = hipSuccess;
   if (m->plan.input_buf >= 0) {
     const Plan& pl = m->plan;
-    e = launch_pack_input(dents, dfent, dhdr, pl.in_channels, grid_frames, m->ws[pl.input_buf],
-                          pl.input_twin >= 0 ? m->tw[pl.input_twin] : nullptr,
+    e = launch_pack_input(dents, dfent, dhdr, pl.in_channels, grid_frames, ws_at(m, pl.input_buf, base),
+                          tw_at(m, pl.input_twin, base),
                           m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2), pl.input_twin_pre,
                           twin_scale(m, pl.input_twin_layer), hs);
     if (e != hipSuccess) return e;
   }
   for (const Op& op : m->plan.ops) {
-    const LayerArgs a = layer_args(m, op, dents, dfent, dhdr, grid_n, grid_frames);
+    const LayerArgs a = layer_args(m, op, dents, dfent, dhdr, grid_n, grid_frames, base);
     if (m->amax_on && op.layer >= 0) {
       e = launch_amax(a, m->d_amax + op.layer, hs);
       if (e != hipSuccess) return e;
@@ -381,6 +396,27 @@ sc_status ensure_graph(sc_model* m) {
   return SC_OK;
 }
 
+// Where a step splits into two halves of its streams that run at once (the
+// kernels are latency-bound, so two half-size launch sequences overlap each
+// other's waits): the first `*h` streams with `*f` input frames, the rest
+// after them in the workspace.  0 = run the step as one sequence.
+int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t total, int64_t* f) {
+  constexpr int kSplitMinStreams = 32;
+  constexpr int64_t kSplitMinFrames = 512;
+  if ((m->options & SC_MODEL_NO_SPLIT) || n < kSplitMinStreams || total < kSplitMinFrames) return 0;
+  int64_t acc = 0;
+  int h = 0;
+  while (h < n - 1 && 2 * acc < total) acc += n_frames[h++];
+  if (h == 0 || h >= n) return 0;
+  // the second half's workspace offsets must be whole and keep 16-byte alignment
+  for (const sc::Frac& r : m->plan.buf_floats)
+    if (acc * r.num % r.den != 0 || r.of(acc) * (int64_t)sizeof(float) % 16 != 0) return 0;
+  for (const sc::Frac& r : m->plan.twin_elems)
+    if (acc * r.num % r.den != 0 || r.of(acc) * m->tw_esize % 16 != 0) return 0;
+  *f = acc;
+  return h;
+}
+
 sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                    const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
   int64_t total = 0;
@@ -401,6 +437,8 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   // up to the workspace); timed or calibrating steps launch one by one
   const bool graph = m->graph_streams >= n && !m->prof_on && !m->amax_on;
   const int cap = graph ? m->graph_streams : n;
+  int64_t fa = 0;
+  const int h = (graph || m->prof_on || m->amax_on) ? 0 : choose_split(m, n, n_frames, total, &fa);
 
   // ---- descriptors ----
   DescSlot& slot = m->ring[m->ring_next];
@@ -410,7 +448,9 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     slot.pending = false;
   }
-  const size_t need = desc_bytes(cap, total);
+  // a split step's two descriptors sit one after the other in the slot
+  const size_t off_b = h ? (desc_bytes(h, fa) + 255) / 256 * 256 : 0;
+  const size_t need = h ? off_b + desc_bytes(n - h, total - fa) : desc_bytes(cap, total);
   if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
@@ -435,7 +475,18 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
-  fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total);
+  if (h) {
+    fill_descriptor(slot.host, h, h, streams, d_in, n_frames, d_out, fa);
+    fill_descriptor(slot.host + off_b, n - h, n - h, streams + h, d_in + h, n_frames + h, d_out + h, total - fa);
+    if (!m->side) {
+      e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "side stream");
+    }
+  } else {
+    fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total);
+  }
   if (graph) {
     st = ensure_graph(m);
     if (st != SC_OK) return st;
@@ -448,7 +499,17 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   // copy and its engine hand-off before the step's first kernel
   e = launch_upload(slot.host_dev, graph ? m->graph_desc : slot.dev, need, hs);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-  e = graph ? hipGraphLaunch(m->graph_exec, hs) : enqueue_kernels(m, slot.dev, n, total, hs);
+  if (h) {
+    // fork: the second half on the side stream; join before the step's event
+    e = hipEventRecord(m->fork_ev, hs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
+    if (e == hipSuccess) e = enqueue_kernels(m, slot.dev, h, fa, hs, 0);
+    if (e == hipSuccess) e = enqueue_kernels(m, slot.dev + off_b, n - h, total - fa, m->side, fa);
+    if (e == hipSuccess) e = hipEventRecord(m->join_ev, m->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(hs, m->join_ev, 0);
+  } else {
+    e = graph ? hipGraphLaunch(m->graph_exec, hs) : enqueue_kernels(m, slot.dev, n, total, hs);
+  }
   if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
   if (e != hipSuccess) {
     for (int i = 0; i < n; ++i) streams[i]->bad = true;

@@ -150,6 +150,41 @@ def test_step_graph_replays_bitwise(prec):
     log("step graph: %d steps bitwise equal (%s)" % (len(steps), prec))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_split_step_bitwise(prec):
+    """A step of at least 32 streams and 512 input frames runs as two halves
+    of its streams at once (the second half on an internal HIP stream, at a
+    workspace offset); its outputs equal the same steps run as one launch
+    sequence, step by step, including a step too small to split."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = None
+    if prec == "fp8":
+        from paper_2204_07064_amd import calibrate
+        scales = calibrate.act_scales(sc, m, w, [scgen.latents(16, 32, 1)])
+    a = sc.Model(m, w, prec, act_scales=scales)
+    b = sc.Model(m, w, prec, act_scales=scales, options=sc._native.SC_MODEL_NO_SPLIT)
+    S = 64
+    rng = np.random.default_rng(21)
+    steps = [[int(v) for v in rng.choice([1, 2, 4, 8, 16, 32], size=S)] for _ in range(3)]
+    steps.insert(1, [1] * S)                     # 64 frames: below the split threshold
+    assert all(sum(st) >= 512 for k, st in enumerate(steps) if k != 1)
+    xs = [scgen.stream_latents(16, sum(st[i] for st in steps), 300 + i) for i in range(S)]
+    sa = [sc.Stream(a, 32) for _ in range(S)]
+    sb = [sc.Stream(b, 32) for _ in range(S)]
+    pos = [0] * S
+    for k, st in enumerate(steps):
+        ins = [torch.from_numpy(np.ascontiguousarray(xs[i][:, pos[i]:pos[i] + st[i]])).cuda() for i in range(S)]
+        for i in range(S):
+            pos[i] += st[i]
+        ya = sc.process_batch(a, sa, ins)
+        yb = sc.process_batch(b, sb, ins)
+        torch.cuda.synchronize()
+        for i in range(S):
+            assert torch.equal(ya[i], yb[i]), (k, i)
+    log("split steps: %d steps x %d streams bitwise equal (%s)" % (len(steps), S, prec))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_state_export_import_continues_bitwise(prec):
     """A stream checkpointed after some buffers and resumed in a fresh stream
