@@ -119,6 +119,16 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
                      const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total);
 // Enqueues the step's kernels on hs reading the descriptor at `dev`; grids are
 // sized for grid_n streams and grid_frames input frames (>= the actual step).
+// Where a step of n streams splits into two halves that run at once: returns
+// the first half's stream count h (0: no split) and sets *f to its frames.
+int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t total, int64_t* f);
+// Byte offset of the second half's descriptor after the first half's.
+size_t split_desc_offset(int h, int64_t fa);
+// Launches a split step whose two descriptors are at dev and dev +
+// split_desc_offset: the first half on hs, the second on the model's side
+// stream, forked from hs and joined back into it.
+hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, int64_t fa, int64_t total,
+                         hipStream_t hs);
 // `base`: the input-frame offset at which this launch set's frames sit in the
 // workspace (a step's halves use disjoint ranges).
 hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,

@@ -344,6 +344,48 @@ hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, in
   return e;
 }
 
+// Where a step splits into two halves of its streams that run at once (the
+// kernels are latency-bound, so two half-size launch sequences overlap each
+// other's waits): the first `*h` streams with `*f` input frames, the rest
+// after them in the workspace.  0 = run the step as one sequence.
+int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t total, int64_t* f) {
+  constexpr int kSplitMinStreams = 32;
+  constexpr int64_t kSplitMinFrames = 512;
+  if ((m->options & SC_MODEL_NO_SPLIT) || n < kSplitMinStreams || total < kSplitMinFrames) return 0;
+  int64_t acc = 0;
+  int h = 0;
+  while (h < n - 1 && 2 * acc < total) acc += n_frames[h++];
+  if (h == 0 || h >= n) return 0;
+  // the second half's workspace offsets must be whole and keep 16-byte alignment
+  for (const sc::Frac& r : m->plan.buf_floats)
+    if (acc * r.num % r.den != 0 || r.of(acc) * (int64_t)sizeof(float) % 16 != 0) return 0;
+  for (const sc::Frac& r : m->plan.twin_elems)
+    if (acc * r.num % r.den != 0 || r.of(acc) * m->tw_esize % 16 != 0) return 0;
+  *f = acc;
+  return h;
+}
+
+size_t split_desc_offset(int h, int64_t fa) { return (desc_bytes(h, fa) + 255) / 256 * 256; }
+
+hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, int64_t fa, int64_t total,
+                         hipStream_t hs) {
+  hipError_t e = hipSuccess;
+  if (!m->side) {
+    e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  // fork: the second half on the side stream; join before the caller's next work
+  e = hipEventRecord(m->fork_ev, hs);
+  if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
+  if (e == hipSuccess) e = enqueue_kernels(m, dev, h, fa, hs, 0);
+  if (e == hipSuccess) e = enqueue_kernels(m, dev + split_desc_offset(h, fa), n - h, total - fa, m->side, fa);
+  if (e == hipSuccess) e = hipEventRecord(m->join_ev, m->side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(hs, m->join_ev, 0);
+  return e;
+}
+
 void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames) {
   for (int i = 0; i < n; ++i) {
     streams[i]->pos += n_frames[i];
@@ -396,27 +438,6 @@ sc_status ensure_graph(sc_model* m) {
   return SC_OK;
 }
 
-// Where a step splits into two halves of its streams that run at once (the
-// kernels are latency-bound, so two half-size launch sequences overlap each
-// other's waits): the first `*h` streams with `*f` input frames, the rest
-// after them in the workspace.  0 = run the step as one sequence.
-int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t total, int64_t* f) {
-  constexpr int kSplitMinStreams = 32;
-  constexpr int64_t kSplitMinFrames = 512;
-  if ((m->options & SC_MODEL_NO_SPLIT) || n < kSplitMinStreams || total < kSplitMinFrames) return 0;
-  int64_t acc = 0;
-  int h = 0;
-  while (h < n - 1 && 2 * acc < total) acc += n_frames[h++];
-  if (h == 0 || h >= n) return 0;
-  // the second half's workspace offsets must be whole and keep 16-byte alignment
-  for (const sc::Frac& r : m->plan.buf_floats)
-    if (acc * r.num % r.den != 0 || r.of(acc) * (int64_t)sizeof(float) % 16 != 0) return 0;
-  for (const sc::Frac& r : m->plan.twin_elems)
-    if (acc * r.num % r.den != 0 || r.of(acc) * m->tw_esize % 16 != 0) return 0;
-  *f = acc;
-  return h;
-}
-
 sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                    const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
   int64_t total = 0;
@@ -449,7 +470,7 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     slot.pending = false;
   }
   // a split step's two descriptors sit one after the other in the slot
-  const size_t off_b = h ? (desc_bytes(h, fa) + 255) / 256 * 256 : 0;
+  const size_t off_b = h ? split_desc_offset(h, fa) : 0;
   const size_t need = h ? off_b + desc_bytes(n - h, total - fa) : desc_bytes(cap, total);
   if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
@@ -478,12 +499,6 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   if (h) {
     fill_descriptor(slot.host, h, h, streams, d_in, n_frames, d_out, fa);
     fill_descriptor(slot.host + off_b, n - h, n - h, streams + h, d_in + h, n_frames + h, d_out + h, total - fa);
-    if (!m->side) {
-      e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(e, "side stream");
-    }
   } else {
     fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total);
   }
@@ -500,13 +515,7 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   e = launch_upload(slot.host_dev, graph ? m->graph_desc : slot.dev, need, hs);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   if (h) {
-    // fork: the second half on the side stream; join before the step's event
-    e = hipEventRecord(m->fork_ev, hs);
-    if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
-    if (e == hipSuccess) e = enqueue_kernels(m, slot.dev, h, fa, hs, 0);
-    if (e == hipSuccess) e = enqueue_kernels(m, slot.dev + off_b, n - h, total - fa, m->side, fa);
-    if (e == hipSuccess) e = hipEventRecord(m->join_ev, m->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(hs, m->join_ev, 0);
+    e = enqueue_split(m, slot.dev, n, h, fa, total, hs);
   } else {
     e = graph ? hipGraphLaunch(m->graph_exec, hs) : enqueue_kernels(m, slot.dev, n, total, hs);
   }

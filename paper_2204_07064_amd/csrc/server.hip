@@ -31,6 +31,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr int kCtx = 3;
+constexpr size_t kSplitSlack = 512;   // a split step's second descriptor starts 256-byte aligned
 
 struct Ticket {
   int64_t id = 0;
@@ -287,8 +288,22 @@ void worker_main(sc_server* srv) {
       in_off += (int64_t)srv->cin * p.frames;
       out_off += (int64_t)srv->cout * out_frames_of(srv, p.frames);
     }
-    const int cap = srv->cfg.use_graph ? srv->cfg.max_streams : n;
-    fill_descriptor(c.desc_host, n, cap, ss.data(), din.data(), nf.data(), dout.data(), total);
+    // a large step runs as two concurrent halves launched one by one; other
+    // steps replay the context's captured graph (or launch one by one)
+    int64_t fa = 0;
+    const int h = choose_split(srv->m, n, nf.data(), total, &fa);
+    const int cap = (srv->cfg.use_graph && !h) ? srv->cfg.max_streams : n;
+    size_t desc_need;
+    if (h) {
+      const size_t off_b = split_desc_offset(h, fa);
+      fill_descriptor(c.desc_host, h, h, ss.data(), din.data(), nf.data(), dout.data(), fa);
+      fill_descriptor(c.desc_host + off_b, n - h, n - h, ss.data() + h, din.data() + h, nf.data() + h,
+                      dout.data() + h, total - fa);
+      desc_need = off_b + desc_bytes(n - h, total - fa);
+    } else {
+      fill_descriptor(c.desc_host, n, cap, ss.data(), din.data(), nf.data(), dout.data(), total);
+      desc_need = desc_bytes(cap, total);
+    }
     c.parts = std::move(parts);
     c.out_floats = out_off;
     c.busy = true;
@@ -301,9 +316,9 @@ void worker_main(sc_server* srv) {
       e = m->has_last ? hipStreamWaitEvent(srv->hs, m->last_done, 0) : hipSuccess;
       // descriptor and input are read over PCIe by kernels (no DMA hand-off
       // before the step); the output goes back by DMA
-      if (e == hipSuccess) e = launch_upload(c.desc_hdev, c.desc_dev, desc_bytes(cap, total), srv->hs);
+      if (e == hipSuccess) e = launch_upload(c.desc_hdev, c.desc_dev, desc_need, srv->hs);
       if (e == hipSuccess) e = launch_upload(c.in_hdev, c.in_dev, in_off * sizeof(float), srv->hs);
-      if (e == hipSuccess) e = launch_step(srv, c, n, total);
+      if (e == hipSuccess) e = h ? enqueue_split(m, c.desc_dev, n, h, fa, total, srv->hs) : launch_step(srv, c, n, total);
       if (e == hipSuccess)
         e = hipMemcpyAsync(c.out_host, c.out_dev, out_off * sizeof(float), hipMemcpyDeviceToHost, srv->hs);
       if (e == hipSuccess) e = hipEventRecord(c.done, srv->hs);
@@ -344,7 +359,7 @@ void unpin(sc_server* srv) {
 sc_status alloc_ctx(sc_server* srv, StepCtx& c) {
   const int64_t in_f = srv->max_frames * srv->cin;
   const int64_t out_f = out_frames_of(srv, srv->max_frames) * srv->cout;
-  const size_t db = desc_bytes(srv->cfg.max_streams, srv->max_frames);
+  const size_t db = desc_bytes(srv->cfg.max_streams, srv->max_frames) + kSplitSlack;
   // descriptor and input staging: coherent, read by the upload kernel
   const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent;
   void* dh = nullptr;
@@ -442,7 +457,7 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   for (const auto& b : m->plan.buf_floats) ws += b.of(m->ws_cap) * 4;
   for (const auto& t : m->plan.twin_elems) ws += t.of(m->ws_cap) * m->tw_esize;
   const int64_t staging = kCtx * ((srv->max_frames * srv->cin + out_frames_of(srv.get(), srv->max_frames) * srv->cout) *
-                                       4 + (int64_t)desc_bytes(cfg->max_streams, srv->max_frames));
+                                       4 + (int64_t)(desc_bytes(cfg->max_streams, srv->max_frames) + kSplitSlack));
   srv->fixed_bytes = ws + staging;
   srv->per_stream_bytes = std::max<int64_t>(m->plan.state_alloc_floats, 1) * 4;
   int64_t fit = cfg->max_streams;

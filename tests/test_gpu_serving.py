@@ -78,6 +78,28 @@ def test_served_equals_alone(prec, use_graph):
         assert np.array_equal(outs[i], alone), i
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_served_split_steps_equal_alone(prec):
+    """Steps of at least 32 streams and 512 frames run as two concurrent
+    halves (launched one by one, next to the graph replays of small steps);
+    every stream's output still equals its solo run."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    mod = sc.Model(m, w, prec)
+    rng = np.random.default_rng(17)
+    S, B = 64, 4
+    lens = [list(rng.integers(8, 17, size=B)) for _ in range(S)]
+    xs = [scgen.stream_latents(16, int(sum(l)), 500 + i) for i, l in enumerate(lens)]
+    order = [(i, b) for b in range(B) for i in range(S)]
+    outs, lat, st = _serve(sc, mod, lens, xs, order, True, max_buf=32)
+    log("%s split serving: steps %d buffers %d merged %d, %.0f frames per step"
+        % (prec, st["steps"], st["buffers"], st["merged_buffers"], st["frames_in"] / max(st["steps"], 1)))
+    assert st["buffers"] == S * B
+    for i in range(S):
+        alone = run_stream(mod, xs[i], [int(v) for v in lens[i]])
+        assert np.array_equal(outs[i], alone), i
+
+
 def test_graph_replays_equal_eager():
     sc = _sc()
     m, w = weights_for("rave_b")
