@@ -260,37 +260,29 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
   }
 #define SC_LOAD_B(C, ST)                                                                                     \
   {                                                                                                          \
+    const int drow_ = a.dil * k_tap;                                   /* conv: tap offset in rows */        \
+    const int64_t koff_ = (int64_t)drow_ * a.cin + k_ci;               /* conv: elements past (t, 0) */      \
     _Pragma("unroll") for (int p_ = 0; p_ < B_PIECES; ++p_) {                                                \
-      const ColInfo& cc_ = cols[my_col0 + p_ * (kThreads / PPCOL)];                                          \
-      int where_ = 0;                                                                                        \
-      int64_t off_ = 0;                                                                                      \
-      if (cc_.ei >= 0) {                                                                                     \
-        if (CONVT) {                                                                                         \
-          const int kk_ = (C) * KC + my_pp * EPP;                                                            \
-          const int h_ = kk_ >= half_pad;                                                                    \
-          const int ci_ = kk_ - h_ * half_pad;                                                               \
-          const int row_ = cc_.t - 1 + h_;                                                                   \
-          if (ci_ < a.cin && row_ >= 0 && row_ < cc_.Tin) {                                                  \
-            where_ = 1;                                                                                      \
-            off_ = ((int64_t)cc_.in_start + row_) * a.cin + ci_;                                             \
-          }                                                                                                  \
-        } else if ((C) * KC + my_pp * EPP < Kreal) {                                                         \
-          const int row_ = cc_.t + a.dil * k_tap;                                                            \
-          if (row_ < a.L) {                                                                                  \
-            where_ = 2;                                                                                      \
-            off_ = (int64_t)row_ * a.cin + k_ci;                                                             \
-          } else {                                                                                           \
-            where_ = 1;                                                                                      \
-            off_ = ((int64_t)cc_.in_start + row_ - a.L) * a.cin + k_ci;                                      \
-          }                                                                                                  \
-        }                                                                                                    \
+      bool live_;                                                                                            \
+      int64_t off_;                                                                                          \
+      const unsigned char* base_ = in_base;                                                                  \
+      if (CONVT) {                                                                                           \
+        const int kk_ = (C) * KC + my_pp * EPP;                                                              \
+        const int h_ = kk_ >= half_pad;                                                                      \
+        const int ci_ = kk_ - h_ * half_pad;                                                                 \
+        const int row_ = pc_t[p_] - 1 + h_;                                                                  \
+        live_ = pc_ok[p_] && ci_ < a.cin && row_ >= 0 && row_ < pc_lim[p_];                                   \
+        off_ = pc_in[p_] + (int64_t)row_ * a.cin + ci_;                                                      \
+      } else {                                                                                               \
+        /* window row t + dil tap: the cache copy below L, the input above */                                \
+        live_ = pc_ok[p_] && (C) * KC + my_pp * EPP < Kreal;                                                 \
+        base_ = pc_t[p_] + drow_ < a.L ? pc_cache[p_] : pc_inb[p_];                                          \
+        off_ = koff_;                                                                                        \
       }                                                                                                      \
       if constexpr (INTWIN) {                                                                                \
-        const unsigned char* base_ = where_ == 2 ? cc_.tcache : static_cast<const unsigned char*>(a.in_twin); \
-        tb[ST][p_] = where_ ? *reinterpret_cast<const u4*>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};    \
+        tb[ST][p_] = live_ ? *reinterpret_cast<const u4*>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};      \
       } else {                                                                                               \
-        const float* base_ = where_ == 2 ? cc_.cache : a.in_buf;                                             \
-        rb[ST][p_] = where_ ? *reinterpret_cast<const f4*>(base_ + off_) : f4{0.f, 0.f, 0.f, 0.f};           \
+        rb[ST][p_] = live_ ? *reinterpret_cast<const f4*>(base_ + off_ * 4) : f4{0.f, 0.f, 0.f, 0.f};     \
       }                                                                                                      \
     }                                                                                                        \
     if (!CONVT) {                                                                                            \
@@ -335,6 +327,31 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
 
   if (tid < NT) cols[tid] = make_col<CONVT>(a, n0 + tid, n_cols);
   __syncthreads();
+
+  // the columns of this thread's B pieces are the same for every K chunk:
+  // their gather context lives in registers (no LDS reads in the K loop)
+  const unsigned char* in_base = INTWIN ? static_cast<const unsigned char*>(a.in_twin)
+                                        : reinterpret_cast<const unsigned char*>(a.in_buf);
+  constexpr int ES_B = INTWIN ? ES : 4;      // bytes per B source element
+  // conv: pc_cache / pc_inb address window row t of the column (element 0) in
+  // the cache copy and in the input; a chunk adds the thread's tap and channel
+  const unsigned char* pc_cache[B_PIECES];
+  const unsigned char* pc_inb[B_PIECES];
+  int64_t pc_in[B_PIECES];                   // convt: input element offset of the stream's frame 0
+  int32_t pc_t[B_PIECES];                    // conv: local output frame; convt: q
+  int32_t pc_lim[B_PIECES];                  // convt: input frames of the stream
+  bool pc_ok[B_PIECES];                      // not a padding column
+#pragma unroll
+  for (int p = 0; p < B_PIECES; ++p) {
+    const ColInfo& cc = cols[my_col0 + p * (kThreads / PPCOL)];
+    pc_ok[p] = cc.ei >= 0;
+    pc_t[p] = cc.t;
+    pc_lim[p] = cc.Tin;
+    pc_in[p] = (int64_t)cc.in_start * a.cin;
+    const int64_t trow = (int64_t)cc.t * a.cin;
+    pc_cache[p] = (INTWIN ? cc.tcache : reinterpret_cast<const unsigned char*>(cc.cache)) + trow * ES_B;
+    pc_inb[p] = in_base + (((int64_t)cc.in_start - a.L) * a.cin + trow) * ES_B;
+  }
 
   // K position of this thread's B piece, advanced chunk by chunk without
   // division (chunks are gathered in increasing order)
