@@ -198,6 +198,8 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
   const int skipf = cin + 4;              // skip row stride (floats)
   unsigned char* wop = lds;
   float* wskip = reinterpret_cast<float*>(lds + row_cap * rowb);
+  const float** rsrc = reinterpret_cast<const float**>(lds + row_cap * rowb + F * skipf * 4);
+  int32_t* rskip = reinterpret_cast<int32_t*>(rsrc + row_cap);
 
   // weights of the wave's 16 rows, all chunks (independent of the columns: issued first)
   u4 alo[kMaxChunks], ahi[kMaxChunks];
@@ -274,32 +276,42 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
     colseg[tid] = (int8_t)s;
   }
 
+  // each staged row's source (cache or input) and, for a fused residual, the
+  // column whose skip row it is (-1: none); one stream search per row
+  for (int32_t j = tid; j < R; j += kThreads) {
+    int s = 0;
+    while (s + 1 < n_seg && segs[s + 1].base <= j) ++s;
+    const WinSeg& g = segs[s];
+    const int32_t r = g.r0 + (j - g.base);
+    rsrc[j] = r < a.L ? g.cache + (int64_t)r * cin : a.in_buf + ((int64_t)g.in_start + r - a.L) * cin;
+    const int32_t t = r - a.skip_off;
+    rskip[j] = (a.residual && t >= g.t_lo && t <= g.t_hi) ? g.out_start + t - f0 : -1;
+  }
+  __syncthreads();
+
   // ---- stage the window rows: operand form, plus the raw skip rows ----
   {
     const int ppr = cin >> 2;              // 16-byte FP32 source pieces per row
     const int32_t n_pieces = R * ppr;
-    for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * kStageBatch) {
+    // (six chunks of weights in registers leave room for fewer loads in flight)
+    constexpr int SB = KCM > 3 ? 6 : kStageBatch;
+    for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * SB) {
       // all loads of the batch first (one round trip), then the LDS stores;
       // the piece's row and stream are recomputed for the stores to keep
       // registers for the loads only
-      f4 v[kStageBatch];
+      f4 v[SB];
 #pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
+      for (int u = 0; u < SB; ++u) {
         const int32_t idx = i0 + u * kThreads + tid;
         v[u] = f4{0.f, 0.f, 0.f, 0.f};
         if (idx < n_pieces) {
           const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
           const int pc = idx - j * ppr;
-          int s = 0;
-          while (s + 1 < n_seg && segs[s + 1].base <= j) ++s;
-          const int32_t r = segs[s].r0 + (j - segs[s].base);
-          const float* src = r < a.L ? segs[s].cache + (int64_t)r * cin
-                                     : a.in_buf + ((int64_t)segs[s].in_start + r - a.L) * cin;
-          v[u] = *reinterpret_cast<const f4*>(src + pc * 4);
+          v[u] = *reinterpret_cast<const f4*>(rsrc[j] + pc * 4);
         }
       }
 #pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
+      for (int u = 0; u < SB; ++u) {
         const int32_t idx = i0 + u * kThreads + tid;
         if (idx >= n_pieces) continue;
         const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
@@ -317,15 +329,8 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
           *reinterpret_cast<uint32_t*>(dst) =
               wpack_fp8x4(act(x.x, pre) * qs, act(x.y, pre) * qs, act(x.z, pre) * qs, act(x.w, pre) * qs);
         }
-        if (a.residual) {
-          // the row is the skip row of local output frame t = window row - skip_off
-          int sg = 0;
-          while (sg + 1 < n_seg && segs[sg + 1].base <= j) ++sg;
-          const WinSeg& g = segs[sg];
-          const int32_t t = g.r0 + (j - g.base) - a.skip_off;
-          if (t >= g.t_lo && t <= g.t_hi)
-            *reinterpret_cast<f4*>(&wskip[(g.out_start + t - f0) * skipf + pc * 4]) = x;
-        }
+        const int32_t sk = rskip[j];
+        if (sk >= 0) *reinterpret_cast<f4*>(&wskip[sk * skipf + pc * 4]) = x;
       }
     }
   }
@@ -416,8 +421,9 @@ int win_kcm(int prec, int cin) {
   return cin <= 64 ? (prec == 1 ? 3 : 2) : (prec == 1 ? 6 : 3);
 }
 // operand rows plus the skip rows (allocated whether or not the layer has a skip)
+// operand rows, skip rows, then per staged row its source (8 B) and skip slot (4 B)
 int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
-  return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4;
+  return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4 + rows * 12;
 }
 
 }  // namespace
