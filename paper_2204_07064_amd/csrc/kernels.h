@@ -84,6 +84,8 @@ bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec);
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec);
 hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s);
 bool convt_mfma_supported(int cin, int cout, int r, int prec);
+// The layer that reads the model input on the FP32 MFMA gathering kernel.
+bool conv_mfma_fp32_input_supported(int cin, int cout, int k, int stride);
 // Host packing of weights into the MFMA kernels' tile order (and, for FP8,
 // per-output-row scales).  conv: W[cout][cin][k]; convt: W[cin][cout][2r].
 void pack_conv_mfma(const float* w, int cout, int cin, int k, int prec, std::vector<uint8_t>& out,

@@ -150,7 +150,8 @@ __device__ inline void store4(unsigned char* dst, float v0, float v1, float v2, 
   }
 }
 
-// Writes the operand twin of 4 consecutive output elements (element index o).
+// Writes the operand twin of 4 consecutive output elements (element index o)
+// in the consumer's operand type (an FP32 layer may feed a reduced-precision one).
 template <int PREC>
 __device__ inline void store_twin4(const LayerArgs& a, int64_t o, f4 v) {
   if (a.twin_pre) {
@@ -160,7 +161,11 @@ __device__ inline void store_twin4(const LayerArgs& a, int64_t o, f4 v) {
     v.w = lrelu(v.w);
   }
   const float q = a.twin_qs;
-  store4<PREC>(static_cast<unsigned char*>(a.out_twin) + o * Prec<PREC>::kEsize, v.x * q, v.y * q, v.z * q, v.w * q);
+  unsigned char* dst = static_cast<unsigned char*>(a.out_twin);
+  if (a.twin_prec == PREC) store4<PREC>(dst + o * Prec<PREC>::kEsize, v.x * q, v.y * q, v.z * q, v.w * q);
+  else if (a.twin_prec == 0) store4<0>(dst + o * 4, v.x * q, v.y * q, v.z * q, v.w * q);
+  else if (a.twin_prec == 1) store4<1>(dst + o * 2, v.x * q, v.y * q, v.z * q, v.w * q);
+  else store4<2>(dst + o, v.x * q, v.y * q, v.z * q, v.w * q);
 }
 
 // A 2-chunk register pipeline; kernels reading operand twins ask for 4 waves
@@ -607,6 +612,12 @@ bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec) {
   const int es = esize(prec);
   return stride == 1 && (cin * es) % 16 == 0 && cin % 8 == 0 && cout % 16 == 0 && cin >= 32 && cout >= 32 &&
          prec >= 0 && prec <= 2;
+}
+
+bool conv_mfma_fp32_input_supported(int cin, int cout, int k, int stride) {
+  (void)k;
+  // FP32 operands: 16-byte pieces of 4 channels never straddle two taps
+  return stride == 1 && cin % 4 == 0 && cin >= 4 && cout % 16 == 0 && cout >= 32;
 }
 
 bool convt_mfma_supported(int cin, int cout, int r, int prec) {

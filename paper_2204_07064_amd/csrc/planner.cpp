@@ -270,7 +270,10 @@ void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
       int reader = -1, n_mfma = 0;
       for (int o = 0; o < (int)plan.ops.size(); ++o) {
         const Op& op = plan.ops[o];
-        if (op.impl == IMPL_MFMA && op.src == s) { reader = o; ++n_mfma; }
+        if (op.impl == IMPL_MFMA && op.src == s) {
+          reader = o;
+          n_mfma += op.no_twin ? 2 : 1;   // an FP32 reader takes no twin in the model's type
+        }
       }
       if (n_mfma != 1) continue;
       const bool from_input = (s == 0 && plan.input_buf >= 0);

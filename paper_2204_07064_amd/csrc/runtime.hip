@@ -630,13 +630,19 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     if (op.kind == K_DELAY_ADD) continue;
     const float* w = weights + op.w_off;
     const float* b = weights + op.b_off;
-    bool mfma = false;
+    bool mfma = false, fp32_input = false;
     if (!(options & SC_MODEL_NO_MFMA) && op.in_buf >= 0 && op.out_buf >= 0) {
       if (op.kind == K_CONV) mfma = conv_mfma_supported(op.cin, op.cout, op.k, op.stride, prec_id);
       else mfma = convt_mfma_supported(op.cin, op.cout, op.stride, prec_id);
+      // a narrow layer reading the model input (the latents) runs on FP32
+      // MFMA in every precision: its input is never rounded
+      if (!mfma && op.kind == K_CONV && op.in_buf == m->plan.input_buf &&
+          conv_mfma_fp32_input_supported(op.cin, op.cout, op.k, op.stride))
+        mfma = fp32_input = true;
     }
     op.impl = mfma ? IMPL_MFMA : IMPL_VALU;
-    od.prec = mfma ? prec_id : 0;
+    op.no_twin = fp32_input ? 1 : 0;
+    od.prec = (mfma && !fp32_input) ? prec_id : 0;
     if (mfma && op.kind == K_CONV && !(options & SC_MODEL_NO_WIN)) {
       const int64_t min_frames = op.in_rate.of(m->plan.input_multiple);
       od.win_rows = conv_win_rows(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, min_frames, prec_id);
@@ -645,8 +651,8 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     if (mfma) {
       std::vector<uint8_t> packed;
       std::vector<float> wscale;
-      if (op.kind == K_CONV) pack_conv_mfma(w, op.cout, op.cin, op.k, prec_id, packed, wscale);
-      else pack_convt_mfma(w, op.cin, op.cout, op.stride, prec_id, packed, wscale);
+      if (op.kind == K_CONV) pack_conv_mfma(w, op.cout, op.cin, op.k, od.prec, packed, wscale);
+      else pack_convt_mfma(w, op.cin, op.cout, op.stride, od.prec, packed, wscale);
       e = upload(reinterpret_cast<uint8_t**>(&od.W), packed.data(), packed.size());
       if (e == hipSuccess && !wscale.empty()) e = upload(&od.wscale, wscale.data(), wscale.size());
       m->weight_bytes += (int64_t)packed.size() + (int64_t)wscale.size() * 4;

@@ -61,6 +61,7 @@ struct Op {
   int32_t twin_pre = 0;       // producer: the consumer's pre-activation
   int32_t twin_layer = -1;    // producer: the consumer's layer (FP8 activation scale)
   int64_t tstate_off = 0, tstate_len = 0;   // consumer conv: twin cache (floats)
+  int32_t no_twin = 0;        // an MFMA op that computes in FP32 whatever the model's precision
 };
 
 struct Plan {
