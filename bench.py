@@ -65,28 +65,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "16283b4f90559ab493f9d0d15f9eaf7e3ba6d711 617dafaded7a8330ae2c05e6d9cc904adc3f23df 9c5b01c64c454d87da90bad86645835e5fcdd2aa e0543016740a123080c38c42a0fc2741dfd862f2 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "8d26a7eccbd89c3a76963390706c4738277a59c6 89b736d509f1894fa4baa385ab3711550cb6d1e4 9c5b01c64c454d87da90bad86645835e5fcdd2aa 58946c9a8dd2a4ff1dbeefff3e129c6d08e2b780 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('valu', 895.1, 8117.2),
-        2: ('mfma', 10430.3, 22400.3),
-        4: ('mfma', 10303.7, 22084.3),
-        6: ('mfma', 11288.9, 23402.3),
-        8: ('mfma', 14131.8, 27320.7),
-        9: ('mfma', 5216.6, 42293.0),
-        11: ('mfma', 16976.6, 40112.5),
-        13: ('mfma', 17499.3, 40893.7),
-        15: ('mfma', 19004.5, 43023.9),
-        16: ('mfma', 6179.9, 58810.3),
-        18: ('mfma_win', 22650.4, 58339.5),
-        20: ('mfma_win', 24122.3, 57332.6),
-        22: ('mfma_win', 28599.9, 80215.3),
-        23: ('mfma', 10974.4, 57986.3),
-        25: ('mfma_win', 22211.6, 58642.9),
-        27: ('mfma_win', 22945.4, 58400.0),
-        29: ('mfma_win', 25145.1, 58910.9),
-        30: ('valu', 23428.7, 1539.5),
+        1: ('mfma', 756.2, 8720.5),
+        2: ('mfma', 10429.2, 22253.0),
+        4: ('mfma', 10294.3, 21971.4),
+        6: ('mfma', 11278.0, 23107.3),
+        8: ('mfma', 14124.0, 27076.6),
+        9: ('mfma', 5215.6, 42264.4),
+        11: ('mfma', 16994.4, 39549.6),
+        13: ('mfma', 17512.0, 40236.2),
+        15: ('mfma', 19016.7, 42261.4),
+        16: ('mfma', 6177.4, 58263.2),
+        18: ('mfma_win', 22618.3, 56068.2),
+        20: ('mfma_win', 24088.1, 56231.9),
+        22: ('mfma_win', 28559.4, 79899.3),
+        23: ('mfma', 10971.9, 57337.9),
+        25: ('mfma_win', 22188.8, 55649.9),
+        27: ('mfma_win', 22922.0, 55649.6),
+        29: ('mfma_win', 25127.9, 55997.7),
+        30: ('valu', 23428.8, 1539.5),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
