@@ -53,7 +53,7 @@ typedef enum {
                            multiple of the model's total stride */
   SC_EDEVICE = -5,      /* a HIP call or kernel launch failed */
   SC_ESTATE = -6,       /* the stream saw a device error; call stream_reset */
-  SC_EUNSUPPORTED = -7, /* valid model that this build cannot stream */
+  SC_EUNSUPPORTED = -7, /* valid model that the library cannot stream */
   SC_PENDING = 1        /* sc_server_poll: the buffer is not processed yet */
 } sc_status;
 
