@@ -189,30 +189,34 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
   const int tid = threadIdx.x;
   const int32_t n_tiles = n_mt * n_nt;   // tiles of the grid (sized for the largest step)
   int32_t bid = blockIdx.x;
-  // ---- conv cache update blocks (after the GEMM tiles) ----
+  // ---- conv cache update blocks (after the GEMM tiles): 4 channels per item ----
   if (!CONVT && bid >= n_tiles) {
-    const int32_t per_ent = a.L * a.cin;
+    const int32_t per_ent = a.L * a.cin / 4;   // cin is a multiple of 4
     const int32_t total = step_ents(a) * per_ent;
     for (int32_t j = (bid - n_tiles) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
       const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
-      const int32_t rem = j - ei * per_ent;
+      const int32_t rem = (j - ei * per_ent) * 4;
       const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
       const int ci = rem - i * a.cin;
       const Entry& e = a.ents[ei];
       const int32_t Tin = in_frames(a, e.T);
       const int32_t row = Tin + i;
       const int64_t src_in = ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
-      float v;
-      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci];
-      else v = a.in_buf[src_in];
-      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = v;
+      const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
+                                   : a.in_buf + src_in;
+      *reinterpret_cast<f4*>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci) =
+          *reinterpret_cast<const f4*>(src);
       if (INTWIN) {
+        // 4 operand elements: 16, 8 or 4 bytes
         typedef typename Prec<PREC>::Elem T;
-        const T* src = row < a.L
+        const T* tsrc = row < a.L
             ? reinterpret_cast<const T*>(e.state + a.tstate_off + (int64_t)e.parity * a.tstate_len) + (int64_t)row * a.cin + ci
             : static_cast<const T*>(a.in_twin) + src_in;
-        T* dst = reinterpret_cast<T*>(e.state + a.tstate_off + (int64_t)(1 - e.parity) * a.tstate_len);
-        dst[(int64_t)i * a.cin + ci] = *src;
+        T* tdst = reinterpret_cast<T*>(e.state + a.tstate_off + (int64_t)(1 - e.parity) * a.tstate_len) +
+                  (int64_t)i * a.cin + ci;
+        if constexpr (sizeof(T) == 4) *reinterpret_cast<u4*>(tdst) = *reinterpret_cast<const u4*>(tsrc);
+        else if constexpr (sizeof(T) == 2) *reinterpret_cast<uint2*>(tdst) = *reinterpret_cast<const uint2*>(tsrc);
+        else *reinterpret_cast<uint32_t*>(tdst) = *reinterpret_cast<const uint32_t*>(tsrc);
       }
     }
     return;
@@ -576,14 +580,14 @@ hipError_t launch_t(const LayerArgs& a, int64_t n_cols, int Kpad, int Kreal, int
   const int64_t n_nt = (n_cols + NT - 1) / NT;
   int extra = 0;
   if (!CONVT) {
-    const int64_t items = (int64_t)a.n_ent * a.L * a.cin;
+    const int64_t items = (int64_t)a.n_ent * a.L * a.cin / 4;   // 4 channels per item
     extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   }
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((gemm_kernel<PREC, MT, NT, CONVT, INTWIN>), dim3((unsigned)grid), dim3(kThreads), 0, s, a,
                      (int32_t)n_cols, n_mt, (int)n_nt, Kpad, Kreal, half_pad, M, extra,
-                     make_fastdiv((uint32_t)std::max(a.L * a.cin, 1)));
+                     make_fastdiv((uint32_t)std::max(a.L * a.cin / 4, 1)));
   return hipGetLastError();
 }
 

@@ -159,21 +159,22 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
   const int32_t n_tiles = n_mt * n_nt;
   const int32_t bid = blockIdx.x;
 
-  // ---- cache update blocks (after the tiles): new cache = last L window rows ----
+  // ---- cache update blocks (after the tiles): new cache = last L window rows,
+  // 4 channels per item ----
   if (bid >= n_tiles) {
-    const int32_t per_ent = a.L * a.cin;
+    const int32_t per_ent = a.L * a.cin / 4;
     const int32_t total = step_ents(a) * per_ent;
     for (int32_t j = (bid - n_tiles) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
       const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
-      const int32_t rem = j - ei * per_ent;
+      const int32_t rem = (j - ei * per_ent) * 4;
       const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
       const int ci = rem - i * a.cin;
       const Entry& e = a.ents[ei];
       const int32_t row = in_frames(a, e.T) + i;
-      float v;
-      if (row < a.L) v = e.state[a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci];
-      else v = a.in_buf[((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci];
-      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = v;
+      const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
+                                   : a.in_buf + ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
+      *reinterpret_cast<f4*>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci) =
+          *reinterpret_cast<const f4*>(src);
     }
     return;
   }
@@ -457,12 +458,12 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   const int kc = w_kchunk(prec);
   const int Kreal = a.k * a.cin;
   const int Kpad = (Kreal + kc - 1) / kc * kc;
-  const int64_t items = (int64_t)a.n_ent * a.L * a.cin;
+  const int64_t items = (int64_t)a.n_ent * a.L * a.cin / 4;   // 4 channels per cache-update item
   const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
   const size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
-  const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin, 1));
+  const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin / 4, 1));
   const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
 #define SC_WIN(P, M, N, K)                                                                                  \
   if (prec == P && MT == M && NB == N && KCM == K) {                                                       \
