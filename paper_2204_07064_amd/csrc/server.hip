@@ -165,27 +165,38 @@ void finalize(sc_server* srv, StepCtx& c, bool failed = false) {
   srv->cv_done.notify_all();
 }
 
-// Captures (once) and launches the context's step kernels.
+// Captures the context's step kernels, sized for the largest step.  Done at
+// server creation on the creating thread (a capture on the worker thread could
+// be invalidated by device-wide calls, such as a free, from other threads).
+// Called with the model's lock held.
+hipError_t capture_step(sc_server* srv, StepCtx& c) {
+  sc_model* m = srv->m;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(srv->hs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const bool prof = m->prof_on, amax = m->amax_on;
+  m->prof_on = false;
+  m->amax_on = false;
+  const hipError_t le = enqueue_kernels(m, c.desc_dev, srv->cfg.max_streams, srv->max_frames, srv->hs);
+  m->prof_on = prof;
+  m->amax_on = amax;
+  e = hipStreamEndCapture(srv->hs, &g);
+  if (le != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return le;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) c.exec = nullptr;
+  return e;
+}
+
+// Launches the context's step kernels (its captured graph, or one by one).
 hipError_t launch_step(sc_server* srv, StepCtx& c, int n, int64_t total) {
   sc_model* m = srv->m;
   if (!srv->cfg.use_graph) return enqueue_kernels(m, c.desc_dev, n, total, srv->hs);
-  if (!c.exec) {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(srv->hs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    const bool prof = m->prof_on, amax = m->amax_on;
-    m->prof_on = false;
-    m->amax_on = false;
-    const hipError_t le = enqueue_kernels(m, c.desc_dev, srv->cfg.max_streams, srv->max_frames, srv->hs);
-    m->prof_on = prof;
-    m->amax_on = amax;
-    e = hipStreamEndCapture(srv->hs, &g);
-    if (le != hipSuccess) return le;
-    if (e != hipSuccess) return e;
-    e = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) return e;
-  }
+  if (!c.exec) return hipErrorInvalidValue;   // captured at creation
   return hipGraphLaunch(c.exec, srv->hs);
 }
 
@@ -473,6 +484,10 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   }
   for (auto& c : srv->ctx) {
     sc_status st = alloc_ctx(srv.get(), c);
+    if (st == SC_OK && srv->cfg.use_graph) {
+      std::lock_guard<std::mutex> g(srv->m->mu);
+      if (capture_step(srv.get(), c) != hipSuccess) st = srv_fail(SC_EDEVICE, "step graph capture failed");
+    }
     if (st != SC_OK) {
       for (auto& c2 : srv->ctx) free_ctx(c2);
       hipStreamDestroy(srv->hs);
