@@ -65,28 +65,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "8d26a7eccbd89c3a76963390706c4738277a59c6 89b736d509f1894fa4baa385ab3711550cb6d1e4 9c5b01c64c454d87da90bad86645835e5fcdd2aa 58946c9a8dd2a4ff1dbeefff3e129c6d08e2b780 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "2572f236d1201961bb36591badcc93bf7984e123 367e55600ca4408ed081adafd94f477a770ad504 9c5b01c64c454d87da90bad86645835e5fcdd2aa 58946c9a8dd2a4ff1dbeefff3e129c6d08e2b780 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 756.2, 8720.5),
-        2: ('mfma', 10429.2, 22253.0),
-        4: ('mfma', 10294.3, 21971.4),
-        6: ('mfma', 11278.0, 23107.3),
-        8: ('mfma', 14124.0, 27076.6),
-        9: ('mfma', 5215.6, 42264.4),
-        11: ('mfma', 16994.4, 39549.6),
-        13: ('mfma', 17512.0, 40236.2),
-        15: ('mfma', 19016.7, 42261.4),
-        16: ('mfma', 6177.4, 58263.2),
-        18: ('mfma_win', 22618.3, 56068.2),
-        20: ('mfma_win', 24088.1, 56231.9),
-        22: ('mfma_win', 28559.4, 79899.3),
-        23: ('mfma', 10971.9, 57337.9),
-        25: ('mfma_win', 22188.8, 55649.9),
-        27: ('mfma_win', 22922.0, 55649.6),
-        29: ('mfma_win', 25127.9, 55997.7),
-        30: ('valu', 23428.8, 1539.5),
+        1: ('mfma', 733.3, 8754.3),
+        2: ('mfma', 10429.2, 22293.0),
+        4: ('mfma', 10272.9, 21981.8),
+        6: ('mfma', 11261.0, 23115.9),
+        8: ('mfma', 14120.3, 26987.1),
+        9: ('mfma', 5215.6, 42284.3),
+        11: ('mfma', 16997.9, 39537.7),
+        13: ('mfma', 17492.6, 40214.0),
+        15: ('mfma', 19007.3, 42300.8),
+        16: ('mfma', 6178.9, 58239.2),
+        18: ('mfma_win', 22575.3, 55484.5),
+        20: ('mfma_win', 24040.1, 55732.8),
+        22: ('mfma_win', 28472.1, 79387.3),
+        23: ('mfma', 10973.4, 57264.0),
+        25: ('mfma_win', 22148.0, 55394.2),
+        27: ('mfma_win', 22877.9, 55472.6),
+        29: ('mfma_win', 25073.2, 55391.1),
+        30: ('valu', 23429.8, 1539.5),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
