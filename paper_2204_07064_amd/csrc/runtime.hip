@@ -522,6 +522,9 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   if (e == hipSuccess) e = hipEventRecord(slot.done, hs);
   if (e != hipSuccess) {
     for (int i = 0; i < n; ++i) streams[i]->bad = true;
+    // a half already on the side stream must not outlive the failed step
+    // (nothing later orders against it)
+    if (h && m->side) hipStreamSynchronize(m->side);
     return hip_fail(e, "kernel launch");
   }
   slot.pending = true;

@@ -322,6 +322,7 @@ void worker_main(sc_server* srv) {
     lk.unlock();
     sc_model* m = srv->m;
     hipError_t e;
+    hipStream_t side = nullptr;   // the model's side stream (split steps), read under its lock
     {
       std::lock_guard<std::mutex> g(m->mu);
       e = m->has_last ? hipStreamWaitEvent(srv->hs, m->last_done, 0) : hipSuccess;
@@ -338,13 +339,16 @@ void worker_main(sc_server* srv) {
         m->has_last = true;
         commit_step(n, ss.data(), nf.data());
       }
+      side = m->side;
     }
     lk.lock();
     if (e != hipSuccess) {
       srv->worker_error = std::string("step: ") + hipGetErrorString(e);
       for (int i = 0; i < n; ++i) ss[i]->bad = true;
       // finalize the failed context so that waiting callers are released
+      // (a split step's second half may still run on the model's side stream)
       hipStreamSynchronize(srv->hs);
+      if (side) hipStreamSynchronize(side);
       finalize(srv, c, true);
       continue;
     }
