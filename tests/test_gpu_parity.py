@@ -185,6 +185,38 @@ def test_split_step_bitwise(prec):
     log("split steps: %d steps x %d streams bitwise equal (%s)" % (len(steps), S, prec))
 
 
+@pytest.mark.parametrize("name,mult,prec", [("encoder", 128, "fp32"), ("encoder", 128, "bf16"),
+                                            ("branch3", 1, "fp32"), ("strided", 2, "fp32")])
+def test_split_step_bitwise_other_models(name, mult, prec):
+    """Split steps of the strided encoder (input frames a multiple of 128,
+    workspace rates below one frame per input frame), of the four-branch unit
+    (explicit delay lines) and of the strided unit equal one launch sequence."""
+    sc = _sc()
+    m, w = weights_for(name)
+    a = sc.Model(m, w, prec)
+    b = sc.Model(m, w, prec, options=sc._native.SC_MODEL_NO_SPLIT)
+    C = m["in_channels"]
+    S = 40
+    rng = np.random.default_rng(33)
+    choices = [mult * k for k in (4, 8, 16)] if mult > 1 else [8, 16, 24]
+    steps = [[int(v) for v in rng.choice(choices, size=S)] for _ in range(3)]
+    assert all(sum(st) >= 512 for st in steps)
+    top = max(choices)
+    xs = [scgen.stream_latents(C, sum(st[i] for st in steps), 700 + i) for i in range(S)]
+    sa = [sc.Stream(a, top) for _ in range(S)]
+    sb = [sc.Stream(b, top) for _ in range(S)]
+    pos = [0] * S
+    for k, st in enumerate(steps):
+        ins = [torch.from_numpy(np.ascontiguousarray(xs[i][:, pos[i]:pos[i] + st[i]])).cuda() for i in range(S)]
+        for i in range(S):
+            pos[i] += st[i]
+        ya = sc.process_batch(a, sa, ins)
+        yb = sc.process_batch(b, sb, ins)
+        torch.cuda.synchronize()
+        for i in range(S):
+            assert torch.equal(ya[i], yb[i]), (name, k, i)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_state_export_import_continues_bitwise(prec):
     """A stream checkpointed after some buffers and resumed in a fresh stream
