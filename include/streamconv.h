@@ -267,7 +267,9 @@ typedef struct {
   int32_t max_streams;        /* slots: streams admitted at once */
   int32_t max_buffer_frames;  /* per stream per step (also the largest buffer accepted) */
   int64_t hbm_budget_bytes;   /* device memory the server may use (0: no limit) */
-  int32_t use_graph;          /* 1: replay one captured hipGraph per step context */
+  int32_t use_graph;          /* 1: replay one hipGraph per step context, captured by
+                                 sc_server_create on the calling thread; steps large
+                                 enough to split (SC_MODEL_NO_SPLIT) launch one by one */
   uint32_t stream_flags;      /* SC_FLAG_* applied to every stream */
 } sc_server_config;
 typedef struct {
@@ -276,6 +278,8 @@ typedef struct {
   int64_t fixed_bytes, per_stream_bytes;
 } sc_server_stats;
 
+/* Errors: SC_EINVAL, SC_EBUDGET (budget below the fixed memory and one
+ * stream), SC_ENOMEM, SC_EDEVICE (stream creation or graph capture failed). */
 sc_status sc_server_create(sc_model* model, const sc_server_config* config, sc_server** out);
 /* Queue one buffer (host memory [in_channels][n_frames], copied) of stream
  * `stream_id`; the stream is opened on first use.  Sets *ticket. */
