@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxStreams = 8;     // streams one tile may touch (the host guarantees it)
-constexpr int kStageBatch = 8;     // 16-byte staging loads in flight per thread (one round trip for a tile)
+constexpr int kStageBatch = 6;     // 16-byte staging loads in flight per thread (fits 5 waves per SIMD)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -140,7 +140,7 @@ struct WinSeg {
 // row stride cin * ES + 16 bytes), then, for a fused residual, each column's
 // skip row as raw FP32 ([F][cin + 4]).
 template <int PREC, int MT, int NB, int KCM>
-__global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
+__global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
                                                              FastDiv fd_ppr) {
   constexpr int WM = MT / 16;
@@ -294,8 +294,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_win_kernel(LayerArgs a, int 
   {
     const int ppr = cin >> 2;              // 16-byte FP32 source pieces per row
     const int32_t n_pieces = R * ppr;
-    // (six chunks of weights in registers leave room for fewer loads in flight)
-    constexpr int SB = KCM > 3 ? 6 : kStageBatch;
+    constexpr int SB = kStageBatch;
     for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * SB) {
       // all loads of the batch first (one round trip), then the LDS stores;
       // the piece's row and stream are recomputed for the stores to keep
