@@ -51,6 +51,25 @@ def test_fp32_parity(name, frames, buf, options):
     assert err <= FP32_TOL
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_long_buffers(prec):
+    """Long buffers of one stream (1024 and 1000 latent frames: 131072 output
+    samples in one buffer, window tiles and MFMA column tiles all inside one
+    stream, a ragged last tile) match the oracle, and equal the same input
+    streamed in short buffers bitwise."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    x = scgen.stream_latents(16, 2024, 11)
+    mod = sc.Model(m, w, prec)
+    s = run_stream(mod, x, [1024, 1000])
+    if prec == "fp32":
+        err, snr, _ = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
+        log("  long buffers: max-abs %.3e snr %.1f dB" % (err, snr))
+        assert err <= FP32_TOL
+    short = run_stream(mod, x, scgen.split_lengths(2024, 8))
+    assert np.array_equal(s, short)
+
+
 def test_split_invariance_bitwise():
     sc = _sc()
     m, w = weights_for("rave_b")
