@@ -468,8 +468,18 @@ def cpu_baseline(budget_s=12.0):
         samples += y.shape[1]
         n += 1
     dt = time.perf_counter() - t0
+    # the FP64 streaming oracle buffer by buffer, one stream (the paper's
+    # real-time setting): real-time factor per buffer size on a short sample
+    from oracle import streaming
+    sweep = []
+    for buf, frames in ((1, 32), (16, 128), (256, 256)):
+        x = scgen.stream_latents(LATENT, frames, 0)
+        t1 = time.perf_counter()
+        streaming.stream(m, w, x, [buf] * (frames // buf))
+        sweep.append({"frames": buf, "rtf": round((time.perf_counter() - t1) / (frames * SPF / 44100.0), 4),
+                      "sample_frames": frames})
     return {"value": round(samples / dt, 1), "unit": "samples/s", "cores": int(cores), "kind": "oracle",
-            "rtf": round(44100.0 / (samples / dt), 4),
+            "rtf": round(44100.0 / (samples / dt), 4), "streaming_rtf": sweep,
             "sample": "%d streams x 64 latent frames (%d output samples) of the same decoder, "
                       "offline FP64 numpy, %.1f s" % (n, samples, dt)}
 
