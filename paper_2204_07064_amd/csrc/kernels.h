@@ -39,6 +39,7 @@ struct LayerArgs {
   float twin_qs;           // producer: scale applied before rounding (FP8: 448 / amax)
   int32_t twin_pre;        // producer: pre-activation of the consumer
   int32_t twin_prec;
+  int32_t twin_only;       // producer: the FP32 output has no reader; write the twin only
   int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
 };
 

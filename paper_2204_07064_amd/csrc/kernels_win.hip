@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     if (a.residual) v = v + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
     if ((int64_t)t * a.out_den < segs[s].mask_x) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
-    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
+    if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
     if (a.out_twin) {
       f4 w = v;
       if (a.twin_pre) {

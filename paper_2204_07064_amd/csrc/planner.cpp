@@ -262,6 +262,7 @@ void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
   for (auto& op : plan.ops) {
     op.in_twin = op.out_twin = -1;
     op.tstate_len = 0;
+    op.twin_only = 0;
   }
   if (twins) {
     std::vector<int> producer(n, -1);
@@ -292,6 +293,12 @@ void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
         pr.out_twin = t;
         pr.twin_pre = rd.pre_act;
         pr.twin_layer = rd.layer;
+        // a transposed conv reads only the twin (its state is the FP32 carry
+        // of its own sums); with no other reader the FP32 output is dead
+        int readers = 0;
+        for (const Op& o : plan.ops) readers += (o.src == s) + (o.src2 == s);
+        if (rd.kind == K_CONVT && readers == 1 && (pr.impl == IMPL_MFMA || pr.impl == IMPL_WIN))
+          pr.twin_only = 1;
       }
       if (rd.kind == K_CONV && rd.cache_len > 0)
         rd.tstate_len = ((int64_t)rd.cache_len * rd.cin * elem_bytes + 3) / 4;

@@ -159,6 +159,8 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.out_twin = tw_at(m, op.out_twin, base);
   a.twin_prec = m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2);
   a.twin_pre = op.twin_pre;
+  // calibration reads every layer's FP32 input, so keep writing it then
+  a.twin_only = (op.twin_only && a.out_twin && !m->amax_on) ? 1 : 0;
   a.twin_qs = twin_scale(m, op.twin_layer);
   a.tstate_off = op.tstate_off;
   a.tstate_len = op.tstate_len;

@@ -62,6 +62,8 @@ struct Op {
   int32_t twin_layer = -1;    // producer: the consumer's layer (FP8 activation scale)
   int64_t tstate_off = 0, tstate_len = 0;   // consumer conv: twin cache (floats)
   int32_t no_twin = 0;        // an MFMA op that computes in FP32 whatever the model's precision
+  int32_t twin_only = 0;      // producer: its only reader takes the twin and keeps no FP32
+                              // input state (a transposed conv), so the FP32 output is not written
 };
 
 struct Plan {
