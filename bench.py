@@ -65,28 +65,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "2572f236d1201961bb36591badcc93bf7984e123 93815f607d797304d36c1d073c9b4446d540f6dc 9c5b01c64c454d87da90bad86645835e5fcdd2aa 58946c9a8dd2a4ff1dbeefff3e129c6d08e2b780 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 0de52c6700ab6cfd8bf54583f048c10641f4642c 9c5b01c64c454d87da90bad86645835e5fcdd2aa c21a29cf32cb8e4e1c56358444cf31dbd90e8f1d 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 733.3, 8706.6),
-        2: ('mfma', 10429.2, 22290.6),
-        4: ('mfma', 10273.0, 21976.8),
-        6: ('mfma', 11260.6, 23136.1),
-        8: ('mfma', 14118.9, 27001.0),
-        9: ('mfma', 5215.6, 42292.4),
-        11: ('mfma', 16997.3, 39543.0),
-        13: ('mfma', 17491.4, 40216.7),
-        15: ('mfma', 19001.8, 42338.5),
-        16: ('mfma', 6178.9, 58264.8),
-        18: ('mfma_win', 22573.7, 55165.5),
-        20: ('mfma_win', 24040.9, 55245.8),
-        22: ('mfma_win', 28478.3, 79468.8),
-        23: ('mfma', 10973.4, 57363.9),
-        25: ('mfma_win', 22135.8, 54861.6),
-        27: ('mfma_win', 22864.7, 55363.6),
-        29: ('mfma_win', 25059.5, 55247.9),
-        30: ('valu', 23428.7, 1539.5),
+        1: ('mfma', 729.3, 2727.1),
+        2: ('mfma', 10429.7, 22222.1),
+        4: ('mfma', 10278.9, 21959.7),
+        6: ('mfma', 11266.9, 23075.7),
+        8: ('mfma', 14125.4, 12302.2),
+        9: ('mfma', 5216.1, 42277.8),
+        11: ('mfma', 17010.3, 39435.5),
+        13: ('mfma', 17504.9, 40193.0),
+        15: ('mfma', 18943.9, 14236.8),
+        16: ('mfma', 6179.4, 58149.8),
+        18: ('mfma_win', 22574.4, 55197.7),
+        20: ('mfma_win', 24041.4, 55305.1),
+        22: ('mfma_win', 28448.7, 22712.6),
+        23: ('mfma', 10973.9, 57373.6),
+        25: ('mfma_win', 22135.9, 55034.3),
+        27: ('mfma_win', 22864.7, 55313.1),
+        29: ('mfma_win', 25059.3, 55271.2),
+        30: ('valu', 23428.8, 1539.5),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
