@@ -53,6 +53,8 @@ HEADLINE = Shape("rave_b", scgen.rave_decoder_b, N_STREAMS, BUF_CHOICES, LATENT,
 # the wide decoder (128 latent channels, 512 samples per frame) with 1024
 # streams of uneven 1..8-frame buffers
 WIDE = Shape("wide", scgen.wide_decoder, 1024, range(1, 9), 128, 512)
+# the same decoder with 64 streams of fixed 16-frame (2048-sample) buffers
+FIXED16 = Shape("rave_b", scgen.rave_decoder_b, 64, (16,), LATENT, SPF)
 HBM_PEAK = 8.0e12  # B/s
 PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
 PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
@@ -586,7 +588,8 @@ def main():
                     help="run every step as one launch sequence (per-layer kernel traces map launches to layers "
                          "by position; the per-launch profile always runs unsplit)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the single-stream buffer sweep and the wide-decoder 1024-stream runs")
+                    help="skip the single-stream buffer sweep, the wide-decoder 1024-stream runs and the "
+                         "64-stream fixed-buffer run")
     ap.add_argument("--graph", action="store_true",
                     help="replay one captured graph per step (measured slower than one-by-one launches here)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -671,6 +674,10 @@ def main():
                                 "stack3_512": stack_buffer_us(sc, torch)}
         solo.close()
         out["wide_1024_streams"] = wide_runs(sc, torch)
+        r16 = timed_run(sc, torch, model, 3, 20, shape=FIXED16)
+        out["rave_b_64_streams_16_frame_buffers"] = {
+            "samples_per_s": round(r16["samples"] / r16["gpu_s"], 1),
+            "ms_per_step": round(r16["gpu_s"] * 1e3 / 20, 4), "precision": args.precision}
     if not args.no_serving:
         srv = serving_runs(sc, model)
         out["serving"] = srv
