@@ -10,15 +10,17 @@ streaming path over all 256 buffers (closed loop: every stream always has its
 next buffer ready).  Inputs are seeded N(0,1) latents already resident in HBM.
 
 Prints one JSON line: output samples/s, the roofline fraction of the
-dominant kernel (per-launch HIP events on the processing stream), the
-per-step time percentiles, the same workload at the other precisions, the
-serving runs and the FP64 CPU oracle timed on this host.
+dominant kernel (per-launch HIP events on the processing stream) and of the
+whole step, the per-step time percentiles, the same workload at the other
+precisions, the wide decoder with 1024 streams, the decoder with 64 streams
+of fixed 16-frame buffers, one stream buffer by buffer, the serving runs and
+the FP64 CPU oracle timed on this host.
 
 Serving runs (host buffers in and out, so PCIe transfers included): one
 server with 256 stream slots, a 4 GiB HBM budget and graph replay; its
 capacity with every buffer queued at once, then open-loop Poisson buffer
 arrivals per stream at the real-time rate of 256 live 44.1 kHz streams and at
-50% / 80% of the capacity.  Per-buffer latency runs from the scheduled
+50% / 80% / 95% of the capacity.  Per-buffer latency runs from the scheduled
 arrival to the output being on the host (any lag of the Python load
 generator behind its schedule is added, and reported).
 """
