@@ -372,12 +372,10 @@ size_t split_desc_offset(int h, int64_t fa) { return (desc_bytes(h, fa) + 255) /
 hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, int64_t fa, int64_t total,
                          hipStream_t hs) {
   hipError_t e = hipSuccess;
-  if (!m->side) {
-    e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-  }
+  if (!m->side) e = hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !m->fork_ev) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess && !m->join_ev) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
   // fork: the second half on the side stream; join before the caller's next work
   e = hipEventRecord(m->fork_ev, hs);
   if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
