@@ -302,47 +302,74 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
   }
 }
 
+namespace {
+
+// One launch set: a step's (or a split step half's) descriptor on the device,
+// its grid bounds, stream and workspace offset.
+struct LaunchSet {
+  const int32_t* hdr;
+  const Entry* ents;
+  const int32_t* fent;
+  int grid_n;
+  int64_t grid_frames;
+  hipStream_t hs;
+  int64_t base;
+};
+
+LaunchSet launch_set(const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs, int64_t base) {
+  LaunchSet ls;
+  ls.hdr = reinterpret_cast<const int32_t*>(dev);
+  ls.ents = reinterpret_cast<const Entry*>(dev + kDescHeaderBytes);
+  ls.fent = reinterpret_cast<const int32_t*>(dev + kDescHeaderBytes + (size_t)grid_n * sizeof(Entry));
+  ls.grid_n = grid_n;
+  ls.grid_frames = grid_frames;
+  ls.hs = hs;
+  ls.base = base;
+  return ls;
+}
+
+hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
+  const Plan& pl = m->plan;
+  if (pl.input_buf < 0) return hipSuccess;
+  return launch_pack_input(ls.ents, ls.fent, ls.hdr, pl.in_channels, ls.grid_frames, ws_at(m, pl.input_buf, ls.base),
+                           tw_at(m, pl.input_twin, ls.base), m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2),
+                           pl.input_twin_pre, twin_scale(m, pl.input_twin_layer), ls.hs);
+}
+
+// The launch of op `oi` (with its calibration and timing records, if on).
+hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
+  const Op& op = m->plan.ops[oi];
+  const LayerArgs a = layer_args(m, op, ls.ents, ls.fent, ls.hdr, ls.grid_n, ls.grid_frames, ls.base);
+  hipError_t e = hipSuccess;
+  if (m->amax_on && op.layer >= 0) {
+    e = launch_amax(a, m->d_amax + op.layer, ls.hs);
+    if (e != hipSuccess) return e;
+  }
+  const int prec = m->opdev[oi].prec;
+  hipEvent_t ev_end = nullptr;
+  if (m->prof_on) {
+    e = prof_begin(m, (int)oi, a, ls.hs, &ev_end);
+    if (e != hipSuccess) return e;
+  }
+  if (op.kind == K_CONV) {
+    if (op.impl == IMPL_WIN) e = launch_conv_win(a, prec, m->opdev[oi].win_rows, ls.hs);
+    else e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, ls.hs) : launch_conv_valu(a, ls.hs);
+  } else if (op.kind == K_CONVT) {
+    e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, ls.hs) : launch_convt_valu(a, ls.hs);
+  } else {
+    e = launch_delay_add(a, ls.hs);
+  }
+  if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, ls.hs);
+  return e;
+}
+
+}  // namespace
+
 hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
                            int64_t base) {
-  const int32_t* dhdr = reinterpret_cast<const int32_t*>(dev);
-  const Entry* dents = reinterpret_cast<const Entry*>(dev + kDescHeaderBytes);
-  const int32_t* dfent = reinterpret_cast<const int32_t*>(dev + kDescHeaderBytes + (size_t)grid_n * sizeof(Entry));
-  hipError_t e = hipSuccess;
-  if (m->plan.input_buf >= 0) {
-    const Plan& pl = m->plan;
-    e = launch_pack_input(dents, dfent, dhdr, pl.in_channels, grid_frames, ws_at(m, pl.input_buf, base),
-                          tw_at(m, pl.input_twin, base),
-                          m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2), pl.input_twin_pre,
-                          twin_scale(m, pl.input_twin_layer), hs);
-    if (e != hipSuccess) return e;
-  }
-  for (const Op& op : m->plan.ops) {
-    const LayerArgs a = layer_args(m, op, dents, dfent, dhdr, grid_n, grid_frames, base);
-    if (m->amax_on && op.layer >= 0) {
-      e = launch_amax(a, m->d_amax + op.layer, hs);
-      if (e != hipSuccess) return e;
-    }
-    const size_t oi = &op - &m->plan.ops[0];
-    const int prec = m->opdev[oi].prec;
-    hipEvent_t ev_end = nullptr;
-    if (m->prof_on) {
-      e = prof_begin(m, (int)oi, a, hs, &ev_end);
-      if (e != hipSuccess) return e;
-    }
-    if (op.kind == K_CONV) {
-      if (op.impl == IMPL_WIN) e = launch_conv_win(a, prec, m->opdev[oi].win_rows, hs);
-      else e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, hs) : launch_conv_valu(a, hs);
-    } else if (op.kind == K_CONVT) {
-      e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, hs) : launch_convt_valu(a, hs);
-    } else {
-      e = launch_delay_add(a, hs);
-    }
-    if (e != hipSuccess) return e;
-    if (ev_end) {
-      e = hipEventRecord(ev_end, hs);
-      if (e != hipSuccess) return e;
-    }
-  }
+  const LaunchSet ls = launch_set(dev, grid_n, grid_frames, hs, base);
+  hipError_t e = launch_pack(m, ls);
+  for (size_t oi = 0; e == hipSuccess && oi < m->plan.ops.size(); ++oi) e = launch_op(m, oi, ls);
   return e;
 }
 
@@ -376,11 +403,20 @@ hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, in
   if (e == hipSuccess && !m->fork_ev) e = hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess && !m->join_ev) e = hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming);
   if (e != hipSuccess) return e;
-  // fork: the second half on the side stream; join before the caller's next work
+  // fork: the second half on the side stream; join before the caller's next
+  // work.  The two halves' launches are issued alternately, so that the
+  // second half can start at once even when the host issues a step just
+  // before the device runs it.
   e = hipEventRecord(m->fork_ev, hs);
   if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
-  if (e == hipSuccess) e = enqueue_kernels(m, dev, h, fa, hs, 0);
-  if (e == hipSuccess) e = enqueue_kernels(m, dev + split_desc_offset(h, fa), n - h, total - fa, m->side, fa);
+  const LaunchSet la = launch_set(dev, h, fa, hs, 0);
+  const LaunchSet lb = launch_set(dev + split_desc_offset(h, fa), n - h, total - fa, m->side, fa);
+  if (e == hipSuccess) e = launch_pack(m, la);
+  if (e == hipSuccess) e = launch_pack(m, lb);
+  for (size_t oi = 0; e == hipSuccess && oi < m->plan.ops.size(); ++oi) {
+    e = launch_op(m, oi, la);
+    if (e == hipSuccess) e = launch_op(m, oi, lb);
+  }
   if (e == hipSuccess) e = hipEventRecord(m->join_ev, m->side);
   if (e == hipSuccess) e = hipStreamWaitEvent(hs, m->join_ev, 0);
   return e;
