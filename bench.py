@@ -61,7 +61,7 @@ HBM_PEAK = 8.0e12  # B/s
 PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
 PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
 DTYPE = {0: "fp32", 1: "bf16", 2: "fp8e4m3"}
-IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win"}
+IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 
 
 # HBM traffic per launch of every layer of the BF16 256-stream workload from
@@ -107,13 +107,27 @@ def measured_traffic(best):
     return round(rec[1] * t["fetch_bytes_per_kib"] + rec[2] * t["write_bytes_per_kib"])
 
 
-def op_accounting(p):
+def op_accounting(p, tail=None, layer=False):
     """Algorithmic FLOPs and HBM bytes of one op summed over its timed
     launches: inputs read once, outputs written once, state (caches, carries,
     delay lines) read and written once per stream, weights read once per
-    launch."""
+    launch.  `tail`: the one-channel output conv computed in this window
+    conv's epilogue (the op after it, impl 3): this op's own output then never
+    reaches HBM, the output conv's does, and this op moves that conv's input
+    cache (written once here, read once by the tail launch).  `layer`: the
+    op as a layer of its own (every layer's input and output through HBM)."""
     fin, fout, ent, L = p["frames_in"], p["frames_out"], p["entries"], p["launches"]
     wb = {0: 4, 1: 2, 2: 1}[p["precision"]]
+    if tail is not None:
+        flops = 2.0 * fout * p["cin"] * (p["cout"] * p["k"] + tail["k"])
+        byts = 4.0 * (fin * p["cin"] + fout * tail["cout"] + ent * 2 * p["cache_len"] * p["cin"]
+                      + ent * tail["cache_len"] * tail["cin"])
+        byts += L * (wb * p["cout"] * p["cin"] * p["k"] + 4 * p["cout"] + 4 * tail["k"] * tail["cin"])
+        return flops, byts
+    if p["impl"] == 3 and not layer:   # the output conv's frames whose taps reach its cache or the previous tile
+        flops = 2.0 * ent * p["cache_len"] * p["cin"] * p["k"]
+        byts = 4.0 * ent * p["cache_len"] * p["cin"] + L * 4 * p["k"] * p["cin"]
+        return flops, byts
     if p["kind"] == 1:
         flops = 2.0 * fout * p["cout"] * p["cin"] * p["k"]
         byts = 4.0 * (fin * p["cin"] + fout * p["cout"] + ent * 2 * p["cache_len"] * p["cin"])
@@ -128,9 +142,15 @@ def op_accounting(p):
     return flops, byts
 
 
+def fused_tail(prof, p):
+    """The output conv fused into op p (the op after it, impl 3), or None."""
+    i = prof.index(p)
+    return prof[i + 1] if p["impl"] == 2 and i + 1 < len(prof) and prof[i + 1]["impl"] == 3 else None
+
+
 def roofline(prof):
     best = max(prof, key=lambda p: p["ms"])
-    flops, byts = op_accounting(best)
+    flops, byts = op_accounting(best, fused_tail(prof, best))
     sec = best["ms"] * 1e-3
     peak_f = PEAK[best["precision"]] if best["impl"] >= 1 else PEAK[0]
     ridge = peak_f / HBM_PEAK
@@ -241,9 +261,9 @@ def step_roofline(run, value, prec):
     The layer-by-layer figures (every layer's input and output through HBM,
     op_accounting) are the design's own roofline, given beside it."""
     prof, samples = run["prof"], run["samples"]
-    flops = sum(op_accounting(p)[0] for p in prof) / samples
+    flops = sum(op_accounting(p, layer=True)[0] for p in prof) / samples
     byts = run["algorithmic_bytes"] / samples
-    lbl = sum(op_accounting(p)[1] for p in prof) / samples
+    lbl = sum(op_accounting(p, layer=True)[1] for p in prof) / samples
     by_f, by_b = PEAK[prec] / flops, HBM_PEAK / byts
     roof = min(by_f, by_b)
     roof_lbl = min(by_f, HBM_PEAK / lbl)

@@ -135,12 +135,18 @@ enum {
                                chunk by chunk instead of staging each tile's
                                [cache | new frames] window in LDS (same results;
                                for testing) */
-  SC_MODEL_NO_SPLIT = 16u   /* run every step as one launch sequence; by default a
+  SC_MODEL_NO_SPLIT = 16u,  /* run every step as one launch sequence; by default a
                                step of at least 32 streams and 512 input frames runs
                                as two halves of its streams at once, the second on
                                an internal HIP stream joined back into the caller's
                                stream before the step ends (same results; for
                                testing) */
+  SC_MODEL_NO_OUT_FUSION = 32u  /* a one-output-channel conv that writes the model
+                                   output runs as its own launch; by default it is
+                                   computed in the epilogue of an LDS-window conv
+                                   that feeds it, and its launch only finishes the
+                                   frames whose taps cross that conv's tile
+                                   boundaries (same results; for testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,
@@ -225,7 +231,9 @@ sc_status sc_process_batch(sc_model* model, int32_t n, sc_stream* const* streams
 typedef struct {
   int32_t kind;        /* 1 conv (with fused skip if residual), 2 transposed conv, 3 delay-line sum */
   int32_t impl;        /* 0 FP32 wavefront FMA, 1 MFMA implicit GEMM (gathered
-                          operands), 2 MFMA with LDS-staged windows */
+                          operands), 2 MFMA with LDS-staged windows, 3 the
+                          remainder of an output conv computed by the window
+                          conv before it (SC_MODEL_NO_OUT_FUSION) */
   int32_t precision;   /* sc_precision of this launch's operands */
   int32_t node;        /* node whose output the launch writes */
   int32_t cin, cout, k, dilation, stride, cache_len, residual;

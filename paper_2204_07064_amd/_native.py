@@ -26,6 +26,7 @@ SC_MODEL_NO_MFMA = 2
 SC_MODEL_NO_TWIN = 4
 SC_MODEL_NO_WIN = 8
 SC_MODEL_NO_SPLIT = 16
+SC_MODEL_NO_OUT_FUSION = 32
 OPS = {"input": 0, "conv": 1, "convt": 2, "add": 3}
 
 # every symbol the header declares (checked by the CPU test suite)

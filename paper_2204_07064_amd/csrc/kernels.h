@@ -41,6 +41,16 @@ struct LayerArgs {
   int32_t twin_prec;
   int32_t twin_only;       // producer: the FP32 output has no reader; write the twin only
   int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
+  // window conv only: a one-output-channel stride-1 conv that reads this
+  // layer's output and writes the user output, computed in the epilogue
+  // (oc.k == 0: none).  Its input frames and rate are this layer's output.
+  struct {
+    const float* W;        // [k][cin] (cin = this layer's cout)
+    const float* B;        // [1]
+    int32_t k, dil, L, pre_act, post_act;
+    int64_t delay;         // warm-up lag of its output (frames)
+    int64_t state_off, state_len;   // its input cache: copies of [L][cin] (floats)
+  } oc;
 };
 
 // ---- the step's actual size (device header) ----
@@ -84,6 +94,15 @@ bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec);
 // does not qualify); min_frames = the fewest frames a stream brings to the layer.
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec);
 hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s);
+// Output frames per window tile, and whether a one-output-channel conv of
+// k taps, dilation dil (cache L = dil * (k - 1)) can be computed in the
+// epilogue of a window conv of this shape.
+int32_t conv_win_tile_frames(int cin, int cout);
+bool conv_win_out_fusable(int cin, int cout, int k, int dil);
+// The frames of such a fused output conv whose taps reach into the previous
+// tile of the window conv (its output rows there are in a.in_buf); `a` is the
+// output conv's own launch, tile_frames the window conv's tile.
+hipError_t launch_conv_out_tail(const LayerArgs& a, int32_t tile_frames, hipStream_t s);
 bool convt_mfma_supported(int cin, int cout, int r, int prec);
 // The layer that reads the model input on the FP32 MFMA gathering kernel.
 bool conv_mfma_fp32_input_supported(int cin, int cout, int k, int stride);

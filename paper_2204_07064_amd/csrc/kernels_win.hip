@@ -130,7 +130,152 @@ struct WinSeg {
   int32_t base;           // first LDS row of this stream's rows
   int32_t rows;
   int32_t t_lo, t_hi;     // local output frames of the stream inside the tile
+  // fused output conv: the stream's frames in the step, its input cache
+  // (current and next copy), user output and warm-up mask bound
+  int32_t T;
+  const float* cache2;
+  float* cache2_next;
+  float* out2;
+  int64_t mask2_x;
 };
+
+// ---- fused one-output-channel conv (see conv_win_kernel) ----
+// Its output at frame t is  B + sum over taps kk of P_kk(row t - L + dil * kk),
+// where P_kk(row) = sum over channels c of W[kk][c] * act(y[row][c]), added in
+// tap order.  P of a row is formed with FP32 MFMA over 16-channel groups
+// (tap_mfma), the groups added in order -- by the tile for its own rows, and
+// by the tail launch, with the same operands, for rows of earlier steps (the
+// cache) -- so a row's P has the same bits wherever it is formed, and results
+// do not depend on how a stream is cut into buffers or a step into tiles.
+constexpr int kOutTaps = 8;   // taps of a fused output conv, at most
+
+// The wave's P of 16 columns over one 16-channel group, FP32 MFMA: lane
+// (lr, lg) brings W[tap lr][c0 + 4 lg + j] (A) and act(y[c0 + 4 lg + j][column
+// lr]) (B) at step j, and gets D[tap 4 lg + r][column lr], r = 0..3.
+__device__ inline f4 tap_mfma(f4 wa, f4 y) {
+  f4 d = {0.f, 0.f, 0.f, 0.f};
+  d = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.x, y.x, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.y, y.y, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.z, y.z, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.w, y.w, d, 0, 0, 0);
+  return d;
+}
+
+// Frames of a fused output conv left to the tail launch: the first L frames
+// of a stream in the step (their taps reach the cache) and frames whose taps
+// reach into the previous tile.
+__device__ inline bool out_tail_frame(int32_t f, int32_t out_start, int32_t f0, int L) {
+  return f - out_start < L || (out_start < f0 && f - L < f0);
+}
+
+// The epilogue of a window tile with a fused output conv.  w2s: the output
+// conv's weights [k][MT] (LDS).  Dynamic LDS (free once every wave is past
+// the K loop): per-wave channel partials [WM][F][kOutTaps].
+template <int PREC, int MT, int NB, int F>
+__device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int m, f4 bias, f4 wsc, int32_t f0,
+                                          const float* wskip, int skipf, const WinSeg* segs, const int8_t* colseg,
+                                          int n_seg, const float* w2s, unsigned char* lds) {
+  constexpr int WM = MT / 16;
+  constexpr int WN = 4 / WM;
+  constexpr int KO = kOutTaps;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int L2 = a.oc.L, k2 = a.oc.k, d2 = a.oc.dil;
+  const bool pre2 = a.oc.pre_act != 0;
+  f4 v[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = wn * (F / WN) + nb * 16 + lr;
+    const int s = colseg[col];
+    v[nb] = f4{0.f, 0.f, 0.f, 0.f};
+    if (s < 0) continue;
+    const int32_t t = f0 + col - segs[s].out_start;
+    f4 x = acc[nb];
+    if (PREC == 2) x = x * (wsc * a.act_scale);
+    x = x + bias;
+    if (a.residual) x = x + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
+    if ((int64_t)t * a.out_den < segs[s].mask_x) x = f4{0.f, 0.f, 0.f, 0.f};
+    v[nb] = x;
+  }
+  __syncthreads();   // every wave is done with the staged rows and the skip rows
+  float* X = reinterpret_cast<float*>(lds);   // [WM][F][KO]
+  // A operand: tap lr (zero beyond k), channels m .. m + 3, one per step
+  const f4 wa = lr < k2 ? *reinterpret_cast<const f4*>(w2s + lr * MT + m) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = wn * (F / WN) + nb * 16 + lr;
+    const int s = colseg[col];
+    if (s >= 0) {
+      // the output conv's next cache: the stream's last L2 frames (raw)
+      const WinSeg& g = segs[s];
+      const int32_t i = f0 + col - g.out_start - (g.T - L2);
+      if (i >= 0) *reinterpret_cast<f4*>(g.cache2_next + (int64_t)i * MT + m) = v[nb];
+    }
+    // the wave's 16 channels of the 16 columns: D[kk][col] = sum over them of
+    // W[kk][c] * act(y[c][col]) on FP32 MFMA, the accumulator layout serving
+    // as the B operand (lane: channels m .. m + 3 of column col, one per step)
+    const f4 y = {act(v[nb].x, pre2), act(v[nb].y, pre2), act(v[nb].z, pre2), act(v[nb].w, pre2)};
+    const f4 d = tap_mfma(wa, y);
+    // lane: taps 4 lg .. 4 lg + 3 of column col
+    if (lg < KO / 4) *reinterpret_cast<f4*>(&X[(wm * F + col) * KO + lg * 4]) = d;
+  }
+  // old cache rows that stay in the next cache of a stream of fewer than L2
+  // frames (moved by the tile holding the stream's first frame)
+  for (int s = 0; s < n_seg; ++s) {
+    const WinSeg& g = segs[s];
+    if (g.t_lo != 0 || g.T >= L2) continue;   // uniform
+    for (int j = tid; j < (L2 - g.T) * (MT / 4); j += kThreads) {
+      const int i = j / (MT / 4);
+      const int c = (j - i * (MT / 4)) * 4;
+      *reinterpret_cast<f4*>(g.cache2_next + (int64_t)i * MT + c) =
+          *reinterpret_cast<const f4*>(g.cache2 + (int64_t)(g.T + i) * MT + c);
+    }
+  }
+  __syncthreads();
+  // one lane per column: P of the column's row (the 16-channel groups in
+  // order) to out_buf where the tail launch reads it (rows next to a tile
+  // boundary or among a stream's first L2 frames; P_kk at float kk), and the
+  // output conv at the column's frame when all its taps are on the tile
+  if (tid < F) {
+    const int col = tid;
+    const int s = colseg[col];
+    if (s >= 0) {
+      const WinSeg& g = segs[s];
+      const int32_t f = f0 + col;
+      const int32_t t = f - g.out_start;
+      if (col < L2 || col >= F - L2 || t < L2) {
+#pragma unroll
+        for (int kk = 0; kk < KO; ++kk) {
+          if (kk < k2) {
+            float p = X[col * KO + kk];
+#pragma unroll
+            for (int w = 1; w < WM; ++w) p = p + X[(w * F + col) * KO + kk];
+            a.out_buf[(int64_t)f * MT + kk] = p;
+          }
+        }
+      }
+      if (!out_tail_frame(f, g.out_start, f0, L2)) {
+        float o = a.oc.B[0];
+#pragma unroll
+        for (int kk = 0; kk < KO; ++kk) {
+          if (kk < k2) {
+            const int r = col - L2 + d2 * kk;   // the tap's row (a column of this tile)
+            float p = X[r * KO + kk];
+#pragma unroll
+            for (int w = 1; w < WM; ++w) p = p + X[(w * F + r) * KO + kk];
+            o = o + p;
+          }
+        }
+        if (a.oc.post_act == 2) o = tanhf(o);
+        if ((int64_t)t * a.out_den < g.mask2_x) o = 0.f;
+        g.out2[t] = o;
+      }
+    }
+  }
+}
 
 // MT x F tile, 4 waves: MT = 32 -> 2 x 2 waves of 16 x (F / 2); MT = 64 ->
 // 4 x 1 waves of 16 x F.  A wave owns NB column blocks of 16, so F = 16 NB WN;
@@ -139,7 +284,16 @@ struct WinSeg {
 // LDS: the staged window rows in operand form (activated and rounded once,
 // row stride cin * ES + 16 bytes), then, for a fused residual, each column's
 // skip row as raw FP32 ([F][cin + 4]).
-template <int PREC, int MT, int NB, int KCM>
+//
+// FUSE: a one-output-channel conv reading this layer's output (cout == MT, one
+// M tile) runs in the epilogue, which never writes the layer's output itself.
+// From the accumulators it forms each row's per-tap sums P_kk (see
+// tap_partial) and finishes every frame whose taps stay on the tile's rows;
+// a small tail launch finishes the rest (a stream's first L frames, and up to
+// L frames after each tile boundary), reading P of the rows they need, which
+// the tiles store in out_buf (the only values written there).  The tiles
+// also move the output conv's input cache.
+template <int PREC, int MT, int NB, int KCM, bool FUSE>
 __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
                                                              FastDiv fd_ppr) {
@@ -154,6 +308,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
   __shared__ int32_t tile_info[4];   // e_first, n_seg, total rows, ok
+  __shared__ __attribute__((aligned(16))) float w2s[FUSE ? kOutTaps * MT : 4];   // fused output conv's weights
 
   const int tid = threadIdx.x;
   const int32_t n_tiles = n_mt * n_nt;
@@ -221,6 +376,17 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   const f4 bias = m_ok ? *reinterpret_cast<const f4*>(a.B + m) : f4{0.f, 0.f, 0.f, 0.f};
   const f4 wsc = (PREC == 2 && m_ok) ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
 
+  // fused output conv: its weights, loaded now and stored to LDS after the
+  // stream lookup (the load is in flight meanwhile)
+  float w2v[FUSE ? 2 : 1];
+  if constexpr (FUSE) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = tid + u * kThreads;
+      w2v[u] = q < a.oc.k * MT ? a.oc.W[q] : 0.f;
+    }
+  }
+
   // ---- the streams of the tile ----
   if (tid == 0) {
     const int e0 = entry_of_out(a, f0);
@@ -246,7 +412,21 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     g.r0 = g.t_lo;
     g.rows = g.t_hi - g.t_lo + 1 + a.L;
     g.base = 0;
+    g.T = T;
+    if constexpr (FUSE) {
+      g.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
+      g.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
+      g.out2 = e.out;
+      g.mask2_x = (e.flags & SC_FLAG_WARMUP_MASK)
+                      ? a.oc.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
+                      : INT64_MIN;
+    }
     segs[tid] = g;
+  }
+  if constexpr (FUSE) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (tid + u * kThreads < kOutTaps * MT) w2s[tid + u * kThreads] = w2v[u];
   }
   __syncthreads();
   if (tid == 0) {
@@ -367,6 +547,11 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     }
   }
 
+  if constexpr (FUSE) {
+    fused_out_epilogue<PREC, MT, NB, F>(a, acc, m, bias, wsc, f0, wskip, skipf, segs, colseg, n_seg, w2s, lds);
+    return;
+  }
+
   // ---- epilogue: lane holds rows m .. m + 3 of column col for each block ----
   if (!m_ok) return;
 #pragma unroll
@@ -426,7 +611,109 @@ int64_t win_lds_bytes(int64_t rows, int cin, int prec, int F) {
   return rows * (cin * w_esize(prec) + 16) + (int64_t)F * (cin + 4) * 4 + rows * 12;
 }
 
+// The frames of a fused output conv that its window tiles leave (see
+// out_tail_frame).  Blocks [0, bnd_blocks): one lane per frame f0 + i, i < L,
+// after every tile start f0 but the first, P of its rows (all of this step)
+// from out_buf.  Blocks after: one wave per stream of the step, which forms P
+// of the stream's L cache rows (one MFMA column each, L <= 16) and finishes
+// its first L frames.
+template <int CIN>
+__global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, int32_t tile_frames, int32_t n_bnd,
+                                                                 int32_t bnd_blocks) {
+  __shared__ __attribute__((aligned(16))) float pc[kThreads / 64][16][kOutTaps];
+  const float* W = static_cast<const float*>(a.W);   // [k][cin]
+  if ((int32_t)blockIdx.x < bnd_blocks) {
+    const int32_t idx = (int32_t)blockIdx.x * kThreads + (int32_t)threadIdx.x;
+    if (idx >= n_bnd) return;
+    const int32_t b = idx / a.L;
+    const int32_t f0 = (b + 1) * tile_frames;
+    const int32_t f = f0 + (idx - b * a.L);
+    if (f >= step_out(a)) return;   // the grid may be sized for a larger step
+    const Entry& e = a.ents[entry_of_out(a, f)];
+    const int32_t out_start = out_frames(a, e.off);
+    const int32_t t = f - out_start;
+    if (!(out_start < f0 && f - a.L < f0) || t < a.L) return;   // its tile's, or a stream start
+    float p[kOutTaps];
+#pragma unroll
+    for (int kk = 0; kk < kOutTaps; ++kk)
+      p[kk] = kk < a.k ? a.in_buf[(int64_t)(f - a.L + a.dil * kk) * CIN + kk] : 0.f;
+    float o = a.B[0];
+#pragma unroll
+    for (int kk = 0; kk < kOutTaps; ++kk)
+      if (kk < a.k) o = o + p[kk];
+    if (a.post_act == 2) o = tanhf(o);
+    if (masked(a, e, t)) o = 0.f;
+    e.out[t] = o;
+    return;
+  }
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int32_t ei = ((int32_t)blockIdx.x - bnd_blocks) * (kThreads / 64) + wave;
+  const bool live = ei < step_ents(a);   // uniform in the wave
+  const bool pre = a.pre_act != 0;
+  if (live) {
+    const Entry& e = a.ents[ei];
+    const float* cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+    f4 P = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < CIN / 16; ++g) {
+      const int c = g * 16 + lg * 4;
+      const f4 wa = lr < a.k ? *reinterpret_cast<const f4*>(W + lr * CIN + c) : f4{0.f, 0.f, 0.f, 0.f};
+      f4 y = lr < a.L ? *reinterpret_cast<const f4*>(cache + (int64_t)lr * CIN + c) : f4{0.f, 0.f, 0.f, 0.f};
+      y = f4{act(y.x, pre), act(y.y, pre), act(y.z, pre), act(y.w, pre)};
+      const f4 d = tap_mfma(wa, y);
+      P = g == 0 ? d : P + d;
+    }
+    if (lg < kOutTaps / 4) *reinterpret_cast<f4*>(&pc[wave][lr][lg * 4]) = P;   // [cache row][tap]
+  }
+  __syncthreads();
+  if (!live) return;
+  const Entry& e = a.ents[ei];
+  const int32_t t = lane;
+  if (t >= a.L || t >= out_frames(a, e.T)) return;
+  const int32_t out_start = out_frames(a, e.off);
+  float o = a.B[0];
+#pragma unroll
+  for (int kk = 0; kk < kOutTaps; ++kk) {
+    if (kk < a.k) {
+      const int w = t + a.dil * kk;   // row of [cache | new frames]
+      o = o + (w < a.L ? pc[wave][w][kk] : a.in_buf[(int64_t)(out_start + w - a.L) * CIN + kk]);
+    }
+  }
+  if (a.post_act == 2) o = tanhf(o);
+  if (masked(a, e, t)) o = 0.f;
+  e.out[t] = o;
+}
+
 }  // namespace
+
+int32_t conv_win_tile_frames(int cin, int cout) { return win_f(win_mt(cout), win_nb(cin)); }
+
+bool conv_win_out_fusable(int cin, int cout, int k, int dil) {
+  // all output channels in one M tile, a tile shape with fused variants, and
+  // the taps of a boundary frame reaching no further than the previous tile
+  if (cout != win_mt(cout) || win_nb(cin) != 4 || k < 1 || k > kOutTaps || dil < 1) return false;
+  const int L = dil * (k - 1);
+  return L <= 16 && 2 * L <= conv_win_tile_frames(cin, cout);   // the tail forms P of <= 16 cache rows
+}
+
+hipError_t launch_conv_out_tail(const LayerArgs& a, int32_t tile_frames, hipStream_t s) {
+  if (a.L <= 0 || tile_frames <= 0 || a.cin % 4 != 0) return a.L <= 0 ? hipSuccess : hipErrorInvalidValue;
+  const int64_t n_tiles = (a.n_out + tile_frames - 1) / tile_frames;
+  const int64_t n_bnd = std::max<int64_t>(n_tiles - 1, 0) * a.L;
+  const int64_t bnd_blocks = (n_bnd + kThreads - 1) / kThreads;
+  const int64_t blocks = bnd_blocks + ((int64_t)a.n_ent + kThreads / 64 - 1) / (kThreads / 64);
+  if (blocks == 0) return hipSuccess;
+#define SC_TAIL(C)                                                                                         \
+  hipLaunchKernelGGL((conv_out_tail_kernel<C>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a, tile_frames, \
+                     (int32_t)n_bnd, (int32_t)bnd_blocks)
+  if (a.cin == 32) SC_TAIL(32);
+  else if (a.cin == 64) SC_TAIL(64);
+  else return hipErrorInvalidValue;
+#undef SC_TAIL
+  return hipGetLastError();
+}
 
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec) {
   if (!conv_mfma_supported(cin, cout, k, stride, prec)) return 0;
@@ -461,18 +748,25 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  const size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
+  const bool fuse = a.oc.k > 0;
+  if (fuse && (a.cout != MT || NB != 4 || !a.out_buf)) return hipErrorInvalidValue;
+  size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
+  // per-wave partial tap sums of the output conv
+  if (fuse) lds = std::max(lds, (size_t)(MT / 16) * F * kOutTaps * 4);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin / 4, 1));
   const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
-#define SC_WIN(P, M, N, K)                                                                                  \
-  if (prec == P && MT == M && NB == N && KCM == K) {                                                       \
-    hipLaunchKernelGGL((conv_win_kernel<P, M, N, K>), dim3((unsigned)grid), dim3(kThreads), lds, s, a,     \
+#define SC_WIN(P, M, N, K, FU)                                                                              \
+  if (prec == P && MT == M && NB == N && KCM == K && fuse == FU) {                                         \
+    hipLaunchKernelGGL((conv_win_kernel<P, M, N, K, FU>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
                        n_mt, (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                  \
     return hipGetLastError();                                                                              \
   }
-  SC_WIN(0, 32, 4, 3) SC_WIN(0, 64, 4, 3) SC_WIN(0, 64, 4, 6)
-  SC_WIN(1, 32, 4, 3) SC_WIN(1, 64, 4, 3) SC_WIN(1, 64, 2, 6)
-  SC_WIN(2, 32, 4, 2) SC_WIN(2, 64, 4, 2) SC_WIN(2, 64, 2, 3)
+  SC_WIN(0, 32, 4, 3, false) SC_WIN(0, 64, 4, 3, false) SC_WIN(0, 64, 4, 6, false)
+  SC_WIN(1, 32, 4, 3, false) SC_WIN(1, 64, 4, 3, false) SC_WIN(1, 64, 2, 6, false)
+  SC_WIN(2, 32, 4, 2, false) SC_WIN(2, 64, 4, 2, false) SC_WIN(2, 64, 2, 3, false)
+  SC_WIN(0, 32, 4, 3, true) SC_WIN(0, 64, 4, 3, true) SC_WIN(0, 64, 4, 6, true)
+  SC_WIN(1, 32, 4, 3, true) SC_WIN(1, 64, 4, 3, true)
+  SC_WIN(2, 32, 4, 2, true) SC_WIN(2, 64, 4, 2, true)
 #undef SC_WIN
   return hipErrorInvalidValue;
 }

@@ -119,6 +119,30 @@ void* tw_at(const sc_model* m, int t, int64_t base) {
   return t >= 0 ? static_cast<unsigned char*>(m->tw[t]) + m->plan.twin_elems[t].of(base) * m->tw_esize : nullptr;
 }
 
+// A one-output-channel stride-1 conv that writes the model output and reads
+// only the output of the window conv launched just before it, which nothing
+// else reads, is computed in that conv's epilogue (IMPL_TAIL).
+void fuse_output_convs(Plan& pl) {
+  for (size_t i = 1; i < pl.ops.size(); ++i) {
+    Op& c = pl.ops[i];
+    Op& p = pl.ops[i - 1];
+    if (c.kind != K_CONV || c.impl != IMPL_VALU || c.cout != 1 || c.stride != 1 || c.out_buf != -1 ||
+        c.residual || c.in_buf2 >= 0 || (c.post_act != 0 && c.post_act != 2))
+      continue;
+    if (p.kind != K_CONV || p.impl != IMPL_WIN || p.out_buf < 0 || c.in_buf != p.out_buf || p.fuse_out >= 0)
+      continue;
+    if (c.cache_len != c.dil * (c.k - 1) || !conv_win_out_fusable(p.cin, p.cout, c.k, c.dil)) continue;
+    // (workspace buffers are reused, so readers are found by node)
+    bool other = false;
+    for (size_t j = 0; j < pl.ops.size(); ++j)
+      if (j != i && (pl.ops[j].src == p.node || pl.ops[j].src2 == p.node)) other = true;
+    if (other) continue;
+    p.fuse_out = (int32_t)i;
+    c.fuse_out = (int32_t)(i - 1);
+    c.impl = IMPL_TAIL;
+  }
+}
+
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
                      const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base) {
   LayerArgs a{};
@@ -152,7 +176,7 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.state_off2 = op.state_off2; a.state_len2 = op.state_len2;
   a.n_in = op.in_rate.of(total_T);
   a.n_out = op.out_rate.of(total_T);
-  a.tile = (op.kind == K_CONV && op.impl == IMPL_VALU)
+  a.tile = (op.kind == K_CONV && (op.impl == IMPL_VALU || op.impl == IMPL_TAIL))
                ? narrow_conv_tile(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, a.n_out)
                : 0;
   a.in_twin = tw_at(m, op.in_twin, base);
@@ -351,9 +375,31 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
     e = prof_begin(m, (int)oi, a, ls.hs, &ev_end);
     if (e != hipSuccess) return e;
   }
+  // calibration reads the fused output conv's input, so run it on its own then
+  const bool fused = op.fuse_out >= 0 && !m->amax_on;
   if (op.kind == K_CONV) {
-    if (op.impl == IMPL_WIN) e = launch_conv_win(a, prec, m->opdev[oi].win_rows, ls.hs);
-    else e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, ls.hs) : launch_conv_valu(a, ls.hs);
+    if (op.impl == IMPL_WIN) {
+      LayerArgs aw = a;
+      if (fused) {
+        const Op& oc = m->plan.ops[op.fuse_out];
+        aw.oc.W = static_cast<const float*>(m->opdev[op.fuse_out].W);
+        aw.oc.B = m->opdev[op.fuse_out].B;
+        aw.oc.k = oc.k;
+        aw.oc.dil = oc.dil;
+        aw.oc.L = oc.cache_len;
+        aw.oc.pre_act = oc.pre_act;
+        aw.oc.post_act = oc.post_act;
+        aw.oc.delay = oc.out_delay;
+        aw.oc.state_off = oc.state_off;
+        aw.oc.state_len = oc.state_len;
+      }
+      e = launch_conv_win(aw, prec, m->opdev[oi].win_rows, ls.hs);
+    } else if (op.impl == IMPL_TAIL && fused) {
+      const Op& pw = m->plan.ops[op.fuse_out];
+      e = launch_conv_out_tail(a, conv_win_tile_frames(pw.cin, pw.cout), ls.hs);
+    } else {
+      e = (op.impl == IMPL_MFMA) ? launch_conv_mfma(a, prec, ls.hs) : launch_conv_valu(a, ls.hs);
+    }
   } else if (op.kind == K_CONVT) {
     e = (op.impl == IMPL_MFMA) ? launch_convt_mfma(a, prec, ls.hs) : launch_convt_valu(a, ls.hs);
   } else {
@@ -705,6 +751,7 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     m->weight_bytes += (int64_t)op.cout * 4;
     if (e != hipSuccess) { free_model(m); return hip_fail(e, "weight upload"); }
   }
+  if (!(options & SC_MODEL_NO_OUT_FUSION)) fuse_output_convs(m->plan);
   m->tw_esize = prec_id == 0 ? 4 : (prec_id == 1 ? 2 : 1);
   finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN), m->tw_esize);
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));

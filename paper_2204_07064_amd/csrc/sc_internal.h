@@ -30,7 +30,10 @@ enum OpKind : int32_t { K_CONV = 1, K_CONVT = 2, K_DELAY_ADD = 3 };
 // Which kernel family runs an op.
 // IMPL_MFMA gathers each K chunk of the operands from HBM; IMPL_WIN stages
 // each tile's window rows in LDS once (stride-1 convs with narrow inputs).
-enum Impl : int32_t { IMPL_VALU = 0, IMPL_MFMA = 1, IMPL_WIN = 2 };
+// IMPL_TAIL: a one-output-channel conv computed in the epilogue of the window
+// conv before it; its own launch only finishes the frames whose taps cross a
+// tile boundary of that conv.
+enum Impl : int32_t { IMPL_VALU = 0, IMPL_MFMA = 1, IMPL_WIN = 2, IMPL_TAIL = 3 };
 
 // One launch of a processing step (a conv with optional fused residual, a
 // transposed conv, or a delay-line sum).
@@ -62,6 +65,8 @@ struct Op {
   int32_t twin_layer = -1;    // producer: the consumer's layer (FP8 activation scale)
   int64_t tstate_off = 0, tstate_len = 0;   // consumer conv: twin cache (floats)
   int32_t no_twin = 0;        // an MFMA op that computes in FP32 whatever the model's precision
+  int32_t fuse_out = -1;      // window conv: index of the output conv in its epilogue;
+                              // IMPL_TAIL op: index of that window conv
   int32_t twin_only = 0;      // producer: its only reader takes the twin and keeps no FP32
                               // input state (a transposed conv), so the FP32 output is not written
 };

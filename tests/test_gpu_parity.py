@@ -85,8 +85,11 @@ def test_fusion_is_bitwise_equal_to_delay_lines():
     sc = _sc()
     m, w = weights_for("rave_b")
     x = scgen.stream_latents(16, 48, 4)
-    a = run_stream(sc.Model(m, w, "fp32"), x, [5, 11, 32])
-    b = run_stream(sc.Model(m, w, "fp32", options=1), x, [5, 11, 32])
+    # (the output conv runs on its own in both: with explicit delay lines the
+    # conv before it is no window conv to fuse it into)
+    nof = sc._native.SC_MODEL_NO_OUT_FUSION
+    a = run_stream(sc.Model(m, w, "fp32", options=nof), x, [5, 11, 32])
+    b = run_stream(sc.Model(m, w, "fp32", options=1 | nof), x, [5, 11, 32])
     assert np.array_equal(a, b)
 
 
@@ -202,6 +205,65 @@ def test_split_step_bitwise(prec):
         for i in range(S):
             assert torch.equal(ya[i], yb[i]), (k, i)
     log("split steps: %d steps x %d streams bitwise equal (%s)" % (len(steps), S, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_output_conv_fusion_matches(prec):
+    """The decoder's one-channel output conv computed in the epilogue of the
+    last window conv (plus the tail launch for frames whose taps cross a tile
+    boundary, and the move of its input cache) matches its own launch: streams
+    that span several tiles, 1-frame buffers, warm-up masks, split and unsplit
+    steps, state carried across steps.  Both add the same FP32 products of the
+    same inputs, in different orders (the fused one by channel groups, the
+    standalone one channel after channel), so they agree to FP32 rounding of
+    a 224-term sum: 1e-5 absolute on outputs in (-1, 1), the FP32 bound
+    against the oracle.  Masked frames are exact zeros in both."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = None
+    if prec == "fp8":
+        from paper_2204_07064_amd import calibrate
+        scales = calibrate.act_scales(sc, m, w, [scgen.latents(16, 32, 1)])
+    a = sc.Model(m, w, prec, act_scales=scales)
+    b = sc.Model(m, w, prec, act_scales=scales, options=sc._native.SC_MODEL_NO_OUT_FUSION)
+    S = 48
+    rng = np.random.default_rng(33)
+    steps = [[int(v) for v in rng.choice([1, 2, 3, 5, 8, 16, 32], size=S)] for _ in range(4)]
+    steps.insert(1, [1] * S)                     # one tile per stream, below the split threshold
+    xs = [scgen.stream_latents(16, sum(st[i] for st in steps), 700 + i) for i in range(S)]
+    sa = [sc.Stream(a, 32, warmup_mask=(i % 3 == 0)) for i in range(S)]
+    sb = [sc.Stream(b, 32, warmup_mask=(i % 3 == 0)) for i in range(S)]
+    pos = [0] * S
+    worst = 0.0
+    for k, st in enumerate(steps):
+        ins = [torch.from_numpy(np.ascontiguousarray(xs[i][:, pos[i]:pos[i] + st[i]])).cuda() for i in range(S)]
+        for i in range(S):
+            pos[i] += st[i]
+        ya = sc.process_batch(a, sa, ins)
+        yb = sc.process_batch(b, sb, ins)
+        torch.cuda.synchronize()
+        for i in range(S):
+            assert torch.equal(ya[i] == 0, yb[i] == 0), (k, i)
+            err = (ya[i] - yb[i]).abs().max().item()
+            assert err <= 1e-5, (k, i, err)
+            worst = max(worst, err)
+    # the same streams as single-stream calls (one tile each, no tail frames),
+    # timed per launch (which also runs steps unsplit)
+    a.profile(True)
+    for k in range(3):
+        for i in range(0, S, 7):
+            x = torch.from_numpy(np.ascontiguousarray(scgen.stream_latents(16, 1, 900 + 10 * k + i))).cuda()
+            ya = sa[i].process(x)
+            yb = sb[i].process(x)
+            torch.cuda.synchronize()
+            err = (ya - yb).abs().max().item()
+            assert err <= 1e-5, (k, i, err)
+            worst = max(worst, err)
+    impls = [p["impl"] for p in a.profile_read()]
+    assert impls[-1] == 3 and impls[-2] == 2, impls   # the fused pair ran
+    a.profile(False)
+    log("output conv fusion: %d steps x %d streams, max |fused - own launch| %.2e (%s)" % (
+        len(steps), S, worst, prec))
 
 
 @pytest.mark.parametrize("name,mult,prec", [("encoder", 128, "fp32"), ("encoder", 128, "bf16"),
