@@ -69,28 +69,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 0de52c6700ab6cfd8bf54583f048c10641f4642c 9c5b01c64c454d87da90bad86645835e5fcdd2aa c21a29cf32cb8e4e1c56358444cf31dbd90e8f1d 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 b6b5f40ad78c9db2c381add1c455b24310a08d6b 9c5b01c64c454d87da90bad86645835e5fcdd2aa dca89fa298389451e6327df2b3e9eb87f3ba1764 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 729.3, 2727.1),
-        2: ('mfma', 10429.7, 22222.1),
-        4: ('mfma', 10278.9, 21959.7),
-        6: ('mfma', 11266.9, 23075.7),
-        8: ('mfma', 14125.4, 12302.2),
-        9: ('mfma', 5216.1, 42277.8),
-        11: ('mfma', 17010.3, 39435.5),
-        13: ('mfma', 17504.9, 40193.0),
-        15: ('mfma', 18943.9, 14236.8),
-        16: ('mfma', 6179.4, 58149.8),
-        18: ('mfma_win', 22574.4, 55197.7),
-        20: ('mfma_win', 24041.4, 55305.1),
-        22: ('mfma_win', 28448.7, 22712.6),
-        23: ('mfma', 10973.9, 57373.6),
-        25: ('mfma_win', 22135.9, 55034.3),
-        27: ('mfma_win', 22864.7, 55313.1),
-        29: ('mfma_win', 25059.3, 55271.2),
-        30: ('valu', 23428.8, 1539.5),
+        1: ('mfma', 729.7, 2727.1),
+        2: ('mfma', 10430.2, 22176.8),
+        4: ('mfma', 10279.5, 21954.9),
+        6: ('mfma', 11267.3, 23075.3),
+        8: ('mfma', 14126.6, 12302.2),
+        9: ('mfma', 5216.6, 42261.6),
+        11: ('mfma', 17010.6, 39415.7),
+        13: ('mfma', 17506.0, 40072.4),
+        15: ('mfma', 18945.0, 14236.8),
+        16: ('mfma', 6179.9, 58171.2),
+        18: ('mfma_win', 22572.3, 55306.9),
+        20: ('mfma_win', 24043.6, 55354.4),
+        22: ('mfma_win', 28449.2, 22712.6),
+        23: ('mfma', 10974.4, 57389.9),
+        25: ('mfma_win', 22142.8, 55282.7),
+        27: ('mfma_win', 22871.7, 55764.0),
+        29: ('mfma_win', 25095.0, 3126.2),
+        30: ('tail', 2106.1, 85.4),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
