@@ -170,7 +170,7 @@ __device__ inline bool out_tail_frame(int32_t f, int32_t out_start, int32_t f0, 
 
 // The epilogue of a window tile with a fused output conv.  w2s: the output
 // conv's weights [k][MT] (LDS).  Dynamic LDS (free once every wave is past
-// the K loop): per-wave channel partials [WM][F][kOutTaps].
+// the K loop): per-wave channel partials [WM][kOutTaps][F].
 template <int PREC, int MT, int NB, int F>
 __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int m, f4 bias, f4 wsc, int32_t f0,
                                           const float* wskip, int skipf, const WinSeg* segs, const int8_t* colseg,
@@ -201,7 +201,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     v[nb] = x;
   }
   __syncthreads();   // every wave is done with the staged rows and the skip rows
-  float* X = reinterpret_cast<float*>(lds);   // [WM][F][KO]
+  float* X = reinterpret_cast<float*>(lds);   // [WM][KO][F]
   // A operand: tap lr (zero beyond k), channels m .. m + 3, one per step
   const f4 wa = lr < k2 ? *reinterpret_cast<const f4*>(w2s + lr * MT + m) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -220,7 +220,13 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     const f4 y = {act(v[nb].x, pre2), act(v[nb].y, pre2), act(v[nb].z, pre2), act(v[nb].w, pre2)};
     const f4 d = tap_mfma(wa, y);
     // lane: taps 4 lg .. 4 lg + 3 of column col
-    if (lg < KO / 4) *reinterpret_cast<f4*>(&X[(wm * F + col) * KO + lg * 4]) = d;
+    if (lg < KO / 4) {
+      float* xr = X + (wm * KO + lg * 4) * F + col;
+      xr[0] = d.x;
+      xr[F] = d.y;
+      xr[2 * F] = d.z;
+      xr[3 * F] = d.w;
+    }
   }
   // old cache rows that stay in the next cache of a stream of fewer than L2
   // frames (moved by the tile holding the stream's first frame)
@@ -235,44 +241,42 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     }
   }
   __syncthreads();
-  // one lane per column: P of the column's row (the 16-channel groups in
-  // order) to out_buf where the tail launch reads it (rows next to a tile
-  // boundary or among a stream's first L2 frames; P_kk at float kk), and the
-  // output conv at the column's frame when all its taps are on the tile
+  // P of a row: the 16-channel groups in order
+  auto prow = [&](int r, int kk) {
+    float p = X[kk * F + r];
+#pragma unroll
+    for (int w = 1; w < WM; ++w) p = p + X[(w * KO + kk) * F + r];
+    return p;
+  };
   if (tid < F) {
+    // one lane per column: the output conv at the column's frame when all its
+    // taps are on the tile's rows
     const int col = tid;
     const int s = colseg[col];
     if (s >= 0) {
       const WinSeg& g = segs[s];
       const int32_t f = f0 + col;
       const int32_t t = f - g.out_start;
-      if (col < L2 || col >= F - L2 || t < L2) {
-#pragma unroll
-        for (int kk = 0; kk < KO; ++kk) {
-          if (kk < k2) {
-            float p = X[col * KO + kk];
-#pragma unroll
-            for (int w = 1; w < WM; ++w) p = p + X[(w * F + col) * KO + kk];
-            a.out_buf[(int64_t)f * MT + kk] = p;
-          }
-        }
-      }
       if (!out_tail_frame(f, g.out_start, f0, L2)) {
         float o = a.oc.B[0];
 #pragma unroll
-        for (int kk = 0; kk < KO; ++kk) {
-          if (kk < k2) {
-            const int r = col - L2 + d2 * kk;   // the tap's row (a column of this tile)
-            float p = X[r * KO + kk];
-#pragma unroll
-            for (int w = 1; w < WM; ++w) p = p + X[(w * F + r) * KO + kk];
-            o = o + p;
-          }
-        }
+        for (int kk = 0; kk < KO; ++kk)
+          if (kk < k2) o = o + prow(col - L2 + d2 * kk, kk);
         if (a.oc.post_act == 2) o = tanhf(o);
         if ((int64_t)t * a.out_den < g.mask2_x) o = 0.f;
         g.out2[t] = o;
       }
+    }
+  } else if (tid - F < F) {
+    // P of the column's row to out_buf where the tail launch reads it (rows
+    // next to a tile boundary or among a stream's first L2 frames; P_kk at
+    // float kk of the row)
+    const int col = tid - F;
+    const int s = colseg[col];
+    if (s >= 0 && (col < L2 || col >= F - L2 || f0 + col - segs[s].out_start < L2)) {
+#pragma unroll
+      for (int kk = 0; kk < KO; ++kk)
+        if (kk < k2) a.out_buf[(int64_t)(f0 + col) * MT + kk] = prow(col, kk);
     }
   }
 }
