@@ -155,8 +155,22 @@ def encoder(name="encoder", ratios=(4, 4, 4, 2), widths=(16, 32, 64, 128, 256), 
     return {"name": name, "nodes": nodes, "in_channels": 1, "out_channels": latent}
 
 
+def outconv_unit():
+    """Input conv 8->64 (k3), a transposed conv 64->32 (ratio 32), one residual
+    block x + Conv_k3,d3(LeakyReLU(x)) at 32 channels, then a one-channel
+    output conv with dilation and no tanh: Conv_k5,d3(LeakyReLU(x)), padding
+    6/6."""
+    nodes = [_input(8),
+             _conv(0, 8, 64, 3, 1),
+             _convt(1, 64, 32, 32),
+             _conv(2, 32, 32, 3, 3, pre_act=ACT_LRELU),
+             _add(2, 3),
+             _conv(4, 32, 1, 5, 3, pre_act=ACT_LRELU)]
+    return {"name": "outconv", "nodes": nodes, "in_channels": 8, "out_channels": 1}
+
+
 def model_by_name(name):
-    table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder,
+    table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder, "outconv": outconv_unit,
              "strided": lambda: strided_unit(False),
              "strided_aligned": lambda: strided_unit(True),
              "branch": branch_unit, "branch3": branch3_unit, "encoder": encoder}

@@ -37,6 +37,8 @@ def _need_gpu():
     ("branch", 300, 7, 0),              # Eq. 3 branch delays (3, 0)
     ("branch3", 301, 5, 0),             # four branches, three adds, a rate excursion
     ("encoder", 128 * 40, 128 * 3, 0),  # strided encoder, buffers multiple of 128
+    ("outconv", 96, 3, 0),              # output conv (k5, d3, no tanh) fused into a window conv
+    ("outconv", 96, 3, 32),             # the same as its own launch
 ])
 def test_fp32_parity(name, frames, buf, options):
     sc = _sc()
@@ -207,8 +209,9 @@ def test_split_step_bitwise(prec):
     log("split steps: %d steps x %d streams bitwise equal (%s)" % (len(steps), S, prec))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_output_conv_fusion_matches(prec):
+@pytest.mark.parametrize("name,prec", [("rave_b", "fp32"), ("rave_b", "bf16"), ("rave_b", "fp8"),
+                                       ("outconv", "fp32"), ("outconv", "bf16")])
+def test_output_conv_fusion_matches(name, prec):
     """The decoder's one-channel output conv computed in the epilogue of the
     last window conv (plus the tail launch for frames whose taps cross a tile
     boundary, and the move of its input cache) matches its own launch: streams
@@ -219,18 +222,19 @@ def test_output_conv_fusion_matches(prec):
     a 224-term sum: 1e-5 absolute on outputs in (-1, 1), the FP32 bound
     against the oracle.  Masked frames are exact zeros in both."""
     sc = _sc()
-    m, w = weights_for("rave_b")
+    m, w = weights_for(name)
+    C = m["in_channels"]
     scales = None
     if prec == "fp8":
         from paper_2204_07064_amd import calibrate
-        scales = calibrate.act_scales(sc, m, w, [scgen.latents(16, 32, 1)])
+        scales = calibrate.act_scales(sc, m, w, [scgen.latents(C, 32, 1)])
     a = sc.Model(m, w, prec, act_scales=scales)
     b = sc.Model(m, w, prec, act_scales=scales, options=sc._native.SC_MODEL_NO_OUT_FUSION)
     S = 48
     rng = np.random.default_rng(33)
     steps = [[int(v) for v in rng.choice([1, 2, 3, 5, 8, 16, 32], size=S)] for _ in range(4)]
     steps.insert(1, [1] * S)                     # one tile per stream, below the split threshold
-    xs = [scgen.stream_latents(16, sum(st[i] for st in steps), 700 + i) for i in range(S)]
+    xs = [scgen.stream_latents(C, sum(st[i] for st in steps), 700 + i) for i in range(S)]
     sa = [sc.Stream(a, 32, warmup_mask=(i % 3 == 0)) for i in range(S)]
     sb = [sc.Stream(b, 32, warmup_mask=(i % 3 == 0)) for i in range(S)]
     pos = [0] * S
@@ -252,7 +256,7 @@ def test_output_conv_fusion_matches(prec):
     a.profile(True)
     for k in range(3):
         for i in range(0, S, 7):
-            x = torch.from_numpy(np.ascontiguousarray(scgen.stream_latents(16, 1, 900 + 10 * k + i))).cuda()
+            x = torch.from_numpy(np.ascontiguousarray(scgen.stream_latents(C, 1, 900 + 10 * k + i))).cuda()
             ya = sa[i].process(x)
             yb = sb[i].process(x)
             torch.cuda.synchronize()
@@ -262,8 +266,8 @@ def test_output_conv_fusion_matches(prec):
     impls = [p["impl"] for p in a.profile_read()]
     assert impls[-1] == 3 and impls[-2] == 2, impls   # the fused pair ran
     a.profile(False)
-    log("output conv fusion: %d steps x %d streams, max |fused - own launch| %.2e (%s)" % (
-        len(steps), S, worst, prec))
+    log("output conv fusion %s: %d steps x %d streams, max |fused - own launch| %.2e (%s)" % (
+        name, len(steps), S, worst, prec))
 
 
 @pytest.mark.parametrize("name,mult,prec", [("encoder", 128, "fp32"), ("encoder", 128, "bf16"),
