@@ -69,27 +69,27 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 b6b5f40ad78c9db2c381add1c455b24310a08d6b 9c5b01c64c454d87da90bad86645835e5fcdd2aa dca89fa298389451e6327df2b3e9eb87f3ba1764 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 3284f9bf6a2de745d504a9c52dbb9bada2690e3a 9c5b01c64c454d87da90bad86645835e5fcdd2aa dca89fa298389451e6327df2b3e9eb87f3ba1764 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 729.7, 2727.1),
-        2: ('mfma', 10430.2, 22176.8),
-        4: ('mfma', 10279.5, 21954.9),
-        6: ('mfma', 11267.3, 23075.3),
-        8: ('mfma', 14126.6, 12302.2),
-        9: ('mfma', 5216.6, 42261.6),
-        11: ('mfma', 17010.6, 39415.7),
-        13: ('mfma', 17506.0, 40072.4),
-        15: ('mfma', 18945.0, 14236.8),
-        16: ('mfma', 6179.9, 58171.2),
-        18: ('mfma_win', 22572.3, 55306.9),
-        20: ('mfma_win', 24043.6, 55354.4),
-        22: ('mfma_win', 28449.2, 22712.6),
-        23: ('mfma', 10974.4, 57389.9),
-        25: ('mfma_win', 22142.8, 55282.7),
-        27: ('mfma_win', 22871.7, 55764.0),
-        29: ('mfma_win', 25095.0, 3126.2),
+        1: ('mfma', 729.8, 2727.1),
+        2: ('mfma', 10430.2, 22167.3),
+        4: ('mfma', 10279.6, 21905.6),
+        6: ('mfma', 11267.4, 23060.8),
+        8: ('mfma', 14126.8, 12302.2),
+        9: ('mfma', 5216.6, 42259.0),
+        11: ('mfma', 17007.9, 39361.0),
+        13: ('mfma', 17508.2, 40081.0),
+        15: ('mfma', 18948.5, 14236.9),
+        16: ('mfma', 6179.9, 58201.0),
+        18: ('mfma_win', 22571.9, 55187.7),
+        20: ('mfma_win', 24040.6, 55307.7),
+        22: ('mfma_win', 28448.9, 22712.6),
+        23: ('mfma', 10974.4, 57292.8),
+        25: ('mfma_win', 22143.3, 55370.9),
+        27: ('mfma_win', 22872.1, 55588.2),
+        29: ('mfma_win', 25094.1, 3126.2),
         30: ('tail', 2106.1, 85.4),
     },
 }

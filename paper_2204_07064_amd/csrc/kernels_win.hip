@@ -130,13 +130,17 @@ struct WinSeg {
   int32_t base;           // first LDS row of this stream's rows
   int32_t rows;
   int32_t t_lo, t_hi;     // local output frames of the stream inside the tile
-  // fused output conv: the stream's frames in the step, its input cache
-  // (current and next copy), user output and warm-up mask bound
-  int32_t T;
+};
+
+// Per-stream part of a tile for a fused output conv (LDS): the stream's frames
+// in the step, the conv's input cache (current and next copy), the user
+// output and the conv's warm-up mask bound.
+struct WinSeg2 {
   const float* cache2;
   float* cache2_next;
   float* out2;
   int64_t mask2_x;
+  int32_t T;
 };
 
 // ---- fused one-output-channel conv (see conv_win_kernel) ----
@@ -168,13 +172,14 @@ __device__ inline bool out_tail_frame(int32_t f, int32_t out_start, int32_t f0, 
   return f - out_start < L || (out_start < f0 && f - L < f0);
 }
 
-// The epilogue of a window tile with a fused output conv.  w2s: the output
-// conv's weights [k][MT] (LDS).  Dynamic LDS (free once every wave is past
-// the K loop): per-wave channel partials [WM][kOutTaps][F].
+// The epilogue of a window tile with a fused output conv.  wa: the lane's
+// A operand (tap lr, channels m .. m + 3; zero beyond k).  Dynamic LDS (free
+// once every wave is past the K loop): per-wave channel partials
+// [WM][kOutTaps][F].
 template <int PREC, int MT, int NB, int F>
 __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int m, f4 bias, f4 wsc, int32_t f0,
-                                          const float* wskip, int skipf, const WinSeg* segs, const int8_t* colseg,
-                                          int n_seg, const float* w2s, unsigned char* lds) {
+                                          const float* wskip, int skipf, const WinSeg* segs, const WinSeg2* segs2,
+                                          const int8_t* colseg, int n_seg, f4 wa, unsigned char* lds) {
   constexpr int WM = MT / 16;
   constexpr int WN = 4 / WM;
   constexpr int KO = kOutTaps;
@@ -202,17 +207,15 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
   }
   __syncthreads();   // every wave is done with the staged rows and the skip rows
   float* X = reinterpret_cast<float*>(lds);   // [WM][KO][F]
-  // A operand: tap lr (zero beyond k), channels m .. m + 3, one per step
-  const f4 wa = lr < k2 ? *reinterpret_cast<const f4*>(w2s + lr * MT + m) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int col = wn * (F / WN) + nb * 16 + lr;
     const int s = colseg[col];
     if (s >= 0) {
       // the output conv's next cache: the stream's last L2 frames (raw)
-      const WinSeg& g = segs[s];
-      const int32_t i = f0 + col - g.out_start - (g.T - L2);
-      if (i >= 0) *reinterpret_cast<f4*>(g.cache2_next + (int64_t)i * MT + m) = v[nb];
+      const WinSeg2& g2 = segs2[s];
+      const int32_t i = f0 + col - segs[s].out_start - (g2.T - L2);
+      if (i >= 0) *reinterpret_cast<f4*>(g2.cache2_next + (int64_t)i * MT + m) = v[nb];
     }
     // the wave's 16 channels of the 16 columns: D[kk][col] = sum over them of
     // W[kk][c] * act(y[c][col]) on FP32 MFMA, the accumulator layout serving
@@ -231,13 +234,13 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
   // old cache rows that stay in the next cache of a stream of fewer than L2
   // frames (moved by the tile holding the stream's first frame)
   for (int s = 0; s < n_seg; ++s) {
-    const WinSeg& g = segs[s];
-    if (g.t_lo != 0 || g.T >= L2) continue;   // uniform
-    for (int j = tid; j < (L2 - g.T) * (MT / 4); j += kThreads) {
+    const WinSeg2& g2 = segs2[s];
+    if (segs[s].t_lo != 0 || g2.T >= L2) continue;   // uniform
+    for (int j = tid; j < (L2 - g2.T) * (MT / 4); j += kThreads) {
       const int i = j / (MT / 4);
       const int c = (j - i * (MT / 4)) * 4;
-      *reinterpret_cast<f4*>(g.cache2_next + (int64_t)i * MT + c) =
-          *reinterpret_cast<const f4*>(g.cache2 + (int64_t)(g.T + i) * MT + c);
+      *reinterpret_cast<f4*>(g2.cache2_next + (int64_t)i * MT + c) =
+          *reinterpret_cast<const f4*>(g2.cache2 + (int64_t)(g2.T + i) * MT + c);
     }
   }
   __syncthreads();
@@ -263,8 +266,8 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
         for (int kk = 0; kk < KO; ++kk)
           if (kk < k2) o = o + prow(col - L2 + d2 * kk, kk);
         if (a.oc.post_act == 2) o = tanhf(o);
-        if ((int64_t)t * a.out_den < g.mask2_x) o = 0.f;
-        g.out2[t] = o;
+        if ((int64_t)t * a.out_den < segs2[s].mask2_x) o = 0.f;
+        segs2[s].out2[t] = o;
       }
     }
   } else if (tid - F < F) {
@@ -287,7 +290,8 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
 //
 // LDS: the staged window rows in operand form (activated and rounded once,
 // row stride cin * ES + 16 bytes), then, for a fused residual, each column's
-// skip row as raw FP32 ([F][cin + 4]).
+// skip row as raw FP32 ([F][cin + 4]), then per staged row its source pointer
+// and skip slot.
 //
 // FUSE: a one-output-channel conv reading this layer's output (cout == MT, one
 // M tile) runs in the epilogue, which never writes the layer's output itself.
@@ -309,10 +313,10 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
+  __shared__ WinSeg2 segs2[FUSE ? kMaxStreams : 1];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
   __shared__ int32_t tile_info[4];   // e_first, n_seg, total rows, ok
-  __shared__ __attribute__((aligned(16))) float w2s[FUSE ? kOutTaps * MT : 4];   // fused output conv's weights
 
   const int tid = threadIdx.x;
   const int32_t n_tiles = n_mt * n_nt;
@@ -380,15 +384,12 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   const f4 bias = m_ok ? *reinterpret_cast<const f4*>(a.B + m) : f4{0.f, 0.f, 0.f, 0.f};
   const f4 wsc = (PREC == 2 && m_ok) ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
 
-  // fused output conv: its weights, loaded now and stored to LDS after the
-  // stream lookup (the load is in flight meanwhile)
-  float w2v[FUSE ? 2 : 1];
+  // fused output conv: the lane's A operand of its per-tap sums (tap lr,
+  // channels m .. m + 3), loaded now and held through the K loop
+  f4 wa2 = {0.f, 0.f, 0.f, 0.f};
   if constexpr (FUSE) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = tid + u * kThreads;
-      w2v[u] = q < a.oc.k * MT ? a.oc.W[q] : 0.f;
-    }
+    const int m2 = wm * 16 + lg * 4;
+    if (lr < a.oc.k) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * MT + m2);
   }
 
   // ---- the streams of the tile ----
@@ -416,21 +417,18 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     g.r0 = g.t_lo;
     g.rows = g.t_hi - g.t_lo + 1 + a.L;
     g.base = 0;
-    g.T = T;
-    if constexpr (FUSE) {
-      g.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
-      g.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
-      g.out2 = e.out;
-      g.mask2_x = (e.flags & SC_FLAG_WARMUP_MASK)
-                      ? a.oc.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
-                      : INT64_MIN;
-    }
     segs[tid] = g;
-  }
-  if constexpr (FUSE) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (tid + u * kThreads < kOutTaps * MT) w2s[tid + u * kThreads] = w2v[u];
+    if constexpr (FUSE) {
+      WinSeg2 g2;
+      g2.T = T;
+      g2.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
+      g2.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
+      g2.out2 = e.out;
+      g2.mask2_x = (e.flags & SC_FLAG_WARMUP_MASK)
+                       ? a.oc.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
+                       : INT64_MIN;
+      segs2[tid] = g2;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -552,7 +550,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   }
 
   if constexpr (FUSE) {
-    fused_out_epilogue<PREC, MT, NB, F>(a, acc, m, bias, wsc, f0, wskip, skipf, segs, colseg, n_seg, w2s, lds);
+    fused_out_epilogue<PREC, MT, NB, F>(a, acc, m, bias, wsc, f0, wskip, skipf, segs, segs2, colseg, n_seg, wa2, lds);
     return;
   }
 
