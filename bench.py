@@ -57,6 +57,10 @@ HEADLINE = Shape("rave_b", scgen.rave_decoder_b, N_STREAMS, BUF_CHOICES, LATENT,
 WIDE = Shape("wide", scgen.wide_decoder, 1024, range(1, 9), 128, 512)
 # the same decoder with 64 streams of fixed 16-frame (2048-sample) buffers
 FIXED16 = Shape("rave_b", scgen.rave_decoder_b, 64, (16,), LATENT, SPF)
+# audio in, audio out: the strided encoder feeding the decoder, 256 streams of
+# white-noise buffers of 128 x {1,2,4,8,16,32} samples (one output sample per
+# input sample)
+AUTOENC = Shape("autoencoder", scgen.autoencoder, N_STREAMS, tuple(128 * c for c in BUF_CHOICES), 1, 1)
 HBM_PEAK = 8.0e12  # B/s
 PEAK = {0: 157.3e12, 1: 2.5e15, 2: 5.0e15}          # FP32, BF16, FP8 dense
 PREC_NAME = {"fp32": 0, "bf16": 1, "fp8": 2}
@@ -700,6 +704,15 @@ def main():
         out["rave_b_64_streams_16_frame_buffers"] = {
             "samples_per_s": round(r16["samples"] / r16["gpu_s"], 1),
             "ms_per_step": round(r16["gpu_s"] * 1e3 / 20, 4), "precision": args.precision}
+        ma = AUTOENC.model_fn()
+        amod = sc.Model(ma, scgen.init_weights(ma), args.precision)
+        ra = timed_run(sc, torch, amod, 3, 20, shape=AUTOENC)
+        out["autoencoder_256_streams"] = {
+            "workload": "strided encoder (ratios 4,4,4,2 to 16 latent channels) feeding the decoder: 256 "
+                        "streams, white-noise buffers of 128 x {1,2,4,8,16,32} samples, closed loop",
+            "samples_per_s": round(ra["samples"] / ra["gpu_s"], 1),
+            "ms_per_step": round(ra["gpu_s"] * 1e3 / 20, 4), "precision": args.precision}
+        amod.close()
     if not args.no_serving:
         srv = serving_runs(sc, model)
         out["serving"] = srv

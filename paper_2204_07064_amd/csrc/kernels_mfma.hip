@@ -1,11 +1,12 @@
 // MFMA implicit-GEMM kernels for the wide layers (gfx950).
 //
-// A cached stride-1 conv is the GEMM  Out[n][m] = sum_kk A[m][kk] * B[kk][n]
+// A cached conv is the GEMM  Out[n][m] = sum_kk A[m][kk] * B[kk][n]
 // with m the output channel, n a frame of the step's packed frame space
 // (frames of all streams back to back, so one tile may span several
 // streams), and kk = tap * cin + ci.  Column n of B is gathered from the
-// window [cache | new frames] of n's stream: row t + dilation * tap, with
-// LeakyReLU and the operand rounding applied on the way into LDS.
+// window [cache | new frames] of n's stream: row t * stride + dilation * tap
+// for its local output frame t, with LeakyReLU and the operand rounding
+// applied on the way into LDS.
 //
 // A transposed conv with kernel 2r is, per input frame q, the GEMM row block
 // m = phi * cout + co over kk = h * cin + ci, where h = 0 reads frame q - 1
@@ -347,17 +348,17 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
   const unsigned char* pc_cache[B_PIECES];
   const unsigned char* pc_inb[B_PIECES];
   int64_t pc_in[B_PIECES];                   // convt: input element offset of the stream's frame 0
-  int32_t pc_t[B_PIECES];                    // conv: local output frame; convt: q
+  int32_t pc_t[B_PIECES];                    // conv: window row of tap 0 (t * stride); convt: q
   int32_t pc_lim[B_PIECES];                  // convt: input frames of the stream
   bool pc_ok[B_PIECES];                      // not a padding column
 #pragma unroll
   for (int p = 0; p < B_PIECES; ++p) {
     const ColInfo& cc = cols[my_col0 + p * (kThreads / PPCOL)];
     pc_ok[p] = cc.ei >= 0;
-    pc_t[p] = cc.t;
+    pc_t[p] = CONVT ? cc.t : cc.t * a.stride;   // conv: the window row of tap 0
     pc_lim[p] = cc.Tin;
     pc_in[p] = (int64_t)cc.in_start * a.cin;
-    const int64_t trow = (int64_t)cc.t * a.cin;
+    const int64_t trow = (int64_t)pc_t[p] * a.cin;
     pc_cache[p] = (INTWIN ? cc.tcache : reinterpret_cast<const unsigned char*>(cc.cache)) + trow * ES_B;
     pc_inb[p] = in_base + (((int64_t)cc.in_start - a.L) * a.cin + trow) * ES_B;
   }
@@ -612,10 +613,13 @@ hipError_t dispatch(const LayerArgs& a, int prec, int64_t n_cols, int Kpad, int 
 
 bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec) {
   (void)k;
-  // 16-byte operand pieces never straddle two taps: cin * element size % 16 == 0
+  // 16-byte operand pieces never straddle two taps: cin * element size % 16 == 0.
+  // Stride-1 convs narrower than 32 input channels stay on the wavefront
+  // kernels (measured faster there, and the decoder's 16-channel input conv
+  // must not round its input); strided ones have no fast wavefront form.
   const int es = esize(prec);
-  return stride == 1 && (cin * es) % 16 == 0 && cin % 8 == 0 && cout % 16 == 0 && cin >= 32 && cout >= 32 &&
-         prec >= 0 && prec <= 2;
+  return stride >= 1 && (cin * es) % 16 == 0 && cin % 8 == 0 && cout % 16 == 0 &&
+         cin >= (stride > 1 ? 16 : 32) && cout >= 16 && prec >= 0 && prec <= 2;
 }
 
 bool conv_mfma_fp32_input_supported(int cin, int cout, int k, int stride) {

@@ -260,38 +260,40 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
   stage_cache(a, cs, e_first, e_last, ld);
   __syncthreads();
-  for (int i = tid; i < F; i += kBlock) {
+  // one lane per (frame, output channel): consecutive lanes write consecutive
+  // channels of a frame
+  for (int idx = tid; idx < F * a.cout; idx += kBlock) {
+    const int i = (int)fdiv(a.fd_cout, (uint32_t)idx);
+    const int co = idx - i * a.cout;
     const FrameInfo f = fi[i];
     if (f.ei < 0) continue;
-    for (int co = 0; co < a.cout; ++co) {
-      float acc = a.B[co];
-      for (int kk = 0; kk < a.k; ++kk) {
-        const int w = f.t * S + a.dil * kk;       // window row
-        const float* wp = ws + kk * a.cin * a.cout + co;
-        if (w >= a.L) {
-          const float* x = xs + (i * S + a.dil * kk) * ld;
-          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
-        } else if (f.ei - e_first < kCacheSlots) {
-          const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
-          for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
-        } else {
-          const float* x = f.cache + (int64_t)w * a.cin;
-          for (int ci = 0; ci < a.cin; ++ci) {
-            float v = x[ci];
-            if (a.pre_act) v = lrelu(v);
-            acc = fmaf(wp[ci * a.cout], v, acc);
-          }
+    float acc = a.B[co];
+    for (int kk = 0; kk < a.k; ++kk) {
+      const int w = f.t * S + a.dil * kk;       // window row
+      const float* wp = ws + kk * a.cin * a.cout + co;
+      if (w >= a.L) {
+        const float* x = xs + (i * S + a.dil * kk) * ld;
+        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
+      } else if (f.ei - e_first < kCacheSlots) {
+        const float* x = cs + ((f.ei - e_first) * a.L + w) * ld;
+        for (int ci = 0; ci < a.cin; ++ci) acc = fmaf(wp[ci * a.cout], x[ci], acc);
+      } else {
+        const float* x = f.cache + (int64_t)w * a.cin;
+        for (int ci = 0; ci < a.cin; ++ci) {
+          float v = x[ci];
+          if (a.pre_act) v = lrelu(v);
+          acc = fmaf(wp[ci * a.cout], v, acc);
         }
       }
-      if (a.residual) acc = acc + skip_value(a, f, co);
-      if (a.post_act == 2) acc = tanhf(acc);
-      if (f.masked) acc = 0.f;
-      if (a.out_buf) {
-        a.out_buf[(n0 + i) * a.cout + co] = acc;
-        if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
-      } else {
-        f.out[(int64_t)co * f.tout] = acc;
-      }
+    }
+    if (a.residual) acc = acc + skip_value(a, f, co);
+    if (a.post_act == 2) acc = tanhf(acc);
+    if (f.masked) acc = 0.f;
+    if (a.out_buf) {
+      a.out_buf[(n0 + i) * a.cout + co] = acc;
+      if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
+    } else {
+      f.out[(int64_t)co * f.tout] = acc;
     }
   }
 }

@@ -718,7 +718,7 @@ hipError_t launch_conv_out_tail(const LayerArgs& a, int32_t tile_frames, hipStre
 }
 
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec) {
-  if (!conv_mfma_supported(cin, cout, k, stride, prec)) return 0;
+  if (stride != 1 || !conv_mfma_supported(cin, cout, k, stride, prec)) return 0;
   // up to 64 input channels: measured slower than the gathering kernel at 128
   // (32-frame tiles re-stage too large a halo per output)
   if (cin > 64 || cin % 16 != 0 || cout % 16 != 0 || min_frames < 1) return 0;

@@ -717,7 +717,9 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     const float* b = weights + op.b_off;
     bool mfma = false, fp32_input = false;
     if (!(options & SC_MODEL_NO_MFMA) && op.in_buf >= 0 && op.out_buf >= 0) {
-      if (op.kind == K_CONV) mfma = conv_mfma_supported(op.cin, op.cout, op.k, op.stride, prec_id);
+      // (a fused skip reads the window at the output rate: stride-1 convs only)
+      if (op.kind == K_CONV) mfma = conv_mfma_supported(op.cin, op.cout, op.k, op.stride, prec_id) &&
+                                    (op.stride == 1 || !op.residual);
       else mfma = convt_mfma_supported(op.cin, op.cout, op.stride, prec_id);
       // a narrow layer reading the model input (the latents) runs on FP32
       // MFMA in every precision: its input is never rounded

@@ -15,6 +15,8 @@ from .models import (  # noqa: F401
     strided_unit,
     branch_unit,
     encoder,
+    autoencoder,
+    outconv_unit,
     model_by_name,
     n_weights,
 )

@@ -155,6 +155,22 @@ def encoder(name="encoder", ratios=(4, 4, 4, 2), widths=(16, 32, 64, 128, 256), 
     return {"name": name, "nodes": nodes, "in_channels": 1, "out_channels": latent}
 
 
+def autoencoder():
+    """Audio in, audio out: the strided encoder (ratios 4,4,4,2 to 16 latent
+    channels) feeding the rave_b decoder (ratios 4,4,4,2 back to one channel);
+    input buffers are multiples of 128 samples."""
+    enc, dec = encoder(), rave_decoder_b()
+    base = len(enc["nodes"]) - 1   # the decoder's input is the encoder's output
+    nodes = [dict(n) for n in enc["nodes"]]
+    for n in dec["nodes"][1:]:
+        n = dict(n)
+        for key in ("src", "src2"):
+            if key in n:
+                n[key] = n[key] + base
+        nodes.append(n)
+    return {"name": "autoencoder", "nodes": nodes, "in_channels": 1, "out_channels": 1}
+
+
 def outconv_unit():
     """Input conv 8->64 (k3), a transposed conv 64->32 (ratio 32), one residual
     block x + Conv_k3,d3(LeakyReLU(x)) at 32 channels, then a one-channel
@@ -171,6 +187,7 @@ def outconv_unit():
 
 def model_by_name(name):
     table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder, "outconv": outconv_unit,
+             "autoencoder": autoencoder,
              "strided": lambda: strided_unit(False),
              "strided_aligned": lambda: strided_unit(True),
              "branch": branch_unit, "branch3": branch3_unit, "encoder": encoder}

@@ -37,6 +37,7 @@ def _need_gpu():
     ("branch", 300, 7, 0),              # Eq. 3 branch delays (3, 0)
     ("branch3", 301, 5, 0),             # four branches, three adds, a rate excursion
     ("encoder", 128 * 40, 128 * 3, 0),  # strided encoder, buffers multiple of 128
+    ("autoencoder", 128 * 24, 128 * 3, 0),  # strided encoder feeding the decoder, audio in and out
     ("outconv", 96, 3, 0),              # output conv (k5, d3, no tanh) fused into a window conv
     ("outconv", 96, 3, 32),             # the same as its own launch
 ])
@@ -271,6 +272,7 @@ def test_output_conv_fusion_matches(name, prec):
 
 
 @pytest.mark.parametrize("name,mult,prec", [("encoder", 128, "fp32"), ("encoder", 128, "bf16"),
+                                            ("autoencoder", 128, "bf16"),
                                             ("branch3", 1, "fp32"), ("strided", 2, "fp32")])
 def test_split_step_bitwise_other_models(name, mult, prec):
     """Split steps of the strided encoder (input frames a multiple of 128,

@@ -136,6 +136,21 @@ def test_single_stream_precision(prec):
         assert snr >= 15.0           # see test_fp8_snr_target for the 30 dB target
 
 
+def test_autoencoder_bf16_snr():
+    """Audio in, audio out (strided encoder feeding the decoder), BF16, one
+    stream of white noise in 128-sample multiples, against the FP64 oracle: the
+    encoder's strided and narrow layers run in FP32, the decoder's wide layers
+    on BF16 operands, so the BF16 SNR target applies to the whole path."""
+    sc = _sc()
+    m, w = weights_for("autoencoder")
+    mod = sc.Model(m, w, "bf16")
+    x = scgen.stream_latents(1, 128 * 48, 3)
+    s = run_stream(mod, x, [128 * k for k in (1, 4, 16, 2, 8, 1, 16)])
+    err, snr, _ = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
+    log("autoencoder bf16: vs oracle max-abs %.3e SNR %.2f dB" % (err, snr))
+    assert snr >= BF16_SNR
+
+
 def _one_layer_model(kind, c_in, c_out, dil=3, ratio=4):
     """identity k1 conv (FP32 wavefront, exact copy) -> layer under test (MFMA)
     -> identity k1 conv to the output (exact copy)."""
