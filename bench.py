@@ -73,27 +73,27 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "7f68300e73a228027e6620984e4e31a679719837 3284f9bf6a2de745d504a9c52dbb9bada2690e3a 9c5b01c64c454d87da90bad86645835e5fcdd2aa dca89fa298389451e6327df2b3e9eb87f3ba1764 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 0e938b832c7292671313d16cd376d76aa7c9dfba 68a968160e98c49ff56f018350b6d75000c4d00b dca89fa298389451e6327df2b3e9eb87f3ba1764 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
         1: ('mfma', 729.8, 2727.1),
-        2: ('mfma', 10430.2, 22167.3),
-        4: ('mfma', 10279.6, 21905.6),
-        6: ('mfma', 11267.4, 23060.8),
-        8: ('mfma', 14126.8, 12302.2),
-        9: ('mfma', 5216.6, 42259.0),
-        11: ('mfma', 17007.9, 39361.0),
-        13: ('mfma', 17508.2, 40081.0),
-        15: ('mfma', 18948.5, 14236.9),
-        16: ('mfma', 6179.9, 58201.0),
-        18: ('mfma_win', 22571.9, 55187.7),
-        20: ('mfma_win', 24040.6, 55307.7),
-        22: ('mfma_win', 28448.9, 22712.6),
-        23: ('mfma', 10974.4, 57292.8),
-        25: ('mfma_win', 22143.3, 55370.9),
-        27: ('mfma_win', 22872.1, 55588.2),
-        29: ('mfma_win', 25094.1, 3126.2),
+        2: ('mfma', 10430.2, 22178.0),
+        4: ('mfma', 10279.6, 21946.3),
+        6: ('mfma', 11267.3, 23085.9),
+        8: ('mfma', 14124.4, 12302.2),
+        9: ('mfma', 5216.6, 42255.4),
+        11: ('mfma', 17007.1, 39499.4),
+        13: ('mfma', 17502.6, 40170.2),
+        15: ('mfma', 18943.5, 14237.2),
+        16: ('mfma', 6177.9, 58174.5),
+        18: ('mfma_win', 22572.1, 55228.9),
+        20: ('mfma_win', 24042.2, 55260.2),
+        22: ('mfma_win', 28449.7, 22712.6),
+        23: ('mfma', 10972.4, 57560.1),
+        25: ('mfma_win', 22143.4, 55262.7),
+        27: ('mfma_win', 22872.2, 56043.0),
+        29: ('mfma_win', 25094.2, 3126.2),
         30: ('tail', 2106.1, 85.4),
     },
 }
