@@ -17,6 +17,7 @@ from .models import (  # noqa: F401
     encoder,
     autoencoder,
     outconv_unit,
+    outconv64_unit,
     model_by_name,
     n_weights,
 )

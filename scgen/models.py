@@ -185,9 +185,23 @@ def outconv_unit():
     return {"name": "outconv", "nodes": nodes, "in_channels": 8, "out_channels": 1}
 
 
+def outconv64_unit():
+    """Input conv 8->64 (k3), a transposed conv 64->64 (ratio 10), one residual
+    block x + Conv_k3,d1(LeakyReLU(x)) at 64 channels, then a one-channel
+    output conv Conv_k5,d3(LeakyReLU(x)) (padding 6/6) whose 12-frame cache is
+    longer than the 10 frames a 1-frame buffer brings it."""
+    nodes = [_input(8),
+             _conv(0, 8, 64, 3, 1),
+             _convt(1, 64, 64, 10),
+             _conv(2, 64, 64, 3, 1, pre_act=ACT_LRELU),
+             _add(2, 3),
+             _conv(4, 64, 1, 5, 3, pre_act=ACT_LRELU)]
+    return {"name": "outconv64", "nodes": nodes, "in_channels": 8, "out_channels": 1}
+
+
 def model_by_name(name):
     table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder, "outconv": outconv_unit,
-             "autoencoder": autoencoder,
+             "autoencoder": autoencoder, "outconv64": outconv64_unit,
              "strided": lambda: strided_unit(False),
              "strided_aligned": lambda: strided_unit(True),
              "branch": branch_unit, "branch3": branch3_unit, "encoder": encoder}

@@ -40,6 +40,8 @@ def _need_gpu():
     ("autoencoder", 128 * 24, 128 * 3, 0),  # strided encoder feeding the decoder, audio in and out
     ("outconv", 96, 3, 0),              # output conv (k5, d3, no tanh) fused into a window conv
     ("outconv", 96, 3, 32),             # the same as its own launch
+    ("outconv64", 60, 1, 0),            # 64-channel fused form; 10-frame buffers, 12-frame cache
+    ("outconv64", 97, 3, 0),
 ])
 def test_fp32_parity(name, frames, buf, options):
     sc = _sc()
@@ -211,7 +213,8 @@ def test_split_step_bitwise(prec):
 
 
 @pytest.mark.parametrize("name,prec", [("rave_b", "fp32"), ("rave_b", "bf16"), ("rave_b", "fp8"),
-                                       ("outconv", "fp32"), ("outconv", "bf16")])
+                                       ("outconv", "fp32"), ("outconv", "bf16"),
+                                       ("outconv64", "fp32"), ("outconv64", "bf16")])
 def test_output_conv_fusion_matches(name, prec):
     """The decoder's one-channel output conv computed in the epilogue of the
     last window conv (plus the tail launch for frames whose taps cross a tile

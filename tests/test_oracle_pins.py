@@ -149,7 +149,8 @@ def torch_forward(model, weights, x):
 
 
 @pytest.mark.parametrize("name,frames", [("stack3", 300), ("rave_b", 12), ("strided", 40),
-                                         ("branch", 50), ("branch3", 50), ("encoder", 256), ("outconv", 20)])
+                                         ("branch", 50), ("branch3", 50), ("encoder", 256), ("outconv", 20),
+                                         ("outconv64", 20)])
 def test_forward_vs_torch_graph(name, frames):
     m = scgen.model_by_name(name)
     w = scgen.init_weights(m, 0, "kaiming" if name == "stack3" else "calibrated")
