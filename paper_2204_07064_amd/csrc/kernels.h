@@ -12,7 +12,7 @@ namespace sc {
 // Arguments common to the conv-like kernels of one op in one step.
 struct LayerArgs {
   const Entry* ents;
-  const int32_t* fent;     // entry of every input frame of the step
+  const int32_t* fent;     // entry of every granule (input_multiple input frames) of the step
   const int32_t* hdr;      // device step header: [0] streams, [1] input frames of the step
   int32_t n_ent;           // host: upper bounds used to size grids (the header has the
                            // actual values, so a captured launch serves any smaller step)
@@ -26,7 +26,7 @@ struct LayerArgs {
   int32_t cin, cout, k, dil, stride, L, pre_act, post_act, residual, skip_off;
   int32_t A0, A1;
   uint32_t in_num, in_den, out_num, out_den;   // frames per input frame of input / output
-  FastDiv fd_in_num, fd_in_den, fd_out_num, fd_out_den, fd_cin, fd_cout;
+  FastDiv fd_in_num, fd_in_den, fd_out_num, fd_out_den, fd_cin, fd_cout;   // fd_*_num: by num * granule
   FastDiv fd_per_ent_narrow;   // L * cin
   int64_t delay;           // output lag (frames at the output rate) for the warm-up mask
   int64_t state_off, state_len, state_off2, state_len2;
@@ -61,7 +61,9 @@ __device__ inline int32_t step_frames(const LayerArgs& a) { return a.hdr[1]; }
 // frames of the input / output rate for x input frames of the step
 __device__ inline int32_t in_frames(const LayerArgs& a, int32_t x) { return (int32_t)fdiv(a.fd_in_den, (uint32_t)x * a.in_num); }
 __device__ inline int32_t out_frames(const LayerArgs& a, int32_t x) { return (int32_t)fdiv(a.fd_out_den, (uint32_t)x * a.out_num); }
-// stream (entry) of packed frame n at the input / output rate
+// stream (entry) of packed frame n at the input / output rate: the frame
+// table has one entry per granule of input frames (fd_*_num divide by the
+// rate's numerator times the granule)
 __device__ inline int entry_of_in(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_in_num, (uint32_t)n * a.in_den)]; }
 __device__ inline int entry_of_out(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_out_num, (uint32_t)n * a.out_den)]; }
 // warm-up mask of local output frame t of stream e: pos*num/den + t < delay,
@@ -78,7 +80,7 @@ int32_t narrow_conv_tile(int cin, int cout, int k, int dil, int stride, int L, i
 
 hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s);
 // Channel-major user inputs of a step -> packed channels-last [frame][C].
-hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, const int32_t* hdr, int32_t C,
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t granule, const int32_t* hdr, int32_t C,
                              int64_t max_frames, float* out, void* twin, int32_t twin_prec, int32_t twin_pre,
                              float twin_qs, hipStream_t s);
 hipError_t launch_convt_valu(const LayerArgs& a, hipStream_t s);

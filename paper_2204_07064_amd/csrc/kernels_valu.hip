@@ -472,15 +472,15 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
 
 // Channel-major user input [C][T] of every stream -> packed channels-last
 // [frame][C] for the step.
-__global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, const int32_t* hdr,
-                                                           int32_t C, float* out, void* twin, int32_t twin_prec,
-                                                           int32_t twin_pre, float twin_qs) {
+__global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, FastDiv fd_gran,
+                                                           const int32_t* hdr, int32_t C, float* out, void* twin,
+                                                           int32_t twin_prec, int32_t twin_pre, float twin_qs) {
   const int32_t n_frames = hdr[1];
   const int32_t total = n_frames * C;
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     const int c = idx / n_frames;   // frame fastest: coalesced reads of each channel row
     const int32_t f = idx - c * n_frames;
-    const Entry& e = ents[fent[f]];
+    const Entry& e = ents[fent[fdiv(fd_gran, (uint32_t)f)]];
     const float v = e.in[(int64_t)c * e.T + (f - e.off)];
     out[(int64_t)f * C + c] = v;
     if (twin) store_twin1(twin, (int64_t)f * C + c, twin_prec, twin_pre, twin_qs, v);
@@ -701,11 +701,11 @@ hipError_t launch_conv_valu(const LayerArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, const int32_t* hdr, int32_t C,
+hipError_t launch_pack_input(const Entry* ents, const int32_t* fent, int32_t granule, const int32_t* hdr, int32_t C,
                              int64_t max_frames, float* out, void* twin, int32_t twin_prec, int32_t twin_pre,
                              float twin_qs, hipStream_t s) {
-  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(max_frames * C)), dim3(kBlock), 0, s, ents, fent, hdr, C, out,
-                     twin, twin_prec, twin_pre, twin_qs);
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(max_frames * C)), dim3(kBlock), 0, s, ents, fent,
+                     make_fastdiv((uint32_t)std::max(granule, 1)), hdr, C, out, twin, twin_prec, twin_pre, twin_qs);
   return hipGetLastError();
 }
 

@@ -104,26 +104,29 @@ struct sc_stream {
 
 namespace sc {
 
-// Bytes of a step descriptor for n streams and `frames` input frames.
-inline size_t desc_bytes(int n, int64_t frames) {  // n: entry capacity
-  return kDescHeaderBytes + (size_t)n * sizeof(Entry) + (size_t)frames * sizeof(int32_t);
+// Bytes of a step descriptor for n streams and `frames` input frames; the
+// frame -> entry table has one entry per `granule` input frames (the model's
+// input multiple: every buffer is a whole number of granules).
+inline size_t desc_bytes(int n, int64_t frames, int64_t granule) {  // n: entry capacity
+  return kDescHeaderBytes + (size_t)n * sizeof(Entry) + (size_t)((frames + granule - 1) / granule) * sizeof(int32_t);
 }
 
 // Checks a step's arguments; sets *total to its input frames.  No stream state
 // changes (only the duplicate-check marks).
 sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                         const int32_t* n_frames, float* const* d_out, int64_t* total);
-// Writes the step descriptor (header, entries, frame -> entry) into `host`;
-// the frame table starts after `ent_capacity` entries (>= n).
+// Writes the step descriptor (header, entries, granule -> entry) into `host`;
+// the granule table starts after `ent_capacity` entries (>= n).
 void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* const* streams,
-                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total);
+                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total,
+                     int64_t granule);
 // Enqueues the step's kernels on hs reading the descriptor at `dev`; grids are
 // sized for grid_n streams and grid_frames input frames (>= the actual step).
 // Where a step of n streams splits into two halves that run at once: returns
 // the first half's stream count h (0: no split) and sets *f to its frames.
 int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t total, int64_t* f);
 // Byte offset of the second half's descriptor after the first half's.
-size_t split_desc_offset(int h, int64_t fa);
+size_t split_desc_offset(int h, int64_t fa, int64_t granule);
 // Launches a split step whose two descriptors are at dev and dev +
 // split_desc_offset: the first half on hs, the second on the model's side
 // stream, forked from hs and joined back into it.

@@ -164,9 +164,10 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.A0 = op.A0; a.A1 = op.A1;
   a.in_num = (uint32_t)op.in_rate.num; a.in_den = (uint32_t)op.in_rate.den;
   a.out_num = (uint32_t)op.out_rate.num; a.out_den = (uint32_t)op.out_rate.den;
-  a.fd_in_num = make_fastdiv(a.in_num);
+  // the step's frame table has one entry per input_multiple input frames
+  a.fd_in_num = make_fastdiv(a.in_num * (uint32_t)m->plan.input_multiple);
   a.fd_in_den = make_fastdiv(a.in_den);
-  a.fd_out_num = make_fastdiv(a.out_num);
+  a.fd_out_num = make_fastdiv(a.out_num * (uint32_t)m->plan.input_multiple);
   a.fd_out_den = make_fastdiv(a.out_den);
   a.fd_cin = make_fastdiv((uint32_t)std::max(op.cin, 1));
   a.fd_cout = make_fastdiv((uint32_t)std::max(op.cout, 1));
@@ -304,7 +305,8 @@ sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const flo
 }
 
 void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* const* streams,
-                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total) {
+                     const float* const* d_in, const int32_t* n_frames, float* const* d_out, int64_t total,
+                     int64_t granule) {
   int32_t* hhdr = reinterpret_cast<int32_t*>(host);
   hhdr[0] = n;
   hhdr[1] = (int32_t)total;
@@ -321,7 +323,7 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
     en.parity = streams[i]->parity;
     en.flags = (int32_t)streams[i]->flags;
     en.pos = streams[i]->pos;
-    for (int32_t f = 0; f < n_frames[i]; ++f) hfent[off + f] = i;
+    for (int32_t f = 0; f < n_frames[i]; f += (int32_t)granule) hfent[(off + f) / granule] = i;
     off += n_frames[i];
   }
 }
@@ -355,7 +357,8 @@ LaunchSet launch_set(const unsigned char* dev, int grid_n, int64_t grid_frames, 
 hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
   const Plan& pl = m->plan;
   if (pl.input_buf < 0) return hipSuccess;
-  return launch_pack_input(ls.ents, ls.fent, ls.hdr, pl.in_channels, ls.grid_frames, ws_at(m, pl.input_buf, ls.base),
+  return launch_pack_input(ls.ents, ls.fent, pl.input_multiple, ls.hdr, pl.in_channels, ls.grid_frames,
+                           ws_at(m, pl.input_buf, ls.base),
                            tw_at(m, pl.input_twin, ls.base), m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2),
                            pl.input_twin_pre, twin_scale(m, pl.input_twin_layer), ls.hs);
 }
@@ -440,7 +443,7 @@ int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t tota
   return h;
 }
 
-size_t split_desc_offset(int h, int64_t fa) { return (desc_bytes(h, fa) + 255) / 256 * 256; }
+size_t split_desc_offset(int h, int64_t fa, int64_t granule) { return (desc_bytes(h, fa, granule) + 255) / 256 * 256; }
 
 hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, int64_t fa, int64_t total,
                          hipStream_t hs) {
@@ -456,7 +459,7 @@ hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, in
   e = hipEventRecord(m->fork_ev, hs);
   if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
   const LaunchSet la = launch_set(dev, h, fa, hs, 0);
-  const LaunchSet lb = launch_set(dev + split_desc_offset(h, fa), n - h, total - fa, m->side, fa);
+  const LaunchSet lb = launch_set(dev + split_desc_offset(h, fa, m->plan.input_multiple), n - h, total - fa, m->side, fa);
   if (e == hipSuccess) e = launch_pack(m, la);
   if (e == hipSuccess) e = launch_pack(m, lb);
   for (size_t oi = 0; e == hipSuccess && oi < m->plan.ops.size(); ++oi) {
@@ -491,7 +494,7 @@ sc_status ensure_graph(sc_model* m) {
     hipGraphExecDestroy(m->graph_exec);
     m->graph_exec = nullptr;
   }
-  const size_t bytes = desc_bytes(m->graph_streams, m->ws_cap);
+  const size_t bytes = desc_bytes(m->graph_streams, m->ws_cap, m->plan.input_multiple);
   if (m->graph_desc_bytes < bytes) {
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -552,8 +555,9 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     slot.pending = false;
   }
   // a split step's two descriptors sit one after the other in the slot
-  const size_t off_b = h ? split_desc_offset(h, fa) : 0;
-  const size_t need = h ? off_b + desc_bytes(n - h, total - fa) : desc_bytes(cap, total);
+  const int64_t gr = m->plan.input_multiple;
+  const size_t off_b = h ? split_desc_offset(h, fa, gr) : 0;
+  const size_t need = h ? off_b + desc_bytes(n - h, total - fa, gr) : desc_bytes(cap, total, gr);
   if (slot.cap < need) {
     if (slot.host) hipHostFree(slot.host);
     if (slot.dev) hipFree(slot.dev);
@@ -579,10 +583,10 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   }
   if (h) {
-    fill_descriptor(slot.host, h, h, streams, d_in, n_frames, d_out, fa);
-    fill_descriptor(slot.host + off_b, n - h, n - h, streams + h, d_in + h, n_frames + h, d_out + h, total - fa);
+    fill_descriptor(slot.host, h, h, streams, d_in, n_frames, d_out, fa, gr);
+    fill_descriptor(slot.host + off_b, n - h, n - h, streams + h, d_in + h, n_frames + h, d_out + h, total - fa, gr);
   } else {
-    fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total);
+    fill_descriptor(slot.host, n, cap, streams, d_in, n_frames, d_out, total, gr);
   }
   if (graph) {
     st = ensure_graph(m);

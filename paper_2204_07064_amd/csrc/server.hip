@@ -305,15 +305,16 @@ void worker_main(sc_server* srv) {
     const int h = choose_split(srv->m, n, nf.data(), total, &fa);
     const int cap = (srv->cfg.use_graph && !h) ? srv->cfg.max_streams : n;
     size_t desc_need;
+    const int64_t gr = srv->m->plan.input_multiple;
     if (h) {
-      const size_t off_b = split_desc_offset(h, fa);
-      fill_descriptor(c.desc_host, h, h, ss.data(), din.data(), nf.data(), dout.data(), fa);
+      const size_t off_b = split_desc_offset(h, fa, gr);
+      fill_descriptor(c.desc_host, h, h, ss.data(), din.data(), nf.data(), dout.data(), fa, gr);
       fill_descriptor(c.desc_host + off_b, n - h, n - h, ss.data() + h, din.data() + h, nf.data() + h,
-                      dout.data() + h, total - fa);
-      desc_need = off_b + desc_bytes(n - h, total - fa);
+                      dout.data() + h, total - fa, gr);
+      desc_need = off_b + desc_bytes(n - h, total - fa, gr);
     } else {
-      fill_descriptor(c.desc_host, n, cap, ss.data(), din.data(), nf.data(), dout.data(), total);
-      desc_need = desc_bytes(cap, total);
+      fill_descriptor(c.desc_host, n, cap, ss.data(), din.data(), nf.data(), dout.data(), total, gr);
+      desc_need = desc_bytes(cap, total, gr);
     }
     c.parts = std::move(parts);
     c.out_floats = out_off;
@@ -374,7 +375,7 @@ void unpin(sc_server* srv) {
 sc_status alloc_ctx(sc_server* srv, StepCtx& c) {
   const int64_t in_f = srv->max_frames * srv->cin;
   const int64_t out_f = out_frames_of(srv, srv->max_frames) * srv->cout;
-  const size_t db = desc_bytes(srv->cfg.max_streams, srv->max_frames) + kSplitSlack;
+  const size_t db = desc_bytes(srv->cfg.max_streams, srv->max_frames, srv->m->plan.input_multiple) + kSplitSlack;
   // descriptor and input staging: coherent, read by the upload kernel
   const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent;
   void* dh = nullptr;
@@ -472,7 +473,8 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   for (const auto& b : m->plan.buf_floats) ws += b.of(m->ws_cap) * 4;
   for (const auto& t : m->plan.twin_elems) ws += t.of(m->ws_cap) * m->tw_esize;
   const int64_t staging = kCtx * ((srv->max_frames * srv->cin + out_frames_of(srv.get(), srv->max_frames) * srv->cout) *
-                                       4 + (int64_t)(desc_bytes(cfg->max_streams, srv->max_frames) + kSplitSlack));
+                                       4 + (int64_t)(desc_bytes(cfg->max_streams, srv->max_frames,
+                                                                m->plan.input_multiple) + kSplitSlack));
   srv->fixed_bytes = ws + staging;
   srv->per_stream_bytes = std::max<int64_t>(m->plan.state_alloc_floats, 1) * 4;
   int64_t fit = cfg->max_streams;
