@@ -100,6 +100,29 @@ def test_served_split_steps_equal_alone(prec):
         assert np.array_equal(outs[i], alone), i
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_served_audio_model_equals_alone(use_graph):
+    """Audio in, audio out (the strided encoder feeding the decoder) through
+    the server: buffers are whole 128-sample granules of the step's frame
+    table, queued buffers merge, steps of 32+ streams split; every stream's
+    output equals its solo run bit for bit."""
+    sc = _sc()
+    m, w = weights_for("autoencoder")
+    mod = sc.Model(m, w, "bf16")
+    rng = np.random.default_rng(23)
+    S, B = 40, 3
+    lens = [[128 * int(v) for v in rng.integers(1, 9, size=B)] for _ in range(S)]
+    xs = [scgen.stream_latents(1, int(sum(l)), 800 + i) for i, l in enumerate(lens)]
+    order = [(i, b) for b in range(B) for i in range(S)]
+    outs, lat, st = _serve(sc, mod, lens, xs, order, use_graph, max_buf=128 * 16)
+    log("audio model serving (graph %s): steps %d buffers %d merged %d"
+        % (use_graph, st["steps"], st["buffers"], st["merged_buffers"]))
+    assert st["buffers"] == S * B
+    for i in range(S):
+        alone = run_stream(mod, xs[i], lens[i])
+        assert np.array_equal(outs[i], alone), i
+
+
 def test_graph_replays_equal_eager():
     sc = _sc()
     m, w = weights_for("rave_b")
