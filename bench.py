@@ -620,6 +620,10 @@ def main():
                     help="replay one captured graph per step (measured slower than one-by-one launches here)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--workload", default="decoder", choices=["decoder", "audio"],
+                    help="decoder: the headline 256-stream decoder mix; audio: the strided encoder feeding "
+                         "the decoder, 256 streams of 128 x {1..32}-sample buffers (its own JSON line, "
+                         "for profiling; no extra, serving or CPU sections)")
     ap.add_argument("--summarize", metavar="DIR", help="print per-layer figures from rocprofv3 CSVs under DIR")
     ap.add_argument("--summarize-copy", metavar="DIR", help="print the copy-probe counter factors under DIR")
     args = ap.parse_args()
@@ -644,7 +648,10 @@ def main():
         return
     import paper_2204_07064_amd as sc
 
-    m = scgen.rave_decoder_b()
+    shape = AUTOENC if args.workload == "audio" else HEADLINE
+    if args.workload == "audio":
+        args.no_extra = args.no_serving = args.no_cpu_baseline = True
+    m = shape.model_fn()
     w = scgen.init_weights(m)
 
     options = sc._native.SC_MODEL_NO_SPLIT if args.no_split else 0
@@ -652,12 +659,12 @@ def main():
     def make(prec):
         scales = None
         if prec == "fp8":
-            scales = calibrate(sc, torch, m, w)
+            scales = calibrate(sc, torch, m, w, frames=64 * sc.plan(m)["input_multiple"], latent=shape.latent)
         return sc.Model(m, w, prec, act_scales=scales, options=options)
 
     model = make(args.precision)
-    run = timed_run(sc, torch, model, args.warmup, args.steps, graph=args.graph)
-    prof_run = timed_run(sc, torch, model, args.warmup, args.steps, profile=True)
+    run = timed_run(sc, torch, model, args.warmup, args.steps, graph=args.graph, shape=shape)
+    prof_run = timed_run(sc, torch, model, args.warmup, args.steps, profile=True, shape=shape)
     prof = prof_run["prof"]
     used = sorted({p["precision"] for p in prof if p["impl"] >= 1})
     value = run["samples"] / run["gpu_s"]
@@ -670,10 +677,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[max(used)] if used else "fp32",
         "data": "synthetic",
-        "config": {"workload": "rave_b decoder serving mix: 256 streams, buffers uniform over "
-                               "{1,2,4,8,16,32} latent frames, closed loop",
+        "config": {"workload": ("rave_b decoder serving mix: 256 streams, buffers uniform over "
+                                "{1,2,4,8,16,32} latent frames, closed loop") if shape is HEADLINE else
+                               ("strided encoder feeding the rave_b decoder: 256 streams, white-noise buffers "
+                                "of 128 x {1,2,4,8,16,32} samples, closed loop"),
                    "streams": N_STREAMS, "precision": args.precision,
-                   "mean_buffer_frames": float(np.mean(BUF_CHOICES))},
+                   "mean_buffer_frames": float(np.mean(shape.choices))},
         "step_ms": {"p50": round(float(np.percentile(run["step_ms"], 50)), 4),
                     "p99": round(float(np.percentile(run["step_ms"], 99)), 4)},
         "rtf": round(1.0 / (value / N_STREAMS / 44100.0), 6),
@@ -687,7 +696,7 @@ def main():
     for prec in [c for c in args.compare.split(",") if c and c != args.precision]:
         try:
             mod2 = make(prec)
-            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4), graph=args.graph)
+            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4), graph=args.graph, shape=shape)
             comp[prec] = round(r2["samples"] / r2["gpu_s"], 1)
             mod2.close()
         except Exception as e:  # report, do not hide
