@@ -260,6 +260,52 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
   stage_rows(a, xs, (int64_t)n0 * S - a.L, rows, ld);
   stage_cache(a, cs, e_first, e_last, ld);
   __syncthreads();
+  if (a.out_buf && (a.cout & 3) == 0) {
+    // one lane per (frame, 4 output channels): each output summed as below,
+    // one 16-byte store (and one twin store) per lane
+    const int c4 = a.cout >> 2;
+    for (int idx = tid; idx < F * c4; idx += kBlock) {
+      const int i = idx / c4;
+      const int co = (idx - i * c4) * 4;
+      const FrameInfo f = fi[i];
+      if (f.ei < 0) continue;
+      float acc[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = a.B[co + j];
+      for (int kk = 0; kk < a.k; ++kk) {
+        const int w = f.t * S + a.dil * kk;       // window row
+        const float* wp = ws + kk * a.cin * a.cout + co;
+        const float* x = nullptr;
+        if (w >= a.L) x = xs + (i * S + a.dil * kk) * ld;
+        else if (f.ei - e_first < kCacheSlots) x = cs + ((f.ei - e_first) * a.L + w) * ld;
+        if (x) {
+          for (int ci = 0; ci < a.cin; ++ci) {
+            const float xv = x[ci];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = fmaf(wp[ci * a.cout + j], xv, acc[j]);
+          }
+        } else {
+          const float* xg = f.cache + (int64_t)w * a.cin;
+          for (int ci = 0; ci < a.cin; ++ci) {
+            float v = xg[ci];
+            if (a.pre_act) v = lrelu(v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = fmaf(wp[ci * a.cout + j], v, acc[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (a.residual) acc[j] = acc[j] + skip_value(a, f, co + j);
+        if (a.post_act == 2) acc[j] = tanhf(acc[j]);
+        if (f.masked) acc[j] = 0.f;
+      }
+      const int64_t o = (int64_t)(n0 + i) * a.cout + co;
+      *reinterpret_cast<f4v*>(a.out_buf + o) = f4v{acc[0], acc[1], acc[2], acc[3]};
+      if (a.out_twin) store_twin4v(a.out_twin, o, a.twin_prec, a.twin_pre, a.twin_qs, acc[0], acc[1], acc[2], acc[3]);
+    }
+    return;
+  }
   // one lane per (frame, output channel): consecutive lanes write consecutive
   // channels of a frame
   for (int idx = tid; idx < F * a.cout; idx += kBlock) {

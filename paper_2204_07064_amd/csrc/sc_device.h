@@ -73,4 +73,31 @@ __device__ inline void store_twin1(void* base, int64_t idx, int prec, int pre, f
   }
 }
 
+// store_twin1 for 4 consecutive elements (idx a multiple of 4): the same
+// conversions, one 16-, 8- or 4-byte store.
+__device__ inline void store_twin4v(void* base, int64_t idx, int prec, int pre, float qs, float v0, float v1,
+                                    float v2, float v3) {
+  if (pre) {
+    v0 = lrelu(v0);
+    v1 = lrelu(v1);
+    v2 = lrelu(v2);
+    v3 = lrelu(v3);
+  }
+  v0 *= qs;
+  v1 *= qs;
+  v2 *= qs;
+  v3 *= qs;
+  if (prec == 0) {
+    typedef float f4t __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<f4t*>(static_cast<float*>(base) + idx) = f4t{v0, v1, v2, v3};
+  } else if (prec == 1) {
+    typedef __bf16 b4t __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<b4t*>(static_cast<__bf16*>(base) + idx) = b4t{(__bf16)v0, (__bf16)v1, (__bf16)v2, (__bf16)v3};
+  } else {
+    int q = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v0), sat448(v1), 0, false);
+    q = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v2), sat448(v3), q, true);
+    *reinterpret_cast<int*>(static_cast<unsigned char*>(base) + idx) = q;
+  }
+}
+
 }  // namespace sc
