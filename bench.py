@@ -73,27 +73,27 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 0e938b832c7292671313d16cd376d76aa7c9dfba d01eb5093f571ed2a64ac22cfe26de3320ec1729 cdb092dafb0e9fcf0efe9c95bda3e3e2909a7835 1012680b31a1ca9d94ad10f83a611fd69b3a3a5c",
+    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 0e938b832c7292671313d16cd376d76aa7c9dfba 32aa2b2fa22617686caf5b6167557e40417b7f38 cdb092dafb0e9fcf0efe9c95bda3e3e2909a7835 a31fae0a8968db259d99c989d275544815c52b43",
     "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 729.7, 2727.1),
-        2: ('mfma', 10430.2, 22175.1),
-        4: ('mfma', 10279.6, 21945.9),
-        6: ('mfma', 11267.3, 23055.6),
-        8: ('mfma', 14123.2, 12302.2),
-        9: ('mfma', 5216.6, 42228.6),
-        11: ('mfma', 17008.7, 39504.9),
-        13: ('mfma', 17506.1, 40170.8),
-        15: ('mfma', 18948.6, 14237.0),
-        16: ('mfma', 6177.9, 58173.3),
-        18: ('mfma_win', 22571.9, 55422.5),
-        20: ('mfma_win', 24040.4, 55235.3),
-        22: ('mfma_win', 28449.5, 22712.6),
-        23: ('mfma', 10972.4, 57574.9),
-        25: ('mfma_win', 22143.3, 55403.9),
-        27: ('mfma_win', 22872.2, 56037.3),
-        29: ('mfma_win', 25094.2, 3126.2),
+        1: ('mfma', 729.8, 2727.1),
+        2: ('mfma', 10430.1, 22165.1),
+        4: ('mfma', 10279.7, 21944.0),
+        6: ('mfma', 11267.2, 23072.6),
+        8: ('mfma', 14124.1, 12302.2),
+        9: ('mfma', 5216.6, 42244.8),
+        11: ('mfma', 17008.7, 39499.5),
+        13: ('mfma', 17509.7, 40170.6),
+        15: ('mfma', 18951.3, 14237.1),
+        16: ('mfma', 6177.9, 58137.7),
+        18: ('mfma_win', 22572.0, 55181.1),
+        20: ('mfma_win', 24040.8, 55240.7),
+        22: ('mfma_win', 28450.6, 22712.6),
+        23: ('mfma', 10972.4, 57425.9),
+        25: ('mfma_win', 22143.4, 55617.7),
+        27: ('mfma_win', 22872.1, 55922.3),
+        29: ('mfma_win', 25093.9, 3126.2),
         30: ('tail', 2106.1, 85.4),
     },
 }
