@@ -61,3 +61,35 @@ def test_enum_constants_match_header():
     # option bits are distinct powers of two
     opts = [h[k] for k in h if k.startswith("SC_MODEL_NO_")]
     assert len(set(opts)) == len(opts) and all(o & (o - 1) == 0 for o in opts)
+
+
+def _prototypes():
+    """name -> (return type text, parameter count) of every function the header declares."""
+    text = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)
+    protos = {}
+    for m in re.finditer(r"([A-Za-z_][A-Za-z0-9_ \*]*?)\b([a-z_][a-z0-9_]*)\s*\(([^;{]*?)\)\s*;", text):
+        ret, name, params = m.group(1).strip(), m.group(2), m.group(3).strip()
+        if name not in n.EXPORTS:
+            continue
+        count = 0 if params in ("", "void") else params.count(",") + 1
+        protos[name] = (ret, count)
+    return protos
+
+
+def test_function_signatures_match_header():
+    protos = _prototypes()
+    L = n.lib() if os.path.exists(n.LIB_PATH) else None
+    if L is None:
+        pytest.skip("library not built")
+    assert sorted(protos) == sorted(n.EXPORTS)
+    for name, (ret, count) in protos.items():
+        f = getattr(L, name)
+        assert len(f.argtypes) == count, (name, count, f.argtypes)
+        if ret.endswith("void") and "*" not in ret:
+            assert f.restype is None, name
+        elif ret == "sc_status" or ret.endswith("int32_t"):
+            assert f.restype is ctypes.c_int32, name
+        elif ret.endswith("int64_t"):
+            assert f.restype is ctypes.c_int64, name
+        elif "char" in ret:
+            assert f.restype is ctypes.c_char_p, name
