@@ -151,6 +151,24 @@ enum {
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,
                           uint32_t options, int32_t device, sc_model** out);
+/* sc_model_create with a precision per layer: `layer_precision` is a host
+ * array of sc_model_n_layers values (sc_precision, one per CONV/CONVT node in
+ * node order) giving the operand type of that layer's convolution; each
+ * producer writes the copy of its output that a reduced-precision reader
+ * takes in that reader's type.  Caches, carries, the residual stream and all
+ * accumulation stay FP32 in every layer.  A layer that runs on FP32 wavefront
+ * FMA in every precision (too few channels, the model input, the model
+ * output) stays FP32 whatever its entry.  act_scales as for sc_model_create;
+ * they are used by the FP8 layers only.  This is the mixed-precision form of
+ * the reduced-precision path: with e4m3's three mantissa bits, one rounding
+ * of a full-width layer costs ~28 dB of SNR, so a target above that over
+ * many layers in series is met by putting only some layers on FP8.
+ * Errors: as sc_model_create; SC_EINVAL also for a null array or an unknown
+ * precision in it. */
+sc_status sc_model_create_mixed(const sc_node* nodes, int32_t n_nodes, const float* weights,
+                                size_t n_weights, const int32_t* layer_precision,
+                                const float* act_scales, uint32_t options, int32_t device,
+                                sc_model** out);
 sc_status sc_model_info_get(const sc_model* model, sc_model_info* out);
 /* Number of CONV/CONVT nodes (the length of an act_scales array). */
 int32_t sc_model_n_layers(const sc_model* model);
@@ -171,7 +189,9 @@ sc_status sc_model_reserve(sc_model* model, int64_t max_step_frames);
  * launch one by one.  Errors: SC_EINVAL. */
 sc_status sc_model_enable_graph(sc_model* model, int32_t max_streams);
 /* Replace the static FP8 activation scales (host array, sc_model_n_layers
- * values).  Only between processing calls. */
+ * values).  Only between processing calls.  Errors: SC_EINVAL (a scale not
+ * positive and finite), SC_ESTATE (a server that replays captured step graphs
+ * uses the model: they hold the old scales). */
 sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);
 /* Record, for every CONV/CONVT node, max |pre_act(input)| over all frames
  * processed by `model` (an SC_FP32 model) since the last call with reset=1,
@@ -179,6 +199,15 @@ sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);
  * the model's device work. */
 sc_status sc_model_read_amax(sc_model* model, float* amax_out, int32_t reset);
 sc_status sc_model_enable_amax(sc_model* model, int32_t enable);
+/* The static FP8 activation scales calibrated from the maxima recorded so
+ * far (as sc_model_read_amax, without reset): for each layer, 1.25 x its
+ * max |pre_act(input)| (a margin against peaks the calibration inputs did not
+ * reach), at least 1e-6.  Writes sc_model_n_layers values to the host array
+ * `scales_out`, ready for sc_model_create's act_scales.  A scale is fixed
+ * before streaming starts: a per-buffer scale would make the output depend
+ * on how the input is split into buffers.  Synchronizes the model's device
+ * work.  Errors: SC_EINVAL, SC_EDEVICE. */
+sc_status sc_model_calibrated_scales(sc_model* model, float* scales_out);
 /* Releases the caller's reference.  The model's memory is freed once its
  * last stream has been destroyed as well. */
 void sc_model_destroy(sc_model* model);
@@ -311,9 +340,14 @@ sc_status sc_server_submit_batch(sc_server* server, int32_t n, const int64_t* st
  * (seconds from submission to completion) and sets *n to their number. */
 sc_status sc_server_latencies(sc_server* server, int64_t* tickets, double* latency_s, int64_t max, int64_t* n);
 /* SC_OK: done -- copies the output ([out_channels][n_frames * out_num / out_den])
- * to host_out (may be NULL) and the submit-to-completion latency in seconds
- * to *latency_s (may be NULL), and forgets the ticket.  SC_PENDING: not yet. */
-sc_status sc_server_poll(sc_server* server, int64_t ticket, float* host_out, double* latency_s);
+ * to host_out (may be NULL; it holds out_capacity floats) and the
+ * submit-to-completion latency in seconds to *latency_s (may be NULL), and
+ * forgets the ticket.  SC_PENDING: not yet.  SC_EINVAL: unknown ticket, or
+ * host_out holds fewer floats than the output (the ticket is kept).
+ * SC_EDEVICE: the buffer's step failed, or its stream saw a failed step
+ * before it (the ticket is forgotten). */
+sc_status sc_server_poll(sc_server* server, int64_t ticket, float* host_out, int64_t out_capacity,
+                         double* latency_s);
 /* No more buffers for this stream: its slot is freed once its queued buffers
  * are done (a later submit with the same id opens a new stream). */
 sc_status sc_server_close_stream(sc_server* server, int64_t stream_id);

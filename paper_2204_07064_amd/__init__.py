@@ -37,6 +37,20 @@ def _stream_handle(hip_stream):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _check_device_buffer(t, channels, what, frames=None):
+    """A device tensor the library reads or writes through a raw pointer:
+    CUDA (HIP) float32, contiguous, [channels][>= frames]."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % what)
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("%s must be contiguous float32" % what)
+    if t.dim() != 2 or t.shape[0] != channels:
+        raise ValueError("%s must be [%d][frames], got %s" % (what, channels, tuple(t.shape)))
+    if frames is not None and t.shape[1] < frames:
+        raise ValueError("%s must hold at least %d frames, got %d" % (what, frames, t.shape[1]))
+
+
 def plan(model):
     """Host-only planning (no GPU): latency, warm-up window, state bytes..."""
     arr = nodes_array(model)
@@ -46,7 +60,11 @@ def plan(model):
 
 
 class Model:
-    def __init__(self, model, weights, precision="fp32", act_scales=None, options=0, device=0):
+    def __init__(self, model, weights, precision="fp32", act_scales=None, options=0, device=0,
+                 layer_precision=None):
+        """layer_precision: optional list of "fp32" / "bf16" / "fp8", one per
+        conv / transposed conv in node order (sc_model_create_mixed); then
+        `precision` is ignored and reported as the lowest one used."""
         L = lib()
         self.spec = model
         arr = nodes_array(model)
@@ -55,12 +73,19 @@ class Model:
         sc = None
         if act_scales is not None:
             sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
+        scp = sc.ctypes.data_as(_native.c_fp) if sc is not None else None
         h = ctypes.c_void_p()
-        check(L.sc_model_create(arr, len(arr), w.ctypes.data_as(_native.c_fp), w.size,
-                                _native.PRECISION[precision],
-                                sc.ctypes.data_as(_native.c_fp) if sc is not None else None,
-                                int(options), int(device), ctypes.byref(h)))
+        if layer_precision is None:
+            check(L.sc_model_create(arr, len(arr), w.ctypes.data_as(_native.c_fp), w.size,
+                                    _native.PRECISION[precision], scp, int(options), int(device),
+                                    ctypes.byref(h)))
+        else:
+            lp = (ctypes.c_int32 * max(len(layer_precision), 1))(*[_native.PRECISION[p] for p in layer_precision])
+            check(L.sc_model_create_mixed(arr, len(arr), w.ctypes.data_as(_native.c_fp), w.size, lp, scp,
+                                          int(options), int(device), ctypes.byref(h)))
+            precision = max(layer_precision, key=lambda p: _native.PRECISION[p]) if layer_precision else "fp32"
         self.handle = h
+        self.layer_precision = None if layer_precision is None else list(layer_precision)
         self.precision = precision
         self.device = device
         info = _native.ScModelInfo()
@@ -90,6 +115,13 @@ class Model:
     def read_amax(self, reset=False):
         out = np.zeros(max(self.n_layers, 1), np.float32)
         check(lib().sc_model_read_amax(self.handle, out.ctypes.data_as(_native.c_fp), int(bool(reset))))
+        return out[:self.n_layers]
+
+    def calibrated_scales(self):
+        """Static FP8 activation scales from the maxima recorded so far
+        (sc_model_calibrated_scales)."""
+        out = np.zeros(max(self.n_layers, 1), np.float32)
+        check(lib().sc_model_calibrated_scales(self.handle, out.ctypes.data_as(_native.c_fp)))
         return out[:self.n_layers]
 
     def profile(self, enable=True):
@@ -135,13 +167,16 @@ class Stream:
     def process_into(self, x, out, n_frames=None, hip_stream=None):
         """x: cuda float32 [C_in][T]; out: cuda float32 [C_out][T_out]."""
         T = int(x.shape[-1]) if n_frames is None else int(n_frames)
+        info = self.model.info
+        _check_device_buffer(x, info["in_channels"], "input", T)
+        _check_device_buffer(out, info["out_channels"], "output", self.model.out_frames(T))
         check(lib().stream_process(self.handle, ctypes.c_void_p(x.data_ptr()), T,
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream)))
         return out
 
     def process(self, x, hip_stream=None):
         import torch
-        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        _check_device_buffer(x, self.model.info["in_channels"], "input")
         T = int(x.shape[-1])
         out = torch.empty((self.model.info["out_channels"], self.model.out_frames(T)),
                           dtype=torch.float32, device=x.device)
@@ -182,9 +217,15 @@ def process_batch(model, streams, xs, outs=None, hip_stream=None):
     """One batched step: buffer xs[i] (cuda [C_in][T_i]) for streams[i]."""
     import torch
     n = len(streams)
+    if len(xs) != n or (outs is not None and len(outs) != n):
+        raise ValueError("streams, inputs and outputs differ in length")
+    for x in xs:
+        _check_device_buffer(x, model.info["in_channels"], "input")
     if outs is None:
         outs = [torch.empty((model.info["out_channels"], model.out_frames(int(x.shape[-1]))),
                             dtype=torch.float32, device=x.device) for x in xs]
+    for x, o in zip(xs, outs):
+        _check_device_buffer(o, model.info["out_channels"], "output", model.out_frames(int(x.shape[-1])))
     sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
     ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     ous = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -233,6 +274,8 @@ class Server:
     def submit(self, stream_id, x):
         """x: float32 [in_channels][frames] (host).  Returns a ticket."""
         x = np.ascontiguousarray(x, dtype=np.float32)
+        if x.ndim != 2 or x.shape[0] != self.cin:
+            raise ValueError("input must be [%d][frames], got %s" % (self.cin, x.shape))
         t = ctypes.c_int64()
         check(lib().sc_server_submit(self.handle, int(stream_id), x.ctypes.data_as(_native.c_fp), x.shape[-1],
                                      ctypes.byref(t)))
@@ -268,10 +311,12 @@ class Server:
         return t[:n.value], lat[:n.value]
 
     def poll(self, ticket, frames):
-        """(output [out_channels][frames*rate], latency_s) when done, else None."""
+        """(output [out_channels][frames*rate], latency_s) when done, else None
+        (the library refuses a `frames` smaller than the buffer's)."""
         out = np.empty((self.cout, self.model.out_frames(frames)), np.float32)
         lat = ctypes.c_double()
-        st = lib().sc_server_poll(self.handle, int(ticket), out.ctypes.data_as(_native.c_fp), ctypes.byref(lat))
+        st = lib().sc_server_poll(self.handle, int(ticket), out.ctypes.data_as(_native.c_fp), out.size,
+                                  ctypes.byref(lat))
         if st == _native.SC_PENDING:
             return None
         check(st)

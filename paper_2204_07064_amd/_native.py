@@ -38,6 +38,7 @@ EXPORTS = [
     "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
     "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
     "sc_model_reserve", "sc_model_enable_graph", "sc_stream_state_bytes", "stream_export", "stream_import",
+    "sc_model_create_mixed", "sc_model_calibrated_scales",
 ]
 SC_PENDING = 1
 SC_SUBMIT_DISCARD = 1
@@ -102,6 +103,8 @@ def lib():
     P = ctypes.POINTER
     _sig(L, "sc_plan", c_i32, [P(ScNode), c_i32, P(ScModelInfo)])
     _sig(L, "sc_model_create", c_i32, [P(ScNode), c_i32, c_fp, c_size, c_i32, c_fp, c_u32, c_i32, P(c_vp)])
+    _sig(L, "sc_model_create_mixed", c_i32, [P(ScNode), c_i32, c_fp, c_size, P(c_i32), c_fp, c_u32, c_i32,
+                                              P(c_vp)])
     _sig(L, "sc_model_info_get", c_i32, [c_vp, P(ScModelInfo)])
     _sig(L, "sc_model_n_layers", c_i32, [c_vp])
     _sig(L, "sc_model_reserve", c_i32, [c_vp, c_i64])
@@ -112,6 +115,7 @@ def lib():
     _sig(L, "sc_model_set_act_scales", c_i32, [c_vp, c_fp])
     _sig(L, "sc_model_read_amax", c_i32, [c_vp, c_fp, c_i32])
     _sig(L, "sc_model_enable_amax", c_i32, [c_vp, c_i32])
+    _sig(L, "sc_model_calibrated_scales", c_i32, [c_vp, c_fp])
     _sig(L, "sc_model_destroy", None, [c_vp])
     _sig(L, "stream_create", c_i32, [c_vp, c_i32, c_u32, c_vp, P(c_vp)])
     _sig(L, "stream_process", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
@@ -124,7 +128,7 @@ def lib():
     _sig(L, "sc_model_profile_read", c_i32, [c_vp, P(ScOpProfile), c_i32, P(c_i32)])
     _sig(L, "sc_server_create", c_i32, [c_vp, P(ScServerConfig), P(c_vp)])
     _sig(L, "sc_server_submit", c_i32, [c_vp, c_i64, c_fp, c_i32, P(c_i64)])
-    _sig(L, "sc_server_poll", c_i32, [c_vp, c_i64, c_fp, P(ctypes.c_double)])
+    _sig(L, "sc_server_poll", c_i32, [c_vp, c_i64, c_fp, c_i64, P(ctypes.c_double)])
     _sig(L, "sc_server_close_stream", c_i32, [c_vp, c_i64])
     _sig(L, "sc_server_drain", c_i32, [c_vp])
     _sig(L, "sc_server_stats_get", c_i32, [c_vp, P(ScServerStats)])

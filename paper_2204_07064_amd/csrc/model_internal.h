@@ -44,11 +44,12 @@ struct sc_model {
   std::vector<sc::OpDev> opdev;
   std::vector<float> act_scales;   // per layer (FP8)
   bool have_scales = false;
+  std::vector<int32_t> layer_prec; // per layer: operand precision 0 FP32, 1 BF16, 2 FP8 e4m3
+  bool any_fp8 = false;            // some layer runs on FP8 operands (needs activation scales)
   int64_t weight_bytes = 0;
   // workspace
   std::vector<float*> ws;
   std::vector<void*> tw;           // operand twins
-  int tw_esize = 4;
   int64_t ws_cap = 0;              // input frames
   int ws_pins = 0;                 // server graphs holding the workspace's addresses
   // step graph (sc_model_enable_graph): the kernels of one step captured once,

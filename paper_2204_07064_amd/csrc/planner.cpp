@@ -250,19 +250,22 @@ sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& pl
     for (int i = 0; i < n; ++i)
       if (last_use[i] == o && buf_of[i] >= 0 && i != op.node) busy[buf_of[i]] = false;
   }
-  finalize_plan(plan, false, 4);
+  finalize_plan(plan, false);
   return SC_OK;
 }
 
-void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
+void finalize_plan(Plan& plan, bool twins) {
   const int n = (int)plan.nodes.size();
   // ---- operand twins ----
   plan.twin_elems.clear();
+  plan.twin_esize.clear();
   plan.input_twin = -1;
+  plan.input_twin_prec = 0;
   for (auto& op : plan.ops) {
     op.in_twin = op.out_twin = -1;
     op.tstate_len = 0;
     op.twin_only = 0;
+    op.twin_prec = 0;
   }
   if (twins) {
     std::vector<int> producer(n, -1);
@@ -283,14 +286,18 @@ void finalize_plan(Plan& plan, bool twins, int elem_bytes) {
       const int chans = from_input ? plan.in_channels : plan.ops[producer[s]].cout;
       plan.twin_elems.push_back(plan.rate[s].mul(chans));
       Op& rd = plan.ops[reader];
+      const int elem_bytes = prec_bytes(rd.prec);
+      plan.twin_esize.push_back(elem_bytes);
       rd.in_twin = t;
       if (from_input) {
         plan.input_twin = t;
+        plan.input_twin_prec = rd.prec;
         plan.input_twin_pre = rd.pre_act;
         plan.input_twin_layer = rd.layer;
       } else {
         Op& pr = plan.ops[producer[s]];
         pr.out_twin = t;
+        pr.twin_prec = rd.prec;
         pr.twin_pre = rd.pre_act;
         pr.twin_layer = rd.layer;
         // a transposed conv reads only the twin (its state is the FP32 carry

@@ -107,7 +107,7 @@ void free_model(sc_model* m) {
 // Scale applied before rounding a twin read by `layer`: the reciprocal of that
 // layer's FP8 activation scale (amax / 448), computed as the MFMA kernel does.
 float twin_scale(const sc_model* m, int layer) {
-  if (m->prec != SC_FP8E4M3 || layer < 0 || !m->have_scales) return 1.0f;
+  if (layer < 0 || m->layer_prec[layer] != 2 || !m->have_scales) return 1.0f;
   return 1.0f / (m->act_scales[layer] / 448.0f);
 }
 
@@ -116,7 +116,8 @@ float* ws_at(const sc_model* m, int b, int64_t base) {
   return b >= 0 ? m->ws[b] + m->plan.buf_floats[b].of(base) : nullptr;
 }
 void* tw_at(const sc_model* m, int t, int64_t base) {
-  return t >= 0 ? static_cast<unsigned char*>(m->tw[t]) + m->plan.twin_elems[t].of(base) * m->tw_esize : nullptr;
+  return t >= 0 ? static_cast<unsigned char*>(m->tw[t]) + m->plan.twin_elems[t].of(base) * m->plan.twin_esize[t]
+                : nullptr;
 }
 
 // A one-output-channel stride-1 conv that writes the model output and reads
@@ -182,7 +183,7 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
                : 0;
   a.in_twin = tw_at(m, op.in_twin, base);
   a.out_twin = tw_at(m, op.out_twin, base);
-  a.twin_prec = m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2);
+  a.twin_prec = op.twin_prec;
   a.twin_pre = op.twin_pre;
   // calibration reads every layer's FP32 input, so keep writing it then
   a.twin_only = (op.twin_only && a.out_twin && !m->amax_on) ? 1 : 0;
@@ -194,8 +195,32 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
 
 }  // namespace
 
+namespace {
+
+// The largest per-launch item count (outputs, transposed-conv columns times
+// phases, cache and delay-line items) of a step of n streams and T input
+// frames.  Kernels index items in 32-bit integers with grid-stride loops, so
+// a step is refused when this exceeds half the int32 range.
+int64_t max_step_items(const Plan& pl, int64_t n, int64_t T) {
+  int64_t worst = 0;
+  for (const Op& op : pl.ops) {
+    const int64_t in = op.in_rate.of(T), out = op.out_rate.of(T);
+    int64_t v = in * op.cin;
+    v = std::max(v, out * op.cout + n * ((int64_t)op.cache_len * op.cin + (int64_t)(op.A0 + op.A1) * op.cout));
+    if (op.kind == K_CONVT) v = std::max(v, (in + n) * op.stride * op.cout);
+    worst = std::max(worst, v);
+  }
+  return worst;
+}
+constexpr int64_t kMaxStepItems = INT32_MAX / 2;
+
+}  // namespace
+
 sc_status sc::ensure_workspace(sc_model* m, int64_t frames) {
   if (frames <= m->ws_cap) return SC_OK;
+  // every stream brings at least one granule of input frames
+  if (max_step_items(m->plan, frames / m->plan.input_multiple + 1, frames) > kMaxStepItems)
+    return fail(SC_ELENGTH, "step too large for 32-bit item indexing");
   if (m->ws_pins > 0)
     return fail(SC_ELENGTH, "step larger than the workspace that a server's captured graph holds");
   int64_t cap = std::max<int64_t>(frames, 2 * m->ws_cap);
@@ -212,7 +237,7 @@ sc_status sc::ensure_workspace(sc_model* m, int64_t frames) {
   m->ws.assign(m->plan.buf_floats.size(), nullptr);
   m->tw.assign(m->plan.twin_elems.size(), nullptr);
   for (size_t t = 0; t < m->plan.twin_elems.size(); ++t) {
-    const int64_t bytes = m->plan.twin_elems[t].of(cap) * m->tw_esize + 64;
+    const int64_t bytes = m->plan.twin_elems[t].of(cap) * m->plan.twin_esize[t] + 64;
     e = hipMalloc(&m->tw[t], (size_t)bytes);
     if (e != hipSuccess) {
       m->ws_cap = 0;
@@ -284,7 +309,7 @@ sc_status fail_status(sc_status st, const char* msg) { return fail(st, msg); }
 sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
                         const int32_t* n_frames, float* const* d_out, int64_t* total_out) {
   if (n <= 0 || !streams || !d_in || !n_frames || !d_out) return fail(SC_EINVAL, "null argument or n <= 0");
-  if (m->prec == SC_FP8E4M3 && !m->have_scales) return fail(SC_EINVAL, "FP8 model has no activation scales");
+  if (m->any_fp8 && !m->have_scales) return fail(SC_EINVAL, "FP8 model has no activation scales");
   int64_t total = 0;
   const uint64_t gen = ++m->step_gen;
   for (int i = 0; i < n; ++i) {
@@ -299,7 +324,8 @@ sc_status validate_step(sc_model* m, int n, sc_stream* const* streams, const flo
     if (!d_in[i] || !d_out[i]) return fail(SC_EINVAL, "null device buffer");
     total += T;
   }
-  if (total > INT32_MAX / 4) return fail(SC_ELENGTH, "batch too large");
+  if (total > INT32_MAX / 4 || max_step_items(m->plan, n, total) > kMaxStepItems)
+    return fail(SC_ELENGTH, "batch too large for 32-bit item indexing");
   *total_out = total;
   return SC_OK;
 }
@@ -359,7 +385,7 @@ hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
   if (pl.input_buf < 0) return hipSuccess;
   return launch_pack_input(ls.ents, ls.fent, pl.input_multiple, ls.hdr, pl.in_channels, ls.grid_frames,
                            ws_at(m, pl.input_buf, ls.base),
-                           tw_at(m, pl.input_twin, ls.base), m->prec == SC_FP32 ? 0 : (m->prec == SC_BF16 ? 1 : 2),
+                           tw_at(m, pl.input_twin, ls.base), pl.input_twin_prec,
                            pl.input_twin_pre, twin_scale(m, pl.input_twin_layer), ls.hs);
 }
 
@@ -437,8 +463,10 @@ int choose_split(const sc_model* m, int n, const int32_t* n_frames, int64_t tota
   // the second half's workspace offsets must be whole and keep 16-byte alignment
   for (const sc::Frac& r : m->plan.buf_floats)
     if (acc * r.num % r.den != 0 || r.of(acc) * (int64_t)sizeof(float) % 16 != 0) return 0;
-  for (const sc::Frac& r : m->plan.twin_elems)
-    if (acc * r.num % r.den != 0 || r.of(acc) * m->tw_esize % 16 != 0) return 0;
+  for (size_t t = 0; t < m->plan.twin_elems.size(); ++t) {
+    const sc::Frac& r = m->plan.twin_elems[t];
+    if (acc * r.num % r.den != 0 || r.of(acc) * m->plan.twin_esize[t] % 16 != 0) return 0;
+  }
   *f = acc;
   return h;
 }
@@ -674,20 +702,40 @@ sc_status sc_plan(const sc_node* nodes, int32_t n_nodes, sc_model_info* out) {
   return SC_OK;
 }
 
-sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights, size_t n_weights,
-                          sc_precision precision, const float* act_scales, uint32_t options, int32_t device,
-                          sc_model** out) {
+}  // extern "C"
+
+namespace {
+
+// sc_model_create / sc_model_create_mixed: `precision` for every layer, or
+// one precision per layer (`layer_prec`, node order) when it is not null.
+sc_status create_model(const sc_node* nodes, int32_t n_nodes, const float* weights, size_t n_weights,
+                       sc_precision precision, const int32_t* layer_prec, const float* act_scales,
+                       uint32_t options, int32_t device, sc_model** out) {
   if (!out) return fail(SC_EINVAL, "null output");
   *out = nullptr;
-  if (precision != SC_FP32 && precision != SC_BF16 && precision != SC_FP8E4M3)
-    return fail(SC_EINVAL, "unknown precision");
-  if ((options & SC_MODEL_NO_MFMA) && precision != SC_FP32)
-    return fail(SC_EINVAL, "SC_MODEL_NO_MFMA needs SC_FP32");
+  auto known = [](int32_t p) { return p == SC_FP32 || p == SC_BF16 || p == SC_FP8E4M3; };
+  if (!layer_prec && !known(precision)) return fail(SC_EINVAL, "unknown precision");
   sc_model* m = new (std::nothrow) sc_model();
   if (!m) return fail(SC_ENOMEM, "host allocation failed");
   std::string err;
   sc_status st = build_plan(nodes, n_nodes, options, m->plan, err);
   if (st != SC_OK) { delete m; return fail(st, err); }
+  const int n_layers = (int)m->plan.layer_node.size();
+  auto prec_id_of = [](int32_t p) { return p == SC_FP32 ? 0 : (p == SC_BF16 ? 1 : 2); };
+  m->layer_prec.assign(n_layers, prec_id_of(precision));
+  if (layer_prec) {
+    int lowest = 0;
+    for (int i = 0; i < n_layers; ++i) {
+      if (!known(layer_prec[i])) { delete m; return fail(SC_EINVAL, "unknown precision in layer_precision"); }
+      m->layer_prec[i] = prec_id_of(layer_prec[i]);
+      lowest = std::max(lowest, m->layer_prec[i]);
+    }
+    precision = lowest == 0 ? SC_FP32 : (lowest == 1 ? SC_BF16 : SC_FP8E4M3);
+  }
+  if ((options & SC_MODEL_NO_MFMA) && precision != SC_FP32) {
+    delete m;
+    return fail(SC_EINVAL, "SC_MODEL_NO_MFMA needs SC_FP32");
+  }
   if (!weights || (int64_t)n_weights != m->plan.n_weights) {
     delete m;
     return fail(SC_EINVAL, "weights missing or of the wrong length (expected " +
@@ -704,14 +752,12 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->own_done, hipEventDisableTiming);
   if (e != hipSuccess) { delete m; return hip_fail(e, "device setup"); }
-  const int n_layers = (int)m->plan.layer_node.size();
   if (act_scales) {
     m->act_scales.assign(act_scales, act_scales + n_layers);
     m->have_scales = true;
   } else {
     m->act_scales.assign(n_layers, 1.0f);
   }
-  const int prec_id = precision == SC_FP32 ? 0 : (precision == SC_BF16 ? 1 : 2);
   m->opdev.resize(m->plan.ops.size());
   for (size_t i = 0; i < m->plan.ops.size(); ++i) {
     Op& op = m->plan.ops[i];
@@ -719,6 +765,7 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     if (op.kind == K_DELAY_ADD) continue;
     const float* w = weights + op.w_off;
     const float* b = weights + op.b_off;
+    const int prec_id = op.layer >= 0 ? m->layer_prec[op.layer] : 0;
     bool mfma = false, fp32_input = false;
     if (!(options & SC_MODEL_NO_MFMA) && op.in_buf >= 0 && op.out_buf >= 0) {
       // (a fused skip reads the window at the output rate: stride-1 convs only)
@@ -734,6 +781,8 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     op.impl = mfma ? IMPL_MFMA : IMPL_VALU;
     op.no_twin = fp32_input ? 1 : 0;
     od.prec = (mfma && !fp32_input) ? prec_id : 0;
+    op.prec = od.prec;
+    if (od.prec == 2) m->any_fp8 = true;
     if (mfma && op.kind == K_CONV && !(options & SC_MODEL_NO_WIN)) {
       const int64_t min_frames = op.in_rate.of(m->plan.input_multiple);
       od.win_rows = conv_win_rows(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, min_frames, prec_id);
@@ -758,13 +807,30 @@ sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* we
     if (e != hipSuccess) { free_model(m); return hip_fail(e, "weight upload"); }
   }
   if (!(options & SC_MODEL_NO_OUT_FUSION)) fuse_output_convs(m->plan);
-  m->tw_esize = prec_id == 0 ? 4 : (prec_id == 1 ? 2 : 1);
-  finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN), m->tw_esize);
+  finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN));
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
   if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }
   *out = m;
   return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights, size_t n_weights,
+                          sc_precision precision, const float* act_scales, uint32_t options, int32_t device,
+                          sc_model** out) {
+  return create_model(nodes, n_nodes, weights, n_weights, precision, nullptr, act_scales, options, device, out);
+}
+
+sc_status sc_model_create_mixed(const sc_node* nodes, int32_t n_nodes, const float* weights, size_t n_weights,
+                                const int32_t* layer_precision, const float* act_scales, uint32_t options,
+                                int32_t device, sc_model** out) {
+  if (!layer_precision) return fail(SC_EINVAL, "null layer_precision");
+  return create_model(nodes, n_nodes, weights, n_weights, SC_FP32, layer_precision, act_scales, options, device,
+                      out);
 }
 
 sc_status sc_model_info_get(const sc_model* m, sc_model_info* out) {
@@ -808,6 +874,8 @@ sc_status sc_model_set_act_scales(sc_model* m, const float* s) {
   const int n = (int)m->plan.layer_node.size();
   for (int i = 0; i < n; ++i)
     if (!(s[i] > 0.f) || !std::isfinite(s[i])) return fail(SC_EINVAL, "activation scales must be positive and finite");
+  if (m->ws_pins > 0)
+    return fail(SC_ESTATE, "a server's captured step graphs hold this model's scales; destroy it first");
   if (m->graph_exec) {   // the captured launches hold the old scales
     const hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -835,6 +903,18 @@ sc_status sc_model_read_amax(sc_model* m, float* out, int32_t reset) {
   if (e == hipSuccess && n > 0) e = hipMemcpy(out, m->d_amax, n * sizeof(float), hipMemcpyDeviceToHost);
   if (e == hipSuccess && reset && n > 0) e = hipMemset(m->d_amax, 0, n * sizeof(float));
   if (e != hipSuccess) return hip_fail(e, "amax readback");
+  return SC_OK;
+}
+
+sc_status sc_model_calibrated_scales(sc_model* m, float* out) {
+  if (!m || !out) return fail(SC_EINVAL, "null argument");
+  const sc_status st = sc_model_read_amax(m, out, 0);
+  if (st != SC_OK) return st;
+  // static activation scale of a layer: the largest |activated input| seen
+  // while calibrating, with a 25% margin against unseen peaks
+  constexpr float kMargin = 1.25f, kFloor = 1e-6f;
+  const int n = (int)m->plan.layer_node.size();
+  for (int i = 0; i < n; ++i) out[i] = std::max(out[i] * kMargin, kFloor);
   return SC_OK;
 }
 
@@ -925,13 +1005,14 @@ struct StateHeader {
   int32_t in_channels, out_channels;
   int64_t pos;
   int32_t parity, reserved;
+  uint64_t op_prec_sig;       // per-op operand precisions (the twin cache layout depends on them)
 };
 constexpr uint32_t kStateMagic = 0x54534353u;   // "SCST" little-endian
 
 StateHeader state_header(const sc_model* m) {
   StateHeader h{};
   h.magic = kStateMagic;
-  h.version = 1;
+  h.version = 2;
   h.state_alloc_floats = std::max<int64_t>(m->plan.state_alloc_floats, 1);
   h.latency = m->plan.latency;
   h.warmup = m->plan.warmup;
@@ -939,6 +1020,9 @@ StateHeader state_header(const sc_model* m) {
   h.n_ops = (int32_t)m->plan.ops.size();
   h.in_channels = m->plan.in_channels;
   h.out_channels = m->plan.out_channels;
+  uint64_t sig = 1469598103934665603ull;   // FNV-1a over the ops' precisions
+  for (const Op& op : m->plan.ops) sig = (sig ^ (uint64_t)(op.prec + 1)) * 1099511628211ull;
+  h.op_prec_sig = sig;
   return h;
 }
 }  // namespace
@@ -977,6 +1061,7 @@ sc_status stream_import(sc_stream* s, const void* host, int64_t bytes) {
   if (h.magic != want.magic || h.version != want.version || h.state_alloc_floats != want.state_alloc_floats ||
       h.latency != want.latency || h.warmup != want.warmup || h.precision != want.precision ||
       h.n_ops != want.n_ops || h.in_channels != want.in_channels || h.out_channels != want.out_channels ||
+      h.op_prec_sig != want.op_prec_sig ||
       h.pos < 0 || (h.parity != 0 && h.parity != 1))
     return fail(SC_EINVAL, "state of another graph or precision");
   std::lock_guard<std::mutex> g(m->mu);

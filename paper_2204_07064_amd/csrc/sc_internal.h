@@ -69,6 +69,8 @@ struct Op {
                               // IMPL_TAIL op: index of that window conv
   int32_t twin_only = 0;      // producer: its only reader takes the twin and keeps no FP32
                               // input state (a transposed conv), so the FP32 output is not written
+  int32_t prec = 0;           // operand precision of this op's kernel: 0 FP32, 1 BF16, 2 FP8 e4m3
+  int32_t twin_prec = 0;      // producer: operand precision of the twin's reader
 };
 
 struct Plan {
@@ -82,6 +84,8 @@ struct Plan {
   int32_t input_twin = -1;           // twin of the packed model input
   int32_t input_twin_pre = 0, input_twin_layer = -1;
   std::vector<Frac> twin_elems;      // elements per input frame of each twin buffer
+  std::vector<int32_t> twin_esize;   // bytes per element of each twin buffer (its reader's operand type)
+  int32_t input_twin_prec = 0;       // operand precision of the input twin's reader
   int32_t in_channels = 0, out_channels = 0;
   int32_t input_multiple = 1;
   Frac out_rate;
@@ -95,11 +99,15 @@ struct Plan {
 sc_status build_plan(const sc_node* nodes, int32_t n, uint32_t options, Plan& plan,
                      std::string& err);
 
-// After the runtime has chosen each op's kernel family: assigns operand twins
-// (when `twins`) for inputs of MFMA ops that have exactly one MFMA reader and
-// a producer that can write them, and lays out the per-stream state (caches,
-// carries, delay lines, twin caches of `elem_bytes`-byte operands).
-void finalize_plan(Plan& plan, bool twins, int elem_bytes);
+// After the runtime has chosen each op's kernel family and operand precision
+// (Op::prec): assigns operand twins (when `twins`) for inputs of MFMA ops that
+// have exactly one MFMA reader and a producer that can write them, each in its
+// reader's operand type, and lays out the per-stream state (caches, carries,
+// delay lines, twin caches).
+void finalize_plan(Plan& plan, bool twins);
+
+// Bytes of one operand element of precision 0 (FP32), 1 (BF16) or 2 (FP8).
+inline int prec_bytes(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
 
 void set_error(const std::string& msg);
 

@@ -165,6 +165,25 @@ void finalize(sc_server* srv, StepCtx& c, bool failed = false) {
   srv->cv_done.notify_all();
 }
 
+// Fails every queued buffer of a stream whose state is broken (a step that
+// included it could not be enqueued).  Called with srv->mu held.
+void fail_queued(sc_server* srv, SStream* st) {
+  const auto now = Clock::now();
+  while (!st->queue.empty()) {
+    Ticket* t = st->queue.front();
+    st->queue.pop_front();
+    srv->queued--;
+    if (t->discard) {
+      srv->tickets.erase(t->id);
+      continue;
+    }
+    t->t_done = now;
+    t->done = true;
+    t->failed = true;
+  }
+  srv->cv_done.notify_all();
+}
+
 // Captures the context's step kernels, sized for the largest step.  Done at
 // server creation on the creating thread (a capture on the worker thread could
 // be invalidated by device-wide calls, such as a free, from other threads).
@@ -224,6 +243,25 @@ void worker_main(sc_server* srv) {
       if (c.busy && hipEventQuery(c.done) == hipSuccess) finalize(srv, c);
     bool work = false;
     for (auto& kv : srv->streams) work |= kv.second->admitted && !kv.second->queue.empty();
+    if (work) {
+      // a failed step left these streams' state behind their buffers: their
+      // queued buffers fail rather than continue a broken stream
+      std::vector<int64_t> gone;
+      for (auto& kv : srv->streams) {
+        SStream* st = kv.second.get();
+        if (!st->admitted || !st->s || !st->s->bad || st->queue.empty()) continue;
+        fail_queued(srv, st);
+        if (st->closing && st->inflight == 0) gone.push_back(st->id);
+      }
+      for (int64_t id : gone) {
+        stream_destroy(srv->streams[id]->s);
+        srv->admitted--;
+        srv->streams.erase(id);
+      }
+      work = false;
+      for (auto& kv : srv->streams) work |= kv.second->admitted && !kv.second->queue.empty();
+      if (!work) continue;
+    }
     if (!work) {
       bool any_busy = false;
       for (auto& c : srv->ctx) any_busy |= c.busy;
@@ -262,6 +300,7 @@ void worker_main(sc_server* srv) {
     for (auto& kv : srv->streams) {
       SStream* st = kv.second.get();
       if (!st->admitted || st->queue.empty()) continue;
+      if (st->s->bad) continue;   // (its buffers were failed above)
       Part p;
       p.st = st;
       while (!st->queue.empty() && p.frames + st->queue.front()->frames <= srv->cfg.max_buffer_frames) {
@@ -452,6 +491,10 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   if (cfg->max_streams < 1 || cfg->max_buffer_frames < 1 || cfg->max_buffer_frames % m->plan.input_multiple)
     return srv_fail(SC_EINVAL, "max_streams >= 1 and max_buffer_frames a positive multiple of the total stride");
   if (cfg->stream_flags & ~(uint32_t)SC_FLAG_WARMUP_MASK) return srv_fail(SC_EINVAL, "unknown stream flags");
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    if (m->any_fp8 && !m->have_scales) return srv_fail(SC_EINVAL, "FP8 model has no activation scales");
+  }
   std::unique_ptr<sc_server> srv(new sc_server());
   srv->m = m;
   srv->cfg = *cfg;
@@ -471,7 +514,8 @@ sc_status sc_server_create(sc_model* m, const sc_server_config* cfg, sc_server**
   }
   int64_t ws = 0;
   for (const auto& b : m->plan.buf_floats) ws += b.of(m->ws_cap) * 4;
-  for (const auto& t : m->plan.twin_elems) ws += t.of(m->ws_cap) * m->tw_esize;
+  for (size_t t = 0; t < m->plan.twin_elems.size(); ++t)
+    ws += m->plan.twin_elems[t].of(m->ws_cap) * m->plan.twin_esize[t];
   const int64_t staging = kCtx * ((srv->max_frames * srv->cin + out_frames_of(srv.get(), srv->max_frames) * srv->cout) *
                                        4 + (int64_t)(desc_bytes(cfg->max_streams, srv->max_frames,
                                                                 m->plan.input_multiple) + kSplitSlack));
@@ -568,7 +612,8 @@ sc_status sc_server_latencies(sc_server* srv, int64_t* tickets, double* latency_
   return SC_OK;
 }
 
-sc_status sc_server_poll(sc_server* srv, int64_t ticket, float* host_out, double* latency_s) {
+sc_status sc_server_poll(sc_server* srv, int64_t ticket, float* host_out, int64_t out_capacity,
+                         double* latency_s) {
   if (!srv) return srv_fail(SC_EINVAL, "null server");
   std::lock_guard<std::mutex> g(srv->mu);
   auto it = srv->tickets.find(ticket);
@@ -580,8 +625,12 @@ sc_status sc_server_poll(sc_server* srv, int64_t ticket, float* host_out, double
   }
   if (t->failed) {
     srv->tickets.erase(it);
-    return srv_fail(SC_EDEVICE, srv->worker_error);
+    return srv_fail(SC_EDEVICE, srv->worker_error.empty() ? std::string("the buffer's stream saw a failed step")
+                                                           : srv->worker_error);
   }
+  if (host_out && out_capacity < (int64_t)t->out.size())
+    return srv_fail(SC_EINVAL, "host_out holds fewer floats than the buffer's output (" +
+                                   std::to_string(t->out.size()) + ")");
   if (host_out) std::memcpy(host_out, t->out.data(), t->out.size() * sizeof(float));
   if (latency_s) *latency_s = std::chrono::duration<double>(t->t_done - t->t_submit).count();
   srv->tickets.erase(it);

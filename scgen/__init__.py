@@ -20,6 +20,8 @@ from .models import (  # noqa: F401
     outconv64_unit,
     model_by_name,
     n_weights,
+    FP8_LAYERS,
+    fp8_plan,
 )
 from .weights import init_weights  # noqa: F401
 from .inputs import (  # noqa: F401

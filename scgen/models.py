@@ -208,6 +208,32 @@ def model_by_name(name):
     return table[name]()
 
 
+# Mixed-precision plans: the layers (indices among the conv / transposed-conv
+# nodes, node order) whose operands are FP8 e4m3; every other layer runs on
+# BF16.  e4m3 keeps three mantissa bits, and one rounding of the weights and
+# activations of a full-width layer costs ~28 dB of SNR (~34 dB for a residual
+# branch, whose output is half the size of the stream it is added to); these
+# errors add up over the layers in series, so an all-FP8 decoder stays near
+# 19 dB.  The plans below are the two-layer sets with the most FLOPs that keep
+# the decoder above 30 dB against the FP64 offline model with margin (a third
+# layer brings it to ~30.0 dB).  tests/golden/fp8_plans.py re-derives them
+# from a rounding emulation of the offline model.
+FP8_LAYERS = {
+    # rave_b: the stage-1 residual convs with dilation 1 and 3 (256 channels)
+    "rave_b": (2, 3),
+    # wide: the stage-3 residual convs with dilation 3 and 27 (96 channels)
+    "wide": (13, 15),
+}
+
+
+def fp8_plan(model):
+    """Per-layer precision list ("fp8" / "bf16", one per conv / transposed
+    conv in node order) of the mixed FP8 plan of a decoder model."""
+    layers = [nd for nd in model["nodes"] if nd["op"] in ("conv", "convt")]
+    fp8 = set(FP8_LAYERS[model["name"]])
+    return ["fp8" if i in fp8 else "bf16" for i in range(len(layers))]
+
+
 def n_weights(model):
     """Number of float32 values in the flat weight array of ``model``."""
     n = 0

@@ -39,7 +39,10 @@ def q_fp8(x):
     return t.to(torch.float8_e4m3fn).to(torch.float64).numpy()
 
 
-def forward(model, weights, x, precision, act_scales=None):
+def forward(model, weights, x, precision, act_scales=None, layer_precision=None):
+    """layer_precision: optional per-layer list (one entry per conv / transposed
+    conv, node order) of "fp32" / "bf16" / "fp8" overriding `precision` for the
+    MFMA layers (a mixed-precision plan)."""
     params = offline.unpack_weights(model, weights)
     nodes = model["nodes"]
     outs = []
@@ -55,12 +58,13 @@ def forward(model, weights, x, precision, act_scales=None):
         layer += 1
         w, b = params[i]
         u = offline.apply_pre(nd, outs[nd["src"]])
-        if precision != "fp32" and mfma_layer(nd, i == len(nodes) - 1, nd["src"] == 0, precision):
+        lp = precision if layer_precision is None else layer_precision[layer]
+        if lp != "fp32" and mfma_layer(nd, i == len(nodes) - 1, nd["src"] == 0, lp):
             if nd.get("pre_act", 0) == 1:
                 # the kernel applies LeakyReLU in FP32 before rounding
                 x32 = np.asarray(outs[nd["src"]], np.float32)
                 u = np.where(x32 >= 0, x32, np.float32(0.2) * x32).astype(np.float64)
-            if precision == "bf16":
+            if lp == "bf16":
                 u = q_bf16(u)
                 w = q_bf16(w)
             else:

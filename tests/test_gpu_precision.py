@@ -29,6 +29,14 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
+def _model(sc, m, w, prec, scales, options=0):
+    """prec "mix": the model's mixed FP8 plan (FP8 layers of scgen.fp8_plan,
+    the others on BF16)."""
+    if prec == "mix":
+        return sc.Model(m, w, act_scales=scales, options=options, layer_precision=scgen.fp8_plan(m))
+    return sc.Model(m, w, prec, act_scales=scales if prec == "fp8" else None, options=options)
+
+
 def _fp8_scales(sc, m, w, channels):
     from paper_2204_07064_amd import calibrate
     cal = [scgen.latents(channels, 64, 1 + i) for i in range(4)]
@@ -36,19 +44,21 @@ def _fp8_scales(sc, m, w, channels):
 
 
 @pytest.mark.parametrize("name", ["rave_b", "wide"])
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "mix"])
 def test_operand_twins_bitwise(name, prec):
     """MFMA layers reading the operand copy written by their producer give
     bitwise the same stream as layers that activate and round on load."""
     sc = _sc()
     m, w = weights_for(name)
     c = m["in_channels"]
-    scales = _fp8_scales(sc, m, w, c) if prec == "fp8" else None
+    scales = _fp8_scales(sc, m, w, c) if prec in ("fp8", "mix") else None
     x = scgen.stream_latents(c, 40, 2)
     splits = [1, 3, 16, 8, 12]
-    a = run_stream(sc.Model(m, w, prec, act_scales=scales), x, splits)
-    b = run_stream(sc.Model(m, w, prec, act_scales=scales, options=4), x, splits)
+    a = run_stream(_model(sc, m, w, prec, scales), x, splits)
+    b = run_stream(_model(sc, m, w, prec, scales, options=4), x, splits)
     assert np.array_equal(a, b)
+    if prec == "mix":       # split invariance of the mixed plan
+        assert np.array_equal(a, run_stream(_model(sc, m, w, prec, scales), x, [20, 20]))
 
 
 def _batched_streams(sc, mod, xs, lens):
@@ -71,7 +81,7 @@ def _batched_streams(sc, mod, xs, lens):
 
 
 @pytest.mark.parametrize("name", ["rave_b", "wide"])
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "mix"])
 def test_window_kernel_bitwise(name, prec):
     """Narrow stride-1 MFMA convs that stage each tile's [cache | new frames]
     window in LDS give bitwise the same streams as the chunk-gathering kernel,
@@ -79,7 +89,7 @@ def test_window_kernel_bitwise(name, prec):
     sc = _sc()
     m, w = weights_for(name)
     c = m["in_channels"]
-    scales = _fp8_scales(sc, m, w, c) if prec == "fp8" else None
+    scales = _fp8_scales(sc, m, w, c) if prec in ("fp8", "mix") else None
     rng = np.random.default_rng(5)
     n_str, n_steps = (9, 4) if name == "rave_b" else (5, 3)
     lens = [[int(v) for v in rng.choice([1, 2, 3, 5, 8], size=n_steps)] for _ in range(n_str)]
@@ -87,13 +97,13 @@ def test_window_kernel_bitwise(name, prec):
     # the output conv on its own launch in both (the gathering kernel has no
     # fused form of it)
     nof = sc._native.SC_MODEL_NO_OUT_FUSION
-    win = sc.Model(m, w, prec, act_scales=scales, options=nof)
+    win = _model(sc, m, w, prec, scales, options=nof)
     win.profile(True)
     a = _batched_streams(sc, win, xs, lens)
     impls = {p["node"]: p["impl"] for p in win.profile_read()}
     win.profile(False)
     assert 2 in impls.values(), impls          # the window kernel ran
-    b = _batched_streams(sc, sc.Model(m, w, prec, act_scales=scales, options=8 | nof), xs, lens)
+    b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=8 | nof), xs, lens)
     for i in range(n_str):
         assert np.array_equal(a[i], b[i]), i
 
@@ -122,18 +132,19 @@ def test_single_stream_precision(prec):
     sc = _sc()
     m, w = weights_for("rave_b")
     scales = _fp8_scales(sc, m, w, 16) if prec == "fp8" else None
-    mod = sc.Model(m, w, prec, act_scales=scales)
+    plan = scgen.fp8_plan(m) if prec == "fp8" else None
+    mod = sc.Model(m, w, prec, act_scales=scales, layer_precision=plan)
     x = scgen.stream_latents(16, 256, 0)
     s = run_stream(mod, x, [16] * 16)
     err, snr, y = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
-    ye = emulate.forward(m, w, x, prec, scales)
+    ye = emulate.forward(m, w, x, prec, scales, plan)
     sw, ew = metrics.aligned(s, ye, mod.latency, mod.warmup)
     log("%s: vs oracle max-abs %.3e SNR %.2f dB; vs rounding emulation SNR %.1f dB"
         % (prec, err, snr, metrics.snr_db(sw, ew)))
     if prec == "bf16":
         assert snr >= BF16_SNR
     else:
-        assert snr >= 15.0           # see test_fp8_snr_target for the 30 dB target
+        assert snr >= FP8_SNR        # the mixed plan (scgen.fp8_plan)
 
 
 def test_autoencoder_bf16_snr():
@@ -215,18 +226,48 @@ def test_mfma_layer_rounding(prec, kind, c_in, c_out):
     assert err <= tol * ref
 
 
-@pytest.mark.xfail(reason="plain e4m3 (3 mantissa bits, ~29 dB per rounded layer) on all 16 wide "
-                          "layers of the decoder stays near 20 dB; the 30 dB target needs "
-                          "higher-precision operands on some layers", strict=False)
 def test_fp8_snr_target():
+    """The decoder with its mixed FP8 plan (the FP8 layers of scgen.fp8_plan,
+    every other wide layer on BF16; FP32 state and accumulation) meets the
+    30 dB SNR target against the FP64 oracle on uneven buffers, and its
+    result equals the rounding emulation of the same plan far above that."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = _fp8_scales(sc, m, w, 16)
+    plan = scgen.fp8_plan(m)
+    mod = sc.Model(m, w, act_scales=scales, layer_precision=plan)
+    assert mod.precision == "fp8"
+    x = scgen.stream_latents(16, 128, 0)
+    s = run_stream(mod, x, [16, 1, 31, 8, 8, 3, 29, 16, 16])
+    err, snr, _ = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
+    ye = emulate.forward(m, w, x, "fp8", scales, plan)
+    sw, ew = metrics.aligned(s, ye, mod.latency, mod.warmup)
+    log("fp8 plan %s: vs oracle max-abs %.3e SNR %.2f dB; vs emulation %.1f dB"
+        % ([i for i, p in enumerate(plan) if p == "fp8"], err, snr, metrics.snr_db(sw, ew)))
+    assert snr >= FP8_SNR
+    assert metrics.snr_db(sw, ew) >= 45.0
+
+
+def test_fp8_all_layers_is_format_limited():
+    """Every wide layer on FP8 e4m3 (no mixed plan): the GPU result tracks
+    the CPU emulation of that rounding (so the kernels round as intended) and
+    both sit near 19 dB against the FP64 oracle -- e4m3's three mantissa bits
+    cost ~28 dB per full-width layer, and 16 layers in series add up.  This
+    is the measured reason for the mixed plan; the 30 dB target is not
+    claimed for this configuration."""
     sc = _sc()
     m, w = weights_for("rave_b")
     scales = _fp8_scales(sc, m, w, 16)
     mod = sc.Model(m, w, "fp8", act_scales=scales)
     x = scgen.stream_latents(16, 128, 0)
     s = run_stream(mod, x, [16] * 8)
-    _, snr, _ = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
-    assert snr >= FP8_SNR
+    _, snr, y = oracle_compare(m, w, x, s, mod.latency, mod.warmup)
+    ye = emulate.forward(m, w, x, "fp8", scales)
+    lo, hi = metrics.window(mod.latency, mod.warmup, y.shape[-1])
+    snr_emul = metrics.snr_db(ye[..., lo:hi], y[..., lo:hi])
+    log("all-FP8 decoder: GPU %.2f dB, emulation %.2f dB vs oracle" % (snr, snr_emul))
+    assert abs(snr - snr_emul) <= 1.5
+    assert snr < FP8_SNR
 
 
 def _batched(sc, mod, xs, lens_per_step):
@@ -299,9 +340,11 @@ def test_serving_mix_uneven_buffers_bf16():
     assert np.array_equal(alone, outs[100])
 
 
-def test_wide_decoder_fp8_and_bf16_1024_streams():
+def test_wide_decoder_1024_streams():
     """Wide decoder (128 latents, 768->...->48, ratios 8,8,4,2, dilations up
-    to 27): 1024 streams with uneven 1..8-frame buffers; oracle on 2 streams."""
+    to 27): 1024 streams with uneven 1..8-frame buffers, in FP32, BF16 and the
+    mixed FP8 plan; oracle on sampled streams (FP32 max-abs per stream, BF16
+    and FP8 pooled SNR)."""
     sc = _sc()
     m, w = weights_for("wide")
     scales = _fp8_scales(sc, m, w, 128)
@@ -310,18 +353,23 @@ def test_wide_decoder_fp8_and_bf16_1024_streams():
     frames = [sum(l) for l in lens]
     xs = [scgen.stream_latents(128, frames[i], i) for i in range(n_s)]
     res = {}
-    for prec in ("fp8", "bf16"):
-        mod = sc.Model(m, w, prec, act_scales=scales if prec == "fp8" else None)
+    ys = {i: offline.forward(m, w, xs[i]) for i in (3, 700, 1023)}
+    for prec in ("fp8", "bf16", "fp32"):
+        plan = scgen.fp8_plan(m) if prec == "fp8" else None
+        mod = sc.Model(m, w, prec, act_scales=scales if prec == "fp8" else None, layer_precision=plan)
         outs = _batched(sc, mod, xs, [[lens[i][k] for i in range(n_s)] for k in range(steps)])
         ss, yy = [], []
-        for i in (3, 700):
-            y = offline.forward(m, w, xs[i])
+        for i, y in ys.items():
             sw, yw = metrics.aligned(outs[i], y, mod.latency, mod.warmup)
             assert sw.size > 0
+            if prec == "fp32":
+                e = metrics.max_abs(sw, yw)
+                log("wide fp32 stream %d: max-abs %.3e" % (i, e))
+                assert e <= FP32_TOL
             ss.append(sw)
             yy.append(yw)
         res[prec] = metrics.snr_db(np.concatenate(ss, axis=1), np.concatenate(yy, axis=1))
         mod.close()
     log("wide decoder pooled SNR: %s" % res)
     assert res["bf16"] >= BF16_SNR
-    assert res["fp8"] >= 15.0
+    assert res["fp8"] >= FP8_SNR
