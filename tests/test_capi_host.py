@@ -93,3 +93,17 @@ def test_eq2_in_planner():
     a = sc.plan(scgen.strided_unit(False))
     b = sc.plan(scgen.strided_unit(True))
     assert (a["latency"], b["latency"]) == (2, 1)
+
+
+def test_fp8_plans_match_their_derivation():
+    """The mixed FP8 plans the models state are the ones the rounding
+    emulation derived (tests/golden/fp8_plans.json, written by
+    tests/golden/fp8_plans.py from the oracle only)."""
+    import json
+    import os
+    import scgen
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fp8_plans.json")) as f:
+        plans = json.load(f)
+    for name, rec in plans.items():
+        assert tuple(rec["stated_plan"]) == tuple(scgen.FP8_LAYERS[name]) == tuple(rec["greedy_plan"])
+        assert rec["stated_plan_db"] >= 30.0 > rec["all_fp8_db"]
