@@ -13,10 +13,12 @@ library never calls it and shares no code with it.
   alignment) used only to self-check the invariants the paper claims
   (streamed output = offline output delayed by the cumulative latency,
   independent of the buffer split, Sec. 4.2).
-* ``metrics``   -- comparison window, max-abs, SNR and the waveform distance
-  (Eq. 5).
+* ``metrics``   -- comparison window, max-abs, SNR, the spectral distance
+  (Eq. 4) and the waveform distance (Eq. 5).
+* ``ola``       -- the overlap-add baseline the paper compares with
+  (Sec. 3.3): the offline model on each buffer, tapered and summed.
 
 Inputs are float32 arrays (weights and latents from ``scgen``), up-cast to
 float64 here.
 """
-from . import offline, streaming, metrics  # noqa: F401
+from . import offline, streaming, metrics, ola  # noqa: F401

@@ -43,3 +43,29 @@ def snr_db(s, y):
 def waveform_distance(s, y):
     """Eq. 5: Euclidean distance between raw waveforms."""
     return float(np.linalg.norm(np.asarray(s, np.float64).ravel() - np.asarray(y, np.float64).ravel()))
+
+
+# STFT of the spectral distance (the paper leaves it unstated): 2048-sample
+# frames every 512 samples, periodic Hann analysis window, frames wholly
+# inside the signal, amplitude spectrum.
+STFT_FFT = 2048
+STFT_HOP = 512
+
+
+def stft_amplitude(x, n_fft=STFT_FFT, hop=STFT_HOP):
+    """|STFT| of a 1-D signal: [frames][n_fft // 2 + 1]."""
+    x = np.asarray(x, np.float64).ravel()
+    if x.size < n_fft:
+        return np.zeros((0, n_fft // 2 + 1))
+    w = np.sin(np.pi * np.arange(n_fft) / n_fft) ** 2
+    starts = np.arange(0, x.size - n_fft + 1, hop)
+    frames = np.stack([x[s:s + n_fft] * w for s in starts])
+    return np.abs(np.fft.rfft(frames, axis=1))
+
+
+def spectral_distance(s, y, eps=1.0, n_fft=STFT_FFT, hop=STFT_HOP):
+    """Eq. 4: || log(S(s) + eps) - log(S(y) + eps) ||_2 over every STFT
+    frame and bin of the amplitude spectra (eps = 1 as the paper sets it)."""
+    a = stft_amplitude(s, n_fft, hop)
+    b = stft_amplitude(y, n_fft, hop)
+    return float(np.linalg.norm(np.log(a + eps) - np.log(b + eps)))
