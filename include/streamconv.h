@@ -222,6 +222,26 @@ sc_status stream_create(sc_model* model, int32_t max_buffer_frames, uint32_t fla
  * Errors: SC_ELENGTH (no state change), SC_EINVAL, SC_ESTATE, SC_EDEVICE. */
 sc_status stream_process(sc_stream* stream, const float* d_in, int32_t n_frames, float* d_out,
                          void* hip_stream);
+/* stream_process for callers that cannot allocate device memory while they
+ * process (code under HIP graph capture, tight serving loops, hosts that
+ * forbid allocation): the same kernels and the same result, bitwise, with the
+ * step's workspace (every layer's activations and operand copies) and its
+ * descriptor in a fixed device array of SC_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device from load until the process ends, instead of
+ * the model's growable workspace.  Calls no hipMalloc / hipFree and no other
+ * allocating routine; the stream's own state is the one stream_create made.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls whose work overlaps on one device (other HIP streams, other
+ * models, other threads) race and must be serialized by the caller; ordinary
+ * stream_process / sc_process_batch calls do not touch the array.  Never
+ * splits the step, never replays a graph, refuses to run while profiling or
+ * calibration is on.  Arguments, layouts and ownership as stream_process.
+ * Errors: SC_ELENGTH (no state change) also when the buffer's workspace does
+ * not fit the array (the message gives the bytes needed; fewer frames per call
+ * fit), SC_EINVAL, SC_ESTATE, SC_EDEVICE. */
+#define SC_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+sc_status stream_process_noalloc(sc_stream* stream, const float* d_in, int32_t n_frames, float* d_out,
+                                 void* hip_stream);
 /* Zero all caches, carries and delay lines and the position counter. */
 sc_status stream_reset(sc_stream* stream, void* hip_stream);
 /* Input frames processed since creation / the last reset. */

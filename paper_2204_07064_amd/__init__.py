@@ -174,6 +174,17 @@ class Stream:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream)))
         return out
 
+    def process_into_noalloc(self, x, out, n_frames=None, hip_stream=None):
+        """process_into through stream_process_noalloc: the step's workspace
+        in the library's fixed scratch array (no device allocation)."""
+        T = int(x.shape[-1]) if n_frames is None else int(n_frames)
+        info = self.model.info
+        _check_device_buffer(x, info["in_channels"], "input", T)
+        _check_device_buffer(out, info["out_channels"], "output", self.model.out_frames(T))
+        check(lib().stream_process_noalloc(self.handle, ctypes.c_void_p(x.data_ptr()), T,
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream)))
+        return out
+
     def process(self, x, hip_stream=None):
         import torch
         _check_device_buffer(x, self.model.info["in_channels"], "input")

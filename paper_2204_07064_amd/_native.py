@@ -38,10 +38,11 @@ EXPORTS = [
     "sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_close_stream", "sc_server_drain",
     "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
     "sc_model_reserve", "sc_model_enable_graph", "sc_stream_state_bytes", "stream_export", "stream_import",
-    "sc_model_create_mixed", "sc_model_calibrated_scales",
+    "sc_model_create_mixed", "sc_model_calibrated_scales", "stream_process_noalloc",
 ]
 SC_PENDING = 1
 SC_SUBMIT_DISCARD = 1
+SC_NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 
 
 class ScNode(ctypes.Structure):
@@ -119,6 +120,7 @@ def lib():
     _sig(L, "sc_model_destroy", None, [c_vp])
     _sig(L, "stream_create", c_i32, [c_vp, c_i32, c_u32, c_vp, P(c_vp)])
     _sig(L, "stream_process", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
+    _sig(L, "stream_process_noalloc", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
     _sig(L, "stream_reset", c_i32, [c_vp, c_vp])
     _sig(L, "stream_position", c_i64, [c_vp])
     _sig(L, "stream_destroy", None, [c_vp])

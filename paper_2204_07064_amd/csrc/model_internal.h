@@ -91,6 +91,16 @@ struct sc_model {
   std::mutex mu;
 };
 
+namespace sc {
+// The workspace buffers a launch sequence uses: the model's own (model_ws),
+// or regions of the fixed scratch array (stream_process_noalloc).
+struct WsView {
+  float* const* ws;   // one per plan.buf_floats entry
+  void* const* tw;    // one per plan.twin_elems entry
+};
+inline WsView model_ws(const sc_model* m) { return WsView{m->ws.data(), m->tw.data()}; }
+}  // namespace sc
+
 struct sc_stream {
   sc_model* m = nullptr;
   float* d_state = nullptr;
@@ -137,6 +147,12 @@ hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, in
 // workspace (a step's halves use disjoint ranges).
 hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
                            int64_t base = 0);
+// The same over the workspace buffers `w` instead of the model's own.
+hipError_t enqueue_kernels_ws(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
+                              int64_t base, const WsView& w);
+// Once per device, with that device current: resolves the device address of
+// the library's fixed scratch array (used by stream_process_noalloc).
+hipError_t scratch_setup(int device);
 sc_status ensure_workspace(sc_model* m, int64_t frames);
 // After a successful enqueue: advance positions and flip state copies.
 void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames);

@@ -112,11 +112,11 @@ float twin_scale(const sc_model* m, int layer) {
 }
 
 // Workspace buffer b / operand twin t from input frame `base` on.
-float* ws_at(const sc_model* m, int b, int64_t base) {
-  return b >= 0 ? m->ws[b] + m->plan.buf_floats[b].of(base) : nullptr;
+float* ws_at(const sc_model* m, const WsView& w, int b, int64_t base) {
+  return b >= 0 ? w.ws[b] + m->plan.buf_floats[b].of(base) : nullptr;
 }
-void* tw_at(const sc_model* m, int t, int64_t base) {
-  return t >= 0 ? static_cast<unsigned char*>(m->tw[t]) + m->plan.twin_elems[t].of(base) * m->plan.twin_esize[t]
+void* tw_at(const sc_model* m, const WsView& w, int t, int64_t base) {
+  return t >= 0 ? static_cast<unsigned char*>(w.tw[t]) + m->plan.twin_elems[t].of(base) * m->plan.twin_esize[t]
                 : nullptr;
 }
 
@@ -145,15 +145,15 @@ void fuse_output_convs(Plan& pl) {
 }
 
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
-                     const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base) {
+                     const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base, const WsView& w) {
   LayerArgs a{};
   a.ents = dents;
   a.fent = dfent;
   a.hdr = dhdr;
   a.n_ent = n_ent;
-  a.in_buf = ws_at(m, op.in_buf, base);
-  a.in_buf2 = ws_at(m, op.in_buf2, base);
-  a.out_buf = ws_at(m, op.out_buf, base);
+  a.in_buf = ws_at(m, w, op.in_buf, base);
+  a.in_buf2 = ws_at(m, w, op.in_buf2, base);
+  a.out_buf = ws_at(m, w, op.out_buf, base);
   const size_t oi = &op - &m->plan.ops[0];
   a.W = m->opdev[oi].W;
   a.B = m->opdev[oi].B;
@@ -181,8 +181,8 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.tile = (op.kind == K_CONV && (op.impl == IMPL_VALU || op.impl == IMPL_TAIL))
                ? narrow_conv_tile(op.cin, op.cout, op.k, op.dil, op.stride, op.cache_len, a.n_out)
                : 0;
-  a.in_twin = tw_at(m, op.in_twin, base);
-  a.out_twin = tw_at(m, op.out_twin, base);
+  a.in_twin = tw_at(m, w, op.in_twin, base);
+  a.out_twin = tw_at(m, w, op.out_twin, base);
   a.twin_prec = op.twin_prec;
   a.twin_pre = op.twin_pre;
   // calibration reads every layer's FP32 input, so keep writing it then
@@ -366,10 +366,13 @@ struct LaunchSet {
   int64_t grid_frames;
   hipStream_t hs;
   int64_t base;
+  WsView w;
 };
 
-LaunchSet launch_set(const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs, int64_t base) {
+LaunchSet launch_set(const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs, int64_t base,
+                     const WsView& w) {
   LaunchSet ls;
+  ls.w = w;
   ls.hdr = reinterpret_cast<const int32_t*>(dev);
   ls.ents = reinterpret_cast<const Entry*>(dev + kDescHeaderBytes);
   ls.fent = reinterpret_cast<const int32_t*>(dev + kDescHeaderBytes + (size_t)grid_n * sizeof(Entry));
@@ -384,15 +387,15 @@ hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
   const Plan& pl = m->plan;
   if (pl.input_buf < 0) return hipSuccess;
   return launch_pack_input(ls.ents, ls.fent, pl.input_multiple, ls.hdr, pl.in_channels, ls.grid_frames,
-                           ws_at(m, pl.input_buf, ls.base),
-                           tw_at(m, pl.input_twin, ls.base), pl.input_twin_prec,
+                           ws_at(m, ls.w, pl.input_buf, ls.base),
+                           tw_at(m, ls.w, pl.input_twin, ls.base), pl.input_twin_prec,
                            pl.input_twin_pre, twin_scale(m, pl.input_twin_layer), ls.hs);
 }
 
 // The launch of op `oi` (with its calibration and timing records, if on).
 hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
   const Op& op = m->plan.ops[oi];
-  const LayerArgs a = layer_args(m, op, ls.ents, ls.fent, ls.hdr, ls.grid_n, ls.grid_frames, ls.base);
+  const LayerArgs a = layer_args(m, op, ls.ents, ls.fent, ls.hdr, ls.grid_n, ls.grid_frames, ls.base, ls.w);
   hipError_t e = hipSuccess;
   if (m->amax_on && op.layer >= 0) {
     e = launch_amax(a, m->d_amax + op.layer, ls.hs);
@@ -442,7 +445,12 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
 
 hipError_t enqueue_kernels(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
                            int64_t base) {
-  const LaunchSet ls = launch_set(dev, grid_n, grid_frames, hs, base);
+  return enqueue_kernels_ws(m, dev, grid_n, grid_frames, hs, base, model_ws(m));
+}
+
+hipError_t enqueue_kernels_ws(sc_model* m, const unsigned char* dev, int grid_n, int64_t grid_frames, hipStream_t hs,
+                              int64_t base, const WsView& w) {
+  const LaunchSet ls = launch_set(dev, grid_n, grid_frames, hs, base, w);
   hipError_t e = launch_pack(m, ls);
   for (size_t oi = 0; e == hipSuccess && oi < m->plan.ops.size(); ++oi) e = launch_op(m, oi, ls);
   return e;
@@ -486,8 +494,10 @@ hipError_t enqueue_split(sc_model* m, const unsigned char* dev, int n, int h, in
   // before the device runs it.
   e = hipEventRecord(m->fork_ev, hs);
   if (e == hipSuccess) e = hipStreamWaitEvent(m->side, m->fork_ev, 0);
-  const LaunchSet la = launch_set(dev, h, fa, hs, 0);
-  const LaunchSet lb = launch_set(dev + split_desc_offset(h, fa, m->plan.input_multiple), n - h, total - fa, m->side, fa);
+  const WsView w = model_ws(m);
+  const LaunchSet la = launch_set(dev, h, fa, hs, 0, w);
+  const LaunchSet lb = launch_set(dev + split_desc_offset(h, fa, m->plan.input_multiple), n - h, total - fa, m->side, fa,
+                                  w);
   if (e == hipSuccess) e = launch_pack(m, la);
   if (e == hipSuccess) e = launch_pack(m, lb);
   for (size_t oi = 0; e == hipSuccess && oi < m->plan.ops.size(); ++oi) {
@@ -751,6 +761,8 @@ sc_status create_model(const sc_node* nodes, int32_t n_nodes, const float* weigh
   m->options = options;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->own_done, hipEventDisableTiming);
+  // the no-alloc path's scratch array on this device (once per device)
+  if (e == hipSuccess) e = scratch_setup(device);
   if (e != hipSuccess) { delete m; return hip_fail(e, "device setup"); }
   if (act_scales) {
     m->act_scales.assign(act_scales, act_scales + n_layers);

@@ -58,6 +58,9 @@ def test_enum_constants_match_header():
     assert n.PRECISION == {"fp32": h["SC_FP32"], "bf16": h["SC_BF16"], "fp8": h["SC_FP8E4M3"]}
     assert n.OPS == {"input": h["SC_OP_INPUT"], "conv": h["SC_OP_CONV"], "convt": h["SC_OP_CONVT"],
                      "add": h["SC_OP_ADD"]}
+    # the no-alloc path's scratch size, as the header defines it
+    m = re.search(r"#define\s+SC_NOALLOC_SCRATCH_BYTES\s+\((\d+)u \* (\d+)u \* (\d+)u\)", open(HEADER).read())
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == n.SC_NOALLOC_SCRATCH_BYTES
     # option bits are distinct powers of two
     opts = [h[k] for k in h if k.startswith("SC_MODEL_NO_")]
     assert len(set(opts)) == len(opts) and all(o & (o - 1) == 0 for o in opts)
