@@ -276,6 +276,35 @@ sc_status sc_process_batch(sc_model* model, int32_t n, sc_stream* const* streams
                            const float* const* d_in, const int32_t* n_frames,
                            float* const* d_out, void* hip_stream);
 
+/* ---- offline evaluation and the overlap-add baseline ----
+ * The model as trained, without streaming: each buffer is a finite signal
+ * zero-padded at both ends of every layer (Sec. 2.1), the reference that the
+ * streamed output equals after latency compensation (Sec. 4.2).  Runs on the
+ * streaming kernels: every layer's output outside the buffer's own span is
+ * forced to zero (the padding), and D output samples' worth of zero frames
+ * follow the buffer.  Uses internal stream states and a staging buffer owned
+ * by the model (grown as needed; growing waits for the device). */
+/* n independent buffers: d_in[i] device [in_channels][n_frames[i]] FP32,
+ * d_out[i] device [out_channels][n_frames[i] * out_num / out_den] FP32 (fully
+ * written, output sample j = the offline output at j; no latency).  n_frames
+ * must be whole granules (sc_model_info.input_multiple).  Errors: SC_EINVAL,
+ * SC_ELENGTH, SC_ENOMEM, SC_EDEVICE. */
+sc_status sc_offline_batch(sc_model* model, int32_t n, const float* const* d_in,
+                           const int32_t* n_frames, float* const* d_out, void* hip_stream);
+/* The overlap-add baseline of Sec. 3.3 over a whole signal d_in (device
+ * [in_channels][n_frames]): buffers of `window` input frames start every
+ * window - overlap frames (complete buffers only), each is evaluated offline
+ * on its own, multiplied by a taper of window * out_rate samples that rises as
+ * sin^2 over the first overlap * out_rate samples, is one in between and
+ * falls as the mirror image over the last ones (at overlap = window / 2 the
+ * Hann window sin^2(pi n / N) of the paper), and added at its start.  d_out:
+ * device [out_channels][n_frames * out_rate], fully written (zero where no
+ * complete buffer reaches).  window and overlap are whole granules with
+ * 2 * overlap <= window (overlap 0: non-overlapping buffers).  Errors:
+ * SC_EINVAL, SC_ELENGTH, SC_ENOMEM, SC_EDEVICE. */
+sc_status sc_ola_process(sc_model* model, const float* d_in, int32_t n_frames, int32_t window,
+                         int32_t overlap, float* d_out, void* hip_stream);
+
 /* ---- tracing: per-launch timing with HIP events on the processing stream ---- */
 typedef struct {
   int32_t kind;        /* 1 conv (with fused skip if residual), 2 transposed conv, 3 delay-line sum */

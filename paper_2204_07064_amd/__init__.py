@@ -17,7 +17,8 @@ import numpy as np
 from . import _native
 from ._native import ScError, check, lib, nodes_array  # noqa: F401
 
-__all__ = ["Model", "Stream", "Server", "BatchCall", "process_batch", "plan", "ScError", "lib"]
+__all__ = ["Model", "Stream", "Server", "BatchCall", "process_batch", "offline_batch", "ola_process", "plan",
+           "ScError", "lib"]
 
 
 _EXITING = [False]
@@ -243,6 +244,42 @@ def process_batch(model, streams, xs, outs=None, hip_stream=None):
     tf = (ctypes.c_int32 * n)(*[int(x.shape[-1]) for x in xs])
     check(lib().sc_process_batch(model.handle, n, sh, ins, tf, ous, _stream_handle(hip_stream)))
     return outs
+
+
+def offline_batch(model, xs, outs=None, hip_stream=None):
+    """The model offline (zero-padded at both ends, no latency) on each
+    buffer xs[i] (cuda [C_in][T_i]): outputs cuda [C_out][T_i * out_rate]."""
+    import torch
+    n = len(xs)
+    if n == 0 or (outs is not None and len(outs) != n):
+        raise ValueError("no buffers, or inputs and outputs differ in length")
+    for x in xs:
+        _check_device_buffer(x, model.info["in_channels"], "input")
+    if outs is None:
+        outs = [torch.empty((model.info["out_channels"], model.out_frames(int(x.shape[-1]))),
+                            dtype=torch.float32, device=x.device) for x in xs]
+    for x, o in zip(xs, outs):
+        _check_device_buffer(o, model.info["out_channels"], "output", model.out_frames(int(x.shape[-1])))
+    ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    ous = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    tf = (ctypes.c_int32 * n)(*[int(x.shape[-1]) for x in xs])
+    check(lib().sc_offline_batch(model.handle, n, ins, tf, ous, _stream_handle(hip_stream)))
+    return outs
+
+
+def ola_process(model, x, window, overlap, out=None, hip_stream=None):
+    """The overlap-add baseline over the whole signal x (cuda [C_in][T]):
+    buffers of `window` input frames every window - overlap frames, each
+    evaluated offline, tapered and summed; output cuda [C_out][T * out_rate]."""
+    import torch
+    _check_device_buffer(x, model.info["in_channels"], "input")
+    T = int(x.shape[-1])
+    if out is None:
+        out = torch.empty((model.info["out_channels"], model.out_frames(T)), dtype=torch.float32, device=x.device)
+    _check_device_buffer(out, model.info["out_channels"], "output", model.out_frames(T))
+    check(lib().sc_ola_process(model.handle, ctypes.c_void_p(x.data_ptr()), T, int(window), int(overlap),
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream)))
+    return out
 
 
 class BatchCall:

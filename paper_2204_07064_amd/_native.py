@@ -39,6 +39,7 @@ EXPORTS = [
     "sc_server_stats_get", "sc_server_destroy", "sc_server_submit_batch", "sc_server_latencies",
     "sc_model_reserve", "sc_model_enable_graph", "sc_stream_state_bytes", "stream_export", "stream_import",
     "sc_model_create_mixed", "sc_model_calibrated_scales", "stream_process_noalloc",
+    "sc_offline_batch", "sc_ola_process",
 ]
 SC_PENDING = 1
 SC_SUBMIT_DISCARD = 1
@@ -121,6 +122,8 @@ def lib():
     _sig(L, "stream_create", c_i32, [c_vp, c_i32, c_u32, c_vp, P(c_vp)])
     _sig(L, "stream_process", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
     _sig(L, "stream_process_noalloc", c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp])
+    _sig(L, "sc_offline_batch", c_i32, [c_vp, c_i32, P(c_vp), P(c_i32), P(c_vp), c_vp])
+    _sig(L, "sc_ola_process", c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp])
     _sig(L, "stream_reset", c_i32, [c_vp, c_vp])
     _sig(L, "stream_position", c_i64, [c_vp])
     _sig(L, "stream_destroy", None, [c_vp])

@@ -66,10 +66,20 @@ __device__ inline int32_t out_frames(const LayerArgs& a, int32_t x) { return (in
 // rate's numerator times the granule)
 __device__ inline int entry_of_in(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_in_num, (uint32_t)n * a.in_den)]; }
 __device__ inline int entry_of_out(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_out_num, (uint32_t)n * a.out_den)]; }
-// warm-up mask of local output frame t of stream e: pos*num/den + t < delay,
-// compared exactly as pos*num + t*den < delay*den
+// Output frames of stream e that are zeroed, as a range of t * out_den for
+// local output frame t: below mask_lo the warm-up mask (absolute output frame
+// pos*num/den + t before the layer's delay), from mask_hi on the end of a
+// finite signal (offline frame pos*num/den + t - delay at or past end*num/den,
+// the layer's output length).  Compared exactly in units of 1/den.
+__device__ inline int64_t mask_lo(const Entry& e, int64_t delay, uint32_t num, uint32_t den) {
+  return (e.flags & SC_FLAG_WARMUP_MASK) ? delay * (int64_t)den - (int64_t)e.pos * num : INT64_MIN;
+}
+__device__ inline int64_t mask_hi(const Entry& e, int64_t delay, uint32_t num, uint32_t den) {
+  return e.end > 0 ? delay * (int64_t)den + (e.end - e.pos) * (int64_t)num : INT64_MAX;
+}
 __device__ inline bool masked(const LayerArgs& a, const Entry& e, int64_t t) {
-  return (e.flags & SC_FLAG_WARMUP_MASK) && ((int64_t)e.pos * a.out_num + t * a.out_den < a.delay * (int64_t)a.out_den);
+  const int64_t x = t * a.out_den;
+  return x < mask_lo(e, a.delay, a.out_num, a.out_den) || x >= mask_hi(e, a.delay, a.out_num, a.out_den);
 }
 
 __device__ inline int32_t step_in(const LayerArgs& a) { return in_frames(a, step_frames(a)); }

@@ -123,7 +123,8 @@ __device__ inline f4 mfma32(const u4& alo, const u4& ahi, const u4& blo, const u
 // Per-stream part of a tile (LDS).
 struct WinSeg {
   const float* cache;     // current cache copy [L][cin]
-  int64_t mask_x;         // warm-up mask: local output frame t is zeroed iff t * out_den < mask_x
+  int64_t mask_x;         // local output frame t is zeroed iff t * out_den is outside [mask_x, mask_hi)
+  int64_t mask_hi;
   int32_t in_start;       // first packed input frame of the stream
   int32_t out_start;      // first packed output frame (equal for stride 1)
   int32_t r0;             // first window row staged
@@ -139,7 +140,7 @@ struct WinSeg2 {
   const float* cache2;
   float* cache2_next;
   float* out2;
-  int64_t mask2_x;
+  int64_t mask2_x, mask2_hi;
   int32_t T;
 };
 
@@ -202,7 +203,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     if (PREC == 2) x = x * (wsc * a.act_scale);
     x = x + bias;
     if (a.residual) x = x + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
-    if ((int64_t)t * a.out_den < segs[s].mask_x) x = f4{0.f, 0.f, 0.f, 0.f};
+    if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) x = f4{0.f, 0.f, 0.f, 0.f};
     v[nb] = x;
   }
   __syncthreads();   // every wave is done with the staged rows and the skip rows
@@ -266,7 +267,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
         for (int kk = 0; kk < KO; ++kk)
           if (kk < k2) o = o + prow(col - L2 + d2 * kk, kk);
         if (a.oc.post_act == 2) o = tanhf(o);
-        if ((int64_t)t * a.out_den < segs2[s].mask2_x) o = 0.f;
+        if ((int64_t)t * a.out_den < segs2[s].mask2_x || (int64_t)t * a.out_den >= segs2[s].mask2_hi) o = 0.f;
         segs2[s].out2[t] = o;
       }
     }
@@ -406,9 +407,8 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     const Entry& e = a.ents[e_first + tid];
     WinSeg g;
     g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-    g.mask_x = (e.flags & SC_FLAG_WARMUP_MASK)
-                   ? a.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
-                   : INT64_MIN;
+    g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
+    g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
     g.in_start = in_frames(a, e.off);
     g.out_start = out_frames(a, e.off);
     const int32_t T = out_frames(a, e.T);
@@ -424,9 +424,8 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
       g2.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
       g2.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
       g2.out2 = e.out;
-      g2.mask2_x = (e.flags & SC_FLAG_WARMUP_MASK)
-                       ? a.oc.delay * (int64_t)a.out_den - (int64_t)e.pos * a.out_num
-                       : INT64_MIN;
+      g2.mask2_x = mask_lo(e, a.oc.delay, a.out_num, a.out_den);
+      g2.mask2_hi = mask_hi(e, a.oc.delay, a.out_num, a.out_den);
       segs2[tid] = g2;
     }
   }
@@ -567,7 +566,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     if (PREC == 2) v = v * (wsc * a.act_scale);
     v = v + bias;
     if (a.residual) v = v + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
-    if ((int64_t)t * a.out_den < segs[s].mask_x) v = f4{0.f, 0.f, 0.f, 0.f};
+    if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
     if (a.out_twin) {

@@ -88,6 +88,14 @@ struct sc_model {
   std::vector<int32_t> prof_op;               // op index of each recorded pair
   std::vector<int64_t> prof_in, prof_out, prof_ent;  // per recorded pair
   std::vector<sc_op_profile> prof;            // per op sums
+  // offline evaluation (sc_offline_batch, sc_ola_process): the model run on
+  // finite buffers with zero padding at both ends, through internal streams
+  // whose states sit back to back in one allocation
+  std::vector<sc_stream*> off_streams;
+  float* off_state = nullptr;                 // off_streams.size() state blocks
+  float* off_buf = nullptr;                   // padded inputs and full outputs
+  size_t off_cap = 0;                         // floats in off_buf
+  hipEvent_t off_done = nullptr;
   std::mutex mu;
 };
 
@@ -110,6 +118,7 @@ struct sc_stream {
   int parity = 0;
   bool bad = false;
   uint64_t seen = 0;               // step_gen of the last step that listed it
+  int64_t end = 0;                 // offline evaluation only (Entry::end); 0 for live streams
 };
 
 
@@ -154,6 +163,11 @@ hipError_t enqueue_kernels_ws(sc_model* m, const unsigned char* dev, int grid_n,
 // the library's fixed scratch array (used by stream_process_noalloc).
 hipError_t scratch_setup(int device);
 sc_status ensure_workspace(sc_model* m, int64_t frames);
+// One batched step (sc_process_batch) with the model's lock held.
+sc_status run_step_locked(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                          const int32_t* n_frames, float* const* d_out, hipStream_t hs);
+// Records an error message for the calling thread and returns st.
+sc_status fail_hip(hipError_t e, const char* what);
 // After a successful enqueue: advance positions and flip state copies.
 void commit_step(int n, sc_stream* const* streams, const int32_t* n_frames);
 sc_status fail_status(sc_status st, const char* msg);

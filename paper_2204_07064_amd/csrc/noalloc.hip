@@ -112,6 +112,7 @@ extern "C" sc_status stream_process_noalloc(sc_stream* s, const float* d_in, int
   en.parity = s->parity;
   en.flags = (int32_t)s->flags;
   en.pos = s->pos;
+  en.end = s->end;
   const int32_t n_gran = (int32_t)((total + gr - 1) / gr);
   const unsigned threads = 256, blocks = (unsigned)std::min<int32_t>(std::max<int32_t>((n_gran + 255) / 256, 1), 64);
   write_desc_kernel<<<blocks, threads, 0, hs>>>(en, (int32_t)total, n_gran, base);

@@ -101,6 +101,10 @@ void free_model(sc_model* m) {
   hipFree(m->graph_desc);
   if (m->capture_stream) hipStreamDestroy(m->capture_stream);
   hipFree(m->d_amax);
+  for (sc_stream* s : m->off_streams) delete s;   // their states live in off_state
+  hipFree(m->off_state);
+  hipFree(m->off_buf);
+  if (m->off_done) hipEventDestroy(m->off_done);
   delete m;
 }
 
@@ -349,6 +353,7 @@ void fill_descriptor(unsigned char* host, int n, int ent_capacity, sc_stream* co
     en.parity = streams[i]->parity;
     en.flags = (int32_t)streams[i]->flags;
     en.pos = streams[i]->pos;
+    en.end = streams[i]->end;
     for (int32_t f = 0; f < n_frames[i]; f += (int32_t)granule) hfent[(off + f) / granule] = i;
     off += n_frames[i];
   }
@@ -660,6 +665,13 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
 
 }  // namespace
 
+
+sc_status sc::run_step_locked(sc_model* m, int n, sc_stream* const* streams, const float* const* d_in,
+                              const int32_t* n_frames, float* const* d_out, hipStream_t hs) {
+  return run_step(m, n, streams, d_in, n_frames, d_out, hs);
+}
+
+sc_status sc::fail_hip(hipError_t e, const char* what) { return hip_fail(e, what); }
 
 namespace {
 

@@ -19,6 +19,9 @@ struct Entry {
   int32_t parity;    // state copy holding the current caches (the other is written)
   int32_t flags;     // SC_FLAG_* of the stream
   int64_t pos;       // input frames processed before this buffer
+  int64_t end;       // offline evaluation: input frames of the finite signal
+                     // (every layer's output past its length is zeroed, the
+                     // zero padding of Sec. 2.1 at the right edge); 0 = none
 };
 
 // Frames of `rate` (num/den per input frame) for t input frames (host side).
