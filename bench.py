@@ -381,6 +381,110 @@ def single_stream_sweep(sc, torch, model, sizes=(1, 2, 4, 8, 16, 32, 64, 128, 25
     return res
 
 
+# The paper's comparison with overlap-add (Sec. 3.3; Sec. 4.1 Fig. 7, Sec. 4.2
+# Fig. 8): 60 s of signal, buffer sizes from 512 samples to 11.9 s.
+OLA_SECONDS = 60.0
+OLA_BUFFERS = (4, 16, 64, 256, 1024, 4096)      # latent frames (x 128 samples)
+OLA_RATIOS = (("ola50", 2), ("ola25", 4), ("ola0", 0))   # overlap = buffer / divisor
+STFT_FFT, STFT_HOP = 2048, 512
+
+
+def _stft_amp(x):
+    """|STFT| (2048-sample frames every 512, periodic Hann) of a 1-D signal."""
+    w = (np.sin(np.pi * np.arange(STFT_FFT) / STFT_FFT) ** 2).astype(np.float64)
+    n = (x.size - STFT_FFT) // STFT_HOP + 1
+    idx = np.arange(STFT_FFT)[None, :] + STFT_HOP * np.arange(n)[:, None]
+    return np.abs(np.fft.rfft(x[idx] * w, axis=1))
+
+
+def _distances(s, y):
+    """Eq. 4 (spectral distance, eps = 1) and Eq. 5 (waveform distance) of a
+    method's output s against the offline output y over the same samples."""
+    s = np.asarray(s, np.float64)
+    y = np.asarray(y, np.float64)
+    ls = float(np.linalg.norm(np.log(_stft_amp(s) + 1.0) - np.log(_stft_amp(y) + 1.0)))
+    return round(ls, 6), round(float(np.linalg.norm(s - y)), 6)
+
+
+def _call_us(torch, fn, calls):
+    """GPU time per call of fn() issued back to back (HIP events), after 4 warm-up calls."""
+    for _ in range(4):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / calls
+
+
+def ola_comparison(sc, torch):
+    """Streaming against the overlap-add baseline at 50 / 25 / 0 % overlap on
+    the decoder (FP32, one stream, 60 s of N(0,1) latents standing in for the
+    paper's white noise), per buffer size: the real-time factor of each method
+    run buffer by buffer as a live stream would (streaming: one stream_process
+    call per buffer; overlap-add: one offline evaluation of a whole buffer per
+    hop), and each method's spectral (Eq. 4) and waveform (Eq. 5) distance to
+    the offline output of the whole signal (sc_offline_batch), latency
+    compensated, over the samples every method has produced past the first
+    buffer."""
+    m = scgen.rave_decoder_b()
+    w = scgen.init_weights(m)
+    mod = sc.Model(m, w, "fp32")
+    frames = int(OLA_SECONDS * 44100 / SPF)
+    xd = torch.from_numpy(scgen.stream_latents(LATENT, frames, 2024)).cuda()
+    ref = sc.offline_batch(mod, [xd])[0]
+    torch.cuda.synchronize()
+    ref = ref.cpu().double().numpy()[0]
+    D = mod.latency
+    res = []
+    for N in OLA_BUFFERS:
+        rec = {"buffer_frames": N, "buffer_samples": N * SPF}
+        n_full = frames // N
+        views = [xd[:, k * N:(k + 1) * N].contiguous() for k in range(n_full)]
+        out = torch.empty((1, n_full * N * SPF), device="cuda")
+        st = sc.Stream(mod, N, warmup_mask=True)
+        for k in range(n_full):
+            st.process_into(views[k], out[:, k * N * SPF:(k + 1) * N * SPF], N)
+        olas = {name: sc.ola_process(mod, xd, N, N // div if div else 0) for name, div in OLA_RATIOS}
+        torch.cuda.synchronize()
+        s = out.cpu().double().numpy()[0]
+        lo = N * SPF
+        hi = n_full * N * SPF - D
+        for name, div in OLA_RATIOS:
+            ov = N // div if div else 0
+            last = (frames - N) // (N - ov) * (N - ov)
+            hi = min(hi, (last + N - ov) * SPF)
+        rec["compared_samples"] = int(hi - lo)
+        dist = {"streaming": _distances(s[lo + D:hi + D], ref[lo:hi])}
+        for name, _ in OLA_RATIOS:
+            dist[name] = _distances(olas[name].cpu().double().numpy()[0][lo:hi], ref[lo:hi])
+        rec["spectral_distance"] = {k: v[0] for k, v in dist.items()}
+        rec["waveform_distance"] = {k: v[1] for k, v in dist.items()}
+        calls = max(4, min(64, 1024 // N))
+        it = iter(range(10 ** 9))
+        us = _call_us(torch, lambda: st.process_into(views[next(it) % n_full], out[:, :N * SPF], N), calls)
+        rtf = {"streaming": round(us / (N * SPF / 44100.0 * 1e6), 5)}
+        obuf = [torch.empty((1, N * SPF), device="cuda")]
+        for name, div in OLA_RATIOS:
+            hop = N - (N // div if div else 0)
+            us = _call_us(torch, lambda: sc.offline_batch(mod, [views[next(it) % n_full]], obuf), calls)
+            rtf[name] = round(us / (hop * SPF / 44100.0 * 1e6), 5)
+        rec["rtf"] = rtf
+        st.close()
+        res.append(rec)
+    info = mod.info
+    mod.close()
+    return {"workload": "decoder, FP32, one stream, %.0f s of N(0,1) latents (%d frames); overlap-add buffers "
+                        "evaluated offline on the streaming kernels (each buffer followed by %d zero frames)"
+                        % (OLA_SECONDS, frames, -(-D // SPF)),
+            "stft": {"n_fft": STFT_FFT, "hop": STFT_HOP, "window": "periodic Hann", "eps": 1.0},
+            "stream_state_bytes": info["state_bytes_per_stream"],
+            "by_buffer": res}
+
+
 def stack_buffer_us(sc, torch, n_buf=32, buf=512):
     """The plain three-layer cached conv stack (1 -> 16 -> 16 -> 16 channels,
     dilations 1/2/4), FP32, one stream of 512-sample buffers: GPU time per
@@ -675,6 +779,7 @@ def main():
                          "every wide layer on FP8, below the FP8 SNR target)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
+    ap.add_argument("--no-ola", action="store_true", help="skip the overlap-add comparison")
     ap.add_argument("--no-split", action="store_true",
                     help="run every step as one launch sequence (per-layer kernel traces map launches to layers "
                          "by position; the per-launch profile always runs unsplit)")
@@ -715,7 +820,7 @@ def main():
 
     shape = AUTOENC if args.workload == "audio" else HEADLINE
     if args.workload == "audio":
-        args.no_extra = args.no_serving = args.no_cpu_baseline = True
+        args.no_extra = args.no_serving = args.no_cpu_baseline = args.no_ola = True
     m = shape.model_fn()
     w = scgen.init_weights(m)
 
@@ -800,6 +905,8 @@ def main():
             "samples_per_s": round(ra["samples"] / ra["gpu_s"], 1),
             "ms_per_step": round(ra["gpu_s"] * 1e3 / 20, 4), "precision": args.precision}
         amod.close()
+    if not args.no_ola:
+        out["ola_comparison"] = ola_comparison(sc, torch)
     if not args.no_serving:
         srv = serving_runs(sc, model)
         out["serving"] = srv
