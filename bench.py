@@ -752,6 +752,35 @@ def summarize(run_dir):
     print("\n".join(lines))
 
 
+# The decoder's wide-layer GEMM shapes (M = output rows, K = taps x input
+# channels, N = frames of the headline step), for the library reference.
+LIBRARY_GEMM_SHAPES = {"stage1_conv": (256, 768, 10752), "stage2_conv": (128, 384, 43008),
+                       "stage1_convt": (1024, 1024, 2944), "stage2_convt": (512, 512, 11008)}
+
+
+def library_gemm(torch, reps=200):
+    """Plain dense BF16 GEMMs of the wide layers' shapes through torch.mm
+    (the vendor BLAS), timed by HIP events: what a library kernel reaches on
+    problems of this size, for comparison with this library's layers."""
+    res = {}
+    for name, (M, K, N) in LIBRARY_GEMM_SHAPES.items():
+        a = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(K, N, device="cuda", dtype=torch.bfloat16)
+        c = torch.empty(M, N, device="cuda", dtype=torch.bfloat16)
+        for _ in range(10):
+            torch.mm(a, b, out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.mm(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res[name] = {"MKN": [M, K, N], "us": round(us, 2), "tflops": round(2.0 * M * K * N / us / 1e6, 1)}
+    return res
+
+
 def copy_probe_summary(run_dir, nbytes):
     """Average FETCH_SIZE / WRITE_SIZE (KiB) of the copy kernel of a
     `--copy-probe` run, and the factor that turns each into bytes."""
@@ -780,6 +809,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the server runs (capacity, Poisson latency)")
     ap.add_argument("--no-ola", action="store_true", help="skip the overlap-add comparison")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="only time plain BF16 GEMMs of the wide layers' shapes on the vendor library")
+    ap.add_argument("--model-options", type=int, default=0, metavar="BITS",
+                    help="extra SC_MODEL_* option bits for the timed models (kernel A/B comparisons)")
     ap.add_argument("--no-split", action="store_true",
                     help="run every step as one launch sequence (per-layer kernel traces map launches to layers "
                          "by position; the per-launch profile always runs unsplit)")
@@ -808,6 +841,9 @@ def main():
               "step; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.library_gemm:
+        print(json.dumps({"library_gemm_bf16": library_gemm(torch)}))
+        return
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 4, device="cuda")
         dst = torch.empty_like(src)
@@ -824,7 +860,7 @@ def main():
     m = shape.model_fn()
     w = scgen.init_weights(m)
 
-    options = sc._native.SC_MODEL_NO_SPLIT if args.no_split else 0
+    options = (sc._native.SC_MODEL_NO_SPLIT if args.no_split else 0) | args.model_options
 
     def make(prec):
         """prec "fp8": the model's mixed FP8 plan (scgen.fp8_plan; FP8 SNR
