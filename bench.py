@@ -73,28 +73,28 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 0e938b832c7292671313d16cd376d76aa7c9dfba 32aa2b2fa22617686caf5b6167557e40417b7f38 cdb092dafb0e9fcf0efe9c95bda3e3e2909a7835 a31fae0a8968db259d99c989d275544815c52b43",
-    "fetch_bytes_per_kib": 2457.29, "write_bytes_per_kib": 1024.0,
+    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 801bd55719e0794064f3bc030b6648bba8bddc6e 32aa2b2fa22617686caf5b6167557e40417b7f38 7ce4e197c7829cbe4eb433e22898b26d1e9be71c 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 729.8, 2727.1),
-        2: ('mfma', 10430.1, 22165.1),
-        4: ('mfma', 10279.7, 21944.0),
-        6: ('mfma', 11267.2, 23072.6),
-        8: ('mfma', 14124.1, 12302.2),
-        9: ('mfma', 5216.6, 42244.8),
-        11: ('mfma', 17008.7, 39499.5),
-        13: ('mfma', 17509.7, 40170.6),
-        15: ('mfma', 18951.3, 14237.1),
-        16: ('mfma', 6177.9, 58137.7),
-        18: ('mfma_win', 22572.0, 55181.1),
-        20: ('mfma_win', 24040.8, 55240.7),
-        22: ('mfma_win', 28450.6, 22712.6),
-        23: ('mfma', 10972.4, 57425.9),
-        25: ('mfma_win', 22143.4, 55617.7),
-        27: ('mfma_win', 22872.1, 55922.3),
-        29: ('mfma_win', 25093.9, 3126.2),
-        30: ('tail', 2106.1, 85.4),
+        1: ('mfma', 739.5, 2727.1),
+        2: ('mfma', 10436.3, 21982.3),
+        4: ('mfma', 10284.6, 21554.4),
+        6: ('mfma', 11272.0, 22525.0),
+        8: ('mfma', 14136.7, 12302.2),
+        9: ('mfma', 5222.6, 42075.6),
+        11: ('mfma', 17024.9, 38057.7),
+        13: ('mfma', 17518.2, 38726.1),
+        15: ('mfma', 18965.1, 14243.2),
+        16: ('mfma', 6186.1, 56867.1),
+        18: ('mfma_win', 22582.4, 55577.0),
+        20: ('mfma_win', 24052.2, 55613.1),
+        22: ('mfma_win', 28460.4, 22712.6),
+        23: ('mfma', 10980.4, 55351.2),
+        25: ('mfma_win', 22152.1, 55782.1),
+        27: ('mfma_win', 22880.9, 55702.2),
+        29: ('mfma_win', 25105.4, 3126.2),
+        30: ('tail', 2110.7, 85.4),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
