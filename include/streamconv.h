@@ -146,7 +146,13 @@ enum {
                                    computed in the epilogue of an LDS-window conv
                                    that feeds it, and its launch only finishes the
                                    frames whose taps cross that conv's tile
-                                   boundaries (same results; for testing) */
+                                   boundaries (same results; for testing) */,
+  SC_MODEL_NO_CONVT_FUSION = 64u  /* a transposed conv whose output only the residual
+                                   conv after it reads runs as its own launch; by
+                                   default that conv's tiles compute the frames
+                                   they need in the same launch and the transposed
+                                   conv's output never reaches memory (same
+                                   results, bitwise; for testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,

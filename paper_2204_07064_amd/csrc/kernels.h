@@ -51,6 +51,22 @@ struct LayerArgs {
     int64_t delay;         // warm-up lag of its output (frames)
     int64_t state_off, state_len;   // its input cache: copies of [L][cin] (floats)
   } oc;
+  // window conv only: the transposed conv that produces this layer's input
+  // (its output, this layer's input, never reaches memory: each tile computes
+  // the frames its window needs from the transposed conv's own input).
+  // ct.r == 0: none.
+  struct {
+    const void* W;         // packed MFMA rows [r * cout][Kpad] (as for its own launch)
+    const float* B;        // bias [cout]
+    const float* wscale;   // FP8: per-row weight scale
+    float act_scale;       // FP8: its static activation scale
+    const void* in_twin;   // its input in operand form, [frames][cin] at its input rate
+    int32_t r, cin, half_pad, Kpad;
+    uint32_t in_num, in_den;   // its input rate (frames per model input frame)
+    FastDiv fd_in_den;
+    int64_t delay;         // warm-up lag of its output (frames at this layer's input rate)
+    int64_t state_off, state_len;   // its carry: copies of [r * cout] (floats)
+  } ct;
 };
 
 // ---- the step's actual size (device header) ----
@@ -106,6 +122,13 @@ bool conv_mfma_supported(int cin, int cout, int k, int stride, int prec);
 // does not qualify); min_frames = the fewest frames a stream brings to the layer.
 int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int64_t min_frames, int prec);
 hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s);
+// A window conv with the transposed conv before it computed in the same
+// launch (a.ct): whether a layer pair of this shape qualifies (0 if not, else
+// the window rows a tile needs; *col_cap: the transposed-conv columns a tile
+// computes at most), and its launch.
+int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_cin, int prec, int64_t min_frames,
+                       int32_t* col_cap);
+hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t col_cap, hipStream_t s);
 // Output frames per window tile, and whether a one-output-channel conv of
 // k taps, dilation dil (cache L = dil * (k - 1)) can be computed in the
 // epilogue of a window conv of this shape.

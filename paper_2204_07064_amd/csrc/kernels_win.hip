@@ -593,6 +593,381 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   }
 }
 
+// ---- a window conv with the transposed conv before it in the same launch ----
+//
+// The residual conv's input x is the output of a transposed conv (ratio r,
+// kernel 2r) that nothing else reads.  Each tile computes the x frames its
+// window needs -- its own frames plus the L frames before them -- from the
+// transposed conv's input (operand form, written by that conv's producer),
+// so x never goes to memory.  Frame q * r + phi of x is the transposed-conv
+// GEMM column q, row phi * cout + co, over K = [input q - 1 | input q]
+// (the chunks and MFMA instructions of its own launch); column q = 0 of a
+// buffer starts from the FP32 carry, and the tile that holds a stream's last
+// frame also runs column q = T_in (the carry of the next buffer).  The
+// values of x, its rounding into the conv's operand and the conv itself are
+// bit for bit those of the two separate launches.
+//
+// LDS: region X holds the transposed conv's B operand (one row of K bytes
+// per column) and, once every wave is past those MFMAs, x's window rows in
+// FP32 (the residual skip); region O the window rows in operand form.  The
+// conv's cache is the last L frames of x: written by the tiles that own them
+// (every stream brings at least L frames, so no old cache row survives).
+
+// Per-stream part of a fused tile (LDS): the transposed conv's side.
+struct CtSeg {
+  const float* carry;      // current carry copy [r * cout]
+  float* carry_next;
+  float* cache_next;       // the conv's next cache copy [L][cout]
+  int64_t mask_lo, mask_hi;   // x frame t is zeroed iff t * den is outside [mask_lo, mask_hi)
+  int32_t in_start;        // first packed frame of the transposed conv's input
+  int32_t Tin;             // its input frames of the stream
+  int32_t T;               // x frames of the stream
+  int32_t col0, qa, nq;    // first column of the stream, its first q, q columns (carry column after them)
+  int32_t carry_col;       // 1: the tile computes the carry column
+};
+
+// MBW: transposed-conv M blocks of 16 rows per wave (r * cout / 64); NCB:
+// 16-column blocks of transposed-conv columns per tile, at most.
+template <int PREC, int MT, int NB, int KCM, int KCT, int MBW, int NCB>
+__global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
+                                                                int row_cap, int col_cap) {
+  constexpr int WM = MT / 16;
+  constexpr int WN = 4 / WM;
+  constexpr int F = NB * 16 * WN;
+  constexpr int ES = WPrec<PREC>::kEsize;
+  constexpr int EPP = 16 / ES;                 // operand elements per 16-byte piece
+  constexpr int BROW = KCT * 128 + 16;         // bytes per staged transposed-conv column (padded)
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ WinSeg segs[kMaxStreams];
+  __shared__ CtSeg csegs[kMaxStreams];
+  __shared__ int32_t colbase[F];
+  __shared__ int8_t colseg[F];
+  __shared__ int8_t ccol_seg[NCB * 16];
+  __shared__ int32_t ccol_q[NCB * 16];
+  __shared__ int32_t tile_info[5];   // e_first, n_seg, total rows, ok, transposed-conv columns
+
+  const int tid = threadIdx.x;
+  const int32_t nt = blockIdx.x;
+  if (nt >= n_nt) return;
+  const int32_t f0 = nt * F;
+  const int32_t n_cols = step_out(a);   // the grid may be sized for a larger step
+  if (f0 >= n_cols) return;
+  const int32_t f_last = min(f0 + F, n_cols) - 1;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const bool pre = a.pre_act != 0;
+  const float qs = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
+  const int L = a.L;
+  const int R = a.ct.r;
+  const int rowb = MT * ES + 16;              // operand row stride (bytes)
+  const int nmb = R * MT / 16;                // transposed-conv M blocks (a multiple of 4)
+  unsigned char* X = lds;
+  float* xf = reinterpret_cast<float*>(lds);  // x rows in FP32, [row][MT] (after the transposed-conv MFMAs)
+  unsigned char* wop = lds + (size_t)max(col_cap * BROW, row_cap * MT * 4);
+
+  // the conv's weights: the wave's 16 rows, all chunks (independent of the columns)
+  const int wm = wave % WM, wn = wave / WM;
+  u4 alo[KCM], ahi[KCM];
+  {
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.W) + (int64_t)(wm * 16 + lr) * (Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < KCM; ++c) {
+      if (c * 128 < Kpad * ES) {
+        alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+        ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+      }
+    }
+  }
+
+  // ---- the streams of the tile ----
+  if (tid == 0) {
+    const int e0 = entry_of_out(a, f0);
+    const int e1 = entry_of_out(a, f_last);
+    tile_info[0] = e0;
+    tile_info[1] = e1 - e0 + 1;
+  }
+  __syncthreads();
+  const int e_first = tile_info[0];
+  const int n_seg = tile_info[1];
+  if (tid < n_seg && tid < kMaxStreams) {
+    const Entry& e = a.ents[e_first + tid];
+    WinSeg g;
+    g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+    g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
+    g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
+    g.in_start = in_frames(a, e.off);
+    g.out_start = out_frames(a, e.off);
+    const int32_t T = out_frames(a, e.T);
+    g.t_lo = tid == 0 ? f0 - g.out_start : 0;
+    g.t_hi = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
+    g.r0 = g.t_lo;
+    g.rows = g.t_hi - g.t_lo + 1 + L;
+    g.base = 0;
+    segs[tid] = g;
+    CtSeg c;
+    c.carry = e.state + a.ct.state_off + (int64_t)e.parity * a.ct.state_len;
+    c.carry_next = e.state + a.ct.state_off + (int64_t)(1 - e.parity) * a.ct.state_len;
+    c.cache_next = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
+    // x is this layer's input: its mask runs at the input rate
+    c.mask_lo = mask_lo(e, a.ct.delay, a.in_num, a.in_den);
+    c.mask_hi = mask_hi(e, a.ct.delay, a.in_num, a.in_den);
+    c.in_start = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.off * a.ct.in_num);
+    c.Tin = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.T * a.ct.in_num);
+    c.T = T;
+    // x frames of the window: [max(0, t_lo - L), t_hi] -> q in [qa, t_hi / r]
+    const int32_t ta = max(0, g.t_lo - L);
+    c.qa = ta / R;
+    c.nq = g.t_hi / R - c.qa + 1;
+    c.carry_col = g.t_hi == T - 1 ? 1 : 0;
+    c.col0 = 0;
+    csegs[tid] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int32_t b = 0, col = 0;
+    for (int s = 0; s < n_seg && s < kMaxStreams; ++s) {
+      segs[s].base = b;
+      b += segs[s].rows;
+      csegs[s].col0 = col;
+      col += csegs[s].nq + csegs[s].carry_col;
+    }
+    tile_info[2] = b;
+    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap && col <= col_cap) ? 1 : 0;
+    tile_info[4] = col;
+  }
+  __syncthreads();
+  // the host sizes tiles so that this holds; never index LDS beyond it
+  if (!tile_info[3]) return;
+  const int32_t n_ccol = tile_info[4];
+
+  // column -> stream and window row (the conv), transposed-conv column -> (stream, q)
+  if (tid < F) {
+    const int32_t f = f0 + tid;
+    int s = 0;
+    if (f <= f_last) {
+      while (s + 1 < n_seg && segs[s + 1].out_start <= f) ++s;
+      colbase[tid] = segs[s].base + (f - segs[s].out_start - segs[s].r0);
+    } else {
+      colbase[tid] = 0;
+      s = -1;
+    }
+    colseg[tid] = (int8_t)s;
+  }
+  for (int j = tid; j < NCB * 16; j += kThreads) {
+    int s = -1, q = 0;
+    if (j < n_ccol) {
+      s = 0;
+      while (s + 1 < n_seg && csegs[s + 1].col0 <= j) ++s;
+      q = csegs[s].qa + (j - csegs[s].col0);   // the carry column: q = qa + nq = T_in
+    }
+    ccol_seg[j] = (int8_t)s;
+    ccol_q[j] = q;
+  }
+  __syncthreads();
+
+  // ---- transposed-conv B operand: column (s, q) = [input q - 1 | input q] ----
+  {
+    const int ppc = KCT * 8;                  // 16-byte pieces per column
+    const int32_t n_pieces = n_ccol * ppc;
+    const unsigned char* tin = static_cast<const unsigned char*>(a.ct.in_twin);
+    for (int32_t idx = tid; idx < n_pieces; idx += kThreads) {
+      const int col = idx / ppc;
+      const int pc = idx - col * ppc;
+      const int s = ccol_seg[col];
+      const int q = ccol_q[col];
+      const int kk = pc * EPP;
+      const int h = kk >= a.ct.half_pad;
+      const int ci = kk - h * a.ct.half_pad;
+      const int row = q - 1 + h;
+      u4 v = {0u, 0u, 0u, 0u};
+      if (ci < a.ct.cin && row >= 0 && row < csegs[s].Tin)
+        v = *reinterpret_cast<const u4*>(tin + ((int64_t)(csegs[s].in_start + row) * a.ct.cin + ci) * ES);
+      *reinterpret_cast<u4*>(X + col * BROW + pc * 16) = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- transposed-conv MFMAs: the wave's M blocks x every column block ----
+  const int ncb = (n_ccol + 15) / 16;
+  f4 cacc[MBW][NCB];
+  {
+    const unsigned char* Wt = static_cast<const unsigned char*>(a.ct.W);
+#pragma unroll
+    for (int mi = 0; mi < MBW; ++mi) {
+      const int mb = wave + 4 * mi;
+      if (mb >= nmb) break;
+      u4 tlo[KCT], thi[KCT];
+      const unsigned char* wrow = Wt + (int64_t)(mb * 16 + lr) * (a.ct.Kpad * ES) + lg * 32;
+#pragma unroll
+      for (int c = 0; c < KCT; ++c) {
+        tlo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+        thi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+      }
+      const int m = mb * 16 + lg * 4;          // the lane's rows m .. m + 3 (accumulator layout)
+#pragma unroll
+      for (int nc = 0; nc < NCB; ++nc) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        if (nc < ncb) {
+          const int col = nc * 16 + lr;
+          const int s = ccol_seg[col];
+          // column q = 0 of a buffer starts from the carry
+          if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = *reinterpret_cast<const f4*>(csegs[s].carry + m);
+#pragma unroll
+          for (int c = 0; c < KCT; ++c) {
+            const unsigned char* p = X + col * BROW + c * 128 + lg * 32;
+            acc = mfma32<PREC>(tlo[c], thi[c], *reinterpret_cast<const u4*>(p), *reinterpret_cast<const u4*>(p + 16), acc);
+          }
+        }
+        cacc[mi][nc] = acc;
+      }
+    }
+  }
+  __syncthreads();   // every wave is past the B operand: X now takes x's FP32 rows
+
+  // ---- x: bias, mask, FP32 rows, operand rows, the conv's next cache, the next carry ----
+#pragma unroll
+  for (int mi = 0; mi < MBW; ++mi) {
+    const int mb = wave + 4 * mi;
+    if (mb >= nmb) break;
+    const int m = mb * 16 + lg * 4;
+    const int phi = m / MT;
+    const int co = m - phi * MT;
+    const f4 bias = *reinterpret_cast<const f4*>(a.ct.B + co);
+    const f4 ws = PREC == 2 ? *reinterpret_cast<const f4*>(a.ct.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+    for (int nc = 0; nc < NCB; ++nc) {
+      const int col = nc * 16 + lr;
+      if (nc >= ncb || col >= n_ccol) continue;
+      const int s = ccol_seg[col];
+      const int q = ccol_q[col];
+      const CtSeg& c = csegs[s];
+      if (q == c.Tin) {
+        // the carry of the next buffer, in accumulator units
+        *reinterpret_cast<f4*>(c.carry_next + m) = cacc[mi][nc];
+        continue;
+      }
+      f4 v = cacc[mi][nc];
+      if (PREC == 2) v = v * (ws * a.ct.act_scale);
+      v = v + bias;
+      const int32_t t = q * R + phi;           // x frame of the stream
+      if ((int64_t)t * a.in_den < c.mask_lo || (int64_t)t * a.in_den >= c.mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
+      const WinSeg& g = segs[s];
+      const int32_t r = t + L;                 // its window row
+      if (r >= g.r0 && r < g.r0 + g.rows) {
+        const int32_t j = g.base + (r - g.r0);
+        *reinterpret_cast<f4*>(xf + (size_t)j * MT + co) = v;
+        unsigned char* dst = wop + (size_t)j * rowb + co * ES;
+        if constexpr (PREC == 1) {
+          uint2 u;
+          u.x = wpack_bf16(act(v.x, pre), act(v.y, pre));
+          u.y = wpack_bf16(act(v.z, pre), act(v.w, pre));
+          *reinterpret_cast<uint2*>(dst) = u;
+        } else {
+          *reinterpret_cast<uint32_t*>(dst) =
+              wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
+        }
+      }
+      // the conv's next cache: the stream's last L frames of x, by the tile that owns them
+      if (t >= c.T - L && t >= g.t_lo && t <= g.t_hi)
+        *reinterpret_cast<f4*>(c.cache_next + (int64_t)(t - (c.T - L)) * MT + co) = v;
+    }
+  }
+  // window rows from the conv's cache (rows below L)
+  for (int s = 0; s < n_seg; ++s) {
+    const WinSeg& g = segs[s];
+    const int32_t nc_rows = max(0, min(L - g.r0, g.rows));   // uniform
+    for (int32_t j = tid; j < nc_rows * (MT / 4); j += kThreads) {
+      const int32_t i = j / (MT / 4);
+      const int ch = (j - i * (MT / 4)) * 4;
+      const f4 v = *reinterpret_cast<const f4*>(g.cache + (int64_t)(g.r0 + i) * MT + ch);
+      const int32_t jr = g.base + i;
+      *reinterpret_cast<f4*>(xf + (size_t)jr * MT + ch) = v;
+      unsigned char* dst = wop + (size_t)jr * rowb + ch * ES;
+      if constexpr (PREC == 1) {
+        uint2 u;
+        u.x = wpack_bf16(act(v.x, pre), act(v.y, pre));
+        u.y = wpack_bf16(act(v.z, pre), act(v.w, pre));
+        *reinterpret_cast<uint2*>(dst) = u;
+      } else {
+        *reinterpret_cast<uint32_t*>(dst) =
+            wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- the conv: B operands from the staged rows, the skip from x's FP32 rows ----
+  const int m = wm * 16 + lg * 4;
+  const f4 bias = *reinterpret_cast<const f4*>(a.B + m);
+  const f4 wsc = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  const int n_chunks = Kpad * ES / 128;
+  int cb[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) cb[nb] = colbase[wn * (F / WN) + nb * 16 + lr] * rowb;
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < KCM; ++c) {
+    if (c < n_chunks) {
+      int off[2];
+      bool live[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int kk = (c * 128 + lg * 32 + p * 16) / ES;
+        live[p] = kk < Kreal;
+        const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
+        off[p] = tap * a.dil * rowb + (kk - tap * MT) * ES;
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const u4 z = {0u, 0u, 0u, 0u};
+        const u4 blo = live[0] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]) : z;
+        const u4 bhi = live[1] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]) : z;
+        acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo, bhi, acc[nb]);
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = wn * (F / WN) + nb * 16 + lr;
+    const int s = colseg[col];
+    if (s < 0) continue;
+    const int32_t f = f0 + col;
+    const int32_t t = f - segs[s].out_start;
+    f4 v = acc[nb];
+    if (PREC == 2) v = v * (wsc * a.act_scale);
+    v = v + bias;
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * MT + m);
+    if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t o = (int64_t)f * a.cout + m;
+    if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));
+    if (a.out_twin) {
+      f4 w = v;
+      if (a.twin_pre) {
+        w.x = lrelu(w.x);
+        w.y = lrelu(w.y);
+        w.z = lrelu(w.z);
+        w.w = lrelu(w.w);
+      }
+      const float q = a.twin_qs;
+      unsigned char* dst = static_cast<unsigned char*>(a.out_twin) + o * w_esize_dev(a.twin_prec);
+      if (a.twin_prec == 0) {
+        *reinterpret_cast<f4*>(dst) = w * q;
+      } else if (a.twin_prec == 1) {
+        uint2 u;
+        u.x = wpack_bf16(w.x * q, w.y * q);
+        u.y = wpack_bf16(w.z * q, w.w * q);
+        *reinterpret_cast<uint2*>(dst) = u;
+      } else {
+        *reinterpret_cast<uint32_t*>(dst) = wpack_fp8x4(w.x * q, w.y * q, w.z * q, w.w * q);
+      }
+    }
+  }
+}
+
 int w_esize(int prec) { return prec == 0 ? 4 : (prec == 1 ? 2 : 1); }
 int w_kchunk(int prec) { return prec == 0 ? 32 : (prec == 1 ? 64 : 128); }
 
@@ -769,6 +1144,74 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   SC_WIN(1, 32, 4, 3, true) SC_WIN(1, 64, 4, 3, true)
   SC_WIN(2, 32, 4, 2, true) SC_WIN(2, 64, 4, 2, true)
 #undef SC_WIN
+  return hipErrorInvalidValue;
+}
+
+namespace {
+// the instances of the fused kernel: (precision, M tile, transposed-conv K
+// chunks, M blocks per wave) -> the column blocks a tile may need.  Only the
+// 32-row tile: its 128-frame tiles amortise the transposed conv's weights
+// (r * 32 rows) over enough frames; a 64-row tile covers 64 frames and
+// reloads r * 64 weight rows per tile, which measured slower than the two
+// launches.
+int ct_col_blocks(int prec, int mt, int kct, int mbw) {
+  if (mt == 32 && mbw == 1 && ((prec == 1 && kct == 2) || (prec == 2 && kct == 2))) return 6;
+  return 0;
+}
+int64_t ct_lds_bytes(int64_t rows, int64_t cols, int mt, int prec, int kct) {
+  return std::max(cols * (kct * 128 + 16), rows * mt * 4) + rows * (mt * w_esize(prec) + 16);
+}
+}  // namespace
+
+int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_cin, int prec, int64_t min_frames,
+                       int32_t* col_cap) {
+  *col_cap = 0;
+  if (prec < 1 || prec > 2 || r < 1 || ct_cin < 1) return 0;
+  const int32_t rows = conv_win_rows(cin, cout, k, dil, 1, L, min_frames, prec);
+  const int MT = win_mt(cout);
+  // one M tile, a residual conv (cin == cout), and every stream bringing at
+  // least L frames (the tiles write the whole next cache)
+  if (rows <= 0 || cout != MT || cin != cout || win_nb(cin) != 4 || min_frames < L || (r * MT) % 64 != 0) return 0;
+  const int kc = w_kchunk(prec);
+  const int half = (ct_cin + kc - 1) / kc * kc;
+  const int kct = 2 * half * w_esize(prec) / 128;
+  const int ncb = ct_col_blocks(prec, MT, kct, r * MT / 64);
+  if (ncb == 0) return 0;
+  const int F = win_f(MT, 4);
+  const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;
+  // per stream: its x frames (its own plus L before) over r, two partial
+  // columns at the ends, and the carry column
+  int64_t cols = (F + (int64_t)L * max_seg + r - 1) / r + 3 * max_seg;
+  cols = (cols + 15) / 16 * 16;
+  if (cols > ncb * 16 || ct_lds_bytes(rows, cols, MT, prec, kct) > 64 * 1024) return 0;
+  *col_cap = (int32_t)cols;
+  return rows;
+}
+
+hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t col_cap, hipStream_t s) {
+  const int MT = win_mt(a.cout);
+  const int NB = win_nb(a.cin);
+  const int F = win_f(MT, NB);
+  const int KCM = win_kcm(prec, a.cin);
+  const int kc = w_kchunk(prec);
+  const int Kreal = a.k * a.cin;
+  const int Kpad = (Kreal + kc - 1) / kc * kc;
+  const int kct = a.ct.Kpad * w_esize(prec) / 128;
+  const int mbw = a.ct.r * MT / 64;
+  if (a.cout != MT || NB != 4 || a.ct.r <= 0 || a.fd_cin.d != (uint32_t)a.cin || !a.out_buf ||
+      ct_col_blocks(prec, MT, kct, mbw) * 16 < col_cap)
+    return hipErrorInvalidValue;
+  const int64_t n_nt = (a.n_out + F - 1) / F;
+  if (n_nt <= 0) return hipSuccess;
+  const size_t lds = (size_t)ct_lds_bytes(row_cap, col_cap, MT, prec, kct);
+#define SC_CTWIN(P, M, K, KT, MB, NCB)                                                                      \
+  if (prec == P && MT == M && KCM == K && kct == KT && mbw == MB) {                                        \
+    hipLaunchKernelGGL((convt_win_kernel<P, M, 4, K, KT, MB, NCB>), dim3((unsigned)n_nt), dim3(kThreads), lds, \
+                       s, a, (int)n_nt, Kpad, Kreal, row_cap, col_cap);                                     \
+    return hipGetLastError();                                                                              \
+  }
+  SC_CTWIN(1, 32, 3, 2, 1, 6) SC_CTWIN(2, 32, 2, 2, 1, 6)
+#undef SC_CTWIN
   return hipErrorInvalidValue;
 }
 

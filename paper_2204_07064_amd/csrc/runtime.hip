@@ -148,6 +148,37 @@ void fuse_output_convs(Plan& pl) {
   }
 }
 
+// A transposed conv whose output only a residual window conv reads (the
+// first residual block of a narrow stage) runs inside that conv's launch
+// (launch_convt_win), where the tiles compute the frames their windows need;
+// both ops then share one launch and the transposed conv's output is never
+// written.  It needs the transposed conv to read its input in operand form.
+void fuse_convt_windows(sc_model* m) {
+  Plan& pl = m->plan;
+  for (size_t w = 0; w < pl.ops.size(); ++w) {
+    Op& cv = pl.ops[w];
+    if (cv.kind != K_CONV || cv.impl != IMPL_WIN || !cv.residual || cv.fuse_out >= 0 || cv.prec < 1) continue;
+    int c = -1, readers = 0;
+    for (size_t o = 0; o < pl.ops.size(); ++o) {
+      if (pl.ops[o].node == cv.src) c = (int)o;
+      readers += (pl.ops[o].src == cv.src) + (pl.ops[o].src2 == cv.src);
+    }
+    if (c < 0 || readers != 1) continue;
+    Op& ct = pl.ops[c];
+    if (ct.kind != K_CONVT || ct.impl != IMPL_MFMA || ct.in_twin < 0 || ct.prec != cv.prec || ct.out_twin >= 0)
+      continue;
+    const int64_t min_frames = cv.in_rate.of(pl.input_multiple);
+    int32_t cols = 0;
+    const int32_t rows = convt_win_rows(cv.cin, cv.cout, cv.k, cv.dil, cv.cache_len, ct.stride, ct.cin, cv.prec,
+                                        min_frames, &cols);
+    if (rows <= 0) continue;
+    cv.convt_in = c;
+    ct.convt_in = (int32_t)w;
+    m->opdev[w].ct_rows = rows;
+    m->opdev[w].ct_cols = cols;
+  }
+}
+
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
                      const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base, const WsView& w) {
   LayerArgs a{};
@@ -407,6 +438,10 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
     if (e != hipSuccess) return e;
   }
   const int prec = m->opdev[oi].prec;
+  // a transposed conv computed in the launch of the window conv after it
+  // (calibration reads its output, so it runs on its own then)
+  const bool ct_fused = op.convt_in >= 0 && !m->amax_on;
+  if (ct_fused && op.kind == K_CONVT) return hipSuccess;
   hipEvent_t ev_end = nullptr;
   if (m->prof_on) {
     e = prof_begin(m, (int)oi, a, ls.hs, &ev_end);
@@ -415,7 +450,28 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
   // calibration reads the fused output conv's input, so run it on its own then
   const bool fused = op.fuse_out >= 0 && !m->amax_on;
   if (op.kind == K_CONV) {
-    if (op.impl == IMPL_WIN) {
+    if (op.impl == IMPL_WIN && ct_fused) {
+      const Op& ct = m->plan.ops[op.convt_in];
+      const OpDev& cd = m->opdev[op.convt_in];
+      LayerArgs aw = a;
+      aw.ct.W = cd.W;
+      aw.ct.B = cd.B;
+      aw.ct.wscale = cd.wscale;
+      aw.ct.act_scale = (ct.layer >= 0 && m->have_scales) ? m->act_scales[ct.layer] / 448.0f : 1.0f;
+      aw.ct.in_twin = tw_at(m, ls.w, ct.in_twin, ls.base);
+      aw.ct.r = ct.stride;
+      aw.ct.cin = ct.cin;
+      const int kc = prec == 1 ? 64 : 128;
+      aw.ct.half_pad = (ct.cin + kc - 1) / kc * kc;
+      aw.ct.Kpad = 2 * aw.ct.half_pad;
+      aw.ct.in_num = (uint32_t)ct.in_rate.num;
+      aw.ct.in_den = (uint32_t)ct.in_rate.den;
+      aw.ct.fd_in_den = make_fastdiv(aw.ct.in_den);
+      aw.ct.delay = ct.out_delay;
+      aw.ct.state_off = ct.state_off;
+      aw.ct.state_len = ct.state_len;
+      e = launch_convt_win(aw, prec, m->opdev[oi].ct_rows, m->opdev[oi].ct_cols, ls.hs);
+    } else if (op.impl == IMPL_WIN) {
       LayerArgs aw = a;
       if (fused) {
         const Op& oc = m->plan.ops[op.fuse_out];
@@ -832,6 +888,7 @@ sc_status create_model(const sc_node* nodes, int32_t n_nodes, const float* weigh
   }
   if (!(options & SC_MODEL_NO_OUT_FUSION)) fuse_output_convs(m->plan);
   finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN));
+  if (!(options & SC_MODEL_NO_CONVT_FUSION)) fuse_convt_windows(m);
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
   if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }

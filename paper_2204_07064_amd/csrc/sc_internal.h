@@ -71,6 +71,8 @@ struct Op {
                               // input state (a transposed conv), so the FP32 output is not written
   int32_t prec = 0;           // operand precision of this op's kernel: 0 FP32, 1 BF16, 2 FP8 e4m3
   int32_t twin_prec = 0;      // producer: operand precision of the twin's reader
+  int32_t convt_in = -1;      // window conv: index of the transposed conv computed in its
+                              // launch; that transposed conv: index of the window conv
 };
 
 struct Plan {

@@ -108,6 +108,33 @@ def test_window_kernel_bitwise(name, prec):
         assert np.array_equal(a[i], b[i]), i
 
 
+@pytest.mark.parametrize("prec,split", [("bf16", True), ("bf16", False), ("fp8", True), ("mix", False)])
+def test_convt_window_fusion_bitwise(prec, split):
+    """The narrow stages' transposed conv computed inside the launch of the
+    residual conv after it gives bitwise the same streams as its own launch,
+    in steps of many streams of uneven buffers (1-frame buffers included),
+    split into concurrent halves or not."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = _fp8_scales(sc, m, w, 16) if prec in ("fp8", "mix") else None
+    rng = np.random.default_rng(13)
+    lens = [[int(v) for v in rng.choice([1, 2, 4, 8, 16, 32], size=3)] for _ in range(96)]
+    xs = [scgen.stream_latents(16, sum(l), 700 + i) for i, l in enumerate(lens)]
+    base = 0 if split else sc._native.SC_MODEL_NO_SPLIT
+    fused = _model(sc, m, w, prec, scales, options=base)
+    fused.profile(True)
+    a = _batched_streams(sc, fused, xs, lens)
+    convt = {p["node"]: p["launches"] for p in fused.profile_read() if p["kind"] == 2}
+    fused.profile(False)
+    log("convt fusion %s split=%s launches per transposed conv: %s" % (prec, split, convt))
+    if prec != "mix":       # computed inside the next launch (the 32-channel stage)
+        assert sum(v == 0 for v in convt.values()) >= 1, convt
+    b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base | sc._native.SC_MODEL_NO_CONVT_FUSION),
+                         xs, lens)
+    for i in range(len(lens)):
+        assert np.array_equal(a[i], b[i]), i
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     """The FP32 MFMA path (input conv included) and the FP32 wavefront path
     sum in different orders; each is pinned to the FP64 oracle at 1e-5 by the
