@@ -124,6 +124,8 @@ def step_traffic(prof, samples_per_step):
         return None
     tot = 0.0
     for p in prof:
+        if p["launches"] == 0:      # computed inside another op's launch
+            continue
         rec = t["by_node"].get(p["node"])
         if rec is None or rec[0] != IMPL_NAME[p["impl"]] or p["precision"] not in (0, 1):
             return None
@@ -131,7 +133,7 @@ def step_traffic(prof, samples_per_step):
     return round(tot / samples_per_step, 1)
 
 
-def op_accounting(p, tail=None, layer=False):
+def op_accounting(p, tail=None, layer=False, ct=None):
     """Algorithmic FLOPs and HBM bytes of one op summed over its timed
     launches: inputs read once, outputs written once, state (caches, carries,
     delay lines) read and written once per stream, weights read once per
@@ -139,7 +141,16 @@ def op_accounting(p, tail=None, layer=False):
     conv's epilogue (the op after it, impl 3): this op's own output then never
     reaches HBM, the output conv's does, and this op moves that conv's input
     cache (written once here, read once by the tail launch).  `layer`: the
-    op as a layer of its own (every layer's input and output through HBM)."""
+    op as a layer of its own (every layer's input and output through HBM).
+    `ct`: the transposed conv computed inside this window conv's launch (the
+    op before it, no launches of its own): its FLOPs, input, carry and
+    weights count here, and its output (this op's input) never reaches HBM."""
+    if ct is not None:
+        x = p["frames_in"]
+        rec = dict(ct, frames_in=x // ct["stride"], frames_out=x, entries=p["entries"], launches=p["launches"])
+        f1, b1 = op_accounting(p)
+        f2, b2 = op_accounting(rec)
+        return f1 + f2, b1 + b2 - 2 * 4.0 * x * p["cin"]
     fin, fout, ent, L = p["frames_in"], p["frames_out"], p["entries"], p["launches"]
     wb = {0: 4, 1: 2, 2: 1}[p["precision"]]
     if tail is not None:
@@ -172,6 +183,17 @@ def fused_tail(prof, p):
     return prof[i + 1] if p["impl"] == 2 and i + 1 < len(prof) and prof[i + 1]["impl"] == 3 else None
 
 
+def fused_convt(prof, p):
+    """The transposed conv computed inside window conv p's launch (the op
+    before it, with no launches of its own), or None."""
+    i = prof.index(p)
+    if p["kind"] == 1 and p["impl"] == 2 and p["launches"] > 0 and i > 0:
+        q = prof[i - 1]
+        if q["kind"] == 2 and q["launches"] == 0:
+            return q
+    return None
+
+
 WIDE_MIN_CHANNELS = 64
 
 
@@ -184,7 +206,8 @@ def roofline(prof):
     this layer-by-layer design, not of the method (which moves only the step's
     input, output and state), so they are labelled design traffic."""
     best = max(prof, key=lambda p: p["ms"])
-    flops, byts = op_accounting(best, fused_tail(prof, best))
+    ct = fused_convt(prof, best)
+    flops, byts = op_accounting(best, fused_tail(prof, best), ct=ct)
     sec = best["ms"] * 1e-3
     peak_f = PEAK[best["precision"]] if best["impl"] >= 1 else PEAK[0]
     if best["impl"] in (1, 2) and best["cin"] >= WIDE_MIN_CHANNELS:
@@ -203,6 +226,9 @@ def roofline(prof):
     impl = IMPL_NAME[best["impl"]]
     kernel = "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
         kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"])
+    if ct is not None:
+        kernel += " with the transposed conv node %d (cin %d, cout %d, r %d) in its launch" % (
+            ct["node"], ct["cin"], ct["cout"], ct["stride"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": measured_traffic(best), "basis": basis,
             "flops_per_launch": round(flops / max(best["launches"], 1)),
@@ -302,9 +328,10 @@ def step_roofline(run, value, prec):
     The layer-by-layer figures (every layer's input and output through HBM,
     op_accounting) are the design's own roofline, given beside it."""
     prof, samples = run["prof"], run["samples"]
-    flops = sum(op_accounting(p, layer=True)[0] for p in prof) / samples
+    acc = [op_accounting(p, layer=True, ct=fused_convt(prof, p)) for p in prof]
+    flops = sum(a[0] for a in acc) / samples
     byts = run["algorithmic_bytes"] / samples
-    lbl = sum(op_accounting(p, layer=True)[1] for p in prof) / samples
+    lbl = sum(a[1] for a in acc) / samples
     by_f, by_b = PEAK[prec] / flops, HBM_PEAK / byts
     roof = min(by_f, by_b)
     roof_lbl = min(by_f, HBM_PEAK / lbl)
@@ -690,7 +717,8 @@ def summarize(run_dir):
     import glob
     with open(os.path.join(run_dir, "bench.json")) as f:
         bench = json.loads([ln for ln in f if ln.startswith("{")][-1])
-    ops = bench["per_kernel"]
+    # ops computed inside another op's launch have no dispatch of their own
+    ops = [o for o in bench["per_kernel"] if o.get("launches", 1) > 0]
     lines = []
 
     def ours(name):
@@ -901,7 +929,7 @@ def main():
         "measured_step_bytes_per_sample": (step_traffic(prof, prof_run["samples"] / args.steps)
                                            if shape is HEADLINE and args.precision == "bf16" else None),
         "per_kernel": [{"node": p["node"], "kind": p["kind"], "impl": p["impl"], "prec": p["precision"],
-                        "cin": p["cin"], "cout": p["cout"], "d": p["dilation"],
+                        "cin": p["cin"], "cout": p["cout"], "d": p["dilation"], "launches": p["launches"],
                         "avg_us": round(p["ms"] * 1e3 / max(p["launches"], 1), 2)} for p in prof],
     }
     comp = {}

@@ -124,11 +124,13 @@ int32_t conv_win_rows(int cin, int cout, int k, int dil, int stride, int L, int6
 hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStream_t s);
 // A window conv with the transposed conv before it computed in the same
 // launch (a.ct): whether a layer pair of this shape qualifies (0 if not, else
-// the window rows a tile needs; *col_cap: the transposed-conv columns a tile
-// computes at most), and its launch.
+// the window rows a tile needs; *xrow_cap: the transposed-conv input frames
+// a tile stages at most; *stash_cap: the conv's cache-row pieces of 16 bytes
+// a tile holds at most), and its launch.
 int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_cin, int prec, int64_t min_frames,
-                       int32_t* col_cap);
-hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t col_cap, hipStream_t s);
+                       int32_t* xrow_cap, int32_t* stash_cap);
+hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t xrow_cap, int32_t stash_cap,
+                            hipStream_t s);
 // Output frames per window tile, and whether a one-output-channel conv of
 // k taps, dilation dil (cache L = dil * (k - 1)) can be computed in the
 // epilogue of a window conv of this shape.

@@ -607,11 +607,14 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
 // values of x, its rounding into the conv's operand and the conv itself are
 // bit for bit those of the two separate launches.
 //
-// LDS: region X holds the transposed conv's B operand (one row of K bytes
-// per column) and, once every wave is past those MFMAs, x's window rows in
-// FP32 (the residual skip); region O the window rows in operand form.  The
-// conv's cache is the last L frames of x: written by the tiles that own them
-// (every stream brings at least L frames, so no old cache row survives).
+// LDS: region X holds the transposed conv's input frames, each staged once
+// (column q reads rows q - 1 and q as its two K halves) and, once every wave
+// is past those MFMAs, x's window rows in FP32 (the residual skip); region O
+// the window rows in operand form.  The conv's cache is the last L frames of
+// x: written by the tiles that own them (every stream brings at least L
+// frames, so no old cache row survives).  Every global load that does not
+// depend on the staged data (both layers' weights, biases and scales, the
+// cache rows of the window) is issued before the first barrier.
 
 // Per-stream part of a fused tile (LDS): the transposed conv's side.
 struct CtSeg {
@@ -624,19 +627,26 @@ struct CtSeg {
   int32_t T;               // x frames of the stream
   int32_t col0, qa, nq;    // first column of the stream, its first q, q columns (carry column after them)
   int32_t carry_col;       // 1: the tile computes the carry column
+  int32_t xrow0;           // staged row of input frame qa - 1
 };
 
 // MBW: transposed-conv M blocks of 16 rows per wave (r * cout / 64); NCB:
 // 16-column blocks of transposed-conv columns per tile, at most.
+// KCM: the conv's K chunks (exactly).
 template <int PREC, int MT, int NB, int KCM, int KCT, int MBW, int NCB>
-__global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
-                                                                int row_cap, int col_cap) {
+__global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
+                                                                int row_cap, int xrow_cap, int stash_cap) {
   constexpr int WM = MT / 16;
   constexpr int WN = 4 / WM;
   constexpr int F = NB * 16 * WN;
   constexpr int ES = WPrec<PREC>::kEsize;
   constexpr int EPP = 16 / ES;                 // operand elements per 16-byte piece
-  constexpr int BROW = KCT * 128 + 16;         // bytes per staged transposed-conv column (padded)
+  constexpr int HB = KCT * 64;                 // bytes of one input frame in operand form (half of K)
+  constexpr int XROW = HB + 16;                // staged input row stride (padded)
+  constexpr int CPH = KCT / 2;                 // K chunks per half
+  constexpr int PPR = HB / 16;                 // 16-byte pieces per staged row
+  constexpr int CPRE = 2;                      // cache-row pieces per thread (the host bounds L)
+  constexpr int XP = ((NCB * 16 + kMaxStreams) * PPR + kThreads - 1) / kThreads;   // staged pieces per thread
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
@@ -645,6 +655,7 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
   __shared__ int8_t colseg[F];
   __shared__ int8_t ccol_seg[NCB * 16];
   __shared__ int32_t ccol_q[NCB * 16];
+  __shared__ int32_t ccol_x[NCB * 16];
   __shared__ int32_t tile_info[5];   // e_first, n_seg, total rows, ok, transposed-conv columns
 
   const int tid = threadIdx.x;
@@ -662,24 +673,43 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
   const int L = a.L;
   const int R = a.ct.r;
   const int rowb = MT * ES + 16;              // operand row stride (bytes)
-  const int nmb = R * MT / 16;                // transposed-conv M blocks (a multiple of 4)
   unsigned char* X = lds;
   float* xf = reinterpret_cast<float*>(lds);  // x rows in FP32, [row][MT] (after the transposed-conv MFMAs)
-  unsigned char* wop = lds + (size_t)max(col_cap * BROW, row_cap * MT * 4);
+  // the window's cache rows in FP32 until X is free (stash_cap f4 pieces)
+  f4* stash = reinterpret_cast<f4*>(lds + (size_t)max(xrow_cap * XROW, row_cap * MT * 4));
+  unsigned char* wop = lds + (size_t)max(xrow_cap * XROW, row_cap * MT * 4) + (size_t)stash_cap * 16;
 
-  // the conv's weights: the wave's 16 rows, all chunks (independent of the columns)
+  // both layers' weights, biases and scales (independent of the columns)
   const int wm = wave % WM, wn = wave / WM;
   u4 alo[KCM], ahi[KCM];
   {
     const unsigned char* wrow = static_cast<const unsigned char*>(a.W) + (int64_t)(wm * 16 + lr) * (Kpad * ES) + lg * 32;
 #pragma unroll
     for (int c = 0; c < KCM; ++c) {
-      if (c * 128 < Kpad * ES) {
-        alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
-        ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
-      }
+      alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+      ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
     }
   }
+  // the transposed conv has r * MT = 64 * MBW rows: M block wave + 4 mi
+  u4 tlo[MBW][KCT], thi[MBW][KCT];
+  f4 ct_bias[MBW], ct_ws[MBW];
+#pragma unroll
+  for (int mi = 0; mi < MBW; ++mi) {
+    const int mb = wave + 4 * mi;
+    const unsigned char* wrow =
+        static_cast<const unsigned char*>(a.ct.W) + (int64_t)(mb * 16 + lr) * (a.ct.Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < KCT; ++c) {
+      tlo[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+      thi[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+    }
+    const int m = mb * 16 + lg * 4;
+    ct_bias[mi] = *reinterpret_cast<const f4*>(a.ct.B + (m - (m / MT) * MT));
+    ct_ws[mi] = PREC == 2 ? *reinterpret_cast<const f4*>(a.ct.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  }
+  const int m_cv = wm * 16 + lg * 4;
+  const f4 bias = *reinterpret_cast<const f4*>(a.B + m_cv);
+  const f4 wsc = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m_cv) : f4{1.f, 1.f, 1.f, 1.f};
 
   // ---- the streams of the tile ----
   if (tid == 0) {
@@ -722,19 +752,23 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
     c.nq = g.t_hi / R - c.qa + 1;
     c.carry_col = g.t_hi == T - 1 ? 1 : 0;
     c.col0 = 0;
+    c.xrow0 = 0;
     csegs[tid] = c;
   }
   __syncthreads();
   if (tid == 0) {
-    int32_t b = 0, col = 0;
+    int32_t b = 0, col = 0, cp = 0;
     for (int s = 0; s < n_seg && s < kMaxStreams; ++s) {
       segs[s].base = b;
       b += segs[s].rows;
       csegs[s].col0 = col;
+      csegs[s].xrow0 = col + s;     // one more staged row than columns per stream
       col += csegs[s].nq + csegs[s].carry_col;
+      cp += max(0, min(L - segs[s].r0, segs[s].rows)) * (MT / 4);
     }
     tile_info[2] = b;
-    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap && col <= col_cap) ? 1 : 0;
+    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap && col <= NCB * 16 && col + n_seg <= xrow_cap &&
+                    cp <= stash_cap && cp <= CPRE * kThreads) ? 1 : 0;
     tile_info[4] = col;
   }
   __syncthreads();
@@ -742,7 +776,56 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
   if (!tile_info[3]) return;
   const int32_t n_ccol = tile_info[4];
 
-  // column -> stream and window row (the conv), transposed-conv column -> (stream, q)
+  // ---- transposed-conv input frames qa - 1 .. qa + nq - 1 (+1 with the carry column), each once, and
+  // the window's cache rows (rows below L): every load of the tile in flight at once ----
+  u4 xv[XP];
+  f4 cpre[CPRE];
+  int32_t cdst[CPRE];
+  {
+    const int32_t n_pieces = (n_ccol + n_seg) * PPR;
+    const unsigned char* tin = static_cast<const unsigned char*>(a.ct.in_twin);
+#pragma unroll
+    for (int p = 0; p < XP; ++p) {
+      const int32_t idx = tid + p * kThreads;
+      xv[p] = u4{0u, 0u, 0u, 0u};
+      if (idx < n_pieces) {
+        const int xr = idx / PPR;
+        const int pc = idx - xr * PPR;
+        int s = 0;
+        while (s + 1 < n_seg && csegs[s + 1].xrow0 <= xr) ++s;
+        const int row = csegs[s].qa - 1 + (xr - csegs[s].xrow0);
+        const int ci = pc * EPP;
+        if (ci < a.ct.cin && row >= 0 && row < csegs[s].Tin)
+          xv[p] = *reinterpret_cast<const u4*>(tin + ((int64_t)(csegs[s].in_start + row) * a.ct.cin + ci) * ES);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < CPRE; ++p) {
+      cdst[p] = -1;
+      int32_t idx = tid + p * kThreads;
+      for (int s = 0; s < n_seg; ++s) {
+        const WinSeg& g = segs[s];
+        const int32_t n = max(0, min(L - g.r0, g.rows)) * (MT / 4);
+        if (idx < n) {
+          const int32_t i = idx / (MT / 4);
+          const int ch = (idx - i * (MT / 4)) * 4;
+          cpre[p] = *reinterpret_cast<const f4*>(g.cache + (int64_t)(g.r0 + i) * MT + ch);
+          cdst[p] = (g.base + i) * MT + ch;
+          break;
+        }
+        idx -= n;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < XP; ++p) {
+      const int32_t idx = tid + p * kThreads;
+      if (idx < n_pieces) *reinterpret_cast<u4*>(X + (idx / PPR) * XROW + (idx % PPR) * 16) = xv[p];
+    }
+#pragma unroll
+    for (int p = 0; p < CPRE; ++p)
+      if (cdst[p] >= 0) stash[tid + p * kThreads] = cpre[p];
+  }
+  // column -> stream and window row (the conv), transposed-conv column -> (stream, q, staged row)
   if (tid < F) {
     const int32_t f = f0 + tid;
     int s = 0;
@@ -756,86 +839,52 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
     colseg[tid] = (int8_t)s;
   }
   for (int j = tid; j < NCB * 16; j += kThreads) {
-    int s = -1, q = 0;
+    int s = -1, q = 0, x = 0;
     if (j < n_ccol) {
       s = 0;
       while (s + 1 < n_seg && csegs[s + 1].col0 <= j) ++s;
       q = csegs[s].qa + (j - csegs[s].col0);   // the carry column: q = qa + nq = T_in
+      x = csegs[s].xrow0 + (j - csegs[s].col0);
     }
     ccol_seg[j] = (int8_t)s;
     ccol_q[j] = q;
-  }
-  __syncthreads();
-
-  // ---- transposed-conv B operand: column (s, q) = [input q - 1 | input q] ----
-  {
-    const int ppc = KCT * 8;                  // 16-byte pieces per column
-    const int32_t n_pieces = n_ccol * ppc;
-    const unsigned char* tin = static_cast<const unsigned char*>(a.ct.in_twin);
-    for (int32_t idx = tid; idx < n_pieces; idx += kThreads) {
-      const int col = idx / ppc;
-      const int pc = idx - col * ppc;
-      const int s = ccol_seg[col];
-      const int q = ccol_q[col];
-      const int kk = pc * EPP;
-      const int h = kk >= a.ct.half_pad;
-      const int ci = kk - h * a.ct.half_pad;
-      const int row = q - 1 + h;
-      u4 v = {0u, 0u, 0u, 0u};
-      if (ci < a.ct.cin && row >= 0 && row < csegs[s].Tin)
-        v = *reinterpret_cast<const u4*>(tin + ((int64_t)(csegs[s].in_start + row) * a.ct.cin + ci) * ES);
-      *reinterpret_cast<u4*>(X + col * BROW + pc * 16) = v;
-    }
+    ccol_x[j] = x;
   }
   __syncthreads();
 
   // ---- transposed-conv MFMAs: the wave's M blocks x every column block ----
   const int ncb = (n_ccol + 15) / 16;
   f4 cacc[MBW][NCB];
-  {
-    const unsigned char* Wt = static_cast<const unsigned char*>(a.ct.W);
 #pragma unroll
-    for (int mi = 0; mi < MBW; ++mi) {
-      const int mb = wave + 4 * mi;
-      if (mb >= nmb) break;
-      u4 tlo[KCT], thi[KCT];
-      const unsigned char* wrow = Wt + (int64_t)(mb * 16 + lr) * (a.ct.Kpad * ES) + lg * 32;
+  for (int mi = 0; mi < MBW; ++mi) {
+    const int m = (wave + 4 * mi) * 16 + lg * 4;   // the lane's rows m .. m + 3 (accumulator layout)
 #pragma unroll
-      for (int c = 0; c < KCT; ++c) {
-        tlo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
-        thi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
-      }
-      const int m = mb * 16 + lg * 4;          // the lane's rows m .. m + 3 (accumulator layout)
+    for (int nc = 0; nc < NCB; ++nc) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      if (nc < ncb) {
+        const int col = nc * 16 + lr;
+        const int s = ccol_seg[col];
+        // column q = 0 of a buffer starts from the carry
+        if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = *reinterpret_cast<const f4*>(csegs[s].carry + m);
+        const unsigned char* xb = X + ccol_x[col] * XROW + lg * 32;
 #pragma unroll
-      for (int nc = 0; nc < NCB; ++nc) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        if (nc < ncb) {
-          const int col = nc * 16 + lr;
-          const int s = ccol_seg[col];
-          // column q = 0 of a buffer starts from the carry
-          if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = *reinterpret_cast<const f4*>(csegs[s].carry + m);
-#pragma unroll
-          for (int c = 0; c < KCT; ++c) {
-            const unsigned char* p = X + col * BROW + c * 128 + lg * 32;
-            acc = mfma32<PREC>(tlo[c], thi[c], *reinterpret_cast<const u4*>(p), *reinterpret_cast<const u4*>(p + 16), acc);
-          }
+        for (int c = 0; c < KCT; ++c) {
+          const unsigned char* p = xb + (c / CPH) * XROW + (c % CPH) * 128;
+          acc = mfma32<PREC>(tlo[mi][c], thi[mi][c], *reinterpret_cast<const u4*>(p),
+                             *reinterpret_cast<const u4*>(p + 16), acc);
         }
-        cacc[mi][nc] = acc;
       }
+      cacc[mi][nc] = acc;
     }
   }
-  __syncthreads();   // every wave is past the B operand: X now takes x's FP32 rows
+  __syncthreads();   // every wave is past the staged input: X now takes x's FP32 rows
 
   // ---- x: bias, mask, FP32 rows, operand rows, the conv's next cache, the next carry ----
 #pragma unroll
   for (int mi = 0; mi < MBW; ++mi) {
-    const int mb = wave + 4 * mi;
-    if (mb >= nmb) break;
-    const int m = mb * 16 + lg * 4;
+    const int m = (wave + 4 * mi) * 16 + lg * 4;
     const int phi = m / MT;
     const int co = m - phi * MT;
-    const f4 bias = *reinterpret_cast<const f4*>(a.ct.B + co);
-    const f4 ws = PREC == 2 ? *reinterpret_cast<const f4*>(a.ct.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
 #pragma unroll
     for (int nc = 0; nc < NCB; ++nc) {
       const int col = nc * 16 + lr;
@@ -849,8 +898,8 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
         continue;
       }
       f4 v = cacc[mi][nc];
-      if (PREC == 2) v = v * (ws * a.ct.act_scale);
-      v = v + bias;
+      if (PREC == 2) v = v * (ct_ws[mi] * a.ct.act_scale);
+      v = v + ct_bias[mi];
       const int32_t t = q * R + phi;           // x frame of the stream
       if ((int64_t)t * a.in_den < c.mask_lo || (int64_t)t * a.in_den >= c.mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
       const WinSeg& g = segs[s];
@@ -875,34 +924,29 @@ __global__ void __launch_bounds__(kThreads, 4) convt_win_kernel(LayerArgs a, int
     }
   }
   // window rows from the conv's cache (rows below L)
-  for (int s = 0; s < n_seg; ++s) {
-    const WinSeg& g = segs[s];
-    const int32_t nc_rows = max(0, min(L - g.r0, g.rows));   // uniform
-    for (int32_t j = tid; j < nc_rows * (MT / 4); j += kThreads) {
-      const int32_t i = j / (MT / 4);
-      const int ch = (j - i * (MT / 4)) * 4;
-      const f4 v = *reinterpret_cast<const f4*>(g.cache + (int64_t)(g.r0 + i) * MT + ch);
-      const int32_t jr = g.base + i;
-      *reinterpret_cast<f4*>(xf + (size_t)jr * MT + ch) = v;
-      unsigned char* dst = wop + (size_t)jr * rowb + ch * ES;
-      if constexpr (PREC == 1) {
-        uint2 u;
-        u.x = wpack_bf16(act(v.x, pre), act(v.y, pre));
-        u.y = wpack_bf16(act(v.z, pre), act(v.w, pre));
-        *reinterpret_cast<uint2*>(dst) = u;
-      } else {
-        *reinterpret_cast<uint32_t*>(dst) =
-            wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
-      }
+#pragma unroll
+  for (int p = 0; p < CPRE; ++p) {
+    if (cdst[p] < 0) continue;
+    const f4 v = stash[tid + p * kThreads];
+    *reinterpret_cast<f4*>(xf + cdst[p]) = v;
+    const int32_t jr = cdst[p] / MT;
+    const int ch = cdst[p] - jr * MT;
+    unsigned char* dst = wop + (size_t)jr * rowb + ch * ES;
+    if constexpr (PREC == 1) {
+      uint2 u;
+      u.x = wpack_bf16(act(v.x, pre), act(v.y, pre));
+      u.y = wpack_bf16(act(v.z, pre), act(v.w, pre));
+      *reinterpret_cast<uint2*>(dst) = u;
+    } else {
+      *reinterpret_cast<uint32_t*>(dst) =
+          wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
     }
   }
   __syncthreads();
 
   // ---- the conv: B operands from the staged rows, the skip from x's FP32 rows ----
-  const int m = wm * 16 + lg * 4;
-  const f4 bias = *reinterpret_cast<const f4*>(a.B + m);
-  const f4 wsc = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
-  const int n_chunks = Kpad * ES / 128;
+  const int m = m_cv;
+  constexpr int n_chunks = KCM;
   int cb[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) cb[nb] = colbase[wn * (F / WN) + nb * 16 + lr] * rowb;
@@ -1158,15 +1202,19 @@ int ct_col_blocks(int prec, int mt, int kct, int mbw) {
   if (mt == 32 && mbw == 1 && ((prec == 1 && kct == 2) || (prec == 2 && kct == 2))) return 6;
   return 0;
 }
-int64_t ct_lds_bytes(int64_t rows, int64_t cols, int mt, int prec, int kct) {
-  return std::max(cols * (kct * 128 + 16), rows * mt * 4) + rows * (mt * w_esize(prec) + 16);
+// staged input rows of kct * 64 bytes (+16), overlaid by the FP32 window
+// rows, then the operand rows
+int64_t ct_lds_bytes(int64_t rows, int64_t xrows, int64_t stash, int mt, int prec, int kct) {
+  return std::max(xrows * (kct * 64 + 16), rows * mt * 4) + stash * 16 + rows * (mt * w_esize(prec) + 16);
 }
 }  // namespace
 
 int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_cin, int prec, int64_t min_frames,
-                       int32_t* col_cap) {
-  *col_cap = 0;
-  if (prec < 1 || prec > 2 || r < 1 || ct_cin < 1) return 0;
+                       int32_t* xrow_cap, int32_t* stash_cap) {
+  *xrow_cap = 0;
+  *stash_cap = 0;
+  // the transposed conv's input frames are staged in 16-byte pieces
+  if (prec < 1 || prec > 2 || r < 1 || ct_cin < 1 || ct_cin % (16 / w_esize(prec)) != 0) return 0;
   const int32_t rows = conv_win_rows(cin, cout, k, dil, 1, L, min_frames, prec);
   const int MT = win_mt(cout);
   // one M tile, a residual conv (cin == cout), and every stream bringing at
@@ -1180,37 +1228,45 @@ int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_c
   const int F = win_f(MT, 4);
   const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;
   // per stream: its x frames (its own plus L before) over r, two partial
-  // columns at the ends, and the carry column
-  int64_t cols = (F + (int64_t)L * max_seg + r - 1) / r + 3 * max_seg;
-  cols = (cols + 15) / 16 * 16;
-  if (cols > ncb * 16 || ct_lds_bytes(rows, cols, MT, prec, kct) > 64 * 1024) return 0;
-  *col_cap = (int32_t)cols;
+  // columns at the ends, and the carry column; one staged input row more
+  // than columns per stream; the window's cache rows fit two f4 per thread
+  const int64_t cols = (F + (int64_t)L * max_seg + r - 1) / r + 3 * max_seg;
+  const int64_t xrows = (cols + max_seg + 15) / 16 * 16;
+  const int64_t stash = max_seg * L * (MT / 4);
+  const int kc_conv = w_kchunk(prec);
+  const int kcm = (k * cin + kc_conv - 1) / kc_conv * kc_conv * w_esize(prec) / 128;
+  if (cols > ncb * 16 || stash > 2 * 256 || ct_lds_bytes(rows, xrows, stash, MT, prec, kct) > 64 * 1024 ||
+      kcm != (prec == 1 ? 2 : 1))
+    return 0;
+  *xrow_cap = (int32_t)xrows;
+  *stash_cap = (int32_t)stash;
   return rows;
 }
 
-hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t col_cap, hipStream_t s) {
+hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t xrow_cap, int32_t stash_cap,
+                            hipStream_t s) {
   const int MT = win_mt(a.cout);
   const int NB = win_nb(a.cin);
   const int F = win_f(MT, NB);
-  const int KCM = win_kcm(prec, a.cin);
   const int kc = w_kchunk(prec);
   const int Kreal = a.k * a.cin;
   const int Kpad = (Kreal + kc - 1) / kc * kc;
+  const int KCM = Kpad * w_esize(prec) / 128;
   const int kct = a.ct.Kpad * w_esize(prec) / 128;
   const int mbw = a.ct.r * MT / 64;
-  if (a.cout != MT || NB != 4 || a.ct.r <= 0 || a.fd_cin.d != (uint32_t)a.cin || !a.out_buf ||
-      ct_col_blocks(prec, MT, kct, mbw) * 16 < col_cap)
+  if (a.cout != MT || NB != 4 || a.ct.r <= 0 || a.ct.r * MT != 64 * mbw || kct % 2 != 0 ||
+      a.fd_cin.d != (uint32_t)a.cin || !a.out_buf || ct_col_blocks(prec, MT, kct, mbw) == 0)
     return hipErrorInvalidValue;
   const int64_t n_nt = (a.n_out + F - 1) / F;
   if (n_nt <= 0) return hipSuccess;
-  const size_t lds = (size_t)ct_lds_bytes(row_cap, col_cap, MT, prec, kct);
+  const size_t lds = (size_t)ct_lds_bytes(row_cap, xrow_cap, stash_cap, MT, prec, kct);
 #define SC_CTWIN(P, M, K, KT, MB, NCB)                                                                      \
   if (prec == P && MT == M && KCM == K && kct == KT && mbw == MB) {                                        \
     hipLaunchKernelGGL((convt_win_kernel<P, M, 4, K, KT, MB, NCB>), dim3((unsigned)n_nt), dim3(kThreads), lds, \
-                       s, a, (int)n_nt, Kpad, Kreal, row_cap, col_cap);                                     \
+                       s, a, (int)n_nt, Kpad, Kreal, row_cap, xrow_cap, stash_cap);                                     \
     return hipGetLastError();                                                                              \
   }
-  SC_CTWIN(1, 32, 3, 2, 1, 6) SC_CTWIN(2, 32, 2, 2, 1, 6)
+  SC_CTWIN(1, 32, 2, 2, 1, 6) SC_CTWIN(2, 32, 1, 2, 1, 6)
 #undef SC_CTWIN
   return hipErrorInvalidValue;
 }

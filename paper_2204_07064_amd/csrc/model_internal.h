@@ -21,8 +21,9 @@ struct OpDev {
   float* wscale = nullptr;  // fp8 per-row scales
   int prec = 0;             // precision of this op's kernel
   int32_t win_rows = 0;     // IMPL_WIN: LDS window rows per tile
-  int32_t ct_rows = 0, ct_cols = 0;   // window conv with the transposed conv in its launch:
-                                      // window rows and transposed-conv columns per tile
+  int32_t ct_rows = 0, ct_xrows = 0, ct_stash = 0;   // window conv with the transposed conv in its
+                                                     // launch: window rows, staged transposed-conv input
+                                                     // frames and cache-row pieces per tile
 };
 
 // A slot of the descriptor ring: pinned host staging + device copy + event.

@@ -168,14 +168,15 @@ void fuse_convt_windows(sc_model* m) {
     if (ct.kind != K_CONVT || ct.impl != IMPL_MFMA || ct.in_twin < 0 || ct.prec != cv.prec || ct.out_twin >= 0)
       continue;
     const int64_t min_frames = cv.in_rate.of(pl.input_multiple);
-    int32_t cols = 0;
+    int32_t xrows = 0, stash = 0;
     const int32_t rows = convt_win_rows(cv.cin, cv.cout, cv.k, cv.dil, cv.cache_len, ct.stride, ct.cin, cv.prec,
-                                        min_frames, &cols);
+                                        min_frames, &xrows, &stash);
     if (rows <= 0) continue;
     cv.convt_in = c;
     ct.convt_in = (int32_t)w;
     m->opdev[w].ct_rows = rows;
-    m->opdev[w].ct_cols = cols;
+    m->opdev[w].ct_xrows = xrows;
+    m->opdev[w].ct_stash = stash;
   }
 }
 
@@ -470,7 +471,7 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
       aw.ct.delay = ct.out_delay;
       aw.ct.state_off = ct.state_off;
       aw.ct.state_len = ct.state_len;
-      e = launch_convt_win(aw, prec, m->opdev[oi].ct_rows, m->opdev[oi].ct_cols, ls.hs);
+      e = launch_convt_win(aw, prec, m->opdev[oi].ct_rows, m->opdev[oi].ct_xrows, m->opdev[oi].ct_stash, ls.hs);
     } else if (op.impl == IMPL_WIN) {
       LayerArgs aw = a;
       if (fused) {
