@@ -82,6 +82,55 @@ __device__ inline int32_t out_frames(const LayerArgs& a, int32_t x) { return (in
 // rate's numerator times the granule)
 __device__ inline int entry_of_in(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_in_num, (uint32_t)n * a.in_den)]; }
 __device__ inline int entry_of_out(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_out_num, (uint32_t)n * a.out_den)]; }
+
+// A stream record read whole: seven 8-byte loads issued together, all
+// complete before any field is used (the compiler would otherwise issue each
+// field's load in the branch that uses it, one round trip after another).
+static_assert(sizeof(Entry) == 56, "Entry is read as seven 8-byte words");
+__device__ inline Entry load_entry(const Entry* p) {
+  const uint2* src = reinterpret_cast<const uint2*>(p);
+  uint2 w[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) w[i] = src[i];
+  asm volatile("" ::"v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]), "v"(w[6]));
+  Entry e;
+  __builtin_memcpy(&e, w, sizeof(Entry));
+  return e;
+}
+
+// The step descriptor seen through the constant address space: it is
+// read-only during a launch, so reads whose address is the same for the
+// whole workgroup become scalar loads.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+// The streams of a tile of output frames [f0, f0 + F) of a layer: the step's
+// output frames, the tile's last frame in the step, its first stream and how
+// many streams it touches.  Every wave finds them itself, in one round of
+// scalar loads: the step header and the frame-table entries of the tile's
+// first frame and of f0 + F - 1 -- read before it is known whether that frame
+// lies in the step (the table has spare slots after the step's granules, and
+// the value is used only if it does; otherwise the tile ends at the step's
+// last stream).  The empty asm keeps the compiler from moving the two table
+// reads behind the caller's test of f0 against the step's size.
+struct TileSpan {
+  int32_t n_cols, f_last, e0, n_seg;
+};
+__device__ inline TileSpan tile_span(const LayerArgs& a, int32_t f0, int32_t F) {
+  const cptr<int32_t> hdr = (cptr<int32_t>)a.hdr;
+  const cptr<int32_t> fent = (cptr<int32_t>)a.fent;
+  const int32_t n_ent = hdr[0];
+  const int32_t n_in = hdr[1];
+  const int32_t e0 = fent[fdiv(a.fd_out_num, (uint32_t)f0 * a.out_den)];
+  const int32_t e1 = fent[fdiv(a.fd_out_num, (uint32_t)(f0 + F - 1) * a.out_den)];
+  asm volatile("" ::"s"(n_ent), "s"(n_in), "s"(e0), "s"(e1));
+  TileSpan t;
+  t.n_cols = (int32_t)fdiv(a.fd_out_den, (uint32_t)n_in * a.out_num);
+  t.f_last = min(f0 + F, t.n_cols) - 1;
+  t.e0 = e0;
+  t.n_seg = (f0 + F - 1 < t.n_cols ? e1 : n_ent - 1) - e0 + 1;
+  return t;
+}
 // Output frames of stream e that are zeroed, as a range of t * out_den for
 // local output frame t: below mask_lo the warm-up mask (absolute output frame
 // pos*num/den + t before the layer's delay), from mask_hi on the end of a

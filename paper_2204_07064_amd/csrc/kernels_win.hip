@@ -317,7 +317,6 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   __shared__ WinSeg2 segs2[FUSE ? kMaxStreams : 1];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
-  __shared__ int32_t tile_info[4];   // e_first, n_seg, total rows, ok
 
   const int tid = threadIdx.x;
   const int32_t n_tiles = n_mt * n_nt;
@@ -347,9 +346,9 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   const int32_t nt = (int32_t)((uint32_t)bid / (uint32_t)n_mt);
   const int m0 = mt * MT;
   const int32_t f0 = nt * F;
-  const int32_t n_cols = step_out(a);   // the grid may be sized for a larger step
-  if (f0 >= n_cols) return;
-  const int32_t f_last = min(f0 + F, n_cols) - 1;
+  const TileSpan sp = tile_span(a, f0, F);
+  if (f0 >= sp.n_cols) return;          // the grid may be sized for a larger step
+  const int32_t f_last = sp.f_last;
 
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -393,56 +392,49 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     if (lr < a.oc.k) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * MT + m2);
   }
 
-  // ---- the streams of the tile ----
-  if (tid == 0) {
-    const int e0 = entry_of_out(a, f0);
-    const int e1 = entry_of_out(a, f_last);
-    tile_info[0] = e0;
-    tile_info[1] = e1 - e0 + 1;
-  }
-  __syncthreads();
-  const int e_first = tile_info[0];
-  const int n_seg = tile_info[1];
-  if (tid < n_seg && tid < kMaxStreams) {
-    const Entry& e = a.ents[e_first + tid];
-    WinSeg g;
-    g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-    g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
-    g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
-    g.in_start = in_frames(a, e.off);
-    g.out_start = out_frames(a, e.off);
-    const int32_t T = out_frames(a, e.T);
-    g.t_lo = tid == 0 ? f0 - g.out_start : 0;
-    g.t_hi = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
-    g.r0 = g.t_lo;
-    g.rows = g.t_hi - g.t_lo + 1 + a.L;
-    g.base = 0;
-    segs[tid] = g;
-    if constexpr (FUSE) {
-      WinSeg2 g2;
-      g2.T = T;
-      g2.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
-      g2.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
-      g2.out2 = e.out;
-      g2.mask2_x = mask_lo(e, a.oc.delay, a.out_num, a.out_den);
-      g2.mask2_hi = mask_hi(e, a.oc.delay, a.out_num, a.out_den);
-      segs2[tid] = g2;
+  // ---- the streams of the tile: lane s of every wave forms stream s's
+  // record; wave 0 publishes them ----
+  const int e_first = sp.e0;
+  const int n_seg = sp.n_seg;
+  // the host sizes tiles so that these hold; never index LDS beyond them
+  if (n_seg > kMaxStreams) return;
+  int32_t R = 0;
+  {
+    const Entry e = load_entry(a.ents + e_first + min(lane, n_seg - 1));
+    WinSeg g{};
+    if (lane < n_seg) {
+      g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+      g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
+      g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
+      g.in_start = in_frames(a, e.off);
+      g.out_start = out_frames(a, e.off);
+      g.t_lo = lane == 0 ? f0 - g.out_start : 0;
+      g.t_hi = lane == n_seg - 1 ? f_last - g.out_start : out_frames(a, e.T) - 1;
+      g.r0 = g.t_lo;
+      g.rows = g.t_hi - g.t_lo + 1 + a.L;
+    }
+    // each stream's first LDS row: the rows of the streams before it
+    for (int s = 0; s < n_seg; ++s) {
+      const int32_t r = __shfl(g.rows, s);
+      g.base += s < lane ? r : 0;
+      R += r;
+    }
+    if (wave == 0 && lane < n_seg) {
+      segs[lane] = g;
+      if constexpr (FUSE) {
+        WinSeg2 g2;
+        g2.T = out_frames(a, e.T);
+        g2.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
+        g2.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
+        g2.out2 = e.out;
+        g2.mask2_x = mask_lo(e, a.oc.delay, a.out_num, a.out_den);
+        g2.mask2_hi = mask_hi(e, a.oc.delay, a.out_num, a.out_den);
+        segs2[lane] = g2;
+      }
     }
   }
+  if (R > row_cap) return;
   __syncthreads();
-  if (tid == 0) {
-    int32_t b = 0;
-    for (int s = 0; s < n_seg && s < kMaxStreams; ++s) {
-      segs[s].base = b;
-      b += segs[s].rows;
-    }
-    tile_info[2] = b;
-    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap) ? 1 : 0;
-  }
-  __syncthreads();
-  // the host sizes tiles so that this holds; never index LDS beyond it
-  if (!tile_info[3]) return;
-  const int32_t R = tile_info[2];
 
   // column -> stream, and the LDS row of its window row t
   if (tid < F) {
@@ -656,15 +648,14 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   __shared__ int8_t ccol_seg[NCB * 16];
   __shared__ int32_t ccol_q[NCB * 16];
   __shared__ int32_t ccol_x[NCB * 16];
-  __shared__ int32_t tile_info[5];   // e_first, n_seg, total rows, ok, transposed-conv columns
 
   const int tid = threadIdx.x;
   const int32_t nt = blockIdx.x;
   if (nt >= n_nt) return;
   const int32_t f0 = nt * F;
-  const int32_t n_cols = step_out(a);   // the grid may be sized for a larger step
-  if (f0 >= n_cols) return;
-  const int32_t f_last = min(f0 + F, n_cols) - 1;
+  const TileSpan sp = tile_span(a, f0, F);
+  if (f0 >= sp.n_cols) return;          // the grid may be sized for a larger step
+  const int32_t f_last = sp.f_last;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -711,70 +702,67 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   const f4 bias = *reinterpret_cast<const f4*>(a.B + m_cv);
   const f4 wsc = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m_cv) : f4{1.f, 1.f, 1.f, 1.f};
 
-  // ---- the streams of the tile ----
-  if (tid == 0) {
-    const int e0 = entry_of_out(a, f0);
-    const int e1 = entry_of_out(a, f_last);
-    tile_info[0] = e0;
-    tile_info[1] = e1 - e0 + 1;
-  }
-  __syncthreads();
-  const int e_first = tile_info[0];
-  const int n_seg = tile_info[1];
-  if (tid < n_seg && tid < kMaxStreams) {
-    const Entry& e = a.ents[e_first + tid];
-    WinSeg g;
-    g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-    g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
-    g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
-    g.in_start = in_frames(a, e.off);
-    g.out_start = out_frames(a, e.off);
-    const int32_t T = out_frames(a, e.T);
-    g.t_lo = tid == 0 ? f0 - g.out_start : 0;
-    g.t_hi = tid == n_seg - 1 ? f_last - g.out_start : T - 1;
-    g.r0 = g.t_lo;
-    g.rows = g.t_hi - g.t_lo + 1 + L;
-    g.base = 0;
-    segs[tid] = g;
-    CtSeg c;
-    c.carry = e.state + a.ct.state_off + (int64_t)e.parity * a.ct.state_len;
-    c.carry_next = e.state + a.ct.state_off + (int64_t)(1 - e.parity) * a.ct.state_len;
-    c.cache_next = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
-    // x is this layer's input: its mask runs at the input rate
-    c.mask_lo = mask_lo(e, a.ct.delay, a.in_num, a.in_den);
-    c.mask_hi = mask_hi(e, a.ct.delay, a.in_num, a.in_den);
-    c.in_start = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.off * a.ct.in_num);
-    c.Tin = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.T * a.ct.in_num);
-    c.T = T;
-    // x frames of the window: [max(0, t_lo - L), t_hi] -> q in [qa, t_hi / r]
-    const int32_t ta = max(0, g.t_lo - L);
-    c.qa = ta / R;
-    c.nq = g.t_hi / R - c.qa + 1;
-    c.carry_col = g.t_hi == T - 1 ? 1 : 0;
-    c.col0 = 0;
-    c.xrow0 = 0;
-    csegs[tid] = c;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int32_t b = 0, col = 0, cp = 0;
-    for (int s = 0; s < n_seg && s < kMaxStreams; ++s) {
-      segs[s].base = b;
-      b += segs[s].rows;
-      csegs[s].col0 = col;
-      csegs[s].xrow0 = col + s;     // one more staged row than columns per stream
-      col += csegs[s].nq + csegs[s].carry_col;
-      cp += max(0, min(L - segs[s].r0, segs[s].rows)) * (MT / 4);
+  // ---- the streams of the tile: lane s of every wave forms stream s's
+  // records; wave 0 publishes them ----
+  const int e_first = sp.e0;
+  const int n_seg = sp.n_seg;
+  // the host sizes tiles so that these hold; never index LDS beyond them
+  if (n_seg > kMaxStreams) return;
+  int32_t n_rows = 0, n_ccol = 0, n_cp = 0;
+  {
+    WinSeg g{};
+    CtSeg c{};
+    int32_t ncols = 0, cpieces = 0;
+    const Entry e = load_entry(a.ents + e_first + min(lane, n_seg - 1));
+    if (lane < n_seg) {
+      g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+      g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
+      g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
+      g.in_start = in_frames(a, e.off);
+      g.out_start = out_frames(a, e.off);
+      const int32_t T = out_frames(a, e.T);
+      g.t_lo = lane == 0 ? f0 - g.out_start : 0;
+      g.t_hi = lane == n_seg - 1 ? f_last - g.out_start : T - 1;
+      g.r0 = g.t_lo;
+      g.rows = g.t_hi - g.t_lo + 1 + L;
+      c.carry = e.state + a.ct.state_off + (int64_t)e.parity * a.ct.state_len;
+      c.carry_next = e.state + a.ct.state_off + (int64_t)(1 - e.parity) * a.ct.state_len;
+      c.cache_next = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
+      // x is this layer's input: its mask runs at the input rate
+      c.mask_lo = mask_lo(e, a.ct.delay, a.in_num, a.in_den);
+      c.mask_hi = mask_hi(e, a.ct.delay, a.in_num, a.in_den);
+      c.in_start = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.off * a.ct.in_num);
+      c.Tin = (int32_t)fdiv(a.ct.fd_in_den, (uint32_t)e.T * a.ct.in_num);
+      c.T = T;
+      // x frames of the window: [max(0, t_lo - L), t_hi] -> q in [qa, t_hi / r]
+      const int32_t ta = max(0, g.t_lo - L);
+      c.qa = ta / R;
+      c.nq = g.t_hi / R - c.qa + 1;
+      c.carry_col = g.t_hi == T - 1 ? 1 : 0;
+      ncols = c.nq + c.carry_col;
+      cpieces = max(0, min(L - g.r0, g.rows)) * (MT / 4);
     }
-    tile_info[2] = b;
-    tile_info[3] = (n_seg <= kMaxStreams && b <= row_cap && col <= NCB * 16 && col + n_seg <= xrow_cap &&
-                    cp <= stash_cap && cp <= CPRE * kThreads) ? 1 : 0;
-    tile_info[4] = col;
+    // each stream's first window row, first column and first staged row
+    // (one more staged row than columns per stream): sums over the streams before it
+    for (int s = 0; s < n_seg; ++s) {
+      const int32_t r = __shfl(g.rows, s);
+      const int32_t nc = __shfl(ncols, s);
+      g.base += s < lane ? r : 0;
+      c.col0 += s < lane ? nc : 0;
+      n_rows += r;
+      n_ccol += nc;
+      n_cp += __shfl(cpieces, s);
+    }
+    c.xrow0 = c.col0 + lane;
+    if (wave == 0 && lane < n_seg) {
+      segs[lane] = g;
+      csegs[lane] = c;
+    }
   }
+  if (n_rows > row_cap || n_ccol > NCB * 16 || n_ccol + n_seg > xrow_cap || n_cp > stash_cap ||
+      n_cp > CPRE * kThreads)
+    return;
   __syncthreads();
-  // the host sizes tiles so that this holds; never index LDS beyond it
-  if (!tile_info[3]) return;
-  const int32_t n_ccol = tile_info[4];
 
   // ---- transposed-conv input frames qa - 1 .. qa + nq - 1 (+1 with the carry column), each once, and
   // the window's cache rows (rows below L): every load of the tile in flight at once ----

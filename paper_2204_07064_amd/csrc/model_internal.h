@@ -127,11 +127,18 @@ struct sc_stream {
 
 namespace sc {
 
+// Spare slots after a step's frame -> entry table: kernels read the entry of
+// a tile's last frame before they know whether that frame lies in the step
+// (a tile spans at most 128 frames, so at most 128 granules at any layer
+// rate); the value read there is never used.
+constexpr int64_t kFentPad = 256;
+
 // Bytes of a step descriptor for n streams and `frames` input frames; the
 // frame -> entry table has one entry per `granule` input frames (the model's
 // input multiple: every buffer is a whole number of granules).
 inline size_t desc_bytes(int n, int64_t frames, int64_t granule) {  // n: entry capacity
-  return kDescHeaderBytes + (size_t)n * sizeof(Entry) + (size_t)((frames + granule - 1) / granule) * sizeof(int32_t);
+  return kDescHeaderBytes + (size_t)n * sizeof(Entry) +
+         (size_t)((frames + granule - 1) / granule + kFentPad) * sizeof(int32_t);
 }
 
 // Checks a step's arguments; sets *total to its input frames.  No stream state

@@ -698,7 +698,8 @@ sc_status run_step(sc_model* m, int n, sc_stream* const* streams, const float* c
   }
   // a kernel reads the descriptor over PCIe: one short launch instead of a DMA
   // copy and its engine hand-off before the step's first kernel
-  e = launch_upload(slot.host_dev, graph ? m->graph_desc : slot.dev, need, hs);
+  // (the frame table's spare slots at the end are never used: not copied)
+  e = launch_upload(slot.host_dev, graph ? m->graph_desc : slot.dev, need - kFentPad * sizeof(int32_t), hs);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   if (h) {
     e = enqueue_split(m, slot.dev, n, h, fa, total, hs);
