@@ -69,9 +69,15 @@ struct LayerArgs {
   } ct;
 };
 
+// The step descriptor seen through the constant address space: it is
+// read-only during a launch, so reads whose address is the same for the
+// whole workgroup become scalar loads.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
 // ---- the step's actual size (device header) ----
-__device__ inline int32_t step_ents(const LayerArgs& a) { return a.hdr[0]; }
-__device__ inline int32_t step_frames(const LayerArgs& a) { return a.hdr[1]; }
+__device__ inline int32_t step_ents(const LayerArgs& a) { return ((cptr<int32_t>)a.hdr)[0]; }
+__device__ inline int32_t step_frames(const LayerArgs& a) { return ((cptr<int32_t>)a.hdr)[1]; }
 
 // ---- rate arithmetic without run-time division ----
 // frames of the input / output rate for x input frames of the step
@@ -97,12 +103,6 @@ __device__ inline Entry load_entry(const Entry* p) {
   __builtin_memcpy(&e, w, sizeof(Entry));
   return e;
 }
-
-// The step descriptor seen through the constant address space: it is
-// read-only during a launch, so reads whose address is the same for the
-// whole workgroup become scalar loads.
-template <class T>
-using cptr = const __attribute__((address_space(4))) T*;
 
 // The streams of a tile of output frames [f0, f0 + F) of a layer: the step's
 // output frames, the tile's last frame in the step, its first stream and how
@@ -141,6 +141,18 @@ __device__ inline int64_t mask_lo(const Entry& e, int64_t delay, uint32_t num, u
 }
 __device__ inline int64_t mask_hi(const Entry& e, int64_t delay, uint32_t num, uint32_t den) {
   return e.end > 0 ? delay * (int64_t)den + (e.end - e.pos) * (int64_t)num : INT64_MAX;
+}
+// The same masks as a range of kept local output frames: keep_lo <= t < keep_hi
+// (t * den < lo exactly when t < ceil(lo / den); the bounds clamped to int32).
+__device__ inline int32_t ceil_frames(int64_t x, uint32_t den) {
+  int64_t q = x / (int64_t)den;
+  if (x > 0 && q * (int64_t)den != x) ++q;
+  return (int32_t)max((int64_t)-1, min(q, (int64_t)INT32_MAX));
+}
+__device__ inline void keep_range(const Entry& e, int64_t delay, uint32_t num, uint32_t den, int32_t* lo,
+                                  int32_t* hi) {
+  *lo = ceil_frames(mask_lo(e, delay, num, den), den);
+  *hi = ceil_frames(mask_hi(e, delay, num, den), den);
 }
 __device__ inline bool masked(const LayerArgs& a, const Entry& e, int64_t t) {
   const int64_t x = t * a.out_den;

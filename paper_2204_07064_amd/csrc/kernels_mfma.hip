@@ -108,6 +108,8 @@ struct ColInfo {
   int32_t t;            // conv: local output frame; convt: q (== Tin for a carry column)
   int32_t in_start;     // first packed input frame of the stream
   int32_t Tin;          // input frames of the stream
+  int32_t keep_lo, keep_hi;   // local output frames outside [keep_lo, keep_hi) are zeroed (masks)
+  int32_t parity;       // the stream's current state copy (the other one is written)
 };
 
 template <bool CONVT>
@@ -119,15 +121,20 @@ __device__ inline ColInfo make_col(const LayerArgs& a, int32_t n, int32_t n_cols
   c.t = 0;
   c.in_start = 0;
   c.Tin = 0;
+  c.keep_lo = 0;
+  c.keep_hi = 0;
+  c.parity = 0;
   if (n >= n_cols) return c;
   int ei;
   if (CONVT) ei = n < step_in(a) ? entry_of_in(a, n) : n - (int32_t)step_in(a);
   else ei = entry_of_out(a, n);
-  const Entry& e = a.ents[ei];
+  const Entry e = load_entry(a.ents + ei);
   c.ei = ei;
   c.in_start = in_frames(a, e.off);
   c.Tin = in_frames(a, e.T);
   c.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;   // conv cache / convt carry copy
+  c.parity = e.parity;
+  keep_range(e, a.delay, a.out_num, a.out_den, &c.keep_lo, &c.keep_hi);
   if (CONVT) {
     c.t = n < step_in(a) ? n - c.in_start : c.Tin;
   } else {
@@ -199,7 +206,7 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
       const int32_t rem = (j - ei * per_ent) * 4;
       const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
       const int ci = rem - i * a.cin;
-      const Entry& e = a.ents[ei];
+      const Entry e = load_entry(a.ents + ei);
       const int32_t Tin = in_frames(a, e.T);
       const int32_t row = Tin + i;
       const int64_t src_in = ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
@@ -469,7 +476,6 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
   for (int j = 0; j < 2; ++j) {
     const ColInfo& c = cols[wn * 32 + j * 16 + lr];
     if (c.ei < 0) continue;
-    const Entry& e = a.ents[c.ei];
     const int32_t n = n0 + wn * 32 + j * 16 + lr;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -481,21 +487,21 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
         if (c.t >= c.Tin) {
           // carry column: FP32 partial sums of the next buffer's first frame,
           // kept in accumulator units (before the FP8 dequantization)
-          float* carry_out = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
+          float* carry_out = const_cast<float*>(c.cache) + (int64_t)(1 - 2 * c.parity) * a.state_len;
           *reinterpret_cast<f4*>(carry_out + m) = acc[i][j];
           continue;
         }
         const int phi = (int)fdiv(a.fd_cout, (uint32_t)m);
         v = v + ep_bias[i];
         const int32_t t = c.t * a.stride + phi;
-        if (masked(a, e, t)) v = f4{0.f, 0.f, 0.f, 0.f};
+        if (t < c.keep_lo || t >= c.keep_hi) v = f4{0.f, 0.f, 0.f, 0.f};
         const int64_t o = ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m;
         if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
         if (a.out_twin) store_twin4<PREC>(a, o, v);
       } else {
         v = v + ep_bias[i];
         if (a.residual) v = v + ep_skip[i][j];
-        if (masked(a, e, c.t)) v = f4{0.f, 0.f, 0.f, 0.f};
+        if (c.t < c.keep_lo || c.t >= c.keep_hi) v = f4{0.f, 0.f, 0.f, 0.f};
         if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + (int64_t)n * a.cout + m));
         if (a.out_twin) store_twin4<PREC>(a, (int64_t)n * a.cout + m, v);
       }

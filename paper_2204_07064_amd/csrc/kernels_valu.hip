@@ -521,12 +521,12 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
 __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, const int32_t* fent, FastDiv fd_gran,
                                                            const int32_t* hdr, int32_t C, float* out, void* twin,
                                                            int32_t twin_prec, int32_t twin_pre, float twin_qs) {
-  const int32_t n_frames = hdr[1];
+  const int32_t n_frames = ((cptr<int32_t>)hdr)[1];
   const int32_t total = n_frames * C;
   for (int32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
     const int c = idx / n_frames;   // frame fastest: coalesced reads of each channel row
     const int32_t f = idx - c * n_frames;
-    const Entry& e = ents[fent[fdiv(fd_gran, (uint32_t)f)]];
+    const Entry e = load_entry(ents + fent[fdiv(fd_gran, (uint32_t)f)]);
     const float v = e.in[(int64_t)c * e.T + (f - e.off)];
     out[(int64_t)f * C + c] = v;
     if (twin) store_twin1(twin, (int64_t)f * C + c, twin_prec, twin_pre, twin_qs, v);

@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
       const int32_t rem = (j - ei * per_ent) * 4;
       const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
       const int ci = rem - i * a.cin;
-      const Entry& e = a.ents[ei];
+      const Entry e = load_entry(a.ents + ei);
       const int32_t row = in_frames(a, e.T) + i;
       const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
                                    : a.in_buf + ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
 // x: written by the tiles that own them (every stream brings at least L
 // frames, so no old cache row survives).  Every global load that does not
 // depend on the staged data (both layers' weights, biases and scales, the
-// cache rows of the window) is issued before the first barrier.
+// cache rows of the window) is issued before the staging barrier.
 
 // Per-stream part of a fused tile (LDS): the transposed conv's side.
 struct CtSeg {
@@ -681,23 +681,6 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
     }
   }
-  // the transposed conv has r * MT = 64 * MBW rows: M block wave + 4 mi
-  u4 tlo[MBW][KCT], thi[MBW][KCT];
-  f4 ct_bias[MBW], ct_ws[MBW];
-#pragma unroll
-  for (int mi = 0; mi < MBW; ++mi) {
-    const int mb = wave + 4 * mi;
-    const unsigned char* wrow =
-        static_cast<const unsigned char*>(a.ct.W) + (int64_t)(mb * 16 + lr) * (a.ct.Kpad * ES) + lg * 32;
-#pragma unroll
-    for (int c = 0; c < KCT; ++c) {
-      tlo[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128);
-      thi[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
-    }
-    const int m = mb * 16 + lg * 4;
-    ct_bias[mi] = *reinterpret_cast<const f4*>(a.ct.B + (m - (m / MT) * MT));
-    ct_ws[mi] = PREC == 2 ? *reinterpret_cast<const f4*>(a.ct.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
-  }
   const int m_cv = wm * 16 + lg * 4;
   const f4 bias = *reinterpret_cast<const f4*>(a.B + m_cv);
   const f4 wsc = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m_cv) : f4{1.f, 1.f, 1.f, 1.f};
@@ -763,6 +746,25 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       n_cp > CPRE * kThreads)
     return;
   __syncthreads();
+
+  // the transposed conv's weights, bias and scales (r * MT = 64 * MBW rows: M
+  // block wave + 4 mi), issued with the staging loads below
+  u4 tlo[MBW][KCT], thi[MBW][KCT];
+  f4 ct_bias[MBW], ct_ws[MBW];
+#pragma unroll
+  for (int mi = 0; mi < MBW; ++mi) {
+    const int mb = wave + 4 * mi;
+    const unsigned char* wrow =
+        static_cast<const unsigned char*>(a.ct.W) + (int64_t)(mb * 16 + lr) * (a.ct.Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < KCT; ++c) {
+      tlo[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+      thi[mi][c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+    }
+    const int m = mb * 16 + lg * 4;
+    ct_bias[mi] = *reinterpret_cast<const f4*>(a.ct.B + (m - (m / MT) * MT));
+    ct_ws[mi] = PREC == 2 ? *reinterpret_cast<const f4*>(a.ct.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  }
 
   // ---- transposed-conv input frames qa - 1 .. qa + nq - 1 (+1 with the carry column), each once, and
   // the window's cache rows (rows below L): every load of the tile in flight at once ----
@@ -1037,7 +1039,7 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
     const int32_t f0 = (b + 1) * tile_frames;
     const int32_t f = f0 + (idx - b * a.L);
     if (f >= step_out(a)) return;   // the grid may be sized for a larger step
-    const Entry& e = a.ents[entry_of_out(a, f)];
+    const Entry e = load_entry(a.ents + entry_of_out(a, f));
     const int32_t out_start = out_frames(a, e.off);
     const int32_t t = f - out_start;
     if (!(out_start < f0 && f - a.L < f0) || t < a.L) return;   // its tile's, or a stream start
@@ -1061,7 +1063,7 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
   const bool live = ei < step_ents(a);   // uniform in the wave
   const bool pre = a.pre_act != 0;
   if (live) {
-    const Entry& e = a.ents[ei];
+    const Entry e = load_entry(a.ents + ei);
     const float* cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
     f4 P = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1077,7 +1079,7 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
   }
   __syncthreads();
   if (!live) return;
-  const Entry& e = a.ents[ei];
+  const Entry e = load_entry(a.ents + ei);
   const int32_t t = lane;
   if (t >= a.L || t >= out_frames(a, e.T)) return;
   const int32_t out_start = out_frames(a, e.off);
