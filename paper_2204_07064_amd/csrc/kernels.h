@@ -89,6 +89,23 @@ __device__ inline int32_t out_frames(const LayerArgs& a, int32_t x) { return (in
 __device__ inline int entry_of_in(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_in_num, (uint32_t)n * a.in_den)]; }
 __device__ inline int entry_of_out(const LayerArgs& a, int32_t n) { return a.fent[fdiv(a.fd_out_num, (uint32_t)n * a.out_den)]; }
 
+// Loads and stores through the global address space.  A pointer the
+// compiler cannot prove global (read from memory or LDS, or selected between
+// two) otherwise becomes a flat access, which also counts on the LDS
+// counter: every later wait for an LDS read then waits for it as well, and
+// loads meant to be in flight behind LDS work are waited for at once.
+// (T: a scalar or a native vector type such as f4 and u4)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ inline T gload(const void* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline void gstore(void* p, const T& v) {
+  *(gptr<T>)p = v;
+}
+
 // A stream record read whole: seven 8-byte loads issued together, all
 // complete before any field is used (the compiler would otherwise issue each
 // field's load in the branch that uses it, one round trip after another).

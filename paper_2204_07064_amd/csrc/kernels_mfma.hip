@@ -212,8 +212,8 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
       const int64_t src_in = ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
       const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
                                    : a.in_buf + src_in;
-      *reinterpret_cast<f4*>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci) =
-          *reinterpret_cast<const f4*>(src);
+      gstore<f4>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci,
+                 gload<f4>(src));
       if (INTWIN) {
         // 4 operand elements: 16, 8 or 4 bytes
         typedef typename Prec<PREC>::Elem T;
@@ -222,9 +222,9 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
             : static_cast<const T*>(a.in_twin) + src_in;
         T* tdst = reinterpret_cast<T*>(e.state + a.tstate_off + (int64_t)(1 - e.parity) * a.tstate_len) +
                   (int64_t)i * a.cin + ci;
-        if constexpr (sizeof(T) == 4) *reinterpret_cast<u4*>(tdst) = *reinterpret_cast<const u4*>(tsrc);
-        else if constexpr (sizeof(T) == 2) *reinterpret_cast<uint2*>(tdst) = *reinterpret_cast<const uint2*>(tsrc);
-        else *reinterpret_cast<uint32_t*>(tdst) = *reinterpret_cast<const uint32_t*>(tsrc);
+        if constexpr (sizeof(T) == 4) gstore<u4>(tdst, gload<u4>(tsrc));
+        else if constexpr (sizeof(T) == 2) gstore<uint64_t>(tdst, gload<uint64_t>(tsrc));
+        else gstore<uint32_t>(tdst, gload<uint32_t>(tsrc));
       }
     }
     return;
@@ -297,9 +297,9 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
         off_ = koff_;                                                                                        \
       }                                                                                                      \
       if constexpr (INTWIN) {                                                                                \
-        tb[ST][p_] = live_ ? *reinterpret_cast<const u4*>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};      \
+        tb[ST][p_] = live_ ? gload<u4>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};                         \
       } else {                                                                                               \
-        rb[ST][p_] = live_ ? *reinterpret_cast<const f4*>(base_ + off_ * 4) : f4{0.f, 0.f, 0.f, 0.f};     \
+        rb[ST][p_] = live_ ? gload<f4>(base_ + off_ * 4) : f4{0.f, 0.f, 0.f, 0.f};                       \
       }                                                                                                      \
     }                                                                                                        \
     if (!CONVT) {                                                                                            \
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
       // the lane's rows of this 16-row block: m .. m + 3
       const int m = m0 + wm * 32 + i * 16 + lg * 4;
       f4 cv = {0.f, 0.f, 0.f, 0.f};
-      if (from_carry && m < Mreal) cv = *reinterpret_cast<const f4*>(cj.cache + m);
+      if (from_carry && m < Mreal) cv = gload<f4>(cj.cache + m);
       acc[i][j] = cv;
     }
   }
@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
           const int row = c.t + a.skip_off;
           const float* sp = row < a.L ? c.cache + (int64_t)row * a.cin
                                       : a.in_buf + ((int64_t)c.in_start + row - a.L) * a.cin;
-          ep_skip[i][j] = *reinterpret_cast<const f4*>(sp + m);
+          ep_skip[i][j] = gload<f4>(sp + m);
         }
       }
     }
@@ -488,7 +488,7 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
           // carry column: FP32 partial sums of the next buffer's first frame,
           // kept in accumulator units (before the FP8 dequantization)
           float* carry_out = const_cast<float*>(c.cache) + (int64_t)(1 - 2 * c.parity) * a.state_len;
-          *reinterpret_cast<f4*>(carry_out + m) = acc[i][j];
+          gstore<f4>(carry_out + m, acc[i][j]);
           continue;
         }
         const int phi = (int)fdiv(a.fd_cout, (uint32_t)m);

@@ -216,7 +216,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
       // the output conv's next cache: the stream's last L2 frames (raw)
       const WinSeg2& g2 = segs2[s];
       const int32_t i = f0 + col - segs[s].out_start - (g2.T - L2);
-      if (i >= 0) *reinterpret_cast<f4*>(g2.cache2_next + (int64_t)i * MT + m) = v[nb];
+      if (i >= 0) gstore<f4>(g2.cache2_next + (int64_t)i * MT + m, v[nb]);
     }
     // the wave's 16 channels of the 16 columns: D[kk][col] = sum over them of
     // W[kk][c] * act(y[c][col]) on FP32 MFMA, the accumulator layout serving
@@ -240,8 +240,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     for (int j = tid; j < (L2 - g2.T) * (MT / 4); j += kThreads) {
       const int i = j / (MT / 4);
       const int c = (j - i * (MT / 4)) * 4;
-      *reinterpret_cast<f4*>(g2.cache2_next + (int64_t)i * MT + c) =
-          *reinterpret_cast<const f4*>(g2.cache2 + (int64_t)(g2.T + i) * MT + c);
+      gstore<f4>(g2.cache2_next + (int64_t)i * MT + c, gload<f4>(g2.cache2 + (int64_t)(g2.T + i) * MT + c));
     }
   }
   __syncthreads();
@@ -268,7 +267,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
           if (kk < k2) o = o + prow(col - L2 + d2 * kk, kk);
         if (a.oc.post_act == 2) o = tanhf(o);
         if ((int64_t)t * a.out_den < segs2[s].mask2_x || (int64_t)t * a.out_den >= segs2[s].mask2_hi) o = 0.f;
-        segs2[s].out2[t] = o;
+        gstore<float>(segs2[s].out2 + t, o);
       }
     }
   } else if (tid - F < F) {
@@ -336,8 +335,8 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
       const int32_t row = in_frames(a, e.T) + i;
       const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
                                    : a.in_buf + ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
-      *reinterpret_cast<f4*>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci) =
-          *reinterpret_cast<const f4*>(src);
+      gstore<f4>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci,
+                 gload<f4>(src));
     }
     return;
   }
@@ -480,7 +479,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
         if (idx < n_pieces) {
           const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
           const int pc = idx - j * ppr;
-          v[u] = *reinterpret_cast<const f4*>(rsrc[j] + pc * 4);
+          v[u] = gload<f4>(rsrc[j] + pc * 4);
         }
       }
 #pragma unroll
@@ -786,7 +785,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
         const int row = csegs[s].qa - 1 + (xr - csegs[s].xrow0);
         const int ci = pc * EPP;
         if (ci < a.ct.cin && row >= 0 && row < csegs[s].Tin)
-          xv[p] = *reinterpret_cast<const u4*>(tin + ((int64_t)(csegs[s].in_start + row) * a.ct.cin + ci) * ES);
+          xv[p] = gload<u4>(tin + ((int64_t)(csegs[s].in_start + row) * a.ct.cin + ci) * ES);
       }
     }
 #pragma unroll
@@ -799,7 +798,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
         if (idx < n) {
           const int32_t i = idx / (MT / 4);
           const int ch = (idx - i * (MT / 4)) * 4;
-          cpre[p] = *reinterpret_cast<const f4*>(g.cache + (int64_t)(g.r0 + i) * MT + ch);
+          cpre[p] = gload<f4>(g.cache + (int64_t)(g.r0 + i) * MT + ch);
           cdst[p] = (g.base + i) * MT + ch;
           break;
         }
@@ -855,7 +854,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
         const int col = nc * 16 + lr;
         const int s = ccol_seg[col];
         // column q = 0 of a buffer starts from the carry
-        if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = *reinterpret_cast<const f4*>(csegs[s].carry + m);
+        if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = gload<f4>(csegs[s].carry + m);
         const unsigned char* xb = X + ccol_x[col] * XROW + lg * 32;
 #pragma unroll
         for (int c = 0; c < KCT; ++c) {
@@ -884,7 +883,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       const CtSeg& c = csegs[s];
       if (q == c.Tin) {
         // the carry of the next buffer, in accumulator units
-        *reinterpret_cast<f4*>(c.carry_next + m) = cacc[mi][nc];
+        gstore<f4>(c.carry_next + m, cacc[mi][nc]);
         continue;
       }
       f4 v = cacc[mi][nc];
@@ -910,7 +909,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       }
       // the conv's next cache: the stream's last L frames of x, by the tile that owns them
       if (t >= c.T - L && t >= g.t_lo && t <= g.t_hi)
-        *reinterpret_cast<f4*>(c.cache_next + (int64_t)(t - (c.T - L)) * MT + co) = v;
+        gstore<f4>(c.cache_next + (int64_t)(t - (c.T - L)) * MT + co, v);
     }
   }
   // window rows from the conv's cache (rows below L)
@@ -1046,14 +1045,14 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
     float p[kOutTaps];
 #pragma unroll
     for (int kk = 0; kk < kOutTaps; ++kk)
-      p[kk] = kk < a.k ? a.in_buf[(int64_t)(f - a.L + a.dil * kk) * CIN + kk] : 0.f;
+      p[kk] = kk < a.k ? gload<float>(a.in_buf + (int64_t)(f - a.L + a.dil * kk) * CIN + kk) : 0.f;
     float o = a.B[0];
 #pragma unroll
     for (int kk = 0; kk < kOutTaps; ++kk)
       if (kk < a.k) o = o + p[kk];
     if (a.post_act == 2) o = tanhf(o);
     if (masked(a, e, t)) o = 0.f;
-    e.out[t] = o;
+    gstore<float>(e.out + t, o);
     return;
   }
   const int wave = threadIdx.x >> 6;
@@ -1070,7 +1069,7 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
     for (int g = 0; g < CIN / 16; ++g) {
       const int c = g * 16 + lg * 4;
       const f4 wa = lr < a.k ? *reinterpret_cast<const f4*>(W + lr * CIN + c) : f4{0.f, 0.f, 0.f, 0.f};
-      f4 y = lr < a.L ? *reinterpret_cast<const f4*>(cache + (int64_t)lr * CIN + c) : f4{0.f, 0.f, 0.f, 0.f};
+      f4 y = lr < a.L ? gload<f4>(cache + (int64_t)lr * CIN + c) : f4{0.f, 0.f, 0.f, 0.f};
       y = f4{act(y.x, pre), act(y.y, pre), act(y.z, pre), act(y.w, pre)};
       const f4 d = tap_mfma(wa, y);
       P = g == 0 ? d : P + d;
@@ -1088,12 +1087,12 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
   for (int kk = 0; kk < kOutTaps; ++kk) {
     if (kk < a.k) {
       const int w = t + a.dil * kk;   // row of [cache | new frames]
-      o = o + (w < a.L ? pc[wave][w][kk] : a.in_buf[(int64_t)(out_start + w - a.L) * CIN + kk]);
+      o = o + (w < a.L ? pc[wave][w][kk] : gload<float>(a.in_buf + (int64_t)(out_start + w - a.L) * CIN + kk));
     }
   }
   if (a.post_act == 2) o = tanhf(o);
   if (masked(a, e, t)) o = 0.f;
-  e.out[t] = o;
+  gstore<float>(e.out + t, o);
 }
 
 }  // namespace
