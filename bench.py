@@ -73,28 +73,27 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "4d5964a0e70b468a0c85d22c845934b479efa7d2 801bd55719e0794064f3bc030b6648bba8bddc6e 32aa2b2fa22617686caf5b6167557e40417b7f38 7ce4e197c7829cbe4eb433e22898b26d1e9be71c 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "583ec48d22a0911f06a540efa61f0f2914f60756 5797b40bfd460d0e7cc9219e6ebe2696440f249d 18905ef57a71e2afe993183b63827b2b782d8e66 c42173c605b92b216b3d3a8c5c518a70f93b0b7b 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 739.5, 2727.1),
-        2: ('mfma', 10436.3, 21982.3),
-        4: ('mfma', 10284.6, 21554.4),
-        6: ('mfma', 11272.0, 22525.0),
-        8: ('mfma', 14136.7, 12302.2),
-        9: ('mfma', 5222.6, 42075.6),
-        11: ('mfma', 17024.9, 38057.7),
-        13: ('mfma', 17518.2, 38726.1),
-        15: ('mfma', 18965.1, 14243.2),
-        16: ('mfma', 6186.1, 56867.1),
-        18: ('mfma_win', 22582.4, 55577.0),
-        20: ('mfma_win', 24052.2, 55613.1),
-        22: ('mfma_win', 28460.4, 22712.6),
-        23: ('mfma', 10980.4, 55351.2),
-        25: ('mfma_win', 22152.1, 55782.1),
-        27: ('mfma_win', 22880.9, 55702.2),
-        29: ('mfma_win', 25105.4, 3126.2),
-        30: ('tail', 2110.7, 85.4),
+        1: ('mfma', 748.9, 2727.1),
+        2: ('mfma', 10445.3, 22307.6),
+        4: ('mfma', 10294.4, 22042.7),
+        6: ('mfma', 11284.6, 23303.4),
+        8: ('mfma', 14158.7, 12302.2),
+        9: ('mfma', 5231.6, 42194.7),
+        11: ('mfma', 17026.2, 40721.8),
+        13: ('mfma', 17524.5, 41321.3),
+        15: ('mfma', 18959.3, 14236.3),
+        16: ('mfma', 6193.7, 58608.6),
+        18: ('mfma_win', 22619.6, 53520.7),
+        20: ('mfma_win', 24088.4, 53726.0),
+        22: ('mfma_win', 28502.3, 22712.6),
+        25: ('mfma_win', 11520.3, 55560.7),
+        27: ('mfma_win', 22924.9, 55568.7),
+        29: ('mfma_win', 25150.9, 3126.2),
+        30: ('tail', 2110.9, 85.4),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
