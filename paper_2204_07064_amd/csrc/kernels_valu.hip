@@ -48,11 +48,12 @@ __device__ inline void cache_item(const LayerArgs& a, const FastDiv& fd_per_ent,
   const int32_t rem = j - ei * per_ent;
   const int32_t i = (int32_t)fdiv(a.fd_cin, (uint32_t)rem);
   const int ci = rem - i * a.cin;
-  const Entry& e = a.ents[ei];
+  const Entry e = load_entry(a.ents + ei);
   const int32_t in_start = in_frames(a, e.off);
   const int32_t Tin = in_frames(a, e.T);
   const Row rw = window_row(e, in_start, Tin, Tin + i, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
-  e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci] = rw.p[ci * rw.cs];
+  gstore<float>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci,
+                gload<float>(rw.p + ci * rw.cs));
 }
 
 __device__ inline float finish(const LayerArgs& a, const Entry& e, int32_t t, float acc) {
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a, FastDiv 
     }
     const int32_t n = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
     const int co = idx - n * a.cout;
-    const Entry& e = a.ents[entry_of_out(a, n)];
+    const Entry e = load_entry(a.ents + entry_of_out(a, n));
     const int32_t in_start = in_frames(a, e.off);
     const int32_t Tin = in_frames(a, e.T);
     const int32_t t = n - out_frames(a, e.off);
@@ -84,21 +85,21 @@ __global__ void __launch_bounds__(kBlock) conv_item_kernel(LayerArgs a, FastDiv 
                                 a.in_buf, a.cin);
       const float* wp = W + (int64_t)kk * a.cin * a.cout + co;
       for (int ci = 0; ci < a.cin; ++ci) {
-        float x = rw.p[ci * rw.cs];
+        float x = gload<float>(rw.p + ci * rw.cs);
         if (a.pre_act) x = lrelu(x);
         acc = fmaf(wp[(int64_t)ci * a.cout], x, acc);
       }
     }
     if (a.residual) {
       const Row rw = window_row(e, in_start, Tin, t + a.skip_off, a.L, a.state_off, a.state_len, a.in_buf, a.cin);
-      acc = acc + rw.p[co * rw.cs];
+      acc = acc + gload<float>(rw.p + co * rw.cs);
     }
     acc = finish(a, e, t, acc);
     if (a.out_buf) {
       a.out_buf[(int64_t)n * a.cout + co] = acc;
       if (a.out_twin) store_twin1(a.out_twin, (int64_t)n * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
     } else {
-      e.out[(int64_t)co * out_frames(a, e.T) + t] = acc;
+      gstore<float>(e.out + (int64_t)co * out_frames(a, e.T) + t, acc);
     }
   }
 }
@@ -135,8 +136,8 @@ __device__ inline void stage_cache(const LayerArgs& a, float* cs, int e_first, i
     const int rem = idx - s * per;
     const int w = (int)fdiv(a.fd_cin, (uint32_t)rem);
     const int ci = rem - w * a.cin;
-    const Entry& e = a.ents[e_first + s];
-    const float v = e.state[a.state_off + (int64_t)e.parity * a.state_len + rem];
+    const Entry e = load_entry(a.ents + e_first + s);
+    const float v = gload<float>(e.state + a.state_off + (int64_t)e.parity * a.state_len + rem);
     cs[(s * a.L + w) * ld + ci] = a.pre_act ? lrelu(v) : v;
   }
 }
@@ -210,7 +211,7 @@ __device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int32_t n0
     const int32_t n = n0 + i;
     if (n < step_out(a)) {
       const int ei = entry_of_out(a, n);
-      const Entry& e = a.ents[ei];
+      const Entry e = load_entry(a.ents + ei);
       const int32_t t = n - out_frames(a, e.off);
       f.ei = ei;
       f.t = t;
@@ -226,9 +227,9 @@ __device__ inline void frame_infos(const LayerArgs& a, FrameInfo* fi, int32_t n0
 // Raw (not activated) skip value of window row t + skip_off, channel co.
 __device__ inline float skip_value(const LayerArgs& a, const FrameInfo& f, int co) {
   const int32_t row = f.t + a.skip_off;
-  if (row < a.L) return f.cache[(int64_t)row * a.cin + co];
-  const Entry& e = a.ents[f.ei];
-  return a.in_buf[((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + co];
+  if (row < a.L) return gload<float>(f.cache + (int64_t)row * a.cin + co);
+  const int32_t off = ((cptr<Entry>)a.ents)[f.ei].off;
+  return gload<float>(a.in_buf + ((int64_t)in_frames(a, off) + row - a.L) * a.cin + co);
 }
 
 // Frame-parallel variant (few output channels): one lane per output frame,
@@ -275,10 +276,10 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
       for (int kk = 0; kk < a.k; ++kk) {
         const int w = f.t * S + a.dil * kk;       // window row
         const float* wp = ws + kk * a.cin * a.cout + co;
-        const float* x = nullptr;
-        if (w >= a.L) x = xs + (i * S + a.dil * kk) * ld;
-        else if (f.ei - e_first < kCacheSlots) x = cs + ((f.ei - e_first) * a.L + w) * ld;
-        if (x) {
+        // the row in LDS (staged input or cache rows), else the stream's cache in memory
+        const bool in_lds = w >= a.L || f.ei - e_first < kCacheSlots;
+        const float* x = w >= a.L ? xs + (i * S + a.dil * kk) * ld : cs + ((f.ei - e_first) * a.L + w) * ld;
+        if (in_lds) {
           for (int ci = 0; ci < a.cin; ++ci) {
             const float xv = x[ci];
 #pragma unroll
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
         } else {
           const float* xg = f.cache + (int64_t)w * a.cin;
           for (int ci = 0; ci < a.cin; ++ci) {
-            float v = xg[ci];
+            float v = gload<float>(xg + ci);
             if (a.pre_act) v = lrelu(v);
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[j] = fmaf(wp[ci * a.cout + j], v, acc[j]);
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
       } else {
         const float* x = f.cache + (int64_t)w * a.cin;
         for (int ci = 0; ci < a.cin; ++ci) {
-          float v = x[ci];
+          float v = gload<float>(x + ci);
           if (a.pre_act) v = lrelu(v);
           acc = fmaf(wp[ci * a.cout], v, acc);
         }
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) conv_frames_kernel(LayerArgs a, int32_
       a.out_buf[(n0 + i) * a.cout + co] = acc;
       if (a.out_twin) store_twin1(a.out_twin, (n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
     } else {
-      f.out[(int64_t)co * f.tout] = acc;
+      gstore<float>(f.out + (int64_t)co * f.tout, acc);
     }
   }
 }
@@ -423,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
 #pragma unroll
         for (int ci = 0; ci < CMAX; ++ci) {
           if (ci < a.cin) {
-            float v = x[ci];
+            float v = gload<float>(x + ci);
             if (a.pre_act) v = lrelu(v);
             acc = fmaf(wr[kk][ci], v, acc);
           }
@@ -437,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) conv_chans_kernel(LayerArgs a, int32_t
       a.out_buf[(int64_t)(n0 + i) * a.cout + co] = acc;
       if (a.out_twin) store_twin1(a.out_twin, (int64_t)(n0 + i) * a.cout + co, a.twin_prec, a.twin_pre, a.twin_qs, acc);
     } else {
-      f.out[(int64_t)co * f.tout] = acc;
+      gstore<float>(f.out + (int64_t)co * f.tout, acc);
     }
   }
 }
@@ -481,11 +482,10 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
     for (int kk = 0; kk < KMAX; ++kk) {
       if (kk < a.k) {
         const int w = f.t + a.dil * kk;
-        const float* x;
-        if (w >= a.L) x = xs + (i + a.dil * kk) * LD;
-        else if (f.ei - e_first < kCacheSlots) x = cs + ((f.ei - e_first) * a.L + w) * LD;
-        else x = nullptr;
-        if (x) {
+        // the row in LDS (staged input or cache rows), else the stream's cache in memory
+        const bool in_lds = w >= a.L || f.ei - e_first < kCacheSlots;
+        const float* x = w >= a.L ? xs + (i + a.dil * kk) * LD : cs + ((f.ei - e_first) * a.L + w) * LD;
+        if (in_lds) {
 #pragma unroll
           for (int c4 = 0; c4 < CIN; c4 += 4) {
             const f4v xv = *reinterpret_cast<const f4v*>(x + c4);
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
         } else {
           const float* xg = f.cache + (int64_t)w * CIN;
           for (int ci = 0; ci < CIN; ++ci) {
-            float v = xg[ci];
+            float v = gload<float>(xg + ci);
             if (a.pre_act) v = lrelu(v);
             acc = fmaf(ws[kk * CIN + ci], v, acc);
           }
@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) conv_out1_kernel(LayerArgs a, int32_t 
       a.out_buf[n0 + i] = acc;
       if (a.out_twin) store_twin1(a.out_twin, n0 + i, a.twin_prec, a.twin_pre, a.twin_qs, acc);
     } else {
-      f.out[0] = acc;
+      gstore<float>(f.out, acc);
     }
   }
 }
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(kBlock) pack_input_kernel(const Entry* ents, c
     const int c = idx / n_frames;   // frame fastest: coalesced reads of each channel row
     const int32_t f = idx - c * n_frames;
     const Entry e = load_entry(ents + fent[fdiv(fd_gran, (uint32_t)f)]);
-    const float v = e.in[(int64_t)c * e.T + (f - e.off)];
+    const float v = gload<float>(e.in + (int64_t)c * e.T + (f - e.off));
     out[(int64_t)f * C + c] = v;
     if (twin) store_twin1(twin, (int64_t)f * C + c, twin_prec, twin_pre, twin_qs, v);
   }
@@ -551,12 +551,12 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv
     const int32_t c = (int32_t)fdiv(fd_r, (uint32_t)rest);
     const int phi = rest - c * r;
     const int ei = c < step_in(a) ? entry_of_in(a, c) : c - (int32_t)step_in(a);
-    const Entry& e = a.ents[ei];
+    const Entry e = load_entry(a.ents + ei);
     const int32_t in_start = in_frames(a, e.off);
     const int32_t Tin = in_frames(a, e.T);
     const int32_t q = c < step_in(a) ? c - in_start : Tin;
     const float* carry_in = e.state + a.state_off + (int64_t)e.parity * a.state_len;
-    float acc = (q == 0) ? carry_in[phi * a.cout + co] : 0.f;
+    float acc = (q == 0) ? gload<float>(carry_in + phi * a.cout + co) : 0.f;
     for (int h = 0; h < 2; ++h) {
       const int32_t row = q - 1 + h;
       if (row < 0 || row >= Tin) continue;
@@ -577,10 +577,10 @@ __global__ void __launch_bounds__(kBlock) convt_valu_kernel(LayerArgs a, FastDiv
         a.out_buf[o] = v;
         if (a.out_twin) store_twin1(a.out_twin, o, a.twin_prec, a.twin_pre, a.twin_qs, v);
       } else {
-        e.out[(int64_t)co * (Tin * r) + t] = v;
+        gstore<float>(e.out + (int64_t)co * (Tin * r) + t, v);
       }
     } else {
-      e.state[a.state_off + (int64_t)(1 - e.parity) * a.state_len + phi * a.cout + co] = acc;
+      gstore<float>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + phi * a.cout + co, acc);
     }
   }
 }
@@ -596,25 +596,25 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a, FastDiv 
     if (idx < n_items) {
       const int32_t n = (int32_t)fdiv(a.fd_cout, (uint32_t)idx);
       const int c = idx - n * C;
-      const Entry& e = a.ents[entry_of_out(a, n)];
+      const Entry e = load_entry(a.ents + entry_of_out(a, n));
       const int32_t start = out_frames(a, e.off);
       const int32_t Tn = out_frames(a, e.T);
       const int32_t t = n - start;
       const Row r0 = window_row(e, start, Tn, t, a.A0, a.state_off, a.state_len, a.in_buf, C);
       const Row r1 = window_row(e, start, Tn, t, a.A1, a.state_off2, a.state_len2, a.in_buf2, C);
-      float v = r0.p[c * r0.cs] + r1.p[c * r1.cs];
+      float v = gload<float>(r0.p + c * r0.cs) + gload<float>(r1.p + c * r1.cs);
       if (masked(a, e, t)) v = 0.f;
       if (a.out_buf) {
         a.out_buf[(int64_t)n * C + c] = v;
         if (a.out_twin) store_twin1(a.out_twin, (int64_t)n * C + c, a.twin_prec, a.twin_pre, a.twin_qs, v);
       } else {
-        e.out[(int64_t)c * Tn + t] = v;
+        gstore<float>(e.out + (int64_t)c * Tn + t, v);
       }
     } else {
       const int32_t j = idx - n_items;
       const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
       int32_t rem = j - ei * per_ent;
-      const Entry& e = a.ents[ei];
+      const Entry e = load_entry(a.ents + ei);
       const int32_t start = out_frames(a, e.off);
       const int32_t Tn = out_frames(a, e.T);
       const bool second = rem >= a.A0 * C;
@@ -625,7 +625,7 @@ __global__ void __launch_bounds__(kBlock) delay_add_kernel(LayerArgs a, FastDiv 
       const int64_t soff = second ? a.state_off2 : a.state_off;
       const int64_t slen = second ? a.state_len2 : a.state_len;
       const Row rw = window_row(e, start, Tn, Tn + i, A, soff, slen, second ? a.in_buf2 : a.in_buf, C);
-      e.state[soff + (int64_t)(1 - e.parity) * slen + (int64_t)i * C + c] = rw.p[c * rw.cs];
+      gstore<float>(e.state + soff + (int64_t)(1 - e.parity) * slen + (int64_t)i * C + c, gload<float>(rw.p + c * rw.cs));
     }
   }
 }
