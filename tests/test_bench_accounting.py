@@ -1,0 +1,46 @@
+"""The bench's algorithmic FLOP and byte accounting (host logic, no GPU):
+a window conv that computes the transposed conv before it in its own launch
+is charged both layers' FLOPs, the transposed conv's input, carry and
+weights, and not the transposed conv's output, which never reaches memory."""
+import bench
+
+
+def _ops():
+    ct = {"node": 23, "kind": 2, "impl": 1, "precision": 1, "cin": 64, "cout": 32, "k": 4, "stride": 2,
+          "cache_len": 2, "dilation": 1, "launches": 0, "frames_in": 0, "frames_out": 0, "entries": 0, "ms": 0.0}
+    cv = {"node": 25, "kind": 1, "impl": 2, "precision": 1, "cin": 32, "cout": 32, "k": 3, "stride": 1,
+          "cache_len": 2, "dilation": 1, "launches": 10, "frames_in": 344064 * 10, "frames_out": 344064 * 10,
+          "entries": 2560, "ms": 0.38}
+    return ct, cv
+
+
+def test_fused_convt_is_found_only_without_launches():
+    ct, cv = _ops()
+    assert bench.fused_convt([ct, cv], cv) is ct
+    assert bench.fused_tail([ct, cv], cv) is None
+    ct2 = dict(ct, launches=10)
+    assert bench.fused_convt([ct2, cv], cv) is None
+
+
+def test_fused_pair_accounting():
+    ct, cv = _ops()
+    f_cv, b_cv = bench.op_accounting(cv)
+    x = cv["frames_in"]
+    # the transposed conv as its own layer over the same frames
+    alone = dict(ct, frames_in=x // 2, frames_out=x, entries=cv["entries"], launches=cv["launches"])
+    f_ct, b_ct = bench.op_accounting(alone)
+    f, b = bench.op_accounting(cv, ct=ct)
+    # FLOPs: 2 MACs per output element and tap: conv 3 taps x 32 in, convT 2 taps x 64 in
+    assert f_cv == 2.0 * x * 32 * 32 * 3
+    assert f_ct == 2.0 * x * 32 * 2 * 64
+    assert f == f_cv + f_ct
+    # bytes: both layers less the transposed conv's output written and read back (FP32)
+    assert b == b_cv + b_ct - 2 * 4.0 * x * 32
+    assert b < b_cv + b_ct
+
+
+def test_roofline_names_the_pair():
+    ct, cv = _ops()
+    r = bench.roofline([ct, cv])
+    assert r["bound"] == "hbm" and "transposed conv node 23" in r["kernel"]
+    assert r["flops_per_launch"] == round(bench.op_accounting(cv, ct=ct)[0] / cv["launches"])
