@@ -152,7 +152,13 @@ enum {
                                    default that conv's tiles compute the frames
                                    they need in the same launch and the transposed
                                    conv's output never reaches memory (same
-                                   results, bitwise; for testing) */
+                                   results, bitwise; for testing) */,
+  SC_MODEL_NO_INPUT_DIRECT = 128u  /* the model input is packed channels-last into
+                                   the workspace by its own launch before the first
+                                   layer; by default an FP32 MFMA conv that is the
+                                   input's only reader gathers it straight from the
+                                   callers' channel-major buffers (same results,
+                                   bitwise; for testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,

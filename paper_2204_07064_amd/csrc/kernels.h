@@ -40,6 +40,8 @@ struct LayerArgs {
   int32_t twin_pre;        // producer: pre-activation of the consumer
   int32_t twin_prec;
   int32_t twin_only;       // producer: the FP32 output has no reader; write the twin only
+  int32_t user_in;         // FP32 gathering conv: input rows from each stream's channel-major
+                           // buffer (Entry::in, [cin][T]) instead of the packed input
   int64_t tstate_off, tstate_len;   // consumer conv: twin cache copies (floats)
   // window conv only: a one-output-channel stride-1 conv that reads this
   // layer's output and writes the user output, computed in the epilogue

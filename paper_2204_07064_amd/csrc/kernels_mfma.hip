@@ -212,8 +212,16 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
       const int64_t src_in = ((int64_t)in_frames(a, e.off) + row - a.L) * a.cin + ci;
       const float* src = row < a.L ? e.state + a.state_off + (int64_t)e.parity * a.state_len + (int64_t)row * a.cin + ci
                                    : a.in_buf + src_in;
-      gstore<f4>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci,
-                 gload<f4>(src));
+      f4 v;
+      if (PREC == 0 && MT == 64 && !INTWIN && a.user_in && row >= a.L) {
+        // the caller's channel-major buffer: channels ci .. ci + 3 of input frame row - L
+        const float* u = e.in + (int64_t)ci * e.T + (row - a.L);
+        v = f4{gload<float>(u), gload<float>(u + e.T), gload<float>(u + 2 * (int64_t)e.T),
+               gload<float>(u + 3 * (int64_t)e.T)};
+      } else {
+        v = gload<f4>(src);
+      }
+      gstore<f4>(e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len + (int64_t)i * a.cin + ci, v);
       if (INTWIN) {
         // 4 operand elements: 16, 8 or 4 bytes
         typedef typename Prec<PREC>::Elem T;
@@ -298,6 +306,13 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
       }                                                                                                      \
       if constexpr (INTWIN) {                                                                                \
         tb[ST][p_] = live_ ? gload<u4>(base_ + off_ * ES) : u4{0u, 0u, 0u, 0u};                         \
+      } else if (PREC == 0 && MT == 64 && !CONVT && a.user_in && pc_t[p_] + drow_ >= a.L) {                  \
+        /* the caller's channel-major buffer: channels k_ci .. + 3 of the row, T_e apart */                  \
+        const int64_t ut_ = pc_ut[PREC == 0 && MT == 64 && !INTWIN && !CONVT ? p_ : 0];                                 \
+        const float* u_ = reinterpret_cast<const float*>(pc_inb[p_]) + drow_ + (int64_t)k_ci * ut_;           \
+        rb[ST][p_] = live_ ? f4{gload<float>(u_), gload<float>(u_ + ut_), gload<float>(u_ + 2 * ut_),         \
+                                gload<float>(u_ + 3 * ut_)}                                                  \
+                           : f4{0.f, 0.f, 0.f, 0.f};                                                         \
       } else {                                                                                               \
         rb[ST][p_] = live_ ? gload<f4>(base_ + off_ * 4) : f4{0.f, 0.f, 0.f, 0.f};                       \
       }                                                                                                      \
@@ -357,6 +372,7 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
   int64_t pc_in[B_PIECES];                   // convt: input element offset of the stream's frame 0
   int32_t pc_t[B_PIECES];                    // conv: window row of tap 0 (t * stride); convt: q
   int32_t pc_lim[B_PIECES];                  // convt: input frames of the stream
+  int32_t pc_ut[PREC == 0 && MT == 64 && !INTWIN && !CONVT ? B_PIECES : 1];   // direct model input: channel stride (the stream's T)
   bool pc_ok[B_PIECES];                      // not a padding column
 #pragma unroll
   for (int p = 0; p < B_PIECES; ++p) {
@@ -368,6 +384,13 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
     const int64_t trow = (int64_t)pc_t[p] * a.cin;
     pc_cache[p] = (INTWIN ? cc.tcache : reinterpret_cast<const unsigned char*>(cc.cache)) + trow * ES_B;
     pc_inb[p] = in_base + (((int64_t)cc.in_start - a.L) * a.cin + trow) * ES_B;
+    if (PREC == 0 && MT == 64 && !INTWIN && !CONVT) pc_ut[p] = 0;
+    if (PREC == 0 && MT == 64 && !INTWIN && !CONVT && a.user_in) {
+      // input row r of the column's stream is element (ci, r) of its buffer at in + ci * T + r
+      const Entry e = load_entry(a.ents + max(cc.ei, 0));
+      pc_inb[p] = reinterpret_cast<const unsigned char*>(e.in + ((int64_t)pc_t[p] - a.L));
+      pc_ut[p] = e.T;
+    }
   }
 
   // K position of this thread's B piece, advanced chunk by chunk without

@@ -49,6 +49,8 @@ struct sc_model {
   bool have_scales = false;
   std::vector<int32_t> layer_prec; // per layer: operand precision 0 FP32, 1 BF16, 2 FP8 e4m3
   bool any_fp8 = false;            // some layer runs on FP8 operands (needs activation scales)
+  bool input_direct = false;       // the model input's only reader gathers it from the callers'
+                                   // buffers: no packing launch (except in calibration runs)
   int64_t weight_bytes = 0;
   // workspace
   std::vector<float*> ws;

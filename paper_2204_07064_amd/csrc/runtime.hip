@@ -153,6 +153,29 @@ void fuse_output_convs(Plan& pl) {
 // (launch_convt_win), where the tiles compute the frames their windows need;
 // both ops then share one launch and the transposed conv's output is never
 // written.  It needs the transposed conv to read its input in operand form.
+// The model input read straight from the callers' channel-major buffers by
+// its only reader, an FP32 MFMA conv (no residual, no operand copy of the
+// input): the packing launch goes away.
+void mark_input_direct(sc_model* m) {
+  Plan& pl = m->plan;
+  if (pl.input_buf < 0 || pl.input_twin >= 0) return;
+  int reader = -1, readers = 0;
+  for (size_t o = 0; o < pl.ops.size(); ++o) {
+    const Op& op = pl.ops[o];
+    const int r = (op.src == 0) + (op.src2 == 0);
+    if (r) reader = (int)o;
+    readers += r;
+  }
+  if (readers != 1) return;
+  Op& op = pl.ops[reader];
+  // (the 64-row tile the gathering kernel uses for more than 32 output channels)
+  if (op.kind != K_CONV || op.impl != IMPL_MFMA || op.prec != 0 || op.residual || op.in_twin >= 0 ||
+      op.cin % 4 != 0 || op.cout <= 32)
+    return;
+  op.user_in = 1;
+  m->input_direct = true;
+}
+
 void fuse_convt_windows(sc_model* m) {
   Plan& pl = m->plan;
   for (size_t w = 0; w < pl.ops.size(); ++w) {
@@ -223,6 +246,8 @@ LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const 
   a.twin_pre = op.twin_pre;
   // calibration reads every layer's FP32 input, so keep writing it then
   a.twin_only = (op.twin_only && a.out_twin && !m->amax_on) ? 1 : 0;
+  // calibration reads the packed input, so it is packed then
+  a.user_in = (op.user_in && !m->amax_on) ? 1 : 0;
   a.twin_qs = twin_scale(m, op.twin_layer);
   a.tstate_off = op.tstate_off;
   a.tstate_len = op.tstate_len;
@@ -422,7 +447,7 @@ LaunchSet launch_set(const unsigned char* dev, int grid_n, int64_t grid_frames, 
 
 hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
   const Plan& pl = m->plan;
-  if (pl.input_buf < 0) return hipSuccess;
+  if (pl.input_buf < 0 || (m->input_direct && !m->amax_on)) return hipSuccess;
   return launch_pack_input(ls.ents, ls.fent, pl.input_multiple, ls.hdr, pl.in_channels, ls.grid_frames,
                            ws_at(m, ls.w, pl.input_buf, ls.base),
                            tw_at(m, ls.w, pl.input_twin, ls.base), pl.input_twin_prec,
@@ -891,6 +916,7 @@ sc_status create_model(const sc_node* nodes, int32_t n_nodes, const float* weigh
   if (!(options & SC_MODEL_NO_OUT_FUSION)) fuse_output_convs(m->plan);
   finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN));
   if (!(options & SC_MODEL_NO_CONVT_FUSION)) fuse_convt_windows(m);
+  if (!(options & SC_MODEL_NO_INPUT_DIRECT)) mark_input_direct(m);
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
   if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }

@@ -73,6 +73,7 @@ struct Op {
   int32_t twin_prec = 0;      // producer: operand precision of the twin's reader
   int32_t convt_in = -1;      // window conv: index of the transposed conv computed in its
                               // launch; that transposed conv: index of the window conv
+  int32_t user_in = 0;        // reads the model input from the callers' channel-major buffers
 };
 
 struct Plan {

@@ -135,6 +135,33 @@ def test_convt_window_fusion_bitwise(prec, split):
         assert np.array_equal(a[i], b[i]), i
 
 
+@pytest.mark.parametrize("prec,split", [("fp32", True), ("bf16", False), ("bf16", True), ("fp8", True)])
+def test_direct_input_bitwise(prec, split):
+    """The input conv gathering the latents straight from the callers'
+    channel-major buffers (no packing launch) gives bitwise the same streams
+    as packing them first, in steps of many streams of uneven buffers (1-frame
+    buffers included), split or not, and with the warm-up mask."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = _fp8_scales(sc, m, w, 16) if prec == "fp8" else None
+    rng = np.random.default_rng(17)
+    lens = [[int(v) for v in rng.choice([1, 2, 3, 8, 16, 32], size=3)] for _ in range(72)]
+    xs = [scgen.stream_latents(16, sum(l), 900 + i) for i, l in enumerate(lens)]
+    base = 0 if split else sc._native.SC_MODEL_NO_SPLIT
+    a = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base), xs, lens)
+    b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base | sc._native.SC_MODEL_NO_INPUT_DIRECT),
+                         xs, lens)
+    for i in range(len(lens)):
+        assert np.array_equal(a[i], b[i]), i
+    # one stream with the warm-up mask, buffer by buffer
+    x = scgen.stream_latents(16, 40, 5)
+    outs = []
+    for opt in (base, base | sc._native.SC_MODEL_NO_INPUT_DIRECT):
+        mod = _model(sc, m, w, prec, scales, options=opt)
+        outs.append(run_stream(mod, x, [1, 7, 32], stream=sc.Stream(mod, 32, warmup_mask=True)))
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     """The FP32 MFMA path (input conv included) and the FP32 wavefront path
     sum in different orders; each is pinned to the FP64 oracle at 1e-5 by the
