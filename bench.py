@@ -73,26 +73,26 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "583ec48d22a0911f06a540efa61f0f2914f60756 5797b40bfd460d0e7cc9219e6ebe2696440f249d 18905ef57a71e2afe993183b63827b2b782d8e66 c42173c605b92b216b3d3a8c5c518a70f93b0b7b 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "0ff867a48d3cc7aa884655052a6081db0be19cab 5797b40bfd460d0e7cc9219e6ebe2696440f249d c475d43d80ff2b54661b0920e2ae957339dc5b81 c91a88e5b1fa849ea989eb1fb793788e20e5cb0c 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 748.9, 2727.1),
-        2: ('mfma', 10445.3, 22307.6),
-        4: ('mfma', 10294.4, 22042.7),
-        6: ('mfma', 11284.6, 23303.4),
-        8: ('mfma', 14158.7, 12302.2),
-        9: ('mfma', 5231.6, 42194.7),
-        11: ('mfma', 17026.2, 40721.8),
-        13: ('mfma', 17524.5, 41321.3),
-        15: ('mfma', 18959.3, 14236.3),
-        16: ('mfma', 6193.7, 58608.6),
-        18: ('mfma_win', 22619.6, 53520.7),
-        20: ('mfma_win', 24088.4, 53726.0),
-        22: ('mfma_win', 28502.3, 22712.6),
-        25: ('mfma_win', 11520.3, 55560.7),
-        27: ('mfma_win', 22924.9, 55568.7),
-        29: ('mfma_win', 25150.9, 3126.2),
+        1: ('mfma', 772.6, 2727.1),
+        2: ('mfma', 10445.3, 22316.8),
+        4: ('mfma', 10294.4, 22053.7),
+        6: ('mfma', 11284.6, 23332.9),
+        8: ('mfma', 14158.1, 12302.2),
+        9: ('mfma', 5231.6, 42214.2),
+        11: ('mfma', 17018.8, 40715.6),
+        13: ('mfma', 17514.0, 41285.3),
+        15: ('mfma', 18956.3, 14236.3),
+        16: ('mfma', 6195.2, 58581.6),
+        18: ('mfma_win', 22619.6, 53395.0),
+        20: ('mfma_win', 24088.4, 53711.3),
+        22: ('mfma_win', 28502.7, 22712.6),
+        25: ('mfma_win', 11520.3, 55522.3),
+        27: ('mfma_win', 22925.0, 55330.6),
+        29: ('mfma_win', 25150.8, 3126.2),
         30: ('tail', 2110.9, 85.4),
     },
 }
