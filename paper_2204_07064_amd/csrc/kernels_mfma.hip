@@ -519,13 +519,13 @@ __global__ void __launch_bounds__(kThreads, INTWIN ? (PREC == 2 ? 3 : 4) : 1) ge
         const int32_t t = c.t * a.stride + phi;
         if (t < c.keep_lo || t >= c.keep_hi) v = f4{0.f, 0.f, 0.f, 0.f};
         const int64_t o = ((int64_t)c.in_start * a.stride + (int64_t)c.t * a.stride) * a.cout + m;
-        if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
+        if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
         if (a.out_twin) store_twin4<PREC>(a, o, v);
       } else {
         v = v + ep_bias[i];
         if (a.residual) v = v + ep_skip[i][j];
         if (c.t < c.keep_lo || c.t >= c.keep_hi) v = f4{0.f, 0.f, 0.f, 0.f};
-        if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + (int64_t)n * a.cout + m));
+        if (!a.twin_only) gstore<f4>(a.out_buf + (int64_t)n * a.cout + m, v);
         if (a.out_twin) store_twin4<PREC>(a, (int64_t)n * a.cout + m, v);
       }
     }

@@ -38,6 +38,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct WPrec;
 template <> struct WPrec<0> { static constexpr int kEsize = 4; static constexpr int kKc = 32; };
@@ -301,6 +302,36 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
 // L frames after each tile boundary), reading P of the rows they need, which
 // the tiles store in out_buf (the only values written there).  The tiles
 // also move the output conv's input cache.
+// The B operands of K chunk c for the NB column blocks of a lane: its two
+// 16-byte pieces of each column's window row, element kk -> (tap, channel).
+// Every read is issued before any is used (a piece past the real K reads the
+// column's first row and is zeroed), so the chunk waits once for LDS instead
+// of once per column block behind a branch.
+template <int ES, int NB>
+__device__ inline void win_chunk_reads(const LayerArgs& a, int c, int lg, int Kreal, int cin, int rowb,
+                                       const unsigned char* wop, const int* cb, u4* blo, u4* bhi) {
+  int off[2];
+  bool live[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int kk = (c * 128 + lg * 32 + p * 16) / ES;
+    live[p] = kk < Kreal;
+    const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
+    off[p] = live[p] ? tap * a.dil * rowb + (kk - tap * cin) * ES : 0;
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    blo[nb] = *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]);
+    bhi[nb] = *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]);
+  }
+  const u4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    blo[nb] = live[0] ? blo[nb] : z;
+    bhi[nb] = live[1] ? bhi[nb] : z;
+  }
+}
+
 template <int PREC, int MT, int NB, int KCM, bool FUSE>
 __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
@@ -316,6 +347,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   __shared__ WinSeg2 segs2[FUSE ? kMaxStreams : 1];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
+  __shared__ int8_t colkeep[F];   // per column: -1 past the step, 0 zeroed by a mask, 1 kept
 
   const int tid = threadIdx.x;
   const int32_t n_tiles = n_mt * n_nt;
@@ -439,14 +471,18 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   if (tid < F) {
     const int32_t f = f0 + tid;
     int s = 0;
+    int8_t keep = -1;
     if (f <= f_last) {
       while (s + 1 < n_seg && segs[s + 1].out_start <= f) ++s;
       colbase[tid] = segs[s].base + (f - segs[s].out_start - segs[s].r0);
+      const int64_t x = (int64_t)(f - segs[s].out_start) * a.out_den;
+      keep = x < segs[s].mask_x || x >= segs[s].mask_hi ? 0 : 1;
     } else {
       colbase[tid] = 0;
       s = -1;
     }
     colseg[tid] = (int8_t)s;
+    colkeep[tid] = keep;
   }
 
   // each staged row's source (cache or input) and, for a fused residual, the
@@ -519,23 +555,10 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
 #pragma unroll
   for (int c = 0; c < kMaxChunks; ++c) {
     if (c < n_chunks) {
-      // the lane's two 16-byte pieces of this chunk: element kk -> (tap, ci)
-      int off[2];
-      bool live[2];
+      u4 blo[NB], bhi[NB];
+      win_chunk_reads<ES, NB>(a, c, lg, Kreal, cin, rowb, wop, cb, blo, bhi);
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int kk = (c * 128 + lg * 32 + p * 16) / ES;
-        live[p] = kk < Kreal;
-        const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
-        off[p] = tap * a.dil * rowb + (kk - tap * cin) * ES;
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const u4 z = {0u, 0u, 0u, 0u};
-        const u4 blo = live[0] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]) : z;
-        const u4 bhi = live[1] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]) : z;
-        acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo, bhi, acc[nb]);
-      }
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
   }
 
@@ -549,17 +572,16 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int col = wn * (F / WN) + nb * 16 + lr;
-    const int s = colseg[col];
-    if (s < 0) continue;
+    const int keep = colkeep[col];
+    if (keep < 0) continue;
     const int32_t f = f0 + col;
-    const int32_t t = f - segs[s].out_start;
     f4 v = acc[nb];
     if (PREC == 2) v = v * (wsc * a.act_scale);
     v = v + bias;
     if (a.residual) v = v + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
-    if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
+    if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
-    if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));   // streamed past L2
+    if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
     if (a.out_twin) {
       f4 w = v;
       if (a.twin_pre) {
@@ -644,9 +666,16 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   __shared__ CtSeg csegs[kMaxStreams];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colseg[F];
+  __shared__ int8_t colkeep[F];   // per column: -1 past the step, 0 zeroed by a mask, 1 kept
   __shared__ int8_t ccol_seg[NCB * 16];
   __shared__ int32_t ccol_q[NCB * 16];
   __shared__ int32_t ccol_x[NCB * 16];
+  // per transposed-conv column, in x frames t = q * r + phi: {q * r (-1: the
+  // carry column), LDS row of t = 0, first and end t whose window rows are
+  // staged} and {first and end t kept by the masks, first and last t written
+  // to the conv's next cache}
+  __shared__ i4 ccol_rows[NCB * 16];
+  __shared__ i4 ccol_keep[NCB * 16];
 
   const int tid = threadIdx.x;
   const int32_t nt = blockIdx.x;
@@ -818,14 +847,18 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   if (tid < F) {
     const int32_t f = f0 + tid;
     int s = 0;
+    int8_t keep = -1;
     if (f <= f_last) {
       while (s + 1 < n_seg && segs[s + 1].out_start <= f) ++s;
       colbase[tid] = segs[s].base + (f - segs[s].out_start - segs[s].r0);
+      const int64_t x = (int64_t)(f - segs[s].out_start) * a.out_den;
+      keep = x < segs[s].mask_x || x >= segs[s].mask_hi ? 0 : 1;
     } else {
       colbase[tid] = 0;
       s = -1;
     }
     colseg[tid] = (int8_t)s;
+    colkeep[tid] = keep;
   }
   for (int j = tid; j < NCB * 16; j += kThreads) {
     int s = -1, q = 0, x = 0;
@@ -838,6 +871,17 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     ccol_seg[j] = (int8_t)s;
     ccol_q[j] = q;
     ccol_x[j] = x;
+    i4 rows = {-1, 0, 0, 0}, keep = {0, 0, 0, -1};
+    if (s >= 0) {
+      const CtSeg& c = csegs[s];
+      const WinSeg& g = segs[s];
+      if (q != c.Tin) {
+        rows = i4{q * R, g.base + L - g.r0, g.r0 - L, g.r0 - L + g.rows};
+        keep = i4{ceil_frames(c.mask_lo, a.in_den), ceil_frames(c.mask_hi, a.in_den), max(c.T - L, g.t_lo), g.t_hi};
+      }
+    }
+    ccol_rows[j] = rows;
+    ccol_keep[j] = keep;
   }
   __syncthreads();
 
@@ -852,9 +896,11 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       f4 acc = {0.f, 0.f, 0.f, 0.f};
       if (nc < ncb) {
         const int col = nc * 16 + lr;
-        const int s = ccol_seg[col];
         // column q = 0 of a buffer starts from the carry
-        if (col < n_ccol && ccol_q[col] == 0 && csegs[s].Tin > 0) acc = gload<f4>(csegs[s].carry + m);
+        if (col < n_ccol && ccol_q[col] == 0) {
+          const CtSeg& c = csegs[ccol_seg[col]];
+          if (c.Tin > 0) acc = gload<f4>(c.carry + m);
+        }
         const unsigned char* xb = X + ccol_x[col] * XROW + lg * 32;
 #pragma unroll
         for (int c = 0; c < KCT; ++c) {
@@ -878,23 +924,20 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     for (int nc = 0; nc < NCB; ++nc) {
       const int col = nc * 16 + lr;
       if (nc >= ncb || col >= n_ccol) continue;
-      const int s = ccol_seg[col];
-      const int q = ccol_q[col];
-      const CtSeg& c = csegs[s];
-      if (q == c.Tin) {
+      const i4 rows = ccol_rows[col];
+      const i4 keep = ccol_keep[col];
+      if (rows.x < 0) {
         // the carry of the next buffer, in accumulator units
-        gstore<f4>(c.carry_next + m, cacc[mi][nc]);
+        gstore<f4>(csegs[ccol_seg[col]].carry_next + m, cacc[mi][nc]);
         continue;
       }
       f4 v = cacc[mi][nc];
       if (PREC == 2) v = v * (ct_ws[mi] * a.ct.act_scale);
       v = v + ct_bias[mi];
-      const int32_t t = q * R + phi;           // x frame of the stream
-      if ((int64_t)t * a.in_den < c.mask_lo || (int64_t)t * a.in_den >= c.mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
-      const WinSeg& g = segs[s];
-      const int32_t r = t + L;                 // its window row
-      if (r >= g.r0 && r < g.r0 + g.rows) {
-        const int32_t j = g.base + (r - g.r0);
+      const int32_t t = rows.x + phi;          // x frame of the stream
+      if (t < keep.x || t >= keep.y) v = f4{0.f, 0.f, 0.f, 0.f};
+      if (t >= rows.z && t < rows.w) {         // its window row t + L is staged
+        const int32_t j = rows.y + t;
         *reinterpret_cast<f4*>(xf + (size_t)j * MT + co) = v;
         unsigned char* dst = wop + (size_t)j * rowb + co * ES;
         if constexpr (PREC == 1) {
@@ -908,8 +951,10 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
         }
       }
       // the conv's next cache: the stream's last L frames of x, by the tile that owns them
-      if (t >= c.T - L && t >= g.t_lo && t <= g.t_hi)
+      if (t >= keep.z && t <= keep.w) {
+        const CtSeg& c = csegs[ccol_seg[col]];
         gstore<f4>(c.cache_next + (int64_t)(t - (c.T - L)) * MT + co, v);
+      }
     }
   }
   // window rows from the conv's cache (rows below L)
@@ -945,38 +990,25 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
 #pragma unroll
   for (int c = 0; c < KCM; ++c) {
     if (c < n_chunks) {
-      int off[2];
-      bool live[2];
+      u4 blo[NB], bhi[NB];
+      win_chunk_reads<ES, NB>(a, c, lg, Kreal, MT, rowb, wop, cb, blo, bhi);
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int kk = (c * 128 + lg * 32 + p * 16) / ES;
-        live[p] = kk < Kreal;
-        const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
-        off[p] = tap * a.dil * rowb + (kk - tap * MT) * ES;
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const u4 z = {0u, 0u, 0u, 0u};
-        const u4 blo = live[0] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]) : z;
-        const u4 bhi = live[1] ? *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]) : z;
-        acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo, bhi, acc[nb]);
-      }
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
   }
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int col = wn * (F / WN) + nb * 16 + lr;
-    const int s = colseg[col];
-    if (s < 0) continue;
+    const int keep = colkeep[col];
+    if (keep < 0) continue;
     const int32_t f = f0 + col;
-    const int32_t t = f - segs[s].out_start;
     f4 v = acc[nb];
     if (PREC == 2) v = v * (wsc * a.act_scale);
     v = v + bias;
     if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * MT + m);
-    if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) v = f4{0.f, 0.f, 0.f, 0.f};
+    if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
-    if (!a.twin_only) __builtin_nontemporal_store(v, reinterpret_cast<f4*>(a.out_buf + o));
+    if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
     if (a.out_twin) {
       f4 w = v;
       if (a.twin_pre) {
