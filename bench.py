@@ -141,9 +141,10 @@ def op_accounting(p, tail=None, layer=False, ct=None):
     reaches HBM, the output conv's does, and this op moves that conv's input
     cache (written once here, read once by the tail launch).  `layer`: the
     op as a layer of its own (every layer's input and output through HBM).
-    `ct`: the transposed conv computed inside this window conv's launch (the
-    op before it, no launches of its own): its FLOPs, input, carry and
-    weights count here, and its output (this op's input) never reaches HBM."""
+    `ct`: the layer computed inside this window conv's launch (the op before
+    it, no launches of its own: a transposed conv, or the first conv of a
+    fused residual pair): its FLOPs, input, state and weights count here,
+    and its output (this op's input) never reaches HBM."""
     if ct is not None:
         x = p["frames_in"]
         rec = dict(ct, frames_in=x // ct["stride"], frames_out=x, entries=p["entries"], launches=p["launches"])
@@ -182,13 +183,14 @@ def fused_tail(prof, p):
     return prof[i + 1] if p["impl"] == 2 and i + 1 < len(prof) and prof[i + 1]["impl"] == 3 else None
 
 
-def fused_convt(prof, p):
-    """The transposed conv computed inside window conv p's launch (the op
-    before it, with no launches of its own), or None."""
+def fused_producer(prof, p):
+    """The layer computed inside window conv p's launch (the op before it,
+    with no launches of its own): a transposed conv, or the residual conv
+    before p in a fused pair; None if there is none."""
     i = prof.index(p)
     if p["kind"] == 1 and p["impl"] == 2 and p["launches"] > 0 and i > 0:
         q = prof[i - 1]
-        if q["kind"] == 2 and q["launches"] == 0:
+        if q["kind"] in (1, 2) and q["launches"] == 0:
             return q
     return None
 
@@ -205,7 +207,7 @@ def roofline(prof):
     this layer-by-layer design, not of the method (which moves only the step's
     input, output and state), so they are labelled design traffic."""
     best = max(prof, key=lambda p: p["ms"])
-    ct = fused_convt(prof, best)
+    ct = fused_producer(prof, best)
     flops, byts = op_accounting(best, fused_tail(prof, best), ct=ct)
     sec = best["ms"] * 1e-3
     peak_f = PEAK[best["precision"]] if best["impl"] >= 1 else PEAK[0]
@@ -225,9 +227,12 @@ def roofline(prof):
     impl = IMPL_NAME[best["impl"]]
     kernel = "%s_%s node %d (cin %d, cout %d, k %d, d %d)" % (
         kname, impl, best["node"], best["cin"], best["cout"], best["k"], best["dilation"])
-    if ct is not None:
+    if ct is not None and ct["kind"] == 2:
         kernel += " with the transposed conv node %d (cin %d, cout %d, r %d) in its launch" % (
             ct["node"], ct["cin"], ct["cout"], ct["stride"])
+    elif ct is not None:
+        kernel += " with the residual conv node %d (cin %d, cout %d, k %d, d %d) in its launch" % (
+            ct["node"], ct["cin"], ct["cout"], ct["k"], ct["dilation"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": measured_traffic(best), "basis": basis,
             "flops_per_launch": round(flops / max(best["launches"], 1)),
@@ -327,7 +332,7 @@ def step_roofline(run, value, prec):
     The layer-by-layer figures (every layer's input and output through HBM,
     op_accounting) are the design's own roofline, given beside it."""
     prof, samples = run["prof"], run["samples"]
-    acc = [op_accounting(p, layer=True, ct=fused_convt(prof, p)) for p in prof]
+    acc = [op_accounting(p, layer=True, ct=fused_producer(prof, p)) for p in prof]
     flops = sum(a[0] for a in acc) / samples
     byts = run["algorithmic_bytes"] / samples
     lbl = sum(a[1] for a in acc) / samples

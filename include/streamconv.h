@@ -158,7 +158,15 @@ enum {
                                    layer; by default an FP32 MFMA conv that is the
                                    input's only reader gathers it straight from the
                                    callers' channel-major buffers (same results,
-                                   bitwise; for testing) */
+                                   bitwise; for testing) */,
+  SC_MODEL_NO_PAIR_FUSION = 256u  /* two residual window convs of 64 channels in a
+                                   row (the first one's output read only by the
+                                   second) run as two launches; by default the
+                                   second conv's tiles compute the frames of the
+                                   first that their windows need in the same
+                                   launch, and the first conv's output never
+                                   reaches memory (same results, bitwise; for
+                                   testing) */
 };
 sc_status sc_model_create(const sc_node* nodes, int32_t n_nodes, const float* weights,
                           size_t n_weights, sc_precision precision, const float* act_scales,
@@ -210,6 +218,9 @@ sc_status sc_model_set_act_scales(sc_model* model, const float* act_scales);
  * into the host array `amax_out` (sc_model_n_layers values).  Synchronizes
  * the model's device work. */
 sc_status sc_model_read_amax(sc_model* model, float* amax_out, int32_t reset);
+/* Turn that recording on or off.  Errors: SC_EINVAL (enable on a model that
+ * runs two residual convs in one launch, see SC_MODEL_NO_PAIR_FUSION: the
+ * first one's output is never formed; calibrate on an SC_FP32 model). */
 sc_status sc_model_enable_amax(sc_model* model, int32_t enable);
 /* The static FP8 activation scales calibrated from the maxima recorded so
  * far (as sc_model_read_amax, without reset): for each layer, 1.25 x its

@@ -29,6 +29,7 @@ SC_MODEL_NO_SPLIT = 16
 SC_MODEL_NO_OUT_FUSION = 32
 SC_MODEL_NO_CONVT_FUSION = 64
 SC_MODEL_NO_INPUT_DIRECT = 128
+SC_MODEL_NO_PAIR_FUSION = 256
 OPS = {"input": 0, "conv": 1, "convt": 2, "add": 3}
 
 # every symbol the header declares (checked by the CPU test suite)

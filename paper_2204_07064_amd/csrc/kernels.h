@@ -69,6 +69,20 @@ struct LayerArgs {
     int64_t delay;         // warm-up lag of its output (frames at this layer's input rate)
     int64_t state_off, state_len;   // its carry: copies of [r * cout] (floats)
   } ct;
+  // window conv only: the residual window conv whose output is this layer's
+  // input, computed in the same launch (its output never reaches memory: each
+  // tile computes the frames its window needs from that conv's own input).
+  // pa.L == 0: none.  Channels, rates and kernel size equal this layer's.
+  struct {
+    const void* W;         // packed MFMA rows [cout][Kpad]
+    const float* B;        // bias [cout]
+    const float* wscale;   // FP8: per-row weight scale
+    float act_scale;       // FP8: its static activation scale
+    const float* in_buf;   // its input, packed [frames][cin]
+    int32_t L, dil, skip_off, pre_act;
+    int64_t delay;         // warm-up lag of its output (frames)
+    int64_t state_off, state_len;   // its input cache: copies of [L][cin] (floats)
+  } pa;
 };
 
 // The step descriptor seen through the constant address space: it is
@@ -210,6 +224,14 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
 int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_cin, int prec, int64_t min_frames,
                        int32_t* xrow_cap, int32_t* stash_cap);
 hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t xrow_cap, int32_t stash_cap,
+                            hipStream_t s);
+// Two residual window convs in one launch (a.pa: the first, whose output only
+// the second reads): whether a pair of this shape qualifies (0 if not, else
+// the second conv's window rows a tile needs; *arow_cap: the first conv's
+// window rows, *stash_cap: cache-row pieces of 16 bytes), and its launch.
+int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, int32_t* arow_cap,
+                       int32_t* stash_cap);
+hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32_t arow_cap, int32_t stash_cap,
                             hipStream_t s);
 // Output frames per window tile, and whether a one-output-channel conv of
 // k taps, dilation dil (cache L = dil * (k - 1)) can be computed in the

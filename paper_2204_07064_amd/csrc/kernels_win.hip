@@ -91,6 +91,45 @@ __device__ inline u4 operand16(const float* p, bool pre, float qs) {
   return r;
 }
 
+// Four FP32 values in operand form (pre-activation, FP8 activation scale) at dst.
+template <int PREC>
+__device__ inline void store_operand(unsigned char* dst, f4 v, bool pre, float qs) {
+  if constexpr (PREC == 0) {
+    *reinterpret_cast<f4*>(dst) = f4{act(v.x, pre), act(v.y, pre), act(v.z, pre), act(v.w, pre)};
+  } else if constexpr (PREC == 1) {
+    uint2 w;
+    w.x = wpack_bf16(act(v.x, pre), act(v.y, pre));
+    w.y = wpack_bf16(act(v.z, pre), act(v.w, pre));
+    *reinterpret_cast<uint2*>(dst) = w;
+  } else {
+    *reinterpret_cast<uint32_t*>(dst) =
+        wpack_fp8x4(act(v.x, pre) * qs, act(v.y, pre) * qs, act(v.z, pre) * qs, act(v.w, pre) * qs);
+  }
+}
+
+// The operand copy of output elements o .. o + 3 for the layer's reader, in its type.
+__device__ inline void store_twin(const LayerArgs& a, int64_t o, f4 v) {
+  f4 w = v;
+  if (a.twin_pre) {
+    w.x = lrelu(w.x);
+    w.y = lrelu(w.y);
+    w.z = lrelu(w.z);
+    w.w = lrelu(w.w);
+  }
+  const float q = a.twin_qs;
+  unsigned char* dst = static_cast<unsigned char*>(a.out_twin) + o * w_esize_dev(a.twin_prec);
+  if (a.twin_prec == 0) {
+    *reinterpret_cast<f4*>(dst) = w * q;
+  } else if (a.twin_prec == 1) {
+    uint2 u;
+    u.x = wpack_bf16(w.x * q, w.y * q);
+    u.y = wpack_bf16(w.z * q, w.w * q);
+    *reinterpret_cast<uint2*>(dst) = u;
+  } else {
+    *reinterpret_cast<uint32_t*>(dst) = wpack_fp8x4(w.x * q, w.y * q, w.z * q, w.w * q);
+  }
+}
+
 template <int PREC>
 __device__ inline f4 mfma32(const u4& alo, const u4& ahi, const u4& blo, const u4& bhi, f4 acc) {
   if constexpr (PREC == 0) {
@@ -308,7 +347,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
 // column's first row and is zeroed), so the chunk waits once for LDS instead
 // of once per column block behind a branch.
 template <int ES, int NB>
-__device__ inline void win_chunk_reads(const LayerArgs& a, int c, int lg, int Kreal, int cin, int rowb,
+__device__ inline void win_chunk_reads(const FastDiv& fd_cin, int dil, int c, int lg, int Kreal, int cin, int rowb,
                                        const unsigned char* wop, const int* cb, u4* blo, u4* bhi) {
   int off[2];
   bool live[2];
@@ -316,8 +355,8 @@ __device__ inline void win_chunk_reads(const LayerArgs& a, int c, int lg, int Kr
   for (int p = 0; p < 2; ++p) {
     const int kk = (c * 128 + lg * 32 + p * 16) / ES;
     live[p] = kk < Kreal;
-    const int tap = (int)fdiv(a.fd_cin, (uint32_t)kk);
-    off[p] = live[p] ? tap * a.dil * rowb + (kk - tap * cin) * ES : 0;
+    const int tap = (int)fdiv(fd_cin, (uint32_t)kk);
+    off[p] = live[p] ? tap * dil * rowb + (kk - tap * cin) * ES : 0;
   }
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -556,7 +595,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   for (int c = 0; c < kMaxChunks; ++c) {
     if (c < n_chunks) {
       u4 blo[NB], bhi[NB];
-      win_chunk_reads<ES, NB>(a, c, lg, Kreal, cin, rowb, wop, cb, blo, bhi);
+      win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, cin, rowb, wop, cb, blo, bhi);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
@@ -582,27 +621,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
     if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
-    if (a.out_twin) {
-      f4 w = v;
-      if (a.twin_pre) {
-        w.x = lrelu(w.x);
-        w.y = lrelu(w.y);
-        w.z = lrelu(w.z);
-        w.w = lrelu(w.w);
-      }
-      const float q = a.twin_qs;
-      unsigned char* dst = static_cast<unsigned char*>(a.out_twin) + o * w_esize_dev(a.twin_prec);
-      if (a.twin_prec == 0) {
-        *reinterpret_cast<f4*>(dst) = w * q;
-      } else if (a.twin_prec == 1) {
-        uint2 u;
-        u.x = wpack_bf16(w.x * q, w.y * q);
-        u.y = wpack_bf16(w.z * q, w.w * q);
-        *reinterpret_cast<uint2*>(dst) = u;
-      } else {
-        *reinterpret_cast<uint32_t*>(dst) = wpack_fp8x4(w.x * q, w.y * q, w.z * q, w.w * q);
-      }
-    }
+    if (a.out_twin) store_twin(a, o, v);
   }
 }
 
@@ -991,7 +1010,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   for (int c = 0; c < KCM; ++c) {
     if (c < n_chunks) {
       u4 blo[NB], bhi[NB];
-      win_chunk_reads<ES, NB>(a, c, lg, Kreal, MT, rowb, wop, cb, blo, bhi);
+      win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, MT, rowb, wop, cb, blo, bhi);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
@@ -1009,27 +1028,373 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
-    if (a.out_twin) {
-      f4 w = v;
-      if (a.twin_pre) {
-        w.x = lrelu(w.x);
-        w.y = lrelu(w.y);
-        w.z = lrelu(w.z);
-        w.w = lrelu(w.w);
-      }
-      const float q = a.twin_qs;
-      unsigned char* dst = static_cast<unsigned char*>(a.out_twin) + o * w_esize_dev(a.twin_prec);
-      if (a.twin_prec == 0) {
-        *reinterpret_cast<f4*>(dst) = w * q;
-      } else if (a.twin_prec == 1) {
-        uint2 u;
-        u.x = wpack_bf16(w.x * q, w.y * q);
-        u.y = wpack_bf16(w.z * q, w.w * q);
-        *reinterpret_cast<uint2*>(dst) = u;
-      } else {
-        *reinterpret_cast<uint32_t*>(dst) = wpack_fp8x4(w.x * q, w.y * q, w.z * q, w.w * q);
+    if (a.out_twin) store_twin(a, o, v);
+  }
+}
+
+// ---- two residual window convs in one launch ----
+//
+// Conv A's output x1 has one reader, conv B (the next residual conv of the
+// stack).  Each tile of B's output frames computes the x1 frames its window
+// needs -- its own frames and the L_B before them, back to the start of the
+// stream's buffer -- from A's window, so x1 never goes to memory; B's window
+// rows before the buffer come from B's cache.  x1, its rounding into B's
+// operand and B itself are bit for bit those of the two launches (the same K
+// chunks, MFMA instructions and epilogue order).
+//
+// LDS: region 1 holds A's window rows in operand form and, once every wave is
+// past A's MFMAs, B's window rows in FP32 (B's skip); then B's cache rows in
+// FP32 until region 1 is free, B's window rows in operand form and A's row
+// sources.  A's skip values go to registers with the staging loads.  A's next
+// cache (its last L_A window rows) is written by the blocks after the tiles,
+// B's (the stream's last L_B frames of x1) by the tiles that own those frames
+// (every stream brings at least L_B frames, so no old cache row survives).
+
+// Per-stream part of a pair tile (LDS): conv A's side.
+struct PairSeg {
+  const float* cache_a;    // A's current cache [L_A][C]
+  float* cache_b_next;     // B's next cache copy [L_B][C]
+  int64_t mask_lo, mask_hi;   // x1 frame u is zeroed iff u * den is outside [mask_lo, mask_hi)
+  int32_t in_start;        // first packed frame of A's input
+  int32_t T;               // frames of the stream
+  int32_t ta;              // first x1 frame the tile computes
+  int32_t acol0;           // its A column
+  int32_t abase;           // LDS row of A's window row ta
+};
+
+template <int PREC, int MT, int NB, int KCM, int NCBA>
+__global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
+                                                                int row_cap, int arow_cap, int stash_cap,
+                                                                int extra_blocks, FastDiv fd_per_ent) {
+  static_assert(MT == 64, "one 16-row M block per wave, one wave column");
+  constexpr int C = MT;                        // channels of both convs
+  constexpr int F = NB * 16;
+  constexpr int ES = WPrec<PREC>::kEsize;
+  constexpr int ROWB = C * ES + 16;            // operand row stride (bytes), padded against bank conflicts
+  constexpr int PPR = C / 4;                   // 16-byte FP32 pieces per row
+  constexpr int CPRE = 2;                      // B cache-row pieces per thread (the host bounds L_B)
+  constexpr int NCOL = NCBA * 16;              // A columns a tile holds at most
+  constexpr int SB = kStageBatch;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ WinSeg segs[kMaxStreams];
+  __shared__ PairSeg psegs[kMaxStreams];
+  __shared__ int32_t colbase[F];
+  __shared__ int8_t colkeep[F];
+  __shared__ int32_t acb[NCOL];                // A column: LDS row of its first window row
+  __shared__ int32_t ajb[NCOL];                // A column: LDS row of its frame in B's window
+  __shared__ int8_t aflag[NCOL];               // bit 0: kept by A's masks; bit 1: a row of B's next cache
+  __shared__ const float* askip[NCOL];         // A column: its skip row (A's cache or input)
+  __shared__ float* anext[NCOL];               // A column: its row of B's next cache
+
+  const int tid = threadIdx.x;
+  const int32_t bid = blockIdx.x;
+  const int LA = a.pa.L, LB = a.L;
+
+  // ---- A's cache update blocks (after the tiles): A's next cache = its last
+  // L_A window rows, 4 channels per item ----
+  if (bid >= n_nt) {
+    const int32_t per_ent = LA * C / 4;
+    const int32_t total = step_ents(a) * per_ent;
+    for (int32_t j = (bid - n_nt) * kThreads + tid; j < total; j += extra_blocks * kThreads) {
+      const int ei = (int)fdiv(fd_per_ent, (uint32_t)j);
+      const int32_t rem = (j - ei * per_ent) * 4;
+      const int32_t i = rem / C;
+      const int ci = rem - i * C;
+      const Entry e = load_entry(a.ents + ei);
+      const int32_t row = in_frames(a, e.T) + i;
+      const float* src = row < LA ? e.state + a.pa.state_off + (int64_t)e.parity * a.pa.state_len + (int64_t)row * C + ci
+                                  : a.pa.in_buf + ((int64_t)in_frames(a, e.off) + row - LA) * C + ci;
+      gstore<f4>(e.state + a.pa.state_off + (int64_t)(1 - e.parity) * a.pa.state_len + (int64_t)i * C + ci,
+                 gload<f4>(src));
+    }
+    return;
+  }
+
+  const int32_t f0 = bid * F;
+  const TileSpan sp = tile_span(a, f0, F);
+  if (f0 >= sp.n_cols) return;          // the grid may be sized for a larger step
+  const int32_t f_last = sp.f_last;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int m = wave * 16 + lg * 4;     // the lane's channels m .. m + 3 (both convs)
+  const bool pre_a = a.pa.pre_act != 0, pre_b = a.pre_act != 0;
+  const float qs_a = PREC == 2 ? 1.0f / a.pa.act_scale : 1.0f;
+  const float qs_b = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
+  const size_t r1 = (size_t)max(arow_cap * ROWB, row_cap * C * 4);
+  unsigned char* wop_a = lds;                              // A's window rows, operand form
+  float* xf = reinterpret_cast<float*>(lds);               // B's window rows in FP32 (after A's MFMAs)
+  f4* stash = reinterpret_cast<f4*>(lds + r1);             // B's cache rows until then
+  unsigned char* wop_b = lds + r1 + (size_t)stash_cap * 16;   // B's window rows, operand form
+  const float** rsrc = reinterpret_cast<const float**>(wop_b + (size_t)row_cap * ROWB);
+
+  // A's weights (the wave's 16 rows, every chunk), both convs' biases and scales
+  u4 alo[KCM], ahi[KCM];
+  {
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.pa.W) + (int64_t)(wave * 16 + lr) * (Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < KCM; ++c) {
+      alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+      ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+    }
+  }
+  const f4 bias_a = *reinterpret_cast<const f4*>(a.pa.B + m);
+  const f4 ws_a = PREC == 2 ? *reinterpret_cast<const f4*>(a.pa.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  const f4 bias_b = *reinterpret_cast<const f4*>(a.B + m);
+  const f4 ws_b = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+
+  // ---- the streams of the tile: lane s of every wave forms stream s's
+  // records; wave 0 publishes them ----
+  const int e_first = sp.e0;
+  const int n_seg = sp.n_seg;
+  // the host sizes tiles so that these hold; never index LDS beyond them
+  if (n_seg > kMaxStreams) return;
+  int32_t n_rows = 0, n_acol = 0, n_arows = 0, n_cp = 0;
+  {
+    const Entry e = load_entry(a.ents + e_first + min(lane, n_seg - 1));
+    WinSeg g{};
+    PairSeg p{};
+    int32_t ncol = 0, arows = 0, cpieces = 0;
+    if (lane < n_seg) {
+      g.cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
+      g.mask_x = mask_lo(e, a.delay, a.out_num, a.out_den);
+      g.mask_hi = mask_hi(e, a.delay, a.out_num, a.out_den);
+      g.in_start = in_frames(a, e.off);
+      g.out_start = out_frames(a, e.off);
+      const int32_t T = out_frames(a, e.T);
+      g.t_lo = lane == 0 ? f0 - g.out_start : 0;
+      g.t_hi = lane == n_seg - 1 ? f_last - g.out_start : T - 1;
+      g.r0 = g.t_lo;
+      g.rows = g.t_hi - g.t_lo + 1 + LB;
+      p.cache_a = e.state + a.pa.state_off + (int64_t)e.parity * a.pa.state_len;
+      p.cache_b_next = e.state + a.state_off + (int64_t)(1 - e.parity) * a.state_len;
+      p.mask_lo = mask_lo(e, a.pa.delay, a.out_num, a.out_den);
+      p.mask_hi = mask_hi(e, a.pa.delay, a.out_num, a.out_den);
+      p.in_start = g.in_start;
+      p.T = T;
+      // x1 frames of B's window: [max(0, t_lo - L_B), t_hi]; A's window rows: those plus L_A
+      p.ta = max(0, g.t_lo - LB);
+      ncol = g.t_hi - p.ta + 1;
+      arows = ncol + LA;
+      cpieces = max(0, min(LB - g.r0, g.rows)) * PPR;
+    }
+    // each stream's first B row, A column and A row: sums over the streams before it
+    for (int s = 0; s < n_seg; ++s) {
+      const int32_t r = __shfl(g.rows, s);
+      const int32_t nc = __shfl(ncol, s);
+      const int32_t ar = __shfl(arows, s);
+      g.base += s < lane ? r : 0;
+      p.acol0 += s < lane ? nc : 0;
+      p.abase += s < lane ? ar : 0;
+      n_rows += r;
+      n_acol += nc;
+      n_arows += ar;
+      n_cp += __shfl(cpieces, s);
+    }
+    if (wave == 0 && lane < n_seg) {
+      segs[lane] = g;
+      psegs[lane] = p;
+    }
+  }
+  if (n_rows > row_cap || n_acol > NCOL || n_arows > arow_cap || n_cp > stash_cap || n_cp > CPRE * kThreads) return;
+  __syncthreads();
+
+  // ---- tables: B's columns, A's columns, A's window rows ----
+  if (tid < F) {
+    const int32_t f = f0 + tid;
+    int s = 0;
+    int8_t keep = -1;
+    if (f <= f_last) {
+      while (s + 1 < n_seg && segs[s + 1].out_start <= f) ++s;
+      colbase[tid] = segs[s].base + (f - segs[s].out_start - segs[s].r0);
+      const int64_t x = (int64_t)(f - segs[s].out_start) * a.out_den;
+      keep = x < segs[s].mask_x || x >= segs[s].mask_hi ? 0 : 1;
+    } else {
+      colbase[tid] = 0;
+    }
+    colkeep[tid] = keep;
+  }
+  for (int j = tid; j < NCOL; j += kThreads) {
+    int32_t cb = 0, jb = 0;
+    int8_t fl = 0;
+    const float* sk = a.pa.B;              // a padding column reads a harmless row and is not used
+    float* nx = nullptr;
+    if (j < n_acol) {
+      int s = 0;
+      while (s + 1 < n_seg && psegs[s + 1].acol0 <= j) ++s;
+      const PairSeg& p = psegs[s];
+      const WinSeg& g = segs[s];
+      const int32_t u = p.ta + (j - p.acol0);      // x1 frame of the stream
+      cb = p.abase + (u - p.ta);                   // A's window row u (taps add dil_a rows)
+      jb = g.base + (u + LB - g.r0);               // B's window row u + L_B
+      const int64_t x = (int64_t)u * a.out_den;
+      if (!(x < p.mask_lo || x >= p.mask_hi)) fl |= 1;
+      const int32_t r = u + a.pa.skip_off;         // A's skip: its window row u + skip_off
+      sk = r < LA ? p.cache_a + (int64_t)r * C : a.pa.in_buf + ((int64_t)p.in_start + r - LA) * C;
+      if (u >= p.T - LB && u >= g.t_lo && u <= g.t_hi) {
+        fl |= 2;
+        nx = p.cache_b_next + (int64_t)(u - (p.T - LB)) * C;
       }
     }
+    acb[j] = cb;
+    ajb[j] = jb;
+    aflag[j] = fl;
+    askip[j] = sk;
+    anext[j] = nx;
+  }
+  for (int j = tid; j < n_arows; j += kThreads) {
+    int s = 0;
+    while (s + 1 < n_seg && psegs[s + 1].abase <= j) ++s;
+    const PairSeg& p = psegs[s];
+    const int32_t r = p.ta + (j - p.abase);        // A's window row
+    rsrc[j] = r < LA ? p.cache_a + (int64_t)r * C : a.pa.in_buf + ((int64_t)p.in_start + r - LA) * C;
+  }
+  __syncthreads();
+
+  // ---- loads: B's cache rows, A's skip values of the lane's columns, A's
+  // window rows (operand form) ----
+  f4 cpre[CPRE];
+  int32_t cdst[CPRE];
+#pragma unroll
+  for (int p = 0; p < CPRE; ++p) {
+    cdst[p] = -1;
+    cpre[p] = f4{0.f, 0.f, 0.f, 0.f};
+    int32_t idx = tid + p * kThreads;
+    for (int s = 0; s < n_seg; ++s) {
+      const WinSeg& g = segs[s];
+      const int32_t n = max(0, min(LB - g.r0, g.rows)) * PPR;
+      if (idx < n) {
+        const int32_t i = idx / PPR;
+        const int ch = (idx - i * PPR) * 4;
+        cpre[p] = gload<f4>(g.cache + (int64_t)(g.r0 + i) * C + ch);
+        cdst[p] = (g.base + i) * C + ch;
+        break;
+      }
+      idx -= n;
+    }
+  }
+  f4 skv[NCBA];
+#pragma unroll
+  for (int nc = 0; nc < NCBA; ++nc) skv[nc] = gload<f4>(askip[nc * 16 + lr] + m);
+  {
+    const int32_t n_pieces = n_arows * PPR;
+    for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * SB) {
+      f4 v[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int32_t idx = i0 + u * kThreads + tid;
+        v[u] = f4{0.f, 0.f, 0.f, 0.f};
+        if (idx < n_pieces) v[u] = gload<f4>(rsrc[idx / PPR] + (idx % PPR) * 4);
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int32_t idx = i0 + u * kThreads + tid;
+        if (idx >= n_pieces) continue;
+        unsigned char* dst = wop_a + (idx / PPR) * ROWB + (idx % PPR) * 4 * ES;
+        store_operand<PREC>(dst, v[u], pre_a, qs_a);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < CPRE; ++p)
+    if (cdst[p] >= 0) stash[tid + p * kThreads] = cpre[p];
+  __syncthreads();
+
+  // ---- A: the wave's 16 rows x every A column block ----
+  const int ncba = (n_acol + 15) / 16;
+  f4 aacc[NCBA];
+  {
+    int cb[NCBA];
+#pragma unroll
+    for (int nc = 0; nc < NCBA; ++nc) {
+      cb[nc] = acb[nc * 16 + lr] * ROWB;
+      aacc[nc] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    // two groups of column blocks, each over every chunk (a column's chain of
+    // MFMAs is the same; half the operand registers)
+    constexpr int G = NCBA / 2;
+    static_assert(NCBA % 2 == 0, "two groups");
+#pragma unroll
+    for (int g0 = 0; g0 < NCBA; g0 += G) {
+      if (g0 >= ncba) break;
+#pragma unroll
+      for (int c = 0; c < KCM; ++c) {
+        u4 blo[G], bhi[G];
+        win_chunk_reads<ES, G>(a.fd_cin, a.pa.dil, c, lg, Kreal, C, ROWB, wop_a, cb + g0, blo, bhi);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if (g0 + q < ncba) aacc[g0 + q] = mfma32<PREC>(alo[c], ahi[c], blo[q], bhi[q], aacc[g0 + q]);
+      }
+    }
+  }
+  // B's weights (their latency hides behind x1's epilogue)
+  u4 blw[KCM], bhw[KCM];
+  {
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.W) + (int64_t)(wave * 16 + lr) * (Kpad * ES) + lg * 32;
+#pragma unroll
+    for (int c = 0; c < KCM; ++c) {
+      blw[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
+      bhw[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
+    }
+  }
+  __syncthreads();   // every wave is past A's operand rows: region 1 takes B's FP32 rows
+
+  // ---- x1: A's epilogue, B's window rows (FP32 and operand), B's next cache ----
+#pragma unroll
+  for (int nc = 0; nc < NCBA; ++nc) {
+    const int col = nc * 16 + lr;
+    if (nc >= ncba || col >= n_acol) continue;
+    const int32_t jb = ajb[col];
+    const int fl = aflag[col];
+    f4 v = aacc[nc];
+    if (PREC == 2) v = v * (ws_a * a.pa.act_scale);
+    v = v + bias_a;
+    v = v + skv[nc];
+    if (!(fl & 1)) v = f4{0.f, 0.f, 0.f, 0.f};
+    *reinterpret_cast<f4*>(xf + (size_t)jb * C + m) = v;
+    store_operand<PREC>(wop_b + (size_t)jb * ROWB + m * ES, v, pre_b, qs_b);
+    if (fl & 2) gstore<f4>(anext[col] + m, v);
+  }
+  // B's window rows from its cache (rows below L_B)
+#pragma unroll
+  for (int p = 0; p < CPRE; ++p) {
+    if (cdst[p] < 0) continue;
+    const f4 v = stash[tid + p * kThreads];
+    *reinterpret_cast<f4*>(xf + cdst[p]) = v;
+    const int32_t jr = cdst[p] / C;
+    store_operand<PREC>(wop_b + (size_t)jr * ROWB + (cdst[p] - jr * C) * ES, v, pre_b, qs_b);
+  }
+  __syncthreads();
+
+  // ---- B: operands from its staged rows, the skip from its FP32 rows ----
+  int cbb[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) cbb[nb] = colbase[nb * 16 + lr] * ROWB;
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < KCM; ++c) {
+    u4 blo[NB], bhi[NB];
+    win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, C, ROWB, wop_b, cbb, blo, bhi);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(blw[c], bhw[c], blo[nb], bhi[nb], acc[nb]);
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = nb * 16 + lr;
+    const int keep = colkeep[col];
+    if (keep < 0) continue;
+    const int32_t f = f0 + col;
+    f4 v = acc[nb];
+    if (PREC == 2) v = v * (ws_b * a.act_scale);
+    v = v + bias_b;
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * C + m);
+    if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t o = (int64_t)f * a.cout + m;
+    if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
+    if (a.out_twin) store_twin(a, o, v);
   }
 }
 
@@ -1289,6 +1654,70 @@ hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32
   }
   SC_CTWIN(1, 32, 2, 2, 1, 6) SC_CTWIN(2, 32, 1, 2, 1, 6)
 #undef SC_CTWIN
+  return hipErrorInvalidValue;
+}
+
+
+namespace {
+constexpr int kPairC = 64;       // channels of a fused pair (one 64-row M tile)
+constexpr int kPairCols = 96;    // x1 frames a pair tile computes at most (6 column blocks)
+// A's window rows in operand form, overlaid by B's window rows in FP32; B's
+// cache rows; B's window rows in operand form; A's row sources
+int64_t pair_lds_bytes(int64_t rows, int64_t arows, int64_t stash, int prec) {
+  const int64_t rowb = kPairC * w_esize(prec) + 16;
+  return std::max(arows * rowb, rows * kPairC * 4) + stash * 16 + rows * rowb + arows * 8;
+}
+}  // namespace
+
+int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, int32_t* arow_cap,
+                       int32_t* stash_cap) {
+  *arow_cap = 0;
+  *stash_cap = 0;
+  if (c != kPairC || k != 3 || prec < 1 || prec > 2 || dil_a < 1 || dil_b < 1 || min_frames < 1) return 0;
+  const int LA = dil_a * (k - 1), LB = dil_b * (k - 1);
+  // every stream brings at least L_B frames: B's next cache comes from x1 alone
+  if (min_frames < LB) return 0;
+  const int kc = w_kchunk(prec);
+  const int Kpad = (k * c + kc - 1) / kc * kc;
+  if (Kpad * w_esize(prec) / 128 != win_kcm(prec, c)) return 0;   // the kernel holds exactly these chunks
+  const int F = win_f(kPairC, 4);
+  const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
+  if (max_seg > kMaxStreams) return 0;
+  const int64_t rows = F + (int64_t)LB * max_seg;     // B's window rows
+  const int64_t acols = F + (int64_t)LB * max_seg;    // x1 frames computed
+  const int64_t arows = acols + (int64_t)LA * max_seg;
+  const int64_t stash = (int64_t)LB * max_seg * (c / 4);
+  if (acols > kPairCols || stash > 2 * kThreads || pair_lds_bytes(rows, arows, stash, prec) > 64 * 1024) return 0;
+  *arow_cap = (int32_t)arows;
+  *stash_cap = (int32_t)stash;
+  return (int32_t)rows;
+}
+
+hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32_t arow_cap, int32_t stash_cap,
+                            hipStream_t s) {
+  const int C = kPairC;
+  const int F = win_f(C, 4);
+  const int kc = w_kchunk(prec);
+  const int Kreal = a.k * C;
+  const int Kpad = (Kreal + kc - 1) / kc * kc;
+  if (a.cin != C || a.cout != C || a.k != 3 || a.pa.L != a.pa.dil * 2 || a.L != a.dil * 2 || !a.out_buf ||
+      a.fd_cin.d != (uint32_t)C || Kpad * w_esize(prec) / 128 != win_kcm(prec, C))
+    return hipErrorInvalidValue;
+  const int64_t n_nt = (a.n_out + F - 1) / F;
+  const int64_t items = (int64_t)a.n_ent * a.pa.L * C / 4;   // 4 channels per cache-update item
+  const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
+  const int64_t grid = n_nt + extra;
+  if (grid <= 0) return hipSuccess;
+  const size_t lds = (size_t)pair_lds_bytes(row_cap, arow_cap, stash_cap, prec);
+  const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.pa.L * C / 4, 1));
+#define SC_PAIR(P, K)                                                                                       \
+  if (prec == P) {                                                                                         \
+    hipLaunchKernelGGL((conv_pair_kernel<P, 64, 4, K, kPairCols / 16>), dim3((unsigned)grid), dim3(kThreads), lds, s, \
+                       a, (int)n_nt, Kpad, Kreal, row_cap, arow_cap, stash_cap, extra, fd_per_ent);          \
+    return hipGetLastError();                                                                              \
+  }
+  SC_PAIR(1, 3) SC_PAIR(2, 2)
+#undef SC_PAIR
   return hipErrorInvalidValue;
 }
 

@@ -24,6 +24,9 @@ struct OpDev {
   int32_t ct_rows = 0, ct_xrows = 0, ct_stash = 0;   // window conv with the transposed conv in its
                                                      // launch: window rows, staged transposed-conv input
                                                      // frames and cache-row pieces per tile
+  int32_t pair_rows = 0, pair_arows = 0, pair_stash = 0;   // window conv with the residual conv before it
+                                                           // in its launch: its window rows, the first
+                                                           // conv's window rows, cache-row pieces per tile
 };
 
 // A slot of the descriptor ring: pinned host staging + device copy + event.
@@ -49,6 +52,7 @@ struct sc_model {
   bool have_scales = false;
   std::vector<int32_t> layer_prec; // per layer: operand precision 0 FP32, 1 BF16, 2 FP8 e4m3
   bool any_fp8 = false;            // some layer runs on FP8 operands (needs activation scales)
+  int32_t n_pairs = 0;             // residual conv pairs run as one launch (fuse_conv_pairs)
   bool input_direct = false;       // the model input's only reader gathers it from the callers'
                                    // buffers: no packing launch (except in calibration runs)
   int64_t weight_bytes = 0;

@@ -203,6 +203,71 @@ void fuse_convt_windows(sc_model* m) {
   }
 }
 
+// Two residual window convs launched one after the other, the second the
+// first's only reader (consecutive residual blocks of a 64-channel stage),
+// share one launch (launch_conv_pair): the second conv's tiles compute the
+// frames of the first one's output that their windows need, and that output
+// is never formed.  Pairs are taken greedily in order (blocks 1 + 2 of a
+// stack).  Such a model runs pairs fused always (activation maxima, which
+// need the first conv's output, are refused on it).
+bool pair_candidate(const Op& op) {
+  return op.kind == K_CONV && op.impl == IMPL_WIN && op.residual && op.fuse_out < 0 && op.convt_in < 0 &&
+         op.stride == 1 && op.cin == op.cout && op.prec >= 1;
+}
+
+void fuse_conv_pairs(sc_model* m) {
+  Plan& pl = m->plan;
+  for (size_t b = 0; b < pl.ops.size(); ++b) {
+    Op& cb = pl.ops[b];
+    if (!pair_candidate(cb) || cb.in_twin >= 0) continue;
+    int ia = -1, readers = 0;
+    for (size_t o = 0; o < pl.ops.size(); ++o) {
+      if (pl.ops[o].node == cb.src) ia = (int)o;
+      readers += (pl.ops[o].src == cb.src) + (pl.ops[o].src2 == cb.src);
+    }
+    if (ia < 0 || ia + 1 != (int)b || readers != 1) continue;
+    Op& ca = pl.ops[ia];
+    if (!pair_candidate(ca) || ca.pair_in >= 0 || ca.pair_out >= 0 || ca.out_twin >= 0 || ca.prec != cb.prec ||
+        ca.k != cb.k || ca.cin != cb.cin)
+      continue;
+    const int64_t min_frames = cb.in_rate.of(pl.input_multiple);
+    int32_t arows = 0, stash = 0;
+    const int32_t rows = conv_pair_rows(cb.cin, cb.k, ca.dil, cb.dil, cb.prec, min_frames, &arows, &stash);
+    if (rows <= 0) continue;
+    cb.pair_in = ia;
+    ca.pair_out = (int32_t)b;
+    ++m->n_pairs;
+    // The launch reads A's input while its tiles write B's output.  Where the
+    // planner reused A's input buffer for B's output (A was its last reader),
+    // B's output takes A's output buffer instead -- never written now -- and
+    // the two buffers trade places in every later op (both are free between
+    // A and B, and hold the same sizes); else B's output and its readers move
+    // to a buffer of their own.
+    if (cb.out_buf >= 0 && cb.out_buf == ca.in_buf) {
+      const int32_t P = ca.in_buf, Q = ca.out_buf;
+      if (Q >= 0 && pl.buf_floats[P].num == pl.buf_floats[Q].num && pl.buf_floats[P].den == pl.buf_floats[Q].den) {
+        auto trade = [P, Q](int32_t& x) { x = x == P ? Q : (x == Q ? P : x); };
+        for (size_t o = b; o < pl.ops.size(); ++o) {
+          trade(pl.ops[o].in_buf);
+          trade(pl.ops[o].in_buf2);
+          trade(pl.ops[o].out_buf);
+        }
+      } else {
+        const int32_t nb = (int32_t)pl.buf_floats.size();
+        pl.buf_floats.push_back(pl.buf_floats[cb.out_buf]);
+        for (Op& o : pl.ops) {
+          if (o.src == cb.node) o.in_buf = nb;
+          if (o.src2 == cb.node) o.in_buf2 = nb;
+        }
+        cb.out_buf = nb;
+      }
+    }
+    m->opdev[b].pair_rows = rows;
+    m->opdev[b].pair_arows = arows;
+    m->opdev[b].pair_stash = stash;
+  }
+}
+
 LayerArgs layer_args(const sc_model* m, const Op& op, const Entry* dents, const int32_t* dfent,
                      const int32_t* dhdr, int n_ent, int64_t total_T, int64_t base, const WsView& w) {
   LayerArgs a{};
@@ -468,6 +533,10 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
   // (calibration reads its output, so it runs on its own then)
   const bool ct_fused = op.convt_in >= 0 && !m->amax_on;
   if (ct_fused && op.kind == K_CONVT) return hipSuccess;
+  // a residual conv computed in the launch of the residual conv after it
+  // (always: the model refuses activation maxima, see fuse_conv_pairs)
+  if (op.pair_out >= 0) return hipSuccess;
+  const bool pair = op.pair_in >= 0;
   hipEvent_t ev_end = nullptr;
   if (m->prof_on) {
     e = prof_begin(m, (int)oi, a, ls.hs, &ev_end);
@@ -497,6 +566,24 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
       aw.ct.state_off = ct.state_off;
       aw.ct.state_len = ct.state_len;
       e = launch_convt_win(aw, prec, m->opdev[oi].ct_rows, m->opdev[oi].ct_xrows, m->opdev[oi].ct_stash, ls.hs);
+    } else if (op.impl == IMPL_WIN && pair) {
+      const Op& pa = m->plan.ops[op.pair_in];
+      const OpDev& pd = m->opdev[op.pair_in];
+      LayerArgs aw = a;
+      aw.pa.W = pd.W;
+      aw.pa.B = pd.B;
+      aw.pa.wscale = pd.wscale;
+      aw.pa.act_scale = (pa.layer >= 0 && m->have_scales) ? m->act_scales[pa.layer] / 448.0f : 1.0f;
+      aw.pa.in_buf = ws_at(m, ls.w, pa.in_buf, ls.base);
+      aw.pa.L = pa.cache_len;
+      aw.pa.dil = pa.dil;
+      aw.pa.skip_off = pa.skip_off;
+      aw.pa.pre_act = pa.pre_act;
+      aw.pa.delay = pa.out_delay;
+      aw.pa.state_off = pa.state_off;
+      aw.pa.state_len = pa.state_len;
+      const OpDev& od = m->opdev[oi];
+      e = launch_conv_pair(aw, prec, od.pair_rows, od.pair_arows, od.pair_stash, ls.hs);
     } else if (op.impl == IMPL_WIN) {
       LayerArgs aw = a;
       if (fused) {
@@ -917,6 +1004,7 @@ sc_status create_model(const sc_node* nodes, int32_t n_nodes, const float* weigh
   finalize_plan(m->plan, !(options & SC_MODEL_NO_TWIN));
   if (!(options & SC_MODEL_NO_CONVT_FUSION)) fuse_convt_windows(m);
   if (!(options & SC_MODEL_NO_INPUT_DIRECT)) mark_input_direct(m);
+  if (!(options & SC_MODEL_NO_PAIR_FUSION)) fuse_conv_pairs(m);
   e = hipMalloc(reinterpret_cast<void**>(&m->d_amax), std::max(n_layers, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_amax, 0, std::max(n_layers, 1) * sizeof(float));
   if (e != hipSuccess) { free_model(m); return hip_fail(e, "amax buffer"); }
@@ -999,6 +1087,9 @@ sc_status sc_model_set_act_scales(sc_model* m, const float* s) {
 sc_status sc_model_enable_amax(sc_model* m, int32_t enable) {
   if (!m) return fail(SC_EINVAL, "null model");
   std::lock_guard<std::mutex> g(m->mu);
+  if (enable && m->n_pairs > 0)
+    return fail(SC_EINVAL, "activation maxima need every layer's input: calibrate on an FP32 model (or one created "
+                           "with SC_MODEL_NO_PAIR_FUSION)");
   m->amax_on = enable != 0;
   return SC_OK;
 }

@@ -74,6 +74,9 @@ struct Op {
   int32_t convt_in = -1;      // window conv: index of the transposed conv computed in its
                               // launch; that transposed conv: index of the window conv
   int32_t user_in = 0;        // reads the model input from the callers' channel-major buffers
+  int32_t pair_in = -1;       // residual window conv: index of the residual window conv before
+                              // it, computed in its launch (pair_out: that conv's partner)
+  int32_t pair_out = -1;
 };
 
 struct Plan {

@@ -50,7 +50,7 @@ def _header_constants():
 def test_enum_constants_match_header():
     h = _header_constants()
     for name in ("SC_MODEL_NO_FUSION", "SC_MODEL_NO_MFMA", "SC_MODEL_NO_TWIN", "SC_MODEL_NO_WIN",
-                 "SC_MODEL_NO_SPLIT", "SC_MODEL_NO_OUT_FUSION", "SC_MODEL_NO_CONVT_FUSION", "SC_MODEL_NO_INPUT_DIRECT", "SC_FLAG_WARMUP_MASK",
+                 "SC_MODEL_NO_SPLIT", "SC_MODEL_NO_OUT_FUSION", "SC_MODEL_NO_CONVT_FUSION", "SC_MODEL_NO_INPUT_DIRECT", "SC_MODEL_NO_PAIR_FUSION", "SC_FLAG_WARMUP_MASK",
                  "SC_PENDING",
                  "SC_SUBMIT_DISCARD", "SC_OK"):
         assert getattr(n, name) == h[name], name

@@ -1,7 +1,8 @@
 """The bench's algorithmic FLOP and byte accounting (host logic, no GPU):
-a window conv that computes the transposed conv before it in its own launch
-is charged both layers' FLOPs, the transposed conv's input, carry and
-weights, and not the transposed conv's output, which never reaches memory."""
+a window conv that computes the layer before it in its own launch (a
+transposed conv, or the first conv of a fused residual pair) is charged both
+layers' FLOPs, the first layer's input, state and weights, and not the first
+layer's output, which never reaches memory."""
 import bench
 
 
@@ -14,12 +15,12 @@ def _ops():
     return ct, cv
 
 
-def test_fused_convt_is_found_only_without_launches():
+def test_fused_producer_is_found_only_without_launches():
     ct, cv = _ops()
-    assert bench.fused_convt([ct, cv], cv) is ct
+    assert bench.fused_producer([ct, cv], cv) is ct
     assert bench.fused_tail([ct, cv], cv) is None
     ct2 = dict(ct, launches=10)
-    assert bench.fused_convt([ct2, cv], cv) is None
+    assert bench.fused_producer([ct2, cv], cv) is None
 
 
 def test_fused_pair_accounting():
@@ -44,3 +45,28 @@ def test_roofline_names_the_pair():
     r = bench.roofline([ct, cv])
     assert r["bound"] == "hbm" and "transposed conv node 23" in r["kernel"]
     assert r["flops_per_launch"] == round(bench.op_accounting(cv, ct=ct)[0] / cv["launches"])
+
+
+def _pair():
+    a = {"node": 18, "kind": 1, "impl": 2, "precision": 1, "cin": 64, "cout": 64, "k": 3, "stride": 1,
+         "cache_len": 2, "dilation": 1, "launches": 0, "frames_in": 0, "frames_out": 0, "entries": 0, "ms": 0.0}
+    b = {"node": 20, "kind": 1, "impl": 2, "precision": 1, "cin": 64, "cout": 64, "k": 3, "stride": 1,
+         "cache_len": 6, "dilation": 3, "launches": 10, "frames_in": 172032 * 10, "frames_out": 172032 * 10,
+         "entries": 2560, "ms": 0.47}
+    return a, b
+
+
+def test_residual_pair_accounting():
+    a, b = _pair()
+    assert bench.fused_producer([a, b], b) is a
+    x = b["frames_in"]
+    f_b, b_b = bench.op_accounting(b)
+    f_a, b_a = bench.op_accounting(dict(a, frames_in=x, frames_out=x, entries=b["entries"], launches=b["launches"]))
+    f, byts = bench.op_accounting(b, ct=a)
+    assert f_a == f_b == 2.0 * x * 64 * 64 * 3
+    assert f == f_a + f_b
+    # the first conv's output (FP32) is neither written nor read back
+    assert byts == b_a + b_b - 2 * 4.0 * x * 64
+    r = bench.roofline([a, b])
+    assert "residual conv node 18" in r["kernel"]
+    assert r["bound"] == "mfma" and r["flops_per_launch"] == round(f / b["launches"])

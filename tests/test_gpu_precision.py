@@ -162,6 +162,42 @@ def test_direct_input_bitwise(prec, split):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("prec,split", [("bf16", False), ("bf16", True), ("fp8", True), ("mix", False)])
+def test_conv_pair_fusion_bitwise(prec, split):
+    """Two residual window convs of the 64-channel stage in one launch (the
+    first one's output computed per tile and never written) give bitwise the
+    same streams as two launches: steps of many streams of uneven buffers
+    (1-frame buffers included), split into concurrent halves or not, and one
+    stream with the warm-up mask buffer by buffer; the caches the pair writes
+    carry the next step."""
+    sc = _sc()
+    m, w = weights_for("rave_b")
+    scales = _fp8_scales(sc, m, w, 16) if prec in ("fp8", "mix") else None
+    rng = np.random.default_rng(19)
+    lens = [[int(v) for v in rng.choice([1, 2, 4, 8, 16, 32], size=4)] for _ in range(80)]
+    xs = [scgen.stream_latents(16, sum(l), 1100 + i) for i, l in enumerate(lens)]
+    base = 0 if split else sc._native.SC_MODEL_NO_SPLIT
+    fused = _model(sc, m, w, prec, scales, options=base)
+    fused.profile(True)
+    a = _batched_streams(sc, fused, xs, lens)
+    idle = [p["node"] for p in fused.profile_read() if p["kind"] == 1 and p["launches"] == 0]
+    fused.profile(False)
+    log("pair fusion %s split=%s conv nodes computed inside the next launch: %s" % (prec, split, idle))
+    assert len(idle) == 1, idle       # the first two residual convs of the 64-channel stage
+    with pytest.raises(sc._native.ScError):   # the first conv's output is never formed
+        fused.enable_amax(True)
+    b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base | sc._native.SC_MODEL_NO_PAIR_FUSION),
+                         xs, lens)
+    for i in range(len(lens)):
+        assert np.array_equal(a[i], b[i]), i
+    x = scgen.stream_latents(16, 40, 6)
+    outs = []
+    for opt in (base, base | sc._native.SC_MODEL_NO_PAIR_FUSION):
+        mod = _model(sc, m, w, prec, scales, options=opt)
+        outs.append(run_stream(mod, x, [1, 7, 32], stream=sc.Stream(mod, 32, warmup_mask=True)))
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     """The FP32 MFMA path (input conv included) and the FP32 wavefront path
     sum in different orders; each is pinned to the FP64 oracle at 1e-5 by the
