@@ -346,7 +346,10 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
 // Every read is issued before any is used (a piece past the real K reads the
 // column's first row and is zeroed), so the chunk waits once for LDS instead
 // of once per column block behind a branch.
-template <int ES, int NB>
+// CIN > 0: the input channels are known at compile time (the tap and channel
+// of a piece are then constants of c and lg); KEXACT: the K chunks hold no
+// element past the real K (no piece needs zeroing).
+template <int ES, int NB, int CIN = 0, bool KEXACT = false>
 __device__ inline void win_chunk_reads(const FastDiv& fd_cin, int dil, int c, int lg, int Kreal, int cin, int rowb,
                                        const unsigned char* wop, const int* cb, u4* blo, u4* bhi) {
   int off[2];
@@ -354,24 +357,28 @@ __device__ inline void win_chunk_reads(const FastDiv& fd_cin, int dil, int c, in
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const int kk = (c * 128 + lg * 32 + p * 16) / ES;
-    live[p] = kk < Kreal;
-    const int tap = (int)fdiv(fd_cin, (uint32_t)kk);
-    off[p] = live[p] ? tap * dil * rowb + (kk - tap * cin) * ES : 0;
+    live[p] = KEXACT || kk < Kreal;
+    const int tap = CIN > 0 ? kk / CIN : (int)fdiv(fd_cin, (uint32_t)kk);
+    off[p] = live[p] ? tap * dil * rowb + (kk - tap * (CIN > 0 ? CIN : cin)) * ES : 0;
   }
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     blo[nb] = *reinterpret_cast<const u4*>(wop + cb[nb] + off[0]);
     bhi[nb] = *reinterpret_cast<const u4*>(wop + cb[nb] + off[1]);
   }
-  const u4 z = {0u, 0u, 0u, 0u};
+  if constexpr (!KEXACT) {
+    const u4 z = {0u, 0u, 0u, 0u};
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    blo[nb] = live[0] ? blo[nb] : z;
-    bhi[nb] = live[1] ? bhi[nb] : z;
+    for (int nb = 0; nb < NB; ++nb) {
+      blo[nb] = live[0] ? blo[nb] : z;
+      bhi[nb] = live[1] ? bhi[nb] : z;
+    }
   }
 }
 
-template <int PREC, int MT, int NB, int KCM, bool FUSE>
+// CIN > 0: an instance for cin == CIN (per-row and per-piece arithmetic on
+// constants); KX: K fills the KCM chunks exactly.
+template <int PREC, int MT, int NB, int KCM, bool FUSE, int CIN = 0, bool KX = false>
 __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(LayerArgs a, int n_mt, int n_nt, int Kpad, int Kreal,
                                                              int row_cap, int extra_blocks, FastDiv fd_per_ent,
                                                              FastDiv fd_ppr) {
@@ -427,7 +434,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   const int n_chunks = Kpad * ES / 128;
   const bool pre = a.pre_act != 0;
   const float qs = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
-  const int cin = a.cin;
+  const int cin = CIN > 0 ? CIN : a.cin;
   const int rowb = cin * ES + 16;         // operand row stride (bytes), padded against bank conflicts
   const int skipf = cin + 4;              // skip row stride (floats)
   unsigned char* wop = lds;
@@ -552,7 +559,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
         const int32_t idx = i0 + u * kThreads + tid;
         v[u] = f4{0.f, 0.f, 0.f, 0.f};
         if (idx < n_pieces) {
-          const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
+          const int32_t j = CIN > 0 ? idx / (CIN / 4) : (int32_t)fdiv(fd_ppr, (uint32_t)idx);
           const int pc = idx - j * ppr;
           v[u] = gload<f4>(rsrc[j] + pc * 4);
         }
@@ -561,7 +568,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
       for (int u = 0; u < SB; ++u) {
         const int32_t idx = i0 + u * kThreads + tid;
         if (idx >= n_pieces) continue;
-        const int32_t j = (int32_t)fdiv(fd_ppr, (uint32_t)idx);
+        const int32_t j = CIN > 0 ? idx / (CIN / 4) : (int32_t)fdiv(fd_ppr, (uint32_t)idx);
         const int pc = idx - j * ppr;
         const f4 x = v[u];
         unsigned char* dst = wop + j * rowb + pc * 4 * ES;
@@ -595,7 +602,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   for (int c = 0; c < kMaxChunks; ++c) {
     if (c < n_chunks) {
       u4 blo[NB], bhi[NB];
-      win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, cin, rowb, wop, cb, blo, bhi);
+      win_chunk_reads<ES, NB, CIN, KX>(a.fd_cin, a.dil, c, lg, Kreal, cin, rowb, wop, cb, blo, bhi);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
@@ -1010,7 +1017,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   for (int c = 0; c < KCM; ++c) {
     if (c < n_chunks) {
       u4 blo[NB], bhi[NB];
-      win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, MT, rowb, wop, cb, blo, bhi);
+      win_chunk_reads<ES, NB, MT>(a.fd_cin, a.dil, c, lg, Kreal, MT, rowb, wop, cb, blo, bhi);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(alo[c], ahi[c], blo[nb], bhi[nb], acc[nb]);
     }
@@ -1075,6 +1082,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   constexpr int CPRE = 2;                      // B cache-row pieces per thread (the host bounds L_B)
   constexpr int NCOL = NCBA * 16;              // A columns a tile holds at most
   constexpr int SB = kStageBatch;
+  constexpr bool KX = 3 * C * ES == KCM * 128; // K = 3 C fills the chunks (BF16)
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
@@ -1321,7 +1329,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 #pragma unroll
       for (int c = 0; c < KCM; ++c) {
         u4 blo[G], bhi[G];
-        win_chunk_reads<ES, G>(a.fd_cin, a.pa.dil, c, lg, Kreal, C, ROWB, wop_a, cb + g0, blo, bhi);
+        win_chunk_reads<ES, G, C, KX>(a.fd_cin, a.pa.dil, c, lg, Kreal, C, ROWB, wop_a, cb + g0, blo, bhi);
 #pragma unroll
         for (int q = 0; q < G; ++q)
           if (g0 + q < ncba) aacc[g0 + q] = mfma32<PREC>(alo[c], ahi[c], blo[q], bhi[q], aacc[g0 + q]);
@@ -1341,12 +1349,19 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   __syncthreads();   // every wave is past A's operand rows: region 1 takes B's FP32 rows
 
   // ---- x1: A's epilogue, B's window rows (FP32 and operand), B's next cache ----
+  int32_t jbs[NCBA];
+  int fls[NCBA];
+#pragma unroll
+  for (int nc = 0; nc < NCBA; ++nc) {    // every column's record first: one wait
+    jbs[nc] = ajb[nc * 16 + lr];
+    fls[nc] = aflag[nc * 16 + lr];
+  }
 #pragma unroll
   for (int nc = 0; nc < NCBA; ++nc) {
     const int col = nc * 16 + lr;
     if (nc >= ncba || col >= n_acol) continue;
-    const int32_t jb = ajb[col];
-    const int fl = aflag[col];
+    const int32_t jb = jbs[nc];
+    const int fl = fls[nc];
     f4 v = aacc[nc];
     if (PREC == 2) v = v * (ws_a * a.pa.act_scale);
     v = v + bias_a;
@@ -1377,7 +1392,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 #pragma unroll
   for (int c = 0; c < KCM; ++c) {
     u4 blo[NB], bhi[NB];
-    win_chunk_reads<ES, NB>(a.fd_cin, a.dil, c, lg, Kreal, C, ROWB, wop_b, cbb, blo, bhi);
+    win_chunk_reads<ES, NB, C, KX>(a.fd_cin, a.dil, c, lg, Kreal, C, ROWB, wop_b, cbb, blo, bhi);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(blw[c], bhw[c], blo[nb], bhi[nb], acc[nb]);
   }
@@ -1561,6 +1576,20 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   if (fuse) lds = std::max(lds, (size_t)(MT / 16) * F * kOutTaps * 4);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.L * a.cin / 4, 1));
   const FastDiv fd_ppr = make_fastdiv((uint32_t)(a.cin / 4));   // 16-byte pieces per staged row
+  // an instance for cin == MT where one exists (with kx: K fills the chunks)
+  const int cin_t = a.cin == MT ? MT : 0;
+  const bool kx = cin_t > 0 && Kreal == Kpad && Kpad * w_esize(prec) == KCM * 128;
+#define SC_WINC(P, M, N, K, FU, CI, X)                                                                     \
+  if (prec == P && MT == M && NB == N && KCM == K && fuse == FU && cin_t == CI && kx == X) {              \
+    hipLaunchKernelGGL((conv_win_kernel<P, M, N, K, FU, CI, X>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
+                       n_mt, (int)n_nt, Kpad, Kreal, row_cap, extra, fd_per_ent, fd_ppr);                  \
+    return hipGetLastError();                                                                              \
+  }
+  SC_WINC(1, 32, 4, 3, false, 32, false) SC_WINC(1, 32, 4, 3, true, 32, false)
+  SC_WINC(1, 64, 4, 3, false, 64, true) SC_WINC(1, 64, 4, 3, true, 64, true)
+  SC_WINC(2, 32, 4, 2, false, 32, false) SC_WINC(2, 32, 4, 2, true, 32, false)
+  SC_WINC(2, 64, 4, 2, false, 64, false) SC_WINC(2, 64, 4, 2, true, 64, false)
+#undef SC_WINC
 #define SC_WIN(P, M, N, K, FU)                                                                              \
   if (prec == P && MT == M && NB == N && KCM == K && fuse == FU) {                                         \
     hipLaunchKernelGGL((conv_win_kernel<P, M, N, K, FU>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
