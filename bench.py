@@ -73,26 +73,25 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "0ff867a48d3cc7aa884655052a6081db0be19cab 5797b40bfd460d0e7cc9219e6ebe2696440f249d c475d43d80ff2b54661b0920e2ae957339dc5b81 c91a88e5b1fa849ea989eb1fb793788e20e5cb0c 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "39a0543dffe2a94f3535482401021a871e040bd3 37576851252a29dfa965ccb480e8308edf8b272b c475d43d80ff2b54661b0920e2ae957339dc5b81 6cafeb5eadda802ba945f37301c3219b96021883 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 772.6, 2727.1),
-        2: ('mfma', 10445.3, 22316.8),
-        4: ('mfma', 10294.4, 22053.7),
-        6: ('mfma', 11284.6, 23332.9),
-        8: ('mfma', 14158.1, 12302.2),
-        9: ('mfma', 5231.6, 42214.2),
-        11: ('mfma', 17018.8, 40715.6),
-        13: ('mfma', 17514.0, 41285.3),
-        15: ('mfma', 18956.3, 14236.3),
-        16: ('mfma', 6195.2, 58581.6),
-        18: ('mfma_win', 22619.6, 53395.0),
-        20: ('mfma_win', 24088.4, 53711.3),
-        22: ('mfma_win', 28502.7, 22712.6),
-        25: ('mfma_win', 11520.3, 55522.3),
-        27: ('mfma_win', 22925.0, 55330.6),
-        29: ('mfma_win', 25150.8, 3126.2),
+        1: ('mfma', 773.1, 2727.1),
+        2: ('mfma', 10445.5, 17203.3),
+        4: ('mfma', 10295.1, 16938.9),
+        6: ('mfma', 11286.0, 18474.7),
+        8: ('mfma', 14157.0, 12302.2),
+        9: ('mfma', 5427.8, 32890.7),
+        11: ('mfma', 17114.0, 32735.9),
+        13: ('mfma', 17631.8, 33507.4),
+        15: ('mfma', 18954.4, 14237.3),
+        16: ('mfma', 6196.3, 43377.9),
+        20: ('mfma_win', 24768.1, 43633.3),
+        22: ('mfma_win', 28490.8, 22712.6),
+        25: ('mfma_win', 11523.3, 43249.2),
+        27: ('mfma_win', 22923.0, 43313.2),
+        29: ('mfma_win', 25147.7, 3126.2),
         30: ('tail', 2110.9, 85.4),
     },
 }
