@@ -696,12 +696,11 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   __shared__ int8_t ccol_seg[NCB * 16];
   __shared__ int32_t ccol_q[NCB * 16];
   __shared__ int32_t ccol_x[NCB * 16];
-  // per transposed-conv column, in x frames t = q * r + phi: {q * r (-1: the
-  // carry column), LDS row of t = 0, first and end t whose window rows are
-  // staged} and {first and end t kept by the masks, first and last t written
-  // to the conv's next cache}
-  __shared__ i4 ccol_rows[NCB * 16];
-  __shared__ i4 ccol_keep[NCB * 16];
+  // per transposed-conv column (x frames t = q * r + phi, phi < r): {q * r
+  // (-1: the carry column), LDS row of phi = 0, and as byte pairs [lo, end)
+  // of phi: the phases whose window rows are staged, those kept by the masks,
+  // those written to the conv's next cache}
+  __shared__ i4 ccol_rec[NCB * 16];
 
   const int tid = threadIdx.x;
   const int32_t nt = blockIdx.x;
@@ -718,11 +717,12 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   const int L = a.L;
   const int R = a.ct.r;
   const int rowb = MT * ES + 16;              // operand row stride (bytes)
+  constexpr int XF = MT;                      // FP32 row stride (floats): unpadded, for 5 workgroups per CU
   unsigned char* X = lds;
-  float* xf = reinterpret_cast<float*>(lds);  // x rows in FP32, [row][MT] (after the transposed-conv MFMAs)
+  float* xf = reinterpret_cast<float*>(lds);  // x rows in FP32, [row][XF] (after the transposed-conv MFMAs)
   // the window's cache rows in FP32 until X is free (stash_cap f4 pieces)
-  f4* stash = reinterpret_cast<f4*>(lds + (size_t)max(xrow_cap * XROW, row_cap * MT * 4));
-  unsigned char* wop = lds + (size_t)max(xrow_cap * XROW, row_cap * MT * 4) + (size_t)stash_cap * 16;
+  f4* stash = reinterpret_cast<f4*>(lds + (size_t)max(xrow_cap * XROW, row_cap * XF * 4));
+  unsigned char* wop = lds + (size_t)max(xrow_cap * XROW, row_cap * XF * 4) + (size_t)stash_cap * 16;
 
   // both layers' weights, biases and scales (independent of the columns)
   const int wm = wave % WM, wn = wave / WM;
@@ -897,17 +897,24 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     ccol_seg[j] = (int8_t)s;
     ccol_q[j] = q;
     ccol_x[j] = x;
-    i4 rows = {-1, 0, 0, 0}, keep = {0, 0, 0, -1};
+    i4 rec = {-1, 0, 0, 0};
     if (s >= 0) {
       const CtSeg& c = csegs[s];
       const WinSeg& g = segs[s];
       if (q != c.Tin) {
-        rows = i4{q * R, g.base + L - g.r0, g.r0 - L, g.r0 - L + g.rows};
-        keep = i4{ceil_frames(c.mask_lo, a.in_den), ceil_frames(c.mask_hi, a.in_den), max(c.T - L, g.t_lo), g.t_hi};
+        // a range [lo, end) of x frames as a range of phases of this column
+        const int32_t t0 = q * R;
+        auto ph = [&](int32_t lo, int32_t end) {
+          const int32_t a0 = min(max(lo - t0, 0), R), a1 = min(max(end - t0, 0), R);
+          return (a0 & 0xff) | (a1 & 0xff) << 8;
+        };
+        const int32_t staged = ph(g.r0 - L, g.r0 - L + g.rows);
+        const int32_t kept = ph(ceil_frames(c.mask_lo, a.in_den), ceil_frames(c.mask_hi, a.in_den));
+        const int32_t cached = ph(max(c.T - L, g.t_lo), g.t_hi + 1);
+        rec = i4{t0, g.base + L - g.r0 + t0, staged | kept << 16, cached};
       }
     }
-    ccol_rows[j] = rows;
-    ccol_keep[j] = keep;
+    ccol_rec[j] = rec;
   }
   __syncthreads();
 
@@ -950,9 +957,8 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     for (int nc = 0; nc < NCB; ++nc) {
       const int col = nc * 16 + lr;
       if (nc >= ncb || col >= n_ccol) continue;
-      const i4 rows = ccol_rows[col];
-      const i4 keep = ccol_keep[col];
-      if (rows.x < 0) {
+      const i4 rec = ccol_rec[col];
+      if (rec.x < 0) {
         // the carry of the next buffer, in accumulator units
         gstore<f4>(csegs[ccol_seg[col]].carry_next + m, cacc[mi][nc]);
         continue;
@@ -960,11 +966,11 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
       f4 v = cacc[mi][nc];
       if (PREC == 2) v = v * (ct_ws[mi] * a.ct.act_scale);
       v = v + ct_bias[mi];
-      const int32_t t = rows.x + phi;          // x frame of the stream
-      if (t < keep.x || t >= keep.y) v = f4{0.f, 0.f, 0.f, 0.f};
-      if (t >= rows.z && t < rows.w) {         // its window row t + L is staged
-        const int32_t j = rows.y + t;
-        *reinterpret_cast<f4*>(xf + (size_t)j * MT + co) = v;
+      const int32_t t = rec.x + phi;           // x frame of the stream
+      if (phi < ((rec.z >> 16) & 0xff) || phi >= (rec.z >> 24)) v = f4{0.f, 0.f, 0.f, 0.f};   // masks
+      if (phi >= (rec.z & 0xff) && phi < ((rec.z >> 8) & 0xff)) {   // its window row t + L is staged
+        const int32_t j = rec.y + phi;
+        *reinterpret_cast<f4*>(xf + (size_t)j * XF + co) = v;
         unsigned char* dst = wop + (size_t)j * rowb + co * ES;
         if constexpr (PREC == 1) {
           uint2 u;
@@ -977,7 +983,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
         }
       }
       // the conv's next cache: the stream's last L frames of x, by the tile that owns them
-      if (t >= keep.z && t <= keep.w) {
+      if (phi >= (rec.w & 0xff) && phi < (rec.w >> 8)) {
         const CtSeg& c = csegs[ccol_seg[col]];
         gstore<f4>(c.cache_next + (int64_t)(t - (c.T - L)) * MT + co, v);
       }
@@ -988,9 +994,9 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
   for (int p = 0; p < CPRE; ++p) {
     if (cdst[p] < 0) continue;
     const f4 v = stash[tid + p * kThreads];
-    *reinterpret_cast<f4*>(xf + cdst[p]) = v;
     const int32_t jr = cdst[p] / MT;
     const int ch = cdst[p] - jr * MT;
+    *reinterpret_cast<f4*>(xf + (size_t)jr * XF + ch) = v;
     unsigned char* dst = wop + (size_t)jr * rowb + ch * ES;
     if constexpr (PREC == 1) {
       uint2 u;
@@ -1031,7 +1037,7 @@ __global__ void __launch_bounds__(kThreads, 5) convt_win_kernel(LayerArgs a, int
     f4 v = acc[nb];
     if (PREC == 2) v = v * (wsc * a.act_scale);
     v = v + bias;
-    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * MT + m);
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * XF + m);
     if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
@@ -1078,6 +1084,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   constexpr int F = NB * 16;
   constexpr int ES = WPrec<PREC>::kEsize;
   constexpr int ROWB = C * ES + 16;            // operand row stride (bytes), padded against bank conflicts
+  constexpr int XF = C + 4;                    // FP32 row stride (floats), padded likewise
   constexpr int PPR = C / 4;                   // 16-byte FP32 pieces per row
   constexpr int CPRE = 2;                      // B cache-row pieces per thread (the host bounds L_B)
   constexpr int NCOL = NCBA * 16;              // A columns a tile holds at most
@@ -1130,7 +1137,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   const bool pre_a = a.pa.pre_act != 0, pre_b = a.pre_act != 0;
   const float qs_a = PREC == 2 ? 1.0f / a.pa.act_scale : 1.0f;
   const float qs_b = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
-  const size_t r1 = (size_t)max(arow_cap * ROWB, row_cap * C * 4);
+  const size_t r1 = (size_t)max(arow_cap * ROWB, row_cap * XF * 4);
   unsigned char* wop_a = lds;                              // A's window rows, operand form
   float* xf = reinterpret_cast<float*>(lds);               // B's window rows in FP32 (after A's MFMAs)
   f4* stash = reinterpret_cast<f4*>(lds + r1);             // B's cache rows until then
@@ -1367,7 +1374,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     v = v + bias_a;
     v = v + skv[nc];
     if (!(fl & 1)) v = f4{0.f, 0.f, 0.f, 0.f};
-    *reinterpret_cast<f4*>(xf + (size_t)jb * C + m) = v;
+    *reinterpret_cast<f4*>(xf + (size_t)jb * XF + m) = v;
     store_operand<PREC>(wop_b + (size_t)jb * ROWB + m * ES, v, pre_b, qs_b);
     if (fl & 2) gstore<f4>(anext[col] + m, v);
   }
@@ -1376,9 +1383,10 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   for (int p = 0; p < CPRE; ++p) {
     if (cdst[p] < 0) continue;
     const f4 v = stash[tid + p * kThreads];
-    *reinterpret_cast<f4*>(xf + cdst[p]) = v;
     const int32_t jr = cdst[p] / C;
-    store_operand<PREC>(wop_b + (size_t)jr * ROWB + (cdst[p] - jr * C) * ES, v, pre_b, qs_b);
+    const int ch = cdst[p] - jr * C;
+    *reinterpret_cast<f4*>(xf + (size_t)jr * XF + ch) = v;
+    store_operand<PREC>(wop_b + (size_t)jr * ROWB + ch * ES, v, pre_b, qs_b);
   }
   __syncthreads();
 
@@ -1405,7 +1413,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     f4 v = acc[nb];
     if (PREC == 2) v = v * (ws_b * a.act_scale);
     v = v + bias_b;
-    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * C + m);
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * XF + m);
     if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
@@ -1694,7 +1702,7 @@ constexpr int kPairCols = 96;    // x1 frames a pair tile computes at most (6 co
 // cache rows; B's window rows in operand form; A's row sources
 int64_t pair_lds_bytes(int64_t rows, int64_t arows, int64_t stash, int prec) {
   const int64_t rowb = kPairC * w_esize(prec) + 16;
-  return std::max(arows * rowb, rows * kPairC * 4) + stash * 16 + rows * rowb + arows * 8;
+  return std::max(arows * rowb, rows * (kPairC + 4) * 4) + stash * 16 + rows * rowb + arows * 8;
 }
 }  // namespace
 
