@@ -226,11 +226,13 @@ int32_t convt_win_rows(int cin, int cout, int k, int dil, int L, int r, int ct_c
 hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32_t xrow_cap, int32_t stash_cap,
                             hipStream_t s);
 // Two residual window convs in one launch (a.pa: the first, whose output only
-// the second reads): whether a pair of this shape qualifies (0 if not, else
-// the second conv's window rows a tile needs; *arow_cap: the first conv's
-// window rows, *stash_cap: cache-row pieces of 16 bytes), and its launch.
-int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, int32_t* arow_cap,
-                       int32_t* stash_cap);
+// the second reads; fuse: the second computes the one-output-channel conv
+// after it in its epilogue, a.oc): whether a pair of this shape qualifies (0
+// if not, else the second conv's window rows a tile needs; *arow_cap: the
+// first conv's window rows, *stash_cap: cache-row pieces of 16 bytes), and
+// its launch.
+int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, bool fuse,
+                       int32_t* arow_cap, int32_t* stash_cap);
 hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32_t arow_cap, int32_t stash_cap,
                             hipStream_t s);
 // Output frames per window tile, and whether a one-output-channel conv of

@@ -217,9 +217,10 @@ __device__ inline bool out_tail_frame(int32_t f, int32_t out_start, int32_t f0, 
 // A operand (tap lr, channels m .. m + 3; zero beyond k).  Dynamic LDS (free
 // once every wave is past the K loop): per-wave channel partials
 // [WM][kOutTaps][F].
-template <int PREC, int MT, int NB, int F>
+// skip_at(col): the FP32 skip row of tile column col (its channel 0).
+template <int PREC, int MT, int NB, int F, class SkipAt>
 __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int m, f4 bias, f4 wsc, int32_t f0,
-                                          const float* wskip, int skipf, const WinSeg* segs, const WinSeg2* segs2,
+                                          SkipAt skip_at, const WinSeg* segs, const WinSeg2* segs2,
                                           const int8_t* colseg, int n_seg, f4 wa, unsigned char* lds) {
   constexpr int WM = MT / 16;
   constexpr int WN = 4 / WM;
@@ -242,7 +243,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     f4 x = acc[nb];
     if (PREC == 2) x = x * (wsc * a.act_scale);
     x = x + bias;
-    if (a.residual) x = x + *reinterpret_cast<const f4*>(&wskip[col * skipf + m]);
+    if (a.residual) x = x + *reinterpret_cast<const f4*>(skip_at(col) + m);
     if ((int64_t)t * a.out_den < segs[s].mask_x || (int64_t)t * a.out_den >= segs[s].mask_hi) x = f4{0.f, 0.f, 0.f, 0.f};
     v[nb] = x;
   }
@@ -609,7 +610,8 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   }
 
   if constexpr (FUSE) {
-    fused_out_epilogue<PREC, MT, NB, F>(a, acc, m, bias, wsc, f0, wskip, skipf, segs, segs2, colseg, n_seg, wa2, lds);
+    fused_out_epilogue<PREC, MT, NB, F>(
+        a, acc, m, bias, wsc, f0, [&](int col) { return wskip + col * skipf; }, segs, segs2, colseg, n_seg, wa2, lds);
     return;
   }
 
@@ -1075,13 +1077,20 @@ struct PairSeg {
   int32_t abase;           // LDS row of A's window row ta
 };
 
-template <int PREC, int MT, int NB, int KCM, int NCBA>
+// MT: the channels of both convs (one M tile); waves split B's tile as the
+// window kernel does (WM row blocks x WN column halves) and A's columns the
+// same way.  NCBA: A column blocks a tile holds at most.  FUSE: B computes a
+// one-output-channel conv in its epilogue (fused_out_epilogue).
+template <int PREC, int MT, int NB, int KCM, int NCBA, bool FUSE>
 __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
                                                                 int row_cap, int arow_cap, int stash_cap,
                                                                 int extra_blocks, FastDiv fd_per_ent) {
-  static_assert(MT == 64, "one 16-row M block per wave, one wave column");
+  constexpr int WM = MT / 16;
+  constexpr int WN = 4 / WM;
   constexpr int C = MT;                        // channels of both convs
-  constexpr int F = NB * 16;
+  constexpr int F = NB * 16 * WN;
+  constexpr int NCW = NCBA / WN;               // A column blocks of a wave
+  static_assert(NCW % 2 == 0, "two groups of column blocks per wave");
   constexpr int ES = WPrec<PREC>::kEsize;
   constexpr int ROWB = C * ES + 16;            // operand row stride (bytes), padded against bank conflicts
   constexpr int XF = C + 4;                    // FP32 row stride (floats), padded likewise
@@ -1094,8 +1103,10 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ WinSeg segs[kMaxStreams];
   __shared__ PairSeg psegs[kMaxStreams];
+  __shared__ WinSeg2 segs2[FUSE ? kMaxStreams : 1];
   __shared__ int32_t colbase[F];
   __shared__ int8_t colkeep[F];
+  __shared__ int8_t colseg[F];
   __shared__ int32_t acb[NCOL];                // A column: LDS row of its first window row
   __shared__ int32_t ajb[NCOL];                // A column: LDS row of its frame in B's window
   __shared__ int8_t aflag[NCOL];               // bit 0: kept by A's masks; bit 1: a row of B's next cache
@@ -1133,7 +1144,8 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int m = wave * 16 + lg * 4;     // the lane's channels m .. m + 3 (both convs)
+  const int wm = wave % WM, wn = wave / WM;
+  const int m = wm * 16 + lg * 4;       // the lane's channels m .. m + 3 (both convs)
   const bool pre_a = a.pa.pre_act != 0, pre_b = a.pre_act != 0;
   const float qs_a = PREC == 2 ? 1.0f / a.pa.act_scale : 1.0f;
   const float qs_b = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
@@ -1147,7 +1159,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   // A's weights (the wave's 16 rows, every chunk), both convs' biases and scales
   u4 alo[KCM], ahi[KCM];
   {
-    const unsigned char* wrow = static_cast<const unsigned char*>(a.pa.W) + (int64_t)(wave * 16 + lr) * (Kpad * ES) + lg * 32;
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.pa.W) + (int64_t)(wm * 16 + lr) * (Kpad * ES) + lg * 32;
 #pragma unroll
     for (int c = 0; c < KCM; ++c) {
       alo[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
@@ -1158,6 +1170,11 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   const f4 ws_a = PREC == 2 ? *reinterpret_cast<const f4*>(a.pa.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
   const f4 bias_b = *reinterpret_cast<const f4*>(a.B + m);
   const f4 ws_b = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  // fused output conv: the lane's A operand of its per-tap sums (tap lr, channels m .. m + 3)
+  f4 wa2 = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (FUSE) {
+    if (lr < a.oc.k) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * MT + m);
+  }
 
   // ---- the streams of the tile: lane s of every wave forms stream s's
   // records; wave 0 publishes them ----
@@ -1210,6 +1227,16 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     if (wave == 0 && lane < n_seg) {
       segs[lane] = g;
       psegs[lane] = p;
+      if constexpr (FUSE) {
+        WinSeg2 g2;
+        g2.T = p.T;
+        g2.cache2 = e.state + a.oc.state_off + (int64_t)e.parity * a.oc.state_len;
+        g2.cache2_next = e.state + a.oc.state_off + (int64_t)(1 - e.parity) * a.oc.state_len;
+        g2.out2 = e.out;
+        g2.mask2_x = mask_lo(e, a.oc.delay, a.out_num, a.out_den);
+        g2.mask2_hi = mask_hi(e, a.oc.delay, a.out_num, a.out_den);
+        segs2[lane] = g2;
+      }
     }
   }
   if (n_rows > row_cap || n_acol > NCOL || n_arows > arow_cap || n_cp > stash_cap || n_cp > CPRE * kThreads) return;
@@ -1227,8 +1254,10 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
       keep = x < segs[s].mask_x || x >= segs[s].mask_hi ? 0 : 1;
     } else {
       colbase[tid] = 0;
+      s = -1;
     }
     colkeep[tid] = keep;
+    colseg[tid] = (int8_t)s;
   }
   for (int j = tid; j < NCOL; j += kThreads) {
     int32_t cb = 0, jb = 0;
@@ -1289,9 +1318,9 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
       idx -= n;
     }
   }
-  f4 skv[NCBA];
+  f4 skv[NCW];
 #pragma unroll
-  for (int nc = 0; nc < NCBA; ++nc) skv[nc] = gload<f4>(askip[nc * 16 + lr] + m);
+  for (int i = 0; i < NCW; ++i) skv[i] = gload<f4>(askip[(wn * NCW + i) * 16 + lr] + m);
   {
     const int32_t n_pieces = n_arows * PPR;
     for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * SB) {
@@ -1316,37 +1345,38 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     if (cdst[p] >= 0) stash[tid + p * kThreads] = cpre[p];
   __syncthreads();
 
-  // ---- A: the wave's 16 rows x every A column block ----
+  // ---- A: the wave's 16 rows x its A column blocks (column blocks
+  // wn * NCW .. + NCW - 1) ----
   const int ncba = (n_acol + 15) / 16;
-  f4 aacc[NCBA];
+  const int nc0 = wn * NCW;
+  f4 aacc[NCW];
   {
-    int cb[NCBA];
+    int cb[NCW];
 #pragma unroll
-    for (int nc = 0; nc < NCBA; ++nc) {
-      cb[nc] = acb[nc * 16 + lr] * ROWB;
-      aacc[nc] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < NCW; ++i) {
+      cb[i] = acb[(nc0 + i) * 16 + lr] * ROWB;
+      aacc[i] = f4{0.f, 0.f, 0.f, 0.f};
     }
     // two groups of column blocks, each over every chunk (a column's chain of
     // MFMAs is the same; half the operand registers)
-    constexpr int G = NCBA / 2;
-    static_assert(NCBA % 2 == 0, "two groups");
+    constexpr int G = NCW / 2;
 #pragma unroll
-    for (int g0 = 0; g0 < NCBA; g0 += G) {
-      if (g0 >= ncba) break;
+    for (int g0 = 0; g0 < NCW; g0 += G) {
+      if (nc0 + g0 >= ncba) break;
 #pragma unroll
       for (int c = 0; c < KCM; ++c) {
         u4 blo[G], bhi[G];
         win_chunk_reads<ES, G, C, KX>(a.fd_cin, a.pa.dil, c, lg, Kreal, C, ROWB, wop_a, cb + g0, blo, bhi);
 #pragma unroll
         for (int q = 0; q < G; ++q)
-          if (g0 + q < ncba) aacc[g0 + q] = mfma32<PREC>(alo[c], ahi[c], blo[q], bhi[q], aacc[g0 + q]);
+          if (nc0 + g0 + q < ncba) aacc[g0 + q] = mfma32<PREC>(alo[c], ahi[c], blo[q], bhi[q], aacc[g0 + q]);
       }
     }
   }
   // B's weights (their latency hides behind x1's epilogue)
   u4 blw[KCM], bhw[KCM];
   {
-    const unsigned char* wrow = static_cast<const unsigned char*>(a.W) + (int64_t)(wave * 16 + lr) * (Kpad * ES) + lg * 32;
+    const unsigned char* wrow = static_cast<const unsigned char*>(a.W) + (int64_t)(wm * 16 + lr) * (Kpad * ES) + lg * 32;
 #pragma unroll
     for (int c = 0; c < KCM; ++c) {
       blw[c] = *reinterpret_cast<const u4*>(wrow + c * 128);
@@ -1356,23 +1386,23 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   __syncthreads();   // every wave is past A's operand rows: region 1 takes B's FP32 rows
 
   // ---- x1: A's epilogue, B's window rows (FP32 and operand), B's next cache ----
-  int32_t jbs[NCBA];
-  int fls[NCBA];
+  int32_t jbs[NCW];
+  int fls[NCW];
 #pragma unroll
-  for (int nc = 0; nc < NCBA; ++nc) {    // every column's record first: one wait
-    jbs[nc] = ajb[nc * 16 + lr];
-    fls[nc] = aflag[nc * 16 + lr];
+  for (int i = 0; i < NCW; ++i) {        // every column's record first: one wait
+    jbs[i] = ajb[(nc0 + i) * 16 + lr];
+    fls[i] = aflag[(nc0 + i) * 16 + lr];
   }
 #pragma unroll
-  for (int nc = 0; nc < NCBA; ++nc) {
-    const int col = nc * 16 + lr;
-    if (nc >= ncba || col >= n_acol) continue;
-    const int32_t jb = jbs[nc];
-    const int fl = fls[nc];
-    f4 v = aacc[nc];
+  for (int i = 0; i < NCW; ++i) {
+    const int col = (nc0 + i) * 16 + lr;
+    if (nc0 + i >= ncba || col >= n_acol) continue;
+    const int32_t jb = jbs[i];
+    const int fl = fls[i];
+    f4 v = aacc[i];
     if (PREC == 2) v = v * (ws_a * a.pa.act_scale);
     v = v + bias_a;
-    v = v + skv[nc];
+    v = v + skv[i];
     if (!(fl & 1)) v = f4{0.f, 0.f, 0.f, 0.f};
     *reinterpret_cast<f4*>(xf + (size_t)jb * XF + m) = v;
     store_operand<PREC>(wop_b + (size_t)jb * ROWB + m * ES, v, pre_b, qs_b);
@@ -1393,7 +1423,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   // ---- B: operands from its staged rows, the skip from its FP32 rows ----
   int cbb[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) cbb[nb] = colbase[nb * 16 + lr] * ROWB;
+  for (int nb = 0; nb < NB; ++nb) cbb[nb] = colbase[wn * (F / WN) + nb * 16 + lr] * ROWB;
   f4 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -1404,9 +1434,16 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma32<PREC>(blw[c], bhw[c], blo[nb], bhi[nb], acc[nb]);
   }
+  if constexpr (FUSE) {
+    // the output conv in the epilogue; its per-tap scratch takes B's operand rows
+    fused_out_epilogue<PREC, MT, NB, F>(
+        a, acc, m, bias_b, ws_b, f0, [&](int col) { return xf + (size_t)(colbase[col] + a.skip_off) * XF; }, segs,
+        segs2, colseg, n_seg, wa2, wop_b);
+    return;
+  }
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const int col = nb * 16 + lr;
+    const int col = wn * (F / WN) + nb * 16 + lr;
     const int keep = colkeep[col];
     if (keep < 0) continue;
     const int32_t f = f0 + col;
@@ -1696,35 +1733,42 @@ hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32
 
 
 namespace {
-constexpr int kPairC = 64;       // channels of a fused pair (one 64-row M tile)
-constexpr int kPairCols = 96;    // x1 frames a pair tile computes at most (6 column blocks)
-// A's window rows in operand form, overlaid by B's window rows in FP32; B's
-// cache rows; B's window rows in operand form; A's row sources
-int64_t pair_lds_bytes(int64_t rows, int64_t arows, int64_t stash, int prec) {
-  const int64_t rowb = kPairC * w_esize(prec) + 16;
-  return std::max(arows * rowb, rows * (kPairC + 4) * 4) + stash * 16 + rows * rowb + arows * 8;
+// x1 frames a pair tile computes at most (A column blocks x 16), by channels
+int pair_cols(int c) { return c == 64 ? 96 : 192; }
+// A's window rows in operand form, overlaid by B's window rows in FP32 (row
+// stride c + 4); B's cache rows; B's window rows in operand form and A's row
+// sources, overlaid by the fused output conv's per-tap scratch
+int64_t pair_lds_bytes(int c, int64_t rows, int64_t arows, int64_t stash, int prec, bool fuse) {
+  const int64_t rowb = c * w_esize(prec) + 16;
+  const int64_t scratch = fuse ? (int64_t)(c / 16) * kOutTaps * win_f(c, 4) * 4 : 0;
+  return std::max(arows * rowb, rows * (c + 4) * 4) + stash * 16 + std::max(rows * rowb + arows * 8, scratch);
+}
+int pair_kchunks(int c, int k, int prec) {
+  const int kc = w_kchunk(prec);
+  return (k * c + kc - 1) / kc * kc * w_esize(prec) / 128;
 }
 }  // namespace
 
-int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, int32_t* arow_cap,
-                       int32_t* stash_cap) {
+int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min_frames, bool fuse,
+                       int32_t* arow_cap, int32_t* stash_cap) {
   *arow_cap = 0;
   *stash_cap = 0;
-  if (c != kPairC || k != 3 || prec < 1 || prec > 2 || dil_a < 1 || dil_b < 1 || min_frames < 1) return 0;
+  // instances: 64 channels (no fused output conv) and 32 channels (with or without)
+  if ((c != 64 && c != 32) || (c == 64 && fuse) || k != 3 || prec < 1 || prec > 2 || dil_a < 1 || dil_b < 1 ||
+      min_frames < 1)
+    return 0;
   const int LA = dil_a * (k - 1), LB = dil_b * (k - 1);
   // every stream brings at least L_B frames: B's next cache comes from x1 alone
   if (min_frames < LB) return 0;
-  const int kc = w_kchunk(prec);
-  const int Kpad = (k * c + kc - 1) / kc * kc;
-  if (Kpad * w_esize(prec) / 128 != win_kcm(prec, c)) return 0;   // the kernel holds exactly these chunks
-  const int F = win_f(kPairC, 4);
+  const int F = win_f(c, 4);
   const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
   if (max_seg > kMaxStreams) return 0;
   const int64_t rows = F + (int64_t)LB * max_seg;     // B's window rows
   const int64_t acols = F + (int64_t)LB * max_seg;    // x1 frames computed
   const int64_t arows = acols + (int64_t)LA * max_seg;
   const int64_t stash = (int64_t)LB * max_seg * (c / 4);
-  if (acols > kPairCols || stash > 2 * kThreads || pair_lds_bytes(rows, arows, stash, prec) > 64 * 1024) return 0;
+  if (acols > pair_cols(c) || stash > 2 * kThreads || pair_lds_bytes(c, rows, arows, stash, prec, fuse) > 64 * 1024)
+    return 0;
   *arow_cap = (int32_t)arows;
   *stash_cap = (int32_t)stash;
   return (int32_t)rows;
@@ -1732,28 +1776,31 @@ int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min
 
 hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32_t arow_cap, int32_t stash_cap,
                             hipStream_t s) {
-  const int C = kPairC;
+  const int C = a.cout;
+  const bool fuse = a.oc.k > 0;
   const int F = win_f(C, 4);
   const int kc = w_kchunk(prec);
   const int Kreal = a.k * C;
   const int Kpad = (Kreal + kc - 1) / kc * kc;
-  if (a.cin != C || a.cout != C || a.k != 3 || a.pa.L != a.pa.dil * 2 || a.L != a.dil * 2 || !a.out_buf ||
-      a.fd_cin.d != (uint32_t)C || Kpad * w_esize(prec) / 128 != win_kcm(prec, C))
+  const int KCM = pair_kchunks(C, a.k, prec);
+  if ((C != 64 && C != 32) || a.cin != C || a.k != 3 || a.pa.L != a.pa.dil * 2 || a.L != a.dil * 2 || !a.out_buf ||
+      a.fd_cin.d != (uint32_t)C || (fuse && (C != 32 || a.oc.k > kOutTaps)))
     return hipErrorInvalidValue;
   const int64_t n_nt = (a.n_out + F - 1) / F;
   const int64_t items = (int64_t)a.n_ent * a.pa.L * C / 4;   // 4 channels per cache-update item
   const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   const int64_t grid = n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  const size_t lds = (size_t)pair_lds_bytes(row_cap, arow_cap, stash_cap, prec);
+  const size_t lds = (size_t)pair_lds_bytes(C, row_cap, arow_cap, stash_cap, prec, fuse);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.pa.L * C / 4, 1));
-#define SC_PAIR(P, K)                                                                                       \
-  if (prec == P) {                                                                                         \
-    hipLaunchKernelGGL((conv_pair_kernel<P, 64, 4, K, kPairCols / 16>), dim3((unsigned)grid), dim3(kThreads), lds, s, \
-                       a, (int)n_nt, Kpad, Kreal, row_cap, arow_cap, stash_cap, extra, fd_per_ent);          \
+#define SC_PAIR(P, M, K, NC, FU)                                                                            \
+  if (prec == P && C == M && KCM == K && fuse == FU) {                                                     \
+    hipLaunchKernelGGL((conv_pair_kernel<P, M, 4, K, NC, FU>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
+                       (int)n_nt, Kpad, Kreal, row_cap, arow_cap, stash_cap, extra, fd_per_ent);            \
     return hipGetLastError();                                                                              \
   }
-  SC_PAIR(1, 3) SC_PAIR(2, 2)
+  SC_PAIR(1, 64, 3, 6, false) SC_PAIR(2, 64, 2, 6, false)
+  SC_PAIR(1, 32, 2, 12, false) SC_PAIR(1, 32, 2, 12, true) SC_PAIR(2, 32, 1, 12, false) SC_PAIR(2, 32, 1, 12, true)
 #undef SC_PAIR
   return hipErrorInvalidValue;
 }

@@ -211,8 +211,8 @@ void fuse_convt_windows(sc_model* m) {
 // stack).  Such a model runs pairs fused always (activation maxima, which
 // need the first conv's output, are refused on it).
 bool pair_candidate(const Op& op) {
-  return op.kind == K_CONV && op.impl == IMPL_WIN && op.residual && op.fuse_out < 0 && op.convt_in < 0 &&
-         op.stride == 1 && op.cin == op.cout && op.prec >= 1;
+  return op.kind == K_CONV && op.impl == IMPL_WIN && op.residual && op.convt_in < 0 && op.stride == 1 &&
+         op.cin == op.cout && op.prec >= 1;
 }
 
 void fuse_conv_pairs(sc_model* m) {
@@ -227,12 +227,15 @@ void fuse_conv_pairs(sc_model* m) {
     }
     if (ia < 0 || ia + 1 != (int)b || readers != 1) continue;
     Op& ca = pl.ops[ia];
-    if (!pair_candidate(ca) || ca.pair_in >= 0 || ca.pair_out >= 0 || ca.out_twin >= 0 || ca.prec != cb.prec ||
-        ca.k != cb.k || ca.cin != cb.cin)
+    // (the first conv of a pair computes no output conv in its epilogue; the
+    // second may)
+    if (!pair_candidate(ca) || ca.fuse_out >= 0 || ca.pair_in >= 0 || ca.pair_out >= 0 || ca.out_twin >= 0 ||
+        ca.prec != cb.prec || ca.k != cb.k || ca.cin != cb.cin)
       continue;
     const int64_t min_frames = cb.in_rate.of(pl.input_multiple);
     int32_t arows = 0, stash = 0;
-    const int32_t rows = conv_pair_rows(cb.cin, cb.k, ca.dil, cb.dil, cb.prec, min_frames, &arows, &stash);
+    const int32_t rows =
+        conv_pair_rows(cb.cin, cb.k, ca.dil, cb.dil, cb.prec, min_frames, cb.fuse_out >= 0, &arows, &stash);
     if (rows <= 0) continue;
     cb.pair_in = ia;
     ca.pair_out = (int32_t)b;
@@ -519,6 +522,21 @@ hipError_t launch_pack(sc_model* m, const LaunchSet& ls) {
                            pl.input_twin_pre, twin_scale(m, pl.input_twin_layer), ls.hs);
 }
 
+// The one-output-channel conv computed in the epilogue of window conv `op`.
+void set_out_conv(const sc_model* m, const Op& op, LayerArgs& aw) {
+  const Op& oc = m->plan.ops[op.fuse_out];
+  aw.oc.W = static_cast<const float*>(m->opdev[op.fuse_out].W);
+  aw.oc.B = m->opdev[op.fuse_out].B;
+  aw.oc.k = oc.k;
+  aw.oc.dil = oc.dil;
+  aw.oc.L = oc.cache_len;
+  aw.oc.pre_act = oc.pre_act;
+  aw.oc.post_act = oc.post_act;
+  aw.oc.delay = oc.out_delay;
+  aw.oc.state_off = oc.state_off;
+  aw.oc.state_len = oc.state_len;
+}
+
 // The launch of op `oi` (with its calibration and timing records, if on).
 hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
   const Op& op = m->plan.ops[oi];
@@ -582,23 +600,12 @@ hipError_t launch_op(sc_model* m, size_t oi, const LaunchSet& ls) {
       aw.pa.delay = pa.out_delay;
       aw.pa.state_off = pa.state_off;
       aw.pa.state_len = pa.state_len;
+      if (op.fuse_out >= 0) set_out_conv(m, op, aw);
       const OpDev& od = m->opdev[oi];
       e = launch_conv_pair(aw, prec, od.pair_rows, od.pair_arows, od.pair_stash, ls.hs);
     } else if (op.impl == IMPL_WIN) {
       LayerArgs aw = a;
-      if (fused) {
-        const Op& oc = m->plan.ops[op.fuse_out];
-        aw.oc.W = static_cast<const float*>(m->opdev[op.fuse_out].W);
-        aw.oc.B = m->opdev[op.fuse_out].B;
-        aw.oc.k = oc.k;
-        aw.oc.dil = oc.dil;
-        aw.oc.L = oc.cache_len;
-        aw.oc.pre_act = oc.pre_act;
-        aw.oc.post_act = oc.post_act;
-        aw.oc.delay = oc.out_delay;
-        aw.oc.state_off = oc.state_off;
-        aw.oc.state_len = oc.state_len;
-      }
+      if (fused) set_out_conv(m, op, aw);
       e = launch_conv_win(aw, prec, m->opdev[oi].win_rows, ls.hs);
     } else if (op.impl == IMPL_TAIL && fused) {
       const Op& pw = m->plan.ops[op.fuse_out];

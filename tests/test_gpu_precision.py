@@ -183,7 +183,7 @@ def test_conv_pair_fusion_bitwise(prec, split):
     idle = [p["node"] for p in fused.profile_read() if p["kind"] == 1 and p["launches"] == 0]
     fused.profile(False)
     log("pair fusion %s split=%s conv nodes computed inside the next launch: %s" % (prec, split, idle))
-    assert len(idle) == 1, idle       # the first two residual convs of the 64-channel stage
+    assert len(idle) == 2, idle       # the first conv of each fused pair (64- and 32-channel stages)
     with pytest.raises(sc._native.ScError):   # the first conv's output is never formed
         fused.enable_amax(True)
     b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base | sc._native.SC_MODEL_NO_PAIR_FUSION),
