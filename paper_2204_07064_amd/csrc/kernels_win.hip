@@ -1091,6 +1091,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   constexpr int F = NB * 16 * WN;
   constexpr int NCW = NCBA / WN;               // A column blocks of a wave
   static_assert(NCW % 2 == 0, "two groups of column blocks per wave");
+  static_assert(F * (C + 4) < 0x7fff, "skip-row offsets in 15 bits");
   constexpr int ES = WPrec<PREC>::kEsize;
   constexpr int ROWB = C * ES + 16;            // operand row stride (bytes), padded against bank conflicts
   constexpr int XF = C + 4;                    // FP32 row stride (floats), padded likewise
@@ -1109,6 +1110,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   __shared__ int8_t colseg[F];
   __shared__ int32_t acb[NCOL];                // A column: LDS row of its first window row
   __shared__ int32_t ajb[NCOL];                // A column: LDS row of its frame in B's window
+  __shared__ int16_t aslot[NCOL];              // A column: the B column whose skip row it is (-1: none)
   __shared__ int8_t aflag[NCOL];               // bit 0: kept by A's masks; bit 1: a row of B's next cache
   __shared__ const float* askip[NCOL];         // A column: its skip row (A's cache or input)
   __shared__ float* anext[NCOL];               // A column: its row of B's next cache
@@ -1149,11 +1151,10 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   const bool pre_a = a.pa.pre_act != 0, pre_b = a.pre_act != 0;
   const float qs_a = PREC == 2 ? 1.0f / a.pa.act_scale : 1.0f;
   const float qs_b = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
-  const size_t r1 = (size_t)max(arow_cap * ROWB, row_cap * XF * 4);
+  const size_t r1 = (size_t)max(arow_cap * ROWB, F * XF * 4);
   unsigned char* wop_a = lds;                              // A's window rows, operand form
-  float* xf = reinterpret_cast<float*>(lds);               // B's window rows in FP32 (after A's MFMAs)
-  f4* stash = reinterpret_cast<f4*>(lds + r1);             // B's cache rows until then
-  unsigned char* wop_b = lds + r1 + (size_t)stash_cap * 16;   // B's window rows, operand form
+  float* xf = reinterpret_cast<float*>(lds);               // B's skip row of each column, FP32 (after A's MFMAs)
+  unsigned char* wop_b = lds + r1;                         // B's window rows, operand form
   const float** rsrc = reinterpret_cast<const float**>(wop_b + (size_t)row_cap * ROWB);
 
   // A's weights (the wave's 16 rows, every chunk), both convs' biases and scales
@@ -1260,7 +1261,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     colseg[tid] = (int8_t)s;
   }
   for (int j = tid; j < NCOL; j += kThreads) {
-    int32_t cb = 0, jb = 0;
+    int32_t cb = 0, jb = 0, sl = -1;
     int8_t fl = 0;
     const float* sk = a.pa.B;              // a padding column reads a harmless row and is not used
     float* nx = nullptr;
@@ -1272,6 +1273,8 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
       const int32_t u = p.ta + (j - p.acol0);      // x1 frame of the stream
       cb = p.abase + (u - p.ta);                   // A's window row u (taps add dil_a rows)
       jb = g.base + (u + LB - g.r0);               // B's window row u + L_B
+      const int32_t tt = u + LB - a.skip_off;      // the B frame whose skip row that is
+      if (tt >= g.t_lo && tt <= g.t_hi) sl = g.out_start + tt - f0;
       const int64_t x = (int64_t)u * a.out_den;
       if (!(x < p.mask_lo || x >= p.mask_hi)) fl |= 1;
       const int32_t r = u + a.pa.skip_off;         // A's skip: its window row u + skip_off
@@ -1283,6 +1286,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     }
     acb[j] = cb;
     ajb[j] = jb;
+    aslot[j] = (int16_t)sl;
     aflag[j] = fl;
     askip[j] = sk;
     anext[j] = nx;
@@ -1298,6 +1302,9 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 
   // ---- loads: B's cache rows, A's skip values of the lane's columns, A's
   // window rows (operand form) ----
+  // (B's cache rows stay in registers until region 1 is free)
+  // cdst: the piece's operand offset (C ch + row) in the low 16 bits, its
+  // skip-row offset (XF slot + ch, 0x7fff: none) in the high 15; -1: no piece
   f4 cpre[CPRE];
   int32_t cdst[CPRE];
 #pragma unroll
@@ -1312,7 +1319,9 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
         const int32_t i = idx / PPR;
         const int ch = (idx - i * PPR) * 4;
         cpre[p] = gload<f4>(g.cache + (int64_t)(g.r0 + i) * C + ch);
-        cdst[p] = (g.base + i) * C + ch;
+        const int32_t tt = g.r0 + i - a.skip_off;   // the B frame whose skip row this is
+        const int32_t sk = tt >= g.t_lo && tt <= g.t_hi ? (g.out_start + tt - f0) * XF + ch : 0x7fff;
+        cdst[p] = ((g.base + i) * C + ch) | sk << 16;
         break;
       }
       idx -= n;
@@ -1340,9 +1349,6 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
       }
     }
   }
-#pragma unroll
-  for (int p = 0; p < CPRE; ++p)
-    if (cdst[p] >= 0) stash[tid + p * kThreads] = cpre[p];
   __syncthreads();
 
   // ---- A: the wave's 16 rows x its A column blocks (column blocks
@@ -1386,11 +1392,12 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   __syncthreads();   // every wave is past A's operand rows: region 1 takes B's FP32 rows
 
   // ---- x1: A's epilogue, B's window rows (FP32 and operand), B's next cache ----
-  int32_t jbs[NCW];
+  int32_t jbs[NCW], sls[NCW];
   int fls[NCW];
 #pragma unroll
   for (int i = 0; i < NCW; ++i) {        // every column's record first: one wait
     jbs[i] = ajb[(nc0 + i) * 16 + lr];
+    sls[i] = aslot[(nc0 + i) * 16 + lr];
     fls[i] = aflag[(nc0 + i) * 16 + lr];
   }
 #pragma unroll
@@ -1404,7 +1411,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     v = v + bias_a;
     v = v + skv[i];
     if (!(fl & 1)) v = f4{0.f, 0.f, 0.f, 0.f};
-    *reinterpret_cast<f4*>(xf + (size_t)jb * XF + m) = v;
+    if (sls[i] >= 0) *reinterpret_cast<f4*>(xf + (size_t)sls[i] * XF + m) = v;
     store_operand<PREC>(wop_b + (size_t)jb * ROWB + m * ES, v, pre_b, qs_b);
     if (fl & 2) gstore<f4>(anext[col] + m, v);
   }
@@ -1412,10 +1419,11 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 #pragma unroll
   for (int p = 0; p < CPRE; ++p) {
     if (cdst[p] < 0) continue;
-    const f4 v = stash[tid + p * kThreads];
-    const int32_t jr = cdst[p] / C;
-    const int ch = cdst[p] - jr * C;
-    *reinterpret_cast<f4*>(xf + (size_t)jr * XF + ch) = v;
+    const f4 v = cpre[p];
+    const int32_t od = cdst[p] & 0xffff, sk = cdst[p] >> 16;
+    const int32_t jr = od / C;
+    const int ch = od - jr * C;
+    if (sk != 0x7fff) *reinterpret_cast<f4*>(xf + sk) = v;
     store_operand<PREC>(wop_b + (size_t)jr * ROWB + ch * ES, v, pre_b, qs_b);
   }
   __syncthreads();
@@ -1437,7 +1445,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   if constexpr (FUSE) {
     // the output conv in the epilogue; its per-tap scratch takes B's operand rows
     fused_out_epilogue<PREC, MT, NB, F>(
-        a, acc, m, bias_b, ws_b, f0, [&](int col) { return xf + (size_t)(colbase[col] + a.skip_off) * XF; }, segs,
+        a, acc, m, bias_b, ws_b, f0, [&](int col) { return xf + (size_t)col * XF; }, segs,
         segs2, colseg, n_seg, wa2, wop_b);
     return;
   }
@@ -1450,7 +1458,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
     f4 v = acc[nb];
     if (PREC == 2) v = v * (ws_b * a.act_scale);
     v = v + bias_b;
-    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)(colbase[col] + a.skip_off) * XF + m);
+    if (a.residual) v = v + *reinterpret_cast<const f4*>(xf + (size_t)col * XF + m);
     if (!keep) v = f4{0.f, 0.f, 0.f, 0.f};
     const int64_t o = (int64_t)f * a.cout + m;
     if (!a.twin_only) gstore<f4>(a.out_buf + o, v);
@@ -1735,13 +1743,14 @@ hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32
 namespace {
 // x1 frames a pair tile computes at most (A column blocks x 16), by channels
 int pair_cols(int c) { return c == 64 ? 96 : 192; }
-// A's window rows in operand form, overlaid by B's window rows in FP32 (row
-// stride c + 4); B's cache rows; B's window rows in operand form and A's row
+// A's window rows in operand form, overlaid by B's skip rows in FP32 (one per
+// tile column, row stride c + 4); B's window rows in operand form and A's row
 // sources, overlaid by the fused output conv's per-tap scratch
-int64_t pair_lds_bytes(int c, int64_t rows, int64_t arows, int64_t stash, int prec, bool fuse) {
+int64_t pair_lds_bytes(int c, int64_t rows, int64_t arows, int prec, bool fuse) {
   const int64_t rowb = c * w_esize(prec) + 16;
-  const int64_t scratch = fuse ? (int64_t)(c / 16) * kOutTaps * win_f(c, 4) * 4 : 0;
-  return std::max(arows * rowb, rows * (c + 4) * 4) + stash * 16 + std::max(rows * rowb + arows * 8, scratch);
+  const int64_t F = win_f(c, 4);
+  const int64_t scratch = fuse ? (int64_t)(c / 16) * kOutTaps * F * 4 : 0;
+  return std::max(arows * rowb, F * (c + 4) * 4) + std::max(rows * rowb + arows * 8, scratch);
 }
 int pair_kchunks(int c, int k, int prec) {
   const int kc = w_kchunk(prec);
@@ -1767,7 +1776,7 @@ int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min
   const int64_t acols = F + (int64_t)LB * max_seg;    // x1 frames computed
   const int64_t arows = acols + (int64_t)LA * max_seg;
   const int64_t stash = (int64_t)LB * max_seg * (c / 4);
-  if (acols > pair_cols(c) || stash > 2 * kThreads || pair_lds_bytes(c, rows, arows, stash, prec, fuse) > 64 * 1024)
+  if (acols > pair_cols(c) || stash > 2 * kThreads || pair_lds_bytes(c, rows, arows, prec, fuse) > 64 * 1024)
     return 0;
   *arow_cap = (int32_t)arows;
   *stash_cap = (int32_t)stash;
@@ -1791,7 +1800,7 @@ hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32
   const int extra = (int)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
   const int64_t grid = n_nt + extra;
   if (grid <= 0) return hipSuccess;
-  const size_t lds = (size_t)pair_lds_bytes(C, row_cap, arow_cap, stash_cap, prec, fuse);
+  const size_t lds = (size_t)pair_lds_bytes(C, row_cap, arow_cap, prec, fuse);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.pa.L * C / 4, 1));
 #define SC_PAIR(P, M, K, NC, FU)                                                                            \
   if (prec == P && C == M && KCM == K && fuse == FU) {                                                     \
