@@ -73,25 +73,24 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # the counter reads for a plain copy of known size.  Valid only for the kernel
 # sources the counters were taken with.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "39a0543dffe2a94f3535482401021a871e040bd3 37576851252a29dfa965ccb480e8308edf8b272b c475d43d80ff2b54661b0920e2ae957339dc5b81 6cafeb5eadda802ba945f37301c3219b96021883 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "39a0543dffe2a94f3535482401021a871e040bd3 23d2e340c591e6a99da03b7fd8ea31cb1b6ee22d c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 773.1, 2727.1),
-        2: ('mfma', 10445.5, 17203.3),
-        4: ('mfma', 10295.1, 16938.9),
-        6: ('mfma', 11286.0, 18474.7),
-        8: ('mfma', 14157.0, 12302.2),
-        9: ('mfma', 5427.8, 32890.7),
-        11: ('mfma', 17114.0, 32735.9),
-        13: ('mfma', 17631.8, 33507.4),
-        15: ('mfma', 18954.4, 14237.3),
-        16: ('mfma', 6196.3, 43377.9),
-        20: ('mfma_win', 24768.1, 43633.3),
-        22: ('mfma_win', 28490.8, 22712.6),
-        25: ('mfma_win', 11523.3, 43249.2),
-        27: ('mfma_win', 22923.0, 43313.2),
-        29: ('mfma_win', 25147.7, 3126.2),
+        1: ('mfma', 773.2, 2727.1),
+        2: ('mfma', 10445.3, 17202.0),
+        4: ('mfma', 10295.1, 16938.8),
+        6: ('mfma', 11286.0, 18474.8),
+        8: ('mfma', 14157.5, 12302.2),
+        9: ('mfma', 5428.6, 32886.5),
+        11: ('mfma', 17112.9, 32736.5),
+        13: ('mfma', 17634.7, 33506.4),
+        15: ('mfma', 18953.8, 14237.2),
+        16: ('mfma', 6196.3, 43378.0),
+        20: ('mfma_win', 24778.6, 43633.3),
+        22: ('mfma_win', 28490.9, 22712.6),
+        25: ('mfma_win', 11526.6, 43249.2),
+        29: ('mfma_win', 26052.7, 3318.2),
         30: ('tail', 2110.9, 85.4),
     },
 }
