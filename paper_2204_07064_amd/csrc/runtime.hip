@@ -219,7 +219,8 @@ void fuse_conv_pairs(sc_model* m) {
   Plan& pl = m->plan;
   for (size_t b = 0; b < pl.ops.size(); ++b) {
     Op& cb = pl.ops[b];
-    if (!pair_candidate(cb) || cb.in_twin >= 0) continue;
+    // (the pair writes its output to a workspace buffer: not the model output)
+    if (!pair_candidate(cb) || cb.in_twin >= 0 || cb.out_buf < 0) continue;
     int ia = -1, readers = 0;
     for (size_t o = 0; o < pl.ops.size(); ++o) {
       if (pl.ops[o].node == cb.src) ia = (int)o;
