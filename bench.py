@@ -71,8 +71,9 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # HBM traffic per launch of every layer of the BF16 256-stream workload from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled by what
 # the counter reads for a plain copy of known size.  Valid only for the kernel
-# sources the counters were taken with.
+# sources the counters were taken with, and only for that model's nodes.
 MEASURED_TRAFFIC = {
+    "model": "rave_b",
     "sources_sha1": "39a0543dffe2a94f3535482401021a871e040bd3 23d2e340c591e6a99da03b7fd8ea31cb1b6ee22d c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
@@ -97,13 +98,14 @@ MEASURED_TRAFFIC = {
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
 
 
-def measured_traffic(best):
+def measured_traffic(best, model="rave_b"):
     import hashlib
     d = os.path.join(ROOT, "paper_2204_07064_amd", "csrc")
     sha = " ".join(hashlib.sha1(open(os.path.join(d, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES)
     t = MEASURED_TRAFFIC
     rec = t["by_node"].get(best["node"])
-    if sha != t["sources_sha1"] or rec is None or rec[0] != IMPL_NAME[best["impl"]] or best["precision"] != 1:
+    if (model != t["model"] or sha != t["sources_sha1"] or rec is None or rec[0] != IMPL_NAME[best["impl"]]
+            or best["precision"] != 1):
         return None
     return round(rec[1] * t["fetch_bytes_per_kib"] + rec[2] * t["write_bytes_per_kib"])
 
@@ -196,7 +198,7 @@ def fused_producer(prof, p):
 WIDE_MIN_CHANNELS = 64
 
 
-def roofline(prof):
+def roofline(prof, model="rave_b"):
     """The dominant launch (longest summed time) against its roof.  A wide
     MFMA layer (64+ input channels) is judged on MFMA: its algorithmic FLOPs
     (the layer's MACs x 2) per launch over the launch's average time, against
@@ -232,7 +234,7 @@ def roofline(prof):
         kernel += " with the residual conv node %d (cin %d, cout %d, k %d, d %d) in its launch" % (
             ct["node"], ct["cin"], ct["cout"], ct["k"], ct["dilation"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": measured_traffic(best), "basis": basis,
+            "frac": round(ach / peak, 4), "traffic": measured_traffic(best, model), "basis": basis,
             "flops_per_launch": round(flops / max(best["launches"], 1)),
             "layer_bytes_per_launch": round(byts / max(best["launches"], 1)),
             "kernel": kernel,
@@ -344,13 +346,22 @@ def step_roofline(run, value, prec):
                                "frac": round(value / roof_lbl, 5)}}
 
 
+WORKLOAD_TEXT = {
+    "rave_b": "rave_b decoder serving mix: 256 streams, buffers uniform over {1,2,4,8,16,32} latent frames, "
+              "closed loop",
+    "autoencoder": "strided encoder feeding the rave_b decoder: 256 streams, white-noise buffers of "
+                   "128 x {1,2,4,8,16,32} samples, closed loop",
+    "wide": "wide decoder (128 latent ch, widths 768->384->192->96->48, ratios [8,8,4,2], dilations 1/3/9/27): "
+            "1024 streams, buffers uniform over 1..8 latent frames, closed loop",
+}
+
+
 def wide_runs(sc, torch, precisions=("fp8", "bf16", "fp32", "fp8_all"), warmup=3, steps=10):
     """The wide decoder with 1024 streams (closed loop, buffers uniform over
     1..8 frames) at each precision: samples/s and its step roofline."""
     m = WIDE.model_fn()
     w = scgen.init_weights(m)
-    out = {"workload": "wide decoder (128 latent ch, widths 768->384->192->96->48, ratios [8,8,4,2], "
-                       "dilations 1/3/9/27): 1024 streams, buffers uniform over 1..8 latent frames, closed loop"}
+    out = {"workload": WORKLOAD_TEXT["wide"]}
     for prec in precisions:
         scales = calibrate(sc, torch, m, w, latent=WIDE.latent) if prec in ("fp8", "fp8_all") else None
         if prec == "fp8":       # the mixed plan (SNR target met)
@@ -853,10 +864,11 @@ def main():
                     help="replay one captured graph per step (measured slower than one-by-one launches here)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
-    ap.add_argument("--workload", default="decoder", choices=["decoder", "audio"],
+    ap.add_argument("--workload", default="decoder", choices=["decoder", "audio", "wide"],
                     help="decoder: the headline 256-stream decoder mix; audio: the strided encoder feeding "
-                         "the decoder, 256 streams of 128 x {1..32}-sample buffers (its own JSON line, "
-                         "for profiling; no extra, serving or CPU sections)")
+                         "the decoder, 256 streams of 128 x {1..32}-sample buffers; wide: the wide decoder, "
+                         "1024 streams of 1..8-frame buffers (audio and wide: their own JSON line, for "
+                         "profiling; no extra, serving or CPU sections)")
     ap.add_argument("--summarize", metavar="DIR", help="print per-layer figures from rocprofv3 CSVs under DIR")
     ap.add_argument("--summarize-copy", metavar="DIR", help="print the copy-probe counter factors under DIR")
     args = ap.parse_args()
@@ -884,8 +896,8 @@ def main():
         return
     import paper_2204_07064_amd as sc
 
-    shape = AUTOENC if args.workload == "audio" else HEADLINE
-    if args.workload == "audio":
+    shape = {"audio": AUTOENC, "wide": WIDE}.get(args.workload, HEADLINE)
+    if shape is not HEADLINE:
         args.no_extra = args.no_serving = args.no_cpu_baseline = args.no_ola = True
     m = shape.model_fn()
     w = scgen.init_weights(m)
@@ -917,16 +929,13 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[max(used)] if used else "fp32",
         "data": "synthetic",
-        "config": {"workload": ("rave_b decoder serving mix: 256 streams, buffers uniform over "
-                                "{1,2,4,8,16,32} latent frames, closed loop") if shape is HEADLINE else
-                               ("strided encoder feeding the rave_b decoder: 256 streams, white-noise buffers "
-                                "of 128 x {1,2,4,8,16,32} samples, closed loop"),
-                   "streams": N_STREAMS, "precision": args.precision,
+        "config": {"workload": WORKLOAD_TEXT[shape.name],
+                   "streams": shape.streams, "precision": args.precision,
                    "mean_buffer_frames": float(np.mean(shape.choices))},
         "step_ms": {"p50": round(float(np.percentile(run["step_ms"], 50)), 4),
                     "p99": round(float(np.percentile(run["step_ms"], 99)), 4)},
-        "rtf": round(1.0 / (value / N_STREAMS / 44100.0), 6),
-        "roofline": roofline(prof),
+        "rtf": round(1.0 / (value / shape.streams / 44100.0), 6),
+        "roofline": roofline(prof, shape.name),
         "step_roofline": step_roofline(prof_run, value, PREC_NAME[args.precision]),
         "measured_step_bytes_per_sample": (step_traffic(prof, prof_run["samples"] / args.steps)
                                            if shape is HEADLINE and args.precision == "bf16" else None),

@@ -596,10 +596,12 @@ void pack_rows(int M, int Mpad, int Kpad, int prec, RowFn value, PosFn kpos, int
   }
 }
 
-// Tile shape per GEMM M (output rows).
-void tile_for(int M, int& MT, int& NT) {
-  if (M <= 32) { MT = 32; NT = 128; }
-  else if (M <= 64) { MT = 64; NT = 64; }
+// Tile shape per GEMM M (output rows).  A conv whose M is an odd multiple of
+// 32 (96 channels) takes 32 x 128 tiles, which leave no padding rows: measured
+// 10% faster than 64 x 64 tiles on the 96-channel convs; the transposed conv
+// of that M measured faster on 64 x 64.
+void tile_for(int M, bool convt, int& MT, int& NT) {
+  if (M <= 32 || (!convt && M % 64 == 32)) { MT = 32; NT = 128; }
   else { MT = 64; NT = 64; }
 }
 
@@ -625,7 +627,7 @@ template <bool CONVT>
 hipError_t dispatch(const LayerArgs& a, int prec, int64_t n_cols, int Kpad, int Kreal, int half_pad, int M,
                     hipStream_t s) {
   int MT, NT;
-  tile_for(M, MT, NT);
+  tile_for(M, CONVT, MT, NT);
 #define SC_CASE(P, A, B)                                                                                   \
   if (prec == P && MT == A && NT == B) {                                                                   \
     if (a.in_twin) return launch_t<P, A, B, CONVT, true>(a, n_cols, Kpad, Kreal, half_pad, M, s);         \
@@ -666,7 +668,7 @@ bool convt_mfma_supported(int cin, int cout, int r, int prec) {
 void pack_conv_mfma(const float* w, int cout, int cin, int k, int prec, std::vector<uint8_t>& out,
                     std::vector<float>& wscale) {
   int MT, NT;
-  tile_for(cout, MT, NT);
+  tile_for(cout, false, MT, NT);
   const int Kreal = k * cin;
   const int Kpad = round_up(Kreal, kchunk(prec));
   const int Mpad = round_up(cout, MT);
@@ -680,7 +682,7 @@ void pack_convt_mfma(const float* w, int cin, int cout, int r, int prec, std::ve
                      std::vector<float>& wscale) {
   const int M = r * cout;
   int MT, NT;
-  tile_for(M, MT, NT);
+  tile_for(M, true, MT, NT);
   const int half = round_up(cin, kchunk(prec));
   const int Kpad = 2 * half;
   const int Mpad = round_up(M, MT);

@@ -70,3 +70,13 @@ def test_residual_pair_accounting():
     r = bench.roofline([a, b])
     assert "residual conv node 18" in r["kernel"]
     assert r["bound"] == "mfma" and r["flops_per_launch"] == round(f / b["launches"])
+
+
+def test_measured_traffic_only_for_its_model():
+    """The counter table holds the headline decoder's nodes: another model's
+    node of the same number and kernel family gets no traffic figure."""
+    n, rec = next(iter(bench.MEASURED_TRAFFIC["by_node"].items()))
+    impl = {v: k for k, v in bench.IMPL_NAME.items()}[rec[0]]
+    best = {"node": n, "impl": impl, "precision": 1}
+    assert bench.measured_traffic(best, "wide") is None
+    assert bench.measured_traffic(best, "autoencoder") is None
