@@ -232,13 +232,17 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
   const int lr = lane & 15, lg = lane >> 4;
   const int L2 = a.oc.L, k2 = a.oc.k, d2 = a.oc.dil;
   const bool pre2 = a.oc.pre_act != 0;
+  // the output conv's input channels (this conv's cout: MT, or fewer with the
+  // tile's last rows padding, which stay zero)
+  const int C2 = a.cout;
+  const bool m_ok = m < C2;
   f4 v[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int col = wn * (F / WN) + nb * 16 + lr;
     const int s = colseg[col];
     v[nb] = f4{0.f, 0.f, 0.f, 0.f};
-    if (s < 0) continue;
+    if (s < 0 || !m_ok) continue;
     const int32_t t = f0 + col - segs[s].out_start;
     f4 x = acc[nb];
     if (PREC == 2) x = x * (wsc * a.act_scale);
@@ -257,7 +261,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
       // the output conv's next cache: the stream's last L2 frames (raw)
       const WinSeg2& g2 = segs2[s];
       const int32_t i = f0 + col - segs[s].out_start - (g2.T - L2);
-      if (i >= 0) gstore<f4>(g2.cache2_next + (int64_t)i * MT + m, v[nb]);
+      if (i >= 0 && m_ok) gstore<f4>(g2.cache2_next + (int64_t)i * C2 + m, v[nb]);
     }
     // the wave's 16 channels of the 16 columns: D[kk][col] = sum over them of
     // W[kk][c] * act(y[c][col]) on FP32 MFMA, the accumulator layout serving
@@ -278,10 +282,10 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
   for (int s = 0; s < n_seg; ++s) {
     const WinSeg2& g2 = segs2[s];
     if (segs[s].t_lo != 0 || g2.T >= L2) continue;   // uniform
-    for (int j = tid; j < (L2 - g2.T) * (MT / 4); j += kThreads) {
-      const int i = j / (MT / 4);
-      const int c = (j - i * (MT / 4)) * 4;
-      gstore<f4>(g2.cache2_next + (int64_t)i * MT + c, gload<f4>(g2.cache2 + (int64_t)(g2.T + i) * MT + c));
+    for (int j = tid; j < (L2 - g2.T) * (C2 / 4); j += kThreads) {
+      const int i = j / (C2 / 4);
+      const int c = (j - i * (C2 / 4)) * 4;
+      gstore<f4>(g2.cache2_next + (int64_t)i * C2 + c, gload<f4>(g2.cache2 + (int64_t)(g2.T + i) * C2 + c));
     }
   }
   __syncthreads();
@@ -320,7 +324,7 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
     if (s >= 0 && (col < L2 || col >= F - L2 || f0 + col - segs[s].out_start < L2)) {
 #pragma unroll
       for (int kk = 0; kk < KO; ++kk)
-        if (kk < k2) a.out_buf[(int64_t)(f0 + col) * MT + kk] = prow(col, kk);
+        if (kk < k2) a.out_buf[(int64_t)(f0 + col) * C2 + kk] = prow(col, kk);
     }
   }
 }
@@ -334,8 +338,9 @@ __device__ inline void fused_out_epilogue(const LayerArgs& a, const f4* acc, int
 // skip row as raw FP32 ([F][cin + 4]), then per staged row its source pointer
 // and skip slot.
 //
-// FUSE: a one-output-channel conv reading this layer's output (cout == MT, one
-// M tile) runs in the epilogue, which never writes the layer's output itself.
+// FUSE: a one-output-channel conv reading this layer's output (all of cout in
+// one M tile: cout == MT, or 48 channels on a 64-row tile whose last 16 rows
+// stay zero) runs in the epilogue, which never writes the layer's output itself.
 // From the accumulators it forms each row's per-tap sums P_kk (see
 // tap_partial) and finishes every frame whose taps stay on the tile's rows;
 // a small tail launch finishes the rest (a stream's first L frames, and up to
@@ -467,7 +472,7 @@ __global__ void __launch_bounds__(kThreads, KCM > 3 ? 4 : 5) conv_win_kernel(Lay
   f4 wa2 = {0.f, 0.f, 0.f, 0.f};
   if constexpr (FUSE) {
     const int m2 = wm * 16 + lg * 4;
-    if (lr < a.oc.k) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * MT + m2);
+    if (lr < a.oc.k && m2 < a.cout) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * a.cout + m2);
   }
 
   // ---- the streams of the tile: lane s of every wave forms stream s's
@@ -1567,7 +1572,7 @@ int32_t conv_win_tile_frames(int cin, int cout) { return win_f(win_mt(cout), win
 bool conv_win_out_fusable(int cin, int cout, int k, int dil) {
   // all output channels in one M tile, a tile shape with fused variants, and
   // the taps of a boundary frame reaching no further than the previous tile
-  if (cout != win_mt(cout) || win_nb(cin) != 4 || k < 1 || k > kOutTaps || dil < 1) return false;
+  if (cout > win_mt(cout) || cout % 16 != 0 || win_nb(cin) != 4 || k < 1 || k > kOutTaps || dil < 1) return false;
   const int L = dil * (k - 1);
   return L <= 16 && 2 * L <= conv_win_tile_frames(cin, cout);   // the tail forms P of <= 16 cache rows
 }
@@ -1583,6 +1588,7 @@ hipError_t launch_conv_out_tail(const LayerArgs& a, int32_t tile_frames, hipStre
   hipLaunchKernelGGL((conv_out_tail_kernel<C>), dim3((unsigned)blocks), dim3(kThreads), 0, s, a, tile_frames, \
                      (int32_t)n_bnd, (int32_t)bnd_blocks)
   if (a.cin == 32) SC_TAIL(32);
+  else if (a.cin == 48) SC_TAIL(48);
   else if (a.cin == 64) SC_TAIL(64);
   else return hipErrorInvalidValue;
 #undef SC_TAIL
@@ -1623,7 +1629,7 @@ hipError_t launch_conv_win(const LayerArgs& a, int prec, int32_t row_cap, hipStr
   const int64_t grid = (int64_t)n_mt * n_nt + extra;
   if (grid <= 0) return hipSuccess;
   const bool fuse = a.oc.k > 0;
-  if (fuse && (a.cout != MT || NB != 4 || !a.out_buf)) return hipErrorInvalidValue;
+  if (fuse && (a.cout > MT || a.cout % 16 != 0 || NB != 4 || !a.out_buf)) return hipErrorInvalidValue;
   size_t lds = (size_t)win_lds_bytes(row_cap, a.cin, prec, F);
   // per-wave partial tap sums of the output conv
   if (fuse) lds = std::max(lds, (size_t)(MT / 16) * F * kOutTaps * 4);

@@ -18,6 +18,7 @@ from .models import (  # noqa: F401
     autoencoder,
     outconv_unit,
     outconv64_unit,
+    outconv48_unit,
     model_by_name,
     n_weights,
     FP8_LAYERS,

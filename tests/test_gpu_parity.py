@@ -42,6 +42,8 @@ def _need_gpu():
     ("outconv", 96, 3, 32),             # the same as its own launch
     ("outconv64", 60, 1, 0),            # 64-channel fused form; 10-frame buffers, 12-frame cache
     ("outconv64", 97, 3, 0),
+    ("outconv48", 64, 1, 0),            # 48 channels on a 64-row tile (16 padding rows), tanh, k7
+    ("outconv48", 97, 3, 0),
 ])
 def test_fp32_parity(name, frames, buf, options):
     sc = _sc()
@@ -214,7 +216,8 @@ def test_split_step_bitwise(prec):
 
 @pytest.mark.parametrize("name,prec", [("rave_b", "fp32"), ("rave_b", "bf16"), ("rave_b", "fp8"),
                                        ("outconv", "fp32"), ("outconv", "bf16"),
-                                       ("outconv64", "fp32"), ("outconv64", "bf16")])
+                                       ("outconv64", "fp32"), ("outconv64", "bf16"),
+                                       ("outconv48", "bf16")])   # (FP32 48-channel convs gather)
 def test_output_conv_fusion_matches(name, prec):
     """The decoder's one-channel output conv computed in the epilogue of the
     last window conv (plus the tail launch for frames whose taps cross a tile
