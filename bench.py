@@ -74,25 +74,25 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # sources the counters were taken with, and only for that model's nodes.
 MEASURED_TRAFFIC = {
     "model": "rave_b",
-    "sources_sha1": "39a0543dffe2a94f3535482401021a871e040bd3 23d2e340c591e6a99da03b7fd8ea31cb1b6ee22d c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "bb5fc8e4bf1cf867b3d2958a71adf37676fcc9cb c79a03733073668ab1f7b30274a164a00c989145 c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 773.2, 2727.1),
-        2: ('mfma', 10445.3, 17202.0),
+        1: ('mfma', 773.1, 2727.1),
+        2: ('mfma', 10445.4, 17201.9),
         4: ('mfma', 10295.1, 16938.8),
-        6: ('mfma', 11286.0, 18474.8),
-        8: ('mfma', 14157.5, 12302.2),
-        9: ('mfma', 5428.6, 32886.5),
-        11: ('mfma', 17112.9, 32736.5),
-        13: ('mfma', 17634.7, 33506.4),
-        15: ('mfma', 18953.8, 14237.2),
-        16: ('mfma', 6196.3, 43378.0),
-        20: ('mfma_win', 24778.6, 43633.3),
+        6: ('mfma', 11285.3, 18474.6),
+        8: ('mfma', 14158.0, 12302.2),
+        9: ('mfma', 5427.3, 32879.7),
+        11: ('mfma', 17121.4, 32732.0),
+        13: ('mfma', 17632.9, 33509.1),
+        15: ('mfma', 18959.5, 14237.3),
+        16: ('mfma', 6196.3, 43377.4),
+        20: ('mfma_win', 24775.5, 43633.2),
         22: ('mfma_win', 28490.9, 22712.6),
-        25: ('mfma_win', 11526.6, 43249.2),
-        29: ('mfma_win', 26052.7, 3318.2),
-        30: ('tail', 2110.9, 85.4),
+        25: ('mfma_win', 11528.4, 43249.2),
+        29: ('mfma_win', 26055.0, 3318.2),
+        30: ('tail', 2110.4, 85.4),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
@@ -144,11 +144,13 @@ def op_accounting(p, tail=None, layer=False, ct=None):
     `ct`: the layer computed inside this window conv's launch (the op before
     it, no launches of its own: a transposed conv, or the first conv of a
     fused residual pair): its FLOPs, input, state and weights count here,
-    and its output (this op's input) never reaches HBM."""
+    and its output (this op's input) never reaches HBM.  With both (a pair
+    whose second conv computes the output conv), neither conv's output
+    reaches HBM."""
     if ct is not None:
         x = p["frames_in"]
         rec = dict(ct, frames_in=x // ct["stride"], frames_out=x, entries=p["entries"], launches=p["launches"])
-        f1, b1 = op_accounting(p)
+        f1, b1 = op_accounting(p, tail=tail)
         f2, b2 = op_accounting(rec)
         return f1 + f2, b1 + b2 - 2 * 4.0 * x * p["cin"]
     fin, fout, ent, L = p["frames_in"], p["frames_out"], p["entries"], p["launches"]
@@ -208,7 +210,8 @@ def roofline(prof, model="rave_b"):
     input, output and state), so they are labelled design traffic."""
     best = max(prof, key=lambda p: p["ms"])
     ct = fused_producer(prof, best)
-    flops, byts = op_accounting(best, fused_tail(prof, best), ct=ct)
+    tail = fused_tail(prof, best)
+    flops, byts = op_accounting(best, tail, ct=ct)
     sec = best["ms"] * 1e-3
     peak_f = PEAK[best["precision"]] if best["impl"] >= 1 else PEAK[0]
     if best["impl"] in (1, 2) and best["cin"] >= WIDE_MIN_CHANNELS:
@@ -233,6 +236,9 @@ def roofline(prof, model="rave_b"):
     elif ct is not None:
         kernel += " with the residual conv node %d (cin %d, cout %d, k %d, d %d) in its launch" % (
             ct["node"], ct["cin"], ct["cout"], ct["k"], ct["dilation"])
+    if tail is not None:
+        kernel += " and the output conv node %d (cin %d, cout %d, k %d) in its epilogue" % (
+            tail["node"], tail["cin"], tail["cout"], tail["k"])
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": measured_traffic(best, model), "basis": basis,
             "flops_per_launch": round(flops / max(best["launches"], 1)),
@@ -330,9 +336,13 @@ def step_roofline(run, value, prec):
     written once per buffer; the roofline min(MFMA peak / FLOP, HBM / bytes)
     in samples/s at the step's precision, and the value as a fraction of it.
     The layer-by-layer figures (every layer's input and output through HBM,
-    op_accounting) are the design's own roofline, given beside it."""
+    op_accounting, except what a fused launch keeps on chip) are the design's
+    own roofline, given beside it."""
     prof, samples = run["prof"], run["samples"]
-    acc = [op_accounting(p, layer=True, ct=fused_producer(prof, p)) for p in prof]
+    # an output conv computed in the window conv before it counts with that conv
+    fused = {id(t) for t in (fused_tail(prof, p) for p in prof) if t is not None}
+    acc = [op_accounting(p, tail=fused_tail(prof, p), layer=True, ct=fused_producer(prof, p))
+           for p in prof if id(p) not in fused]
     flops = sum(a[0] for a in acc) / samples
     byts = run["algorithmic_bytes"] / samples
     lbl = sum(a[1] for a in acc) / samples

@@ -80,3 +80,28 @@ def test_measured_traffic_only_for_its_model():
     best = {"node": n, "impl": impl, "precision": 1}
     assert bench.measured_traffic(best, "wide") is None
     assert bench.measured_traffic(best, "autoencoder") is None
+
+
+def test_pair_with_fused_output_conv_accounting():
+    """A pair whose second conv also computes the one-channel output conv:
+    neither conv's 32-channel output reaches HBM, only the model output."""
+    a, b = _pair()
+    a = dict(a, cin=32, cout=32, node=27, dilation=3, cache_len=6)
+    b = dict(b, cin=32, cout=32, node=29, dilation=9, cache_len=18, frames_in=344064 * 10,
+             frames_out=344064 * 10)
+    t = {"node": 30, "kind": 1, "impl": 3, "precision": 0, "cin": 32, "cout": 1, "k": 7, "stride": 1,
+         "cache_len": 6, "dilation": 1, "launches": 10, "frames_in": 344064 * 10, "frames_out": 344064 * 10,
+         "entries": 2560, "ms": 0.06}
+    prof = [a, b, t]
+    assert bench.fused_tail(prof, b) is t and bench.fused_producer(prof, b) is a
+    x = b["frames_in"]
+    f, byts = bench.op_accounting(b, tail=t, ct=a)
+    f_b, b_b = bench.op_accounting(b, tail=t)
+    f_a, b_a = bench.op_accounting(dict(a, frames_in=x, frames_out=x, entries=b["entries"], launches=b["launches"]))
+    assert f == f_a + f_b == 2.0 * x * 32 * (32 * 3 * 2 + 7)
+    assert byts == b_a + b_b - 2 * 4.0 * x * 32
+    # the input of the first conv, the model output, caches and weights: no 32-channel output
+    assert byts < 4.0 * x * 32 + 4.0 * x * 1 + 4.0 * b["entries"] * 32 * 64 + 10 * 1e5
+    r = bench.roofline(prof)
+    assert "output conv node 30" in r["kernel"] and r["bound"] == "hbm"
+    assert r["layer_bytes_per_launch"] == round(byts / 10)
