@@ -1508,14 +1508,16 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
     const int32_t f0 = (b + 1) * tile_frames;
     const int32_t f = f0 + (idx - b * a.L);
     if (f >= step_out(a)) return;   // the grid may be sized for a larger step
-    const Entry e = load_entry(a.ents + entry_of_out(a, f));
-    const int32_t out_start = out_frames(a, e.off);
-    const int32_t t = f - out_start;
-    if (!(out_start < f0 && f - a.L < f0) || t < a.L) return;   // its tile's, or a stream start
+    // P of the frame's rows f - L .. f (all inside this step: f0 >= 2 L) are
+    // read together with the frame's stream record
     float p[kOutTaps];
 #pragma unroll
     for (int kk = 0; kk < kOutTaps; ++kk)
       p[kk] = kk < a.k ? gload<float>(a.in_buf + (int64_t)(f - a.L + a.dil * kk) * CIN + kk) : 0.f;
+    const Entry e = load_entry(a.ents + entry_of_out(a, f));
+    const int32_t out_start = out_frames(a, e.off);
+    const int32_t t = f - out_start;
+    if (!(out_start < f0 && f - a.L < f0) || t < a.L) return;   // its tile's, or a stream start
     float o = a.B[0];
 #pragma unroll
     for (int kk = 0; kk < kOutTaps; ++kk)
@@ -1531,8 +1533,20 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
   const int32_t ei = ((int32_t)blockIdx.x - bnd_blocks) * (kThreads / 64) + wave;
   const bool live = ei < step_ents(a);   // uniform in the wave
   const bool pre = a.pre_act != 0;
+  const Entry e = load_entry(a.ents + (live ? ei : 0));
+  // lane t < L finishes the stream's frame t: P of its rows past the cache
+  // (the stream's first frames, from out_buf) are read before the cache rows'
+  // P are formed
+  const int32_t t = lane;
+  const bool fin = live && t < a.L && t < out_frames(a, e.T);
+  const int32_t out_start = out_frames(a, e.off);
+  float q[kOutTaps];
+#pragma unroll
+  for (int kk = 0; kk < kOutTaps; ++kk) {
+    const int w = t + a.dil * kk;   // row of [cache | new frames]
+    q[kk] = fin && kk < a.k && w >= a.L ? gload<float>(a.in_buf + (int64_t)(out_start + w - a.L) * CIN + kk) : 0.f;
+  }
   if (live) {
-    const Entry e = load_entry(a.ents + ei);
     const float* cache = e.state + a.state_off + (int64_t)e.parity * a.state_len;
     f4 P = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1547,17 +1561,13 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
     if (lg < kOutTaps / 4) *reinterpret_cast<f4*>(&pc[wave][lr][lg * 4]) = P;   // [cache row][tap]
   }
   __syncthreads();
-  if (!live) return;
-  const Entry e = load_entry(a.ents + ei);
-  const int32_t t = lane;
-  if (t >= a.L || t >= out_frames(a, e.T)) return;
-  const int32_t out_start = out_frames(a, e.off);
+  if (!fin) return;
   float o = a.B[0];
 #pragma unroll
   for (int kk = 0; kk < kOutTaps; ++kk) {
     if (kk < a.k) {
-      const int w = t + a.dil * kk;   // row of [cache | new frames]
-      o = o + (w < a.L ? pc[wave][w][kk] : gload<float>(a.in_buf + (int64_t)(out_start + w - a.L) * CIN + kk));
+      const int w = t + a.dil * kk;
+      o = o + (w < a.L ? pc[wave][w][kk] : q[kk]);
     }
   }
   if (a.post_act == 2) o = tanhf(o);
