@@ -957,7 +957,8 @@ def main():
     for prec in [c for c in args.compare.split(",") if c and c != args.precision]:
         try:
             mod2 = make(prec)
-            r2 = timed_run(sc, torch, mod2, args.warmup, max(args.steps // 2, 4), graph=args.graph, shape=shape)
+            # the same steps (seeded buffer mix) as the headline run
+            r2 = timed_run(sc, torch, mod2, args.warmup, args.steps, graph=args.graph, shape=shape)
             comp[prec] = round(r2["samples"] / r2["gpu_s"], 1)
             mod2.close()
             if prec == "fp8" and m["name"] in scgen.FP8_LAYERS:
