@@ -1082,17 +1082,20 @@ struct PairSeg {
   int32_t abase;           // LDS row of A's window row ta
 };
 
-// MT: the channels of both convs (one M tile); waves split B's tile as the
-// window kernel does (WM row blocks x WN column halves) and A's columns the
-// same way.  NCBA: A column blocks a tile holds at most.  FUSE: B computes a
-// one-output-channel conv in its epilogue (fused_out_epilogue).
-template <int PREC, int MT, int NB, int KCM, int NCBA, bool FUSE>
+// MT: the rows of the M tile; CH: the channels of both convs (MT, or 48 on a
+// 64-row tile whose last 16 rows are padding: their lanes write nothing);
+// waves split B's tile as the window kernel does (WM row blocks x WN column
+// halves) and A's columns the same way.  NCBA: A column blocks a tile holds
+// at most.  FUSE: B computes a one-output-channel conv in its epilogue
+// (fused_out_epilogue).
+template <int PREC, int MT, int NB, int KCM, int NCBA, bool FUSE, int CH = MT>
 __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int n_nt, int Kpad, int Kreal,
                                                                 int row_cap, int arow_cap, int stash_cap,
                                                                 int extra_blocks, FastDiv fd_per_ent) {
   constexpr int WM = MT / 16;
   constexpr int WN = 4 / WM;
-  constexpr int C = MT;                        // channels of both convs
+  constexpr int C = CH;                        // channels of both convs
+  static_assert(C <= MT && C % 16 == 0, "the channels fill whole 16-row blocks of the tile");
   constexpr int F = NB * 16 * WN;
   constexpr int NCW = NCBA / WN;               // A column blocks of a wave
   static_assert(NCW % 2 == 0, "two groups of column blocks per wave");
@@ -1153,6 +1156,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   const int lr = lane & 15, lg = lane >> 4;
   const int wm = wave % WM, wn = wave / WM;
   const int m = wm * 16 + lg * 4;       // the lane's channels m .. m + 3 (both convs)
+  const bool m_ok = C == MT || m < C;   // (rows past C: padding)
   const bool pre_a = a.pa.pre_act != 0, pre_b = a.pre_act != 0;
   const float qs_a = PREC == 2 ? 1.0f / a.pa.act_scale : 1.0f;
   const float qs_b = PREC == 2 ? 1.0f / a.act_scale : 1.0f;
@@ -1172,14 +1176,15 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
       ahi[c] = *reinterpret_cast<const u4*>(wrow + c * 128 + 16);
     }
   }
-  const f4 bias_a = *reinterpret_cast<const f4*>(a.pa.B + m);
-  const f4 ws_a = PREC == 2 ? *reinterpret_cast<const f4*>(a.pa.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
-  const f4 bias_b = *reinterpret_cast<const f4*>(a.B + m);
-  const f4 ws_b = PREC == 2 ? *reinterpret_cast<const f4*>(a.wscale + m) : f4{1.f, 1.f, 1.f, 1.f};
+  const f4 f4z = {0.f, 0.f, 0.f, 0.f}, f4o = {1.f, 1.f, 1.f, 1.f};
+  const f4 bias_a = m_ok ? *reinterpret_cast<const f4*>(a.pa.B + m) : f4z;
+  const f4 ws_a = PREC == 2 && m_ok ? *reinterpret_cast<const f4*>(a.pa.wscale + m) : f4o;
+  const f4 bias_b = m_ok ? *reinterpret_cast<const f4*>(a.B + m) : f4z;
+  const f4 ws_b = PREC == 2 && m_ok ? *reinterpret_cast<const f4*>(a.wscale + m) : f4o;
   // fused output conv: the lane's A operand of its per-tap sums (tap lr, channels m .. m + 3)
-  f4 wa2 = {0.f, 0.f, 0.f, 0.f};
+  f4 wa2 = f4z;
   if constexpr (FUSE) {
-    if (lr < a.oc.k) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * MT + m);
+    if (lr < a.oc.k && m_ok) wa2 = *reinterpret_cast<const f4*>(a.oc.W + lr * C + m);
   }
 
   // ---- the streams of the tile: lane s of every wave forms stream s's
@@ -1334,7 +1339,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   }
   f4 skv[NCW];
 #pragma unroll
-  for (int i = 0; i < NCW; ++i) skv[i] = gload<f4>(askip[(wn * NCW + i) * 16 + lr] + m);
+  for (int i = 0; i < NCW; ++i) skv[i] = m_ok ? gload<f4>(askip[(wn * NCW + i) * 16 + lr] + m) : f4z;
   {
     const int32_t n_pieces = n_arows * PPR;
     for (int32_t i0 = 0; i0 < n_pieces; i0 += kThreads * SB) {
@@ -1408,7 +1413,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
 #pragma unroll
   for (int i = 0; i < NCW; ++i) {
     const int col = (nc0 + i) * 16 + lr;
-    if (nc0 + i >= ncba || col >= n_acol) continue;
+    if (nc0 + i >= ncba || col >= n_acol || !m_ok) continue;
     const int32_t jb = jbs[i];
     const int fl = fls[i];
     f4 v = aacc[i];
@@ -1458,7 +1463,7 @@ __global__ void __launch_bounds__(kThreads, 4) conv_pair_kernel(LayerArgs a, int
   for (int nb = 0; nb < NB; ++nb) {
     const int col = wn * (F / WN) + nb * 16 + lr;
     const int keep = colkeep[col];
-    if (keep < 0) continue;
+    if (keep < 0 || !m_ok) continue;
     const int32_t f = f0 + col;
     f4 v = acc[nb];
     if (PREC == 2) v = v * (ws_b * a.act_scale);
@@ -1758,14 +1763,15 @@ hipError_t launch_convt_win(const LayerArgs& a, int prec, int32_t row_cap, int32
 
 namespace {
 // x1 frames a pair tile computes at most (A column blocks x 16), by channels
-int pair_cols(int c) { return c == 64 ? 96 : 192; }
+int pair_cols(int c) { return c == 32 ? 192 : 96; }
 // A's window rows in operand form, overlaid by B's skip rows in FP32 (one per
 // tile column, row stride c + 4); B's window rows in operand form and A's row
 // sources, overlaid by the fused output conv's per-tap scratch
 int64_t pair_lds_bytes(int c, int64_t rows, int64_t arows, int prec, bool fuse) {
   const int64_t rowb = c * w_esize(prec) + 16;
-  const int64_t F = win_f(c, 4);
-  const int64_t scratch = fuse ? (int64_t)(c / 16) * kOutTaps * F * 4 : 0;
+  const int mt = win_mt(c);
+  const int64_t F = win_f(mt, 4);
+  const int64_t scratch = fuse ? (int64_t)(mt / 16) * kOutTaps * F * 4 : 0;
   return std::max(arows * rowb, F * (c + 4) * 4) + std::max(rows * rowb + arows * 8, scratch);
 }
 int pair_kchunks(int c, int k, int prec) {
@@ -1778,14 +1784,15 @@ int32_t conv_pair_rows(int c, int k, int dil_a, int dil_b, int prec, int64_t min
                        int32_t* arow_cap, int32_t* stash_cap) {
   *arow_cap = 0;
   *stash_cap = 0;
-  // instances: 64 channels (no fused output conv) and 32 channels (with or without)
-  if ((c != 64 && c != 32) || (c == 64 && fuse) || k != 3 || prec < 1 || prec > 2 || dil_a < 1 || dil_b < 1 ||
-      min_frames < 1)
+  // instances: 64 channels (no fused output conv), 48 (on a 64-row tile) and
+  // 32 channels (with or without)
+  if ((c != 64 && c != 48 && c != 32) || (c == 64 && fuse) || k != 3 || prec < 1 || prec > 2 || dil_a < 1 ||
+      dil_b < 1 || min_frames < 1)
     return 0;
   const int LA = dil_a * (k - 1), LB = dil_b * (k - 1);
   // every stream brings at least L_B frames: B's next cache comes from x1 alone
   if (min_frames < LB) return 0;
-  const int F = win_f(c, 4);
+  const int F = win_f(win_mt(c), 4);
   const int64_t max_seg = (F - 1 + min_frames - 1) / min_frames + 1;   // streams one tile may touch
   if (max_seg > kMaxStreams) return 0;
   const int64_t rows = F + (int64_t)LB * max_seg;     // B's window rows
@@ -1803,13 +1810,13 @@ hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32
                             hipStream_t s) {
   const int C = a.cout;
   const bool fuse = a.oc.k > 0;
-  const int F = win_f(C, 4);
+  const int F = win_f(win_mt(C), 4);
   const int kc = w_kchunk(prec);
   const int Kreal = a.k * C;
   const int Kpad = (Kreal + kc - 1) / kc * kc;
   const int KCM = pair_kchunks(C, a.k, prec);
-  if ((C != 64 && C != 32) || a.cin != C || a.k != 3 || a.pa.L != a.pa.dil * 2 || a.L != a.dil * 2 || !a.out_buf ||
-      a.fd_cin.d != (uint32_t)C || (fuse && (C != 32 || a.oc.k > kOutTaps)))
+  if ((C != 64 && C != 48 && C != 32) || a.cin != C || a.k != 3 || a.pa.L != a.pa.dil * 2 || a.L != a.dil * 2 ||
+      !a.out_buf || a.fd_cin.d != (uint32_t)C || (fuse && (C == 64 || a.oc.k > kOutTaps)))
     return hipErrorInvalidValue;
   const int64_t n_nt = (a.n_out + F - 1) / F;
   const int64_t items = (int64_t)a.n_ent * a.pa.L * C / 4;   // 4 channels per cache-update item
@@ -1818,14 +1825,17 @@ hipError_t launch_conv_pair(const LayerArgs& a, int prec, int32_t row_cap, int32
   if (grid <= 0) return hipSuccess;
   const size_t lds = (size_t)pair_lds_bytes(C, row_cap, arow_cap, prec, fuse);
   const FastDiv fd_per_ent = make_fastdiv((uint32_t)std::max(a.pa.L * C / 4, 1));
-#define SC_PAIR(P, M, K, NC, FU)                                                                            \
-  if (prec == P && C == M && KCM == K && fuse == FU) {                                                     \
-    hipLaunchKernelGGL((conv_pair_kernel<P, M, 4, K, NC, FU>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
-                       (int)n_nt, Kpad, Kreal, row_cap, arow_cap, stash_cap, extra, fd_per_ent);            \
+#define SC_PAIR(P, M, K, NC, FU, CHN)                                                                      \
+  if (prec == P && C == CHN && KCM == K && fuse == FU) {                                                   \
+    hipLaunchKernelGGL((conv_pair_kernel<P, M, 4, K, NC, FU, CHN>), dim3((unsigned)grid), dim3(kThreads), lds, s, \
+                       a, (int)n_nt, Kpad, Kreal, row_cap, arow_cap, stash_cap, extra, fd_per_ent);         \
     return hipGetLastError();                                                                              \
   }
-  SC_PAIR(1, 64, 3, 6, false) SC_PAIR(2, 64, 2, 6, false)
-  SC_PAIR(1, 32, 2, 12, false) SC_PAIR(1, 32, 2, 12, true) SC_PAIR(2, 32, 1, 12, false) SC_PAIR(2, 32, 1, 12, true)
+  SC_PAIR(1, 64, 3, 6, false, 64) SC_PAIR(2, 64, 2, 6, false, 64)
+  SC_PAIR(1, 64, 3, 6, false, 48) SC_PAIR(1, 64, 3, 6, true, 48) SC_PAIR(2, 64, 2, 6, false, 48)
+  SC_PAIR(2, 64, 2, 6, true, 48)
+  SC_PAIR(1, 32, 2, 12, false, 32) SC_PAIR(1, 32, 2, 12, true, 32) SC_PAIR(2, 32, 1, 12, false, 32)
+  SC_PAIR(2, 32, 1, 12, true, 32)
 #undef SC_PAIR
   return hipErrorInvalidValue;
 }

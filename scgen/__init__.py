@@ -19,6 +19,7 @@ from .models import (  # noqa: F401
     outconv_unit,
     outconv64_unit,
     outconv48_unit,
+    pair48_unit,
     model_by_name,
     n_weights,
     FP8_LAYERS,

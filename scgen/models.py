@@ -213,9 +213,25 @@ def outconv48_unit():
     return {"name": "outconv48", "nodes": nodes, "in_channels": 8, "out_channels": 1}
 
 
+def pair48_unit():
+    """Input conv 8->64 (k3), a transposed conv 64->48 (ratio 32), two residual
+    blocks x + Conv_k3,d(LeakyReLU(x)) at 48 channels (d = 1 then 3: a pair of
+    residual convs on a 64-row tile with 16 padding rows), then the decoder's
+    output conv tanh(Conv_k7(LeakyReLU(x))) to one channel."""
+    nodes = [_input(8),
+             _conv(0, 8, 64, 3, 1),
+             _convt(1, 64, 48, 32),
+             _conv(2, 48, 48, 3, 1, pre_act=ACT_LRELU),
+             _add(2, 3),
+             _conv(4, 48, 48, 3, 3, pre_act=ACT_LRELU),
+             _add(4, 5),
+             _conv(6, 48, 1, 7, 1, pre_act=ACT_LRELU, post_act=ACT_TANH)]
+    return {"name": "pair48", "nodes": nodes, "in_channels": 8, "out_channels": 1}
+
+
 def model_by_name(name):
     table = {"stack3": stack3, "rave_b": rave_decoder_b, "wide": wide_decoder, "outconv": outconv_unit,
-             "autoencoder": autoencoder, "outconv64": outconv64_unit, "outconv48": outconv48_unit,
+             "autoencoder": autoencoder, "outconv64": outconv64_unit, "outconv48": outconv48_unit, "pair48": pair48_unit,
              "strided": lambda: strided_unit(False),
              "strided_aligned": lambda: strided_unit(True),
              "branch": branch_unit, "branch3": branch3_unit, "encoder": encoder}

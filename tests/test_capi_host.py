@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 
 @pytest.mark.parametrize("name", ["stack3", "rave_b", "wide", "strided", "strided_aligned", "branch", "branch3",
-                                  "encoder", "autoencoder", "outconv", "outconv64", "outconv48"])
+                                  "encoder", "autoencoder", "outconv", "outconv64", "outconv48", "pair48"])
 def test_planner_matches_golden(name):
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "delays.json")))[name]
     info = sc.plan(scgen.model_by_name(name))

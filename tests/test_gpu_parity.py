@@ -44,6 +44,7 @@ def _need_gpu():
     ("outconv64", 97, 3, 0),
     ("outconv48", 64, 1, 0),            # 48 channels on a 64-row tile (16 padding rows), tanh, k7
     ("outconv48", 97, 3, 0),
+    ("pair48", 61, 2, 0),
 ])
 def test_fp32_parity(name, frames, buf, options):
     sc = _sc()

@@ -198,6 +198,35 @@ def test_conv_pair_fusion_bitwise(prec, split):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("name,prec", [("pair48", "bf16"), ("pair48", "fp8"), ("wide", "bf16")])
+def test_conv_pair_48_channels_bitwise(name, prec):
+    """The residual pair on a 64-row tile with 48 channels (16 padding rows;
+    the unit model's second conv also computes the output conv) gives bitwise
+    the same streams as two launches: many streams of uneven buffers, split
+    and unsplit steps, state carried across steps."""
+    sc = _sc()
+    m, w = weights_for(name)
+    c = m["in_channels"]
+    scales = _fp8_scales(sc, m, w, c) if prec == "fp8" else None
+    rng = np.random.default_rng(23)
+    n_str = 40 if name == "wide" else 64
+    choices = [1, 2, 3, 5, 8] if name == "wide" else [1, 2, 4, 8, 16, 32]
+    lens = [[int(v) for v in rng.choice(choices, size=3)] for _ in range(n_str)]
+    xs = [scgen.stream_latents(c, sum(l), 1300 + i) for i, l in enumerate(lens)]
+    for base in (0, sc._native.SC_MODEL_NO_SPLIT):
+        fused = _model(sc, m, w, prec, scales, options=base)
+        fused.profile(True)
+        a = _batched_streams(sc, fused, xs, lens)
+        idle = [p["node"] for p in fused.profile_read() if p["kind"] == 1 and p["launches"] == 0]
+        fused.profile(False)
+        log("48-channel pair %s %s options=%d: conv nodes inside the next launch: %s" % (name, prec, base, idle))
+        assert len(idle) == 1, idle
+        b = _batched_streams(sc, _model(sc, m, w, prec, scales, options=base | sc._native.SC_MODEL_NO_PAIR_FUSION),
+                             xs, lens)
+        for i in range(n_str):
+            assert np.array_equal(a[i], b[i]), (base, i)
+
+
 def test_mfma_fp32_matches_wavefront_fp32():
     """The FP32 MFMA path (input conv included) and the FP32 wavefront path
     sum in different orders; each is pinned to the FP64 oracle at 1e-5 by the

@@ -230,7 +230,7 @@ def _golden_delays():
 
 
 @pytest.mark.parametrize("name", ["stack3", "rave_b", "wide", "strided", "strided_aligned", "branch", "branch3",
-                                  "encoder", "autoencoder", "outconv", "outconv64", "outconv48"])
+                                  "encoder", "autoencoder", "outconv", "outconv64", "outconv48", "pair48"])
 def test_latency_and_warmup_closed_form(name):
     g = _golden_delays()[name]
     m = scgen.model_by_name(name)
@@ -242,7 +242,7 @@ def test_latency_and_warmup_closed_form(name):
 @pytest.mark.parametrize("name,frames,buf", [("stack3", 2048, 64), ("rave_b", 48, 5),
                                              ("strided", 64, 6), ("strided_aligned", 64, 4),
                                              ("branch", 60, 7), ("branch3", 61, 5),
-                                             ("outconv", 40, 3), ("outconv64", 48, 5), ("outconv48", 40, 3),
+                                             ("outconv", 40, 3), ("outconv64", 48, 5), ("outconv48", 40, 3), ("pair48", 40, 3),
                                              ("autoencoder", 128 * 40, 128 * 5)])
 def test_latency_and_warmup_empirical(name, frames, buf):
     """Brute-force search: the only lag at which the streamed output matches
