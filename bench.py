@@ -74,25 +74,25 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # sources the counters were taken with, and only for that model's nodes.
 MEASURED_TRAFFIC = {
     "model": "rave_b",
-    "sources_sha1": "bb5fc8e4bf1cf867b3d2958a71adf37676fcc9cb e62cd86d3c689ec83cfe968046cc6e976699a970 c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "bb5fc8e4bf1cf867b3d2958a71adf37676fcc9cb c954f83fbda6c3bb57850b0b56d8e60e72515f04 c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 773.1, 2727.1),
-        2: ('mfma', 10445.4, 17201.7),
-        4: ('mfma', 10295.1, 16938.8),
-        6: ('mfma', 11285.6, 18474.5),
-        8: ('mfma', 14159.5, 12302.2),
-        9: ('mfma', 5419.0, 32886.4),
-        11: ('mfma', 17115.9, 32735.2),
-        13: ('mfma', 17639.5, 33507.1),
-        15: ('mfma', 18954.8, 14236.9),
-        16: ('mfma', 6196.3, 43377.2),
-        20: ('mfma_win', 24773.9, 43633.3),
-        22: ('mfma_win', 28489.2, 22712.6),
-        25: ('mfma_win', 11522.8, 43249.2),
-        29: ('mfma_win', 26055.3, 3318.2),
-        30: ('tail', 2281.4, 85.4),
+        1: ('mfma', 773.2, 2727.1),
+        2: ('mfma', 10445.3, 17201.6),
+        4: ('mfma', 10295.1, 16939.1),
+        6: ('mfma', 11286.1, 18474.8),
+        8: ('mfma', 14157.7, 12302.2),
+        9: ('mfma', 5428.0, 32890.9),
+        11: ('mfma', 17112.2, 32734.6),
+        13: ('mfma', 17632.8, 33506.8),
+        15: ('mfma', 18954.2, 14237.1),
+        16: ('mfma', 6196.3, 43377.9),
+        20: ('mfma_win', 24774.3, 43633.2),
+        22: ('mfma_win', 28491.0, 22712.6),
+        25: ('mfma_win', 11530.1, 43249.2),
+        29: ('mfma_win', 26055.4, 3318.2),
+        30: ('tail', 2284.4, 85.4),
     },
 }
 TRAFFIC_SOURCES = ('kernels_mfma.hip', 'kernels_win.hip', 'kernels_valu.hip', 'kernels.h', 'sc_device.h')
