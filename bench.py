@@ -931,7 +931,8 @@ def main():
     used = sorted({p["precision"] for p in prof if p["impl"] >= 1})
     value = run["samples"] / run["gpu_s"]
     out = {
-        "metric": "output audio samples/sec at 256 streams (BF16/FP8 vs FP32); p99 buffer latency",
+        "metric": ("output audio samples/sec at 256 streams (BF16/FP8 vs FP32); p99 buffer latency"
+                   if shape is HEADLINE else "output audio samples/sec at %d streams (%s)" % (shape.streams, shape.name)),
         "value": round(value, 1),
         "unit": "samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
