@@ -966,6 +966,8 @@ def main():
                 comp["fp8_plan"] = ("layers %s on FP8 e4m3 (%s), the other wide layers on BF16; "
                                     "SNR target met" % (list(scgen.FP8_LAYERS[m["name"]]),
                                                         ", ".join(fp8_layer_names(m))))
+            elif prec == "fp8":
+                comp["fp8_plan"] = "no mixed plan for this model: every wide layer on e4m3 (as fp8_all)"
             if prec == "fp8_all":
                 comp["fp8_all_parity"] = ("unmet: every wide layer on e4m3 reaches ~19 dB against the FP64 "
                                           "oracle (target 30 dB); throughput for reference only")
