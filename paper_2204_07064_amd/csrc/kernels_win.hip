@@ -1585,9 +1585,10 @@ __global__ void __launch_bounds__(kThreads) conv_out_tail_kernel(LayerArgs a, in
 int32_t conv_win_tile_frames(int cin, int cout) { return win_f(win_mt(cout), win_nb(cin)); }
 
 bool conv_win_out_fusable(int cin, int cout, int k, int dil) {
-  // all output channels in one M tile, a tile shape with fused variants, and
-  // the taps of a boundary frame reaching no further than the previous tile
-  if (cout > win_mt(cout) || cout % 16 != 0 || win_nb(cin) != 4 || k < 1 || k > kOutTaps || dil < 1) return false;
+  // all output channels in one M tile (the tail launch has instances for 32,
+  // 48 and 64), a tile shape with fused variants, and the taps of a boundary
+  // frame reaching no further than the previous tile
+  if ((cout != 32 && cout != 48 && cout != 64) || win_nb(cin) != 4 || k < 1 || k > kOutTaps || dil < 1) return false;
   const int L = dil * (k - 1);
   return L <= 16 && 2 * L <= conv_win_tile_frames(cin, cout);   // the tail forms P of <= 16 cache rows
 }
