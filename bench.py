@@ -74,24 +74,24 @@ IMPL_NAME = {0: "valu", 1: "mfma", 2: "mfma_win", 3: "tail"}
 # sources the counters were taken with, and only for that model's nodes.
 MEASURED_TRAFFIC = {
     "model": "rave_b",
-    "sources_sha1": "bb5fc8e4bf1cf867b3d2958a71adf37676fcc9cb c954f83fbda6c3bb57850b0b56d8e60e72515f04 c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
+    "sources_sha1": "bb5fc8e4bf1cf867b3d2958a71adf37676fcc9cb a55555ece14aca1b23d61c87421555991a559fec c475d43d80ff2b54661b0920e2ae957339dc5b81 a27b348627b2f04f320574027b287d93ccfe12bd 4bdff7cd723c7bc3733e9614a9bbbbdc7c48bc6a",
     "fetch_bytes_per_kib": 2457.30, "write_bytes_per_kib": 1024.0,
     # node: (kernel family, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "by_node": {
-        1: ('mfma', 773.2, 2727.1),
-        2: ('mfma', 10445.3, 17201.6),
-        4: ('mfma', 10295.1, 16939.1),
-        6: ('mfma', 11286.1, 18474.8),
-        8: ('mfma', 14157.7, 12302.2),
-        9: ('mfma', 5428.0, 32890.9),
-        11: ('mfma', 17112.2, 32734.6),
-        13: ('mfma', 17632.8, 33506.8),
-        15: ('mfma', 18954.2, 14237.1),
+        1: ('mfma', 773.1, 2727.1),
+        2: ('mfma', 10445.5, 17202.1),
+        4: ('mfma', 10295.1, 16938.6),
+        6: ('mfma', 11285.9, 18475.4),
+        8: ('mfma', 14158.4, 12302.2),
+        9: ('mfma', 5433.4, 32886.2),
+        11: ('mfma', 17112.6, 32731.6),
+        13: ('mfma', 17637.3, 33502.9),
+        15: ('mfma', 18956.2, 14237.0),
         16: ('mfma', 6196.3, 43377.9),
-        20: ('mfma_win', 24774.3, 43633.2),
-        22: ('mfma_win', 28491.0, 22712.6),
-        25: ('mfma_win', 11530.1, 43249.2),
-        29: ('mfma_win', 26055.4, 3318.2),
+        20: ('mfma_win', 24773.6, 43633.2),
+        22: ('mfma_win', 28491.7, 22712.6),
+        25: ('mfma_win', 11530.0, 43249.2),
+        29: ('mfma_win', 26055.3, 3318.2),
         30: ('tail', 2284.4, 85.4),
     },
 }
